@@ -1,0 +1,212 @@
+"""Plain FP64 CPU oracle (test infrastructure only).
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this package.  It wraps ``oracle.c`` (see its header for the
+equations and readings it follows) with ctypes over numpy arrays, and adds the
+tiny-grid numpy tools in :mod:`oracle.tiny`.
+
+Grid description used throughout: a mapping with keys ``n`` (3 ints),
+``coord`` (0 Cartesian z/y/x in km, 1 spherical r km / latitude rad /
+longitude rad), ``o`` and ``h`` (3 floats each).  Fields are numpy float64
+arrays of shape ``n`` (axis 2 fastest).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+        _lib = ctypes.CDLL(path)
+        _lib.tto_misfit.restype = ctypes.c_double
+        _lib.tto_lf_update.restype = ctypes.c_double
+    return _lib
+
+
+def _d(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], "oracle needs contiguous float64"
+    return a.ctypes.data_as(_D)
+
+
+def _i(a):
+    assert a.dtype == np.int32 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_I)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _grid_args(grid):
+    n = np.asarray(grid["n"], dtype=np.int32)
+    o = np.asarray(grid["o"], dtype=np.float64)
+    h = np.asarray(grid["h"], dtype=np.float64)
+    return n, int(grid["coord"]), o, h
+
+
+def _shape(grid):
+    return tuple(int(v) for v in grid["n"])
+
+
+def source_params(grid, s, xi, eta, src_pos):
+    """s0, xi0, eta0 at each source: trilinear interpolation of the model."""
+    n, coord, o, h = _grid_args(grid)
+    src_pos = _f64(src_pos).reshape(-1, 3)
+    out = np.zeros_like(src_pos)
+    rc = lib().tto_source_params(_i(n), coord, _d(o), _d(h), _d(_f64(s)), _d(_f64(xi)), _d(_f64(eta)),
+                                 len(src_pos), _d(src_pos), _d(out))
+    if rc:
+        raise ValueError("source outside the grid")
+    return out
+
+
+def forward(grid, s, xi, eta, src_pos, src_par, kappa, tol, max_iter, order=0, tau_init=None):
+    """One-source forward solve.  Returns (tau, iters, converged, eps_history)."""
+    n, coord, o, h = _grid_args(grid)
+    tau = np.empty(_shape(grid), dtype=np.float64)
+    iters, conv = ctypes.c_int(0), ctypes.c_int(0)
+    hist = np.zeros(max_iter, dtype=np.float64)
+    rc = lib().tto_forward(_i(n), coord, _d(o), _d(h), _d(_f64(s)), _d(_f64(xi)), _d(_f64(eta)),
+                           _d(_f64(src_pos)), _d(_f64(src_par)), ctypes.c_double(kappa),
+                           ctypes.c_double(tol), int(max_iter), int(order),
+                           _d(_f64(tau_init)) if tau_init is not None else None, _d(tau),
+                           ctypes.byref(iters), ctypes.byref(conv), _d(hist))
+    if rc:
+        raise ValueError("invalid arguments")
+    return tau, iters.value, bool(conv.value), hist[: iters.value].copy()
+
+
+def lf_update(grid, s, xi, eta, src_pos, src_par, kappa, tau, i, j, k):
+    n, coord, o, h = _grid_args(grid)
+    return lib().tto_lf_update(_i(n), coord, _d(o), _d(h), _d(_f64(s)), _d(_f64(xi)), _d(_f64(eta)),
+                               _d(_f64(src_pos)), _d(_f64(src_par)), ctypes.c_double(kappa),
+                               _d(_f64(tau)), int(i), int(j), int(k))
+
+
+def factor_field(grid, src_pos, src_par):
+    """T0 [n] and its scaled gradient t [3, n]."""
+    n, coord, o, h = _grid_args(grid)
+    T0 = np.empty(_shape(grid))
+    t = np.empty((3,) + _shape(grid))
+    lib().tto_factor_field(_i(n), coord, _d(o), _d(h), _d(_f64(src_pos)), _d(_f64(src_par)), _d(T0), _d(t))
+    return T0, t
+
+
+def fixed_base(grid, src_pos):
+    n, coord, o, h = _grid_args(grid)
+    fb = np.zeros(3, dtype=np.int32)
+    lib().tto_fixed_base(_i(n), coord, _d(o), _d(h), _d(_f64(src_pos)), _i(fb))
+    return tuple(int(v) for v in fb)
+
+
+def sample(grid, src_pos, src_par, tau, rec_pos):
+    """T at receivers for one source."""
+    n, coord, o, h = _grid_args(grid)
+    rec_pos = _f64(rec_pos).reshape(-1, 3)
+    out = np.zeros(len(rec_pos))
+    rc = lib().tto_sample(_i(n), coord, _d(o), _d(h), _d(_f64(src_pos)), _d(_f64(src_par)), _d(_f64(tau)),
+                          len(rec_pos), _d(rec_pos), _d(out))
+    if rc:
+        raise ValueError("receiver outside the grid")
+    return out
+
+
+def misfit(T, T_obs, w=None, pairs=None, wpair=None, alpha=1.0, beta=1.0):
+    """chi and R = d chi / d T for [nsrc, nrec] traveltimes."""
+    T = _f64(T)
+    nsrc, nrec = T.shape
+    R = np.zeros_like(T)
+    if pairs is None:
+        pairs_a = np.zeros((0, 2), dtype=np.int32)
+    else:
+        pairs_a = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    chi = lib().tto_misfit(nsrc, nrec, _d(T), _d(_f64(T_obs)), _d(_f64(w)) if w is not None else None,
+                           len(pairs_a), _i(pairs_a), _d(_f64(wpair)) if wpair is not None else None,
+                           ctypes.c_double(alpha), ctypes.c_double(beta), _d(R))
+    return chi, R
+
+
+def adjoint_rhs(grid, src_pos, src_par, rec_pos, R):
+    n, coord, o, h = _grid_args(grid)
+    rec_pos = _f64(rec_pos).reshape(-1, 3)
+    g = np.zeros(_shape(grid))
+    rc = lib().tto_adjoint_rhs(_i(n), coord, _d(o), _d(h), _d(_f64(src_pos)), _d(_f64(src_par)),
+                               len(rec_pos), _d(rec_pos), _d(_f64(R)), _d(g))
+    if rc:
+        raise ValueError("receiver outside the grid")
+    return g
+
+
+def adjoint_coeffs(grid, s, xi, eta, src_pos, src_par, kappa, tau):
+    """[7, n]: alpha_0..2, beta_0..2, J_xx at interior non-fixed nodes."""
+    n, coord, o, h = _grid_args(grid)
+    out = np.zeros((7,) + _shape(grid))
+    lib().tto_adjoint_coeffs(_i(n), coord, _d(o), _d(h), _d(_f64(s)), _d(_f64(xi)), _d(_f64(eta)),
+                             _d(_f64(src_pos)), _d(_f64(src_par)), ctypes.c_double(kappa), _d(_f64(tau)), _d(out))
+    return out
+
+
+def adjoint(grid, s, xi, eta, src_pos, src_par, kappa, tau, rhs, tol, max_iter, order=0):
+    """Solve J^T lambda = rhs by transposed Gauss-Seidel sweeps.
+    Returns (lambda, iters, converged, eps_history)."""
+    n, coord, o, h = _grid_args(grid)
+    lam = np.zeros(_shape(grid))
+    iters, conv = ctypes.c_int(0), ctypes.c_int(0)
+    hist = np.zeros(max_iter)
+    rc = lib().tto_adjoint(_i(n), coord, _d(o), _d(h), _d(_f64(s)), _d(_f64(xi)), _d(_f64(eta)),
+                           _d(_f64(src_pos)), _d(_f64(src_par)), ctypes.c_double(kappa), _d(_f64(tau)),
+                           _d(_f64(rhs)), ctypes.c_double(tol), int(max_iter), int(order), _d(lam),
+                           ctypes.byref(iters), ctypes.byref(conv), _d(hist))
+    if rc:
+        raise ValueError("invalid arguments")
+    return lam, iters.value, bool(conv.value), hist[: iters.value].copy()
+
+
+def kernel(grid, s, xi, eta, src_pos, src_par, kappa, tau, lam, grad=None):
+    """Discrete gradients [3, n] (d chi/d s, d chi/d xi, d chi/d eta); adds to grad if given."""
+    n, coord, o, h = _grid_args(grid)
+    acc = grad is not None
+    if grad is None:
+        grad = np.zeros((3,) + _shape(grid))
+    lib().tto_kernel(_i(n), coord, _d(o), _d(h), _d(_f64(s)), _d(_f64(xi)), _d(_f64(eta)),
+                     _d(_f64(src_pos)), _d(_f64(src_par)), ctypes.c_double(kappa), _d(_f64(tau)),
+                     _d(_f64(lam)), _d(grad), int(acc))
+    return grad
+
+
+def node_volume(grid):
+    n, coord, o, h = _grid_args(grid)
+    V = np.zeros(_shape(grid))
+    lib().tto_node_volume(_i(n), coord, _d(o), _d(h), _d(V))
+    return V
+
+
+def solve_source(grid, s, xi, eta, src_pos, src_par, kappa, rec_pos, T_obs=None, R=None,
+                 tol=1e-6, adj_tol=None, max_iter=2000, w=None):
+    """Forward + sample + (misfit) + adjoint + kernel for one source (chi_t only).
+    Returns a dict with tau, T_rec, R, lam, grad and iteration counts."""
+    tau, it_f, cf, _ = forward(grid, s, xi, eta, src_pos, src_par, kappa, tol, max_iter)
+    T_rec = sample(grid, src_pos, src_par, tau, rec_pos)
+    chi = None
+    if R is None:
+        chi, Rm = misfit(T_rec[None, :], np.asarray(T_obs)[None, :], None if w is None else np.asarray(w)[None, :])
+        R = Rm[0]
+    g = adjoint_rhs(grid, src_pos, src_par, rec_pos, R)
+    lam, it_a, ca, _ = adjoint(grid, s, xi, eta, src_pos, src_par, kappa, tau, g,
+                               adj_tol if adj_tol is not None else tol, max_iter)
+    grad = kernel(grid, s, xi, eta, src_pos, src_par, kappa, tau, lam)
+    return dict(tau=tau, T_rec=T_rec, chi=chi, R=R, lam=lam, grad=grad, it_f=it_f, it_a=it_a,
+                conv_f=cf, conv_a=ca)
