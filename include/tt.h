@@ -1,0 +1,144 @@
+/*
+ * tt.h -- C ABI of the MI355X adjoint-state traveltime library (libtt.so).
+ *
+ * Per-source hot path of adjoint-state traveltime tomography (Chen, Nagaso, Xu
+ * & Tong, "TomoATT", arXiv 2412.00031): fast-sweeping solves of the factored
+ * anisotropic Eikonal equation (Sec. 2.1 step 1, Eq. (4); Sec. 3.1), solves of
+ * the discrete adjoint-state equation (Sec. 2.1 step 2, Eq. (5)), and the
+ * sensitivity kernels summed over sources (Eqs. (6)-(9)).
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer to caller-owned, contiguous
+ *     memory; the library never frees or retains it.  Fields are FP64,
+ *     shape [n0][n1][n2] with axis 2 fastest (N = n0*n1*n2 values).  Batched
+ *     fields are [nsrc][N].
+ *   - Axes: coord = 0 Cartesian (z depth, y, x; km), coord = 1 spherical
+ *     (r km ascending with the first index, latitude rad, longitude rad).
+ *     Node (i,j,k) sits at o + (i,j,k) * h.  Every n_a >= 4.
+ *   - Positions (sources, receivers) are [count][3] in the same axis units.
+ *   - stream is a hipStream_t (NULL = default stream).  Work is enqueued on it;
+ *     tt_forward and tt_adjoint additionally wait on it (they poll convergence
+ *     from the host between iterations); the others return without waiting.
+ *   - Workspace: ws/ws_bytes is caller-owned device memory of at least
+ *     tt_workspace_size(...) bytes for the same arguments; its contents on
+ *     entry do not matter and are scratch on exit.  Calls that overlap in
+ *     time must not share a workspace.
+ *   - Receivers and sources are expected inside the grid; positions outside
+ *     are clamped to the nearest cell on the device (the host cannot read
+ *     device data without a synchronisation).
+ *   - Return value: TT_OK, TT_EINVAL (bad arguments, checked on the host before
+ *     anything is enqueued: NULL pointers, sizes, n_a < 4, h <= 0, tol <= 0,
+ *     kappa <= 0, max_iter < 1, too small a workspace), TT_EHIP (a HIP runtime
+ *     error).  tt_last_error() describes the last failure of the calling
+ *     thread.  Conditions that only the device can see (a source that does not
+ *     converge within max_iter) are reported per source in status[].
+ */
+#ifndef TT_H
+#define TT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TT_OK 0
+#define TT_EINVAL (-1)
+#define TT_EHIP (-2)
+
+typedef struct tt_grid {
+    int32_t n[3];   /* nodes per axis, each >= 4 */
+    int32_t coord;  /* 0 Cartesian, 1 spherical */
+    double o[3];    /* coordinate of node 0 per axis */
+    double h[3];    /* spacing per axis, > 0 */
+} tt_grid;
+
+typedef struct tt_opts {
+    double tol;        /* stop at the first iteration whose convergence measure is < tol */
+    int32_t max_iter;  /* >= 1 */
+    double kappa;      /* Lax-Friedrichs viscosity factor, >= max sqrt(1 + 2|xi|) */
+    int32_t tile_k;    /* k-extent of one sweep tile; 0 = library default */
+    int32_t flags;     /* reserved, 0 */
+} tt_opts;
+
+/* Bytes of device workspace needed by tt_forward (which = 0), tt_adjoint
+ * (which = 1), tt_sample (which = 2) or tt_kernel (which = 3) for this grid,
+ * source count and options (tile_k matters; opts may be NULL for defaults).
+ * Returns 0 for invalid arguments. */
+size_t tt_workspace_size(const tt_grid* grid, int32_t nsrc, const tt_opts* opts, int32_t which);
+
+/* Source constants s0, xi0, eta0 of the factorisation T = T0 * tau: the model
+ * interpolated trilinearly at each source (factor of Sec. 3.1).
+ * src_par out: [nsrc][3].  Sources must lie inside the grid (device-side
+ * clamping to the domain; the host cannot check device positions). */
+int tt_source_params(const tt_grid* grid, const double* s, const double* xi, const double* eta,
+                     int32_t nsrc, const double* src_pos, double* src_par, void* stream);
+
+/* Forward solve of Eq. (4) for nsrc sources (Sec. 2.1 step 1, Sec. 3.1):
+ * factored first-order Lax-Friedrichs fast sweeping, 8 directions per
+ * iteration, each directional sweep parallel over 3-D tiles on tile
+ * hyperplanes, every sweep followed by a boundary extrapolation pass.
+ *   s, xi, eta [N]      model (slowness s/km, azimuthal anisotropy xi, eta)
+ *   src_pos [nsrc][3]   source positions; src_par [nsrc][3] = s0, xi0, eta0
+ *   tau_init [nsrc][N]  initial tau (warm start) or NULL for tau = 1
+ *   tau [nsrc][N]       out: tau, with traveltime T = T0 * tau
+ *   status [nsrc]       out: iterations done if converged, -iterations if
+ *                       max_iter was reached without convergence
+ * tau may alias tau_init.  Waits for completion. */
+int tt_forward(const tt_grid* grid, const double* s, const double* xi, const double* eta,
+               int32_t nsrc, const double* src_pos, const double* src_par, const double* tau_init,
+               const tt_opts* opts, double* tau, int32_t* status, void* ws, size_t ws_bytes,
+               void* stream);
+
+/* Traveltimes at receivers, T(x_r) = sum_c w_c T0(c) tau(c) over the trilinear
+ * corners c of the receiver's cell (receiver term of Eqs. (2), (3)).
+ *   tau [nsrc][N], rec_pos [nrec][3], T_rec out [nsrc][nrec]. */
+int tt_sample(const tt_grid* grid, int32_t nsrc, const double* src_pos, const double* src_par,
+              const double* tau, int32_t nrec, const double* rec_pos, double* T_rec, void* ws,
+              size_t ws_bytes, void* stream);
+
+/* Misfit chi = alpha*chi_t + beta*chi_cs (Eqs. (1)-(3)) and adjoint sources
+ * R = d chi / d T(x_r) (Eqs. (A1)-(A3)).
+ *   T_rec, T_obs [nsrc][nrec]; w [nsrc][nrec] or NULL (= 1);
+ *   pairs [npair][2] receiver index pairs shared by every source, each
+ *   unordered pair listed once (npair may be 0, pairs NULL); wpair
+ *   [nsrc][npair] or NULL (= 1).
+ *   R out [nsrc][nrec]; chi out [1] (device scalar). */
+int tt_misfit(int32_t nsrc, int32_t nrec, const double* T_rec, const double* T_obs, const double* w,
+              int32_t npair, const int32_t* pairs, const double* wpair, double alpha, double beta,
+              double* R, double* chi, void* stream);
+
+/* Adjoint solve (Sec. 2.1 step 2, Eq. (5)) as the exact transpose of the
+ * discrete forward system at the converged tau: J^T lambda = d chi / d tau with
+ * d chi / d tau(c) = sum_m R_m w_c(m) T0(c).  Gauss-Seidel sweeps in the same 8
+ * directions and tiles, each followed by the transposed boundary pass.
+ *   tau [nsrc][N] converged forward fields; rec_pos [nrec][3];
+ *   R [nsrc][nrec] adjoint sources (e.g. from tt_misfit);
+ *   lam [nsrc][N] out: adjoint field (0 on boundary rows of fixed nodes);
+ *   status [nsrc] out: as for tt_forward; the convergence measure is
+ *   sum|d lambda| / sum|lambda| over one iteration.
+ * Waits for completion. */
+int tt_adjoint(const tt_grid* grid, const double* s, const double* xi, const double* eta,
+               int32_t nsrc, const double* src_pos, const double* src_par, const double* tau,
+               int32_t nrec, const double* rec_pos, const double* R, const tt_opts* opts,
+               double* lam, int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/* Sensitivity kernels (Eqs. (6)-(8)) as discrete gradients summed over sources
+ * in ascending source order (Eq. (9) relates them to K_s, K_xi, K_eta):
+ *   grad[0] = d chi/d s   = sum_n lambda_n,
+ *   grad[1] = d chi/d xi  = sum_n lambda_n (P_theta^2 - P_phi^2) / H,
+ *   grad[2] = d chi/d eta = sum_n -2 lambda_n P_theta P_phi / H,
+ * zero on boundary and fixed nodes.  grad [3][N]; accumulate != 0 adds to it. */
+int tt_kernel(const tt_grid* grid, const double* s, const double* xi, const double* eta, int32_t nsrc,
+              const double* src_pos, const double* src_par, const double* tau, const double* lam,
+              double* grad, int32_t accumulate, void* ws, size_t ws_bytes, void* stream);
+
+/* Message for the last nonzero return of the calling thread ("" if none). */
+const char* tt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TT_H */

@@ -1,0 +1,184 @@
+"""Python binding of libtt: argument marshalling over torch device tensors.
+
+Every function here hands device pointers to the C ABI (include/tt.h) and
+returns torch tensors; no step of the computation happens in Python.  PyTorch
+provides device memory and the current stream only.
+
+Grid description: a mapping with ``n`` (3 ints), ``coord`` (0 Cartesian
+z/y/x km, 1 spherical r km / latitude rad / longitude rad), ``o`` and ``h``.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+
+_F64 = torch.float64
+
+
+def _grid(grid):
+    g = _lib.TTGrid()
+    for a in range(3):
+        g.n[a] = int(grid["n"][a])
+        g.o[a] = float(grid["o"][a])
+        g.h[a] = float(grid["h"][a])
+    g.coord = int(grid["coord"])
+    return g
+
+
+def _opts(tol, max_iter, kappa, tile_k=0):
+    o = _lib.TTOpts()
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.kappa = float(kappa)
+    o.tile_k = int(tile_k)
+    o.flags = 0
+    return o
+
+
+def _dev(t, name, dtype=_F64, numel=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on a GPU device")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _null():
+    return ctypes.c_void_p(0)
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _N(grid):
+    n = grid["n"]
+    return int(n[0]) * int(n[1]) * int(n[2])
+
+
+def workspace(grid, nsrc, which, tile_k=0, device=None):
+    """Device workspace (uint8 tensor) for forward (0), adjoint (1), sample (2), kernel (3)."""
+    lib = _lib.load()
+    g = _grid(grid)
+    o = _opts(1e-6, 1, 1.0, tile_k)
+    nbytes = lib.tt_workspace_size(ctypes.byref(g), int(nsrc), ctypes.byref(o), int(which))
+    if nbytes == 0:
+        raise ValueError("invalid grid or source count for the workspace")
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def source_params(grid, s, xi, eta, src_pos):
+    """s0, xi0, eta0 at each source (trilinear interpolation of the model)."""
+    lib = _lib.load()
+    N = _N(grid)
+    nsrc = src_pos.shape[0]
+    par = torch.empty((nsrc, 3), dtype=_F64, device=s.device)
+    g = _grid(grid)
+    _lib.check(lib.tt_source_params(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
+                                    _dev(eta, "eta", numel=N), int(nsrc), _dev(src_pos, "src_pos", numel=3 * nsrc),
+                                    _dev(par, "src_par"), _stream(s.device)))
+    return par
+
+
+def forward(grid, s, xi, eta, src_pos, src_par, tol, max_iter, kappa, tau_init=None, tile_k=0, ws=None,
+            out=None):
+    """Batched forward solve.  Returns (tau [nsrc, *n], status int32 [nsrc])."""
+    lib = _lib.load()
+    N = _N(grid)
+    nsrc = int(src_pos.shape[0])
+    dev = s.device
+    tau = out if out is not None else torch.empty((nsrc,) + tuple(int(v) for v in grid["n"]), dtype=_F64, device=dev)
+    status = torch.zeros(nsrc, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(grid, nsrc, 0, tile_k, dev)
+    g = _grid(grid)
+    o = _opts(tol, max_iter, kappa, tile_k)
+    ti = _dev(tau_init, "tau_init", numel=nsrc * N) if tau_init is not None else _null()
+    _lib.check(lib.tt_forward(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
+                              _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
+                              _dev(src_par, "src_par", numel=3 * nsrc), ti, ctypes.byref(o),
+                              _dev(tau, "tau", numel=nsrc * N), _dev(status, "status", torch.int32),
+                              _dev(ws, "ws", torch.uint8), ws.numel(), _stream(dev)))
+    return tau, status
+
+
+def sample(grid, src_pos, src_par, tau, rec_pos, ws=None):
+    """Traveltimes [nsrc, nrec] at the receivers."""
+    lib = _lib.load()
+    N = _N(grid)
+    nsrc, nrec = int(src_pos.shape[0]), int(rec_pos.shape[0])
+    dev = tau.device
+    out = torch.empty((nsrc, nrec), dtype=_F64, device=dev)
+    if ws is None:
+        ws = workspace(grid, nsrc, 2, 0, dev)
+    g = _grid(grid)
+    _lib.check(lib.tt_sample(ctypes.byref(g), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
+                             _dev(src_par, "src_par", numel=3 * nsrc), _dev(tau, "tau", numel=nsrc * N), nrec,
+                             _dev(rec_pos, "rec_pos", numel=3 * nrec), _dev(out, "T_rec"),
+                             _dev(ws, "ws", torch.uint8), ws.numel(), _stream(dev)))
+    return out
+
+
+def misfit(T_rec, T_obs, w=None, pairs=None, wpair=None, alpha=1.0, beta=1.0):
+    """chi (device scalar tensor) and adjoint sources R [nsrc, nrec]."""
+    lib = _lib.load()
+    nsrc, nrec = int(T_rec.shape[0]), int(T_rec.shape[1])
+    dev = T_rec.device
+    R = torch.empty_like(T_rec)
+    chi = torch.empty((), dtype=_F64, device=dev)
+    npair = 0 if pairs is None else int(pairs.shape[0])
+    _lib.check(lib.tt_misfit(nsrc, nrec, _dev(T_rec, "T_rec"), _dev(T_obs, "T_obs", numel=nsrc * nrec),
+                             _dev(w, "w", numel=nsrc * nrec) if w is not None else _null(), npair,
+                             _dev(pairs, "pairs", torch.int32, numel=2 * npair) if npair else _null(),
+                             _dev(wpair, "wpair", numel=nsrc * npair) if wpair is not None else _null(),
+                             float(alpha), float(beta), _dev(R, "R"), _dev(chi, "chi"), _stream(dev)))
+    return chi, R
+
+
+def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, kappa, tile_k=0, ws=None,
+            out=None):
+    """Batched adjoint solve.  Returns (lambda [nsrc, *n], status int32 [nsrc])."""
+    lib = _lib.load()
+    N = _N(grid)
+    nsrc, nrec = int(src_pos.shape[0]), int(rec_pos.shape[0])
+    dev = s.device
+    lam = out if out is not None else torch.empty((nsrc,) + tuple(int(v) for v in grid["n"]), dtype=_F64, device=dev)
+    status = torch.zeros(nsrc, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(grid, nsrc, 1, tile_k, dev)
+    g = _grid(grid)
+    o = _opts(tol, max_iter, kappa, tile_k)
+    _lib.check(lib.tt_adjoint(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
+                              _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
+                              _dev(src_par, "src_par", numel=3 * nsrc), _dev(tau, "tau", numel=nsrc * N), nrec,
+                              _dev(rec_pos, "rec_pos", numel=3 * nrec), _dev(R, "R", numel=nsrc * nrec),
+                              ctypes.byref(o), _dev(lam, "lam", numel=nsrc * N), _dev(status, "status", torch.int32),
+                              _dev(ws, "ws", torch.uint8), ws.numel(), _stream(dev)))
+    return lam, status
+
+
+def kernel(grid, s, xi, eta, src_pos, src_par, tau, lam, grad=None, ws=None):
+    """Discrete gradients [3, *n] summed over sources; adds to grad if given."""
+    lib = _lib.load()
+    N = _N(grid)
+    nsrc = int(src_pos.shape[0])
+    dev = s.device
+    acc = grad is not None
+    if grad is None:
+        grad = torch.empty((3,) + tuple(int(v) for v in grid["n"]), dtype=_F64, device=dev)
+    if ws is None:
+        ws = workspace(grid, max(nsrc, 1), 3, 0, dev)
+    g = _grid(grid)
+    _lib.check(lib.tt_kernel(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
+                             _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
+                             _dev(src_par, "src_par", numel=3 * nsrc), _dev(tau, "tau", numel=nsrc * N),
+                             _dev(lam, "lam", numel=nsrc * N), _dev(grad, "grad", numel=3 * N), int(acc),
+                             _dev(ws, "ws", torch.uint8), ws.numel(), _stream(dev)))
+    return grad

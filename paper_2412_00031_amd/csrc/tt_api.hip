@@ -1,0 +1,375 @@
+// tt_api.hip -- C ABI of libtt (declared in include/tt.h): host-side argument
+// checks, workspace layout, and the iteration loop that polls convergence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tt_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define TT_HIP(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail(TT_EHIP, "%s: %s", #call, hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr int kDefaultTileK = 32;
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int check_grid(const tt_grid* g) {
+    if (!g) return fail(TT_EINVAL, "grid is NULL");
+    if (g->coord != 0 && g->coord != 1) return fail(TT_EINVAL, "grid.coord must be 0 or 1");
+    for (int a = 0; a < 3; ++a) {
+        if (g->n[a] < 4) return fail(TT_EINVAL, "grid.n[%d] = %d < 4", a, g->n[a]);
+        if (g->n[a] > 8192) return fail(TT_EINVAL, "grid.n[%d] = %d > 8192", a, g->n[a]);
+        if (!(g->h[a] > 0.0) || !std::isfinite(g->h[a])) return fail(TT_EINVAL, "grid.h[%d] must be > 0", a);
+        if (!std::isfinite(g->o[a])) return fail(TT_EINVAL, "grid.o[%d] not finite", a);
+    }
+    if (g->coord == 1) {
+        double rmin = g->o[0];
+        if (!(rmin > 0.0)) return fail(TT_EINVAL, "spherical grid needs r > 0");
+        double lat0 = g->o[1], lat1 = g->o[1] + (g->n[1] - 1) * g->h[1];
+        const double lim = 1.5533;  // 89 degrees
+        if (std::fabs(lat0) > lim || std::fabs(lat1) > lim)
+            return fail(TT_EINVAL, "spherical grid latitude must stay within +-89 degrees");
+    }
+    return TT_OK;
+}
+
+int check_opts(const tt_opts* o) {
+    if (!o) return fail(TT_EINVAL, "opts is NULL");
+    if (!(o->tol > 0.0)) return fail(TT_EINVAL, "opts.tol must be > 0");
+    if (o->max_iter < 1) return fail(TT_EINVAL, "opts.max_iter must be >= 1");
+    if (!(o->kappa > 0.0) || !std::isfinite(o->kappa)) return fail(TT_EINVAL, "opts.kappa must be > 0");
+    if (o->tile_k < 0) return fail(TT_EINVAL, "opts.tile_k must be >= 0");
+    return TT_OK;
+}
+
+tt::Geo make_geo(const tt_grid* g, int tk) {
+    tt::Geo G;
+    std::memset(&G, 0, sizeof G);
+    for (int a = 0; a < 3; ++a) {
+        G.n[a] = g->n[a];
+        G.m[a] = g->n[a] - 2;
+        G.o[a] = g->o[a];
+        G.h[a] = g->h[a];
+        G.inv2h[a] = 1.0 / (2.0 * g->h[a]);
+        G.invh[a] = 1.0 / g->h[a];
+    }
+    G.coord = g->coord;
+    G.tk = tk;
+    G.nt[0] = (G.m[0] + tt::kBI - 1) / tt::kBI;
+    G.nt[1] = (G.m[1] + tt::kBJ - 1) / tt::kBJ;
+    G.nt[2] = (G.m[2] + tk - 1) / tk;
+    G.ntiles = G.nt[0] * G.nt[1] * G.nt[2];
+    G.N = (long long)G.n[0] * G.n[1] * G.n[2];
+    G.si = (long long)G.n[1] * G.n[2];
+    G.sj = G.n[2];
+    G.NB = G.N - (long long)G.m[0] * G.m[1] * G.m[2];
+    return G;
+}
+
+// Workspace layout (each region 256-byte aligned):
+//   Src[nsrc] | tab0[n0] | tab1[n1] | tab2[n2] | active[nsrc] | iter[nsrc] | counter |
+//   part[nsrc*nslots] | part2[nsrc*nslots] (adjoint) | coef[nsrc*N*8] (adjoint) |
+//   bnd_in[nsrc*NB] (adjoint)
+struct Layout {
+    size_t off_src, off_t0, off_t1, off_t2, off_active, off_iter, off_counter, off_part, off_part2, off_coef,
+        off_bnd, total;
+};
+
+Layout layout(const tt::Geo& G, int nsrc, int nslots, int which) {
+    Layout L;
+    size_t o = 0;
+    L.off_src = o; o = align_up(o + sizeof(tt::Src) * (size_t)nsrc);
+    L.off_t0 = o; o = align_up(o + sizeof(double) * (size_t)G.n[0]);
+    L.off_t1 = o; o = align_up(o + sizeof(double2) * (size_t)G.n[1]);
+    L.off_t2 = o; o = align_up(o + sizeof(double2) * (size_t)G.n[2]);
+    L.off_active = o; o = align_up(o + sizeof(int) * (size_t)nsrc);
+    L.off_iter = o; o = align_up(o + sizeof(int) * (size_t)nsrc);
+    L.off_counter = o; o = align_up(o + sizeof(int));
+    L.off_part = o;
+    L.off_part2 = o;
+    L.off_coef = o;
+    L.off_bnd = o;
+    if (which == 0 || which == 1) {
+        L.off_part = o; o = align_up(o + sizeof(double) * (size_t)nsrc * nslots);
+    }
+    if (which == 1) {
+        L.off_part2 = o; o = align_up(o + sizeof(double) * (size_t)nsrc * nslots);
+        L.off_coef = o; o = align_up(o + sizeof(double) * 8 * (size_t)nsrc * (size_t)G.N);
+        L.off_bnd = o; o = align_up(o + sizeof(double) * (size_t)nsrc * (size_t)G.NB);
+    }
+    L.total = o;
+    return L;
+}
+
+void fill_plan(tt::Plan& P, const tt::Geo& G, int nsrc) {
+    P.G = G;
+    P.nsrc = nsrc;
+    P.nplanes = G.nt[0] + G.nt[1] + G.nt[2] - 2;
+    P.plane_count.assign(P.nplanes, 0);
+    for (int ti = 0; ti < G.nt[0]; ++ti)
+        for (int tj = 0; tj < G.nt[1]; ++tj)
+            for (int tk = 0; tk < G.nt[2]; ++tk) P.plane_count[ti + tj + tk]++;
+    P.max_plane_tiles = 0;
+    for (int c : P.plane_count) P.max_plane_tiles = c > P.max_plane_tiles ? c : P.max_plane_tiles;
+    P.nbblocks = (int)((G.NB + tt::kBndThreads - 1) / tt::kBndThreads);
+    P.nslots = 8 * G.ntiles + 8 * P.nbblocks;
+}
+
+void bind_workspace(tt::Plan& P, void* ws, const Layout& L) {
+    char* b = static_cast<char*>(ws);
+    P.src = reinterpret_cast<tt::Src*>(b + L.off_src);
+    P.tab0 = reinterpret_cast<double*>(b + L.off_t0);
+    P.tab1 = reinterpret_cast<double2*>(b + L.off_t1);
+    P.tab2 = reinterpret_cast<double2*>(b + L.off_t2);
+    P.active = reinterpret_cast<int*>(b + L.off_active);
+    P.iter = reinterpret_cast<int*>(b + L.off_iter);
+    P.counter = reinterpret_cast<int*>(b + L.off_counter);
+    P.part = reinterpret_cast<double*>(b + L.off_part);
+    P.part2 = reinterpret_cast<double*>(b + L.off_part2);
+    P.coef = reinterpret_cast<double*>(b + L.off_coef);
+    P.bnd_in = reinterpret_cast<double*>(b + L.off_bnd);
+    P.T.t0 = P.tab0;
+    P.T.t1 = P.tab1;
+    P.T.t2 = P.tab2;
+}
+
+int tile_k_of(const tt_opts* o) { return (o && o->tile_k > 0) ? o->tile_k : kDefaultTileK; }
+
+// pinned host word that receives the active-source count of each iteration
+struct Pinned {
+    int* p = nullptr;
+    ~Pinned() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+thread_local Pinned g_pinned;
+
+int pinned_counter(int** out) {
+    if (!g_pinned.p) TT_HIP(hipHostMalloc(reinterpret_cast<void**>(&g_pinned.p), 2 * sizeof(int), hipHostMallocDefault));
+    *out = g_pinned.p;
+    return TT_OK;
+}
+
+// Enqueue iterations until no source is active.  The count of active sources
+// after iteration k is copied to pinned host memory; the host waits for it
+// while iteration k+1 is already queued, so the device never idles on the poll.
+template <typename Launch>
+int run_iterations(const tt::Plan& P, hipStream_t st, Launch launch_one) {
+    int* host = nullptr;
+    int rc = pinned_counter(&host);
+    if (rc) return rc;
+    hipEvent_t ev[2];
+    TT_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    TT_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    int issued = 0;
+    int result = TT_OK;
+    for (;;) {
+        if (issued < P.max_iter) {
+            launch_one();
+            hipError_t e = hipMemcpyAsync(&host[issued & 1], P.counter, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipEventRecord(ev[issued & 1], st);
+            if (e != hipSuccess) {
+                result = fail(TT_EHIP, "iteration enqueue: %s", hipGetErrorString(e));
+                break;
+            }
+            ++issued;
+        }
+        // wait for the previous iteration's count (or the last one when no more can be issued)
+        const int wait_for = (issued < P.max_iter) ? issued - 2 : issued - 1;
+        if (wait_for < 0) continue;
+        hipError_t e = hipEventSynchronize(ev[wait_for & 1]);
+        if (e != hipSuccess) {
+            result = fail(TT_EHIP, "iteration wait: %s", hipGetErrorString(e));
+            break;
+        }
+        if (host[wait_for & 1] == 0 || wait_for == P.max_iter - 1) break;
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess && result == TT_OK) result = fail(TT_EHIP, "stream sync: %s", hipGetErrorString(e));
+    e = hipGetLastError();
+    if (e != hipSuccess && result == TT_OK) result = fail(TT_EHIP, "kernel launch: %s", hipGetErrorString(e));
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    return result;
+}
+
+int check_ptrs(std::initializer_list<const void*> ps) {
+    int q = 0;
+    for (const void* p : ps) {
+        if (!p) return fail(TT_EINVAL, "required pointer argument %d is NULL", q);
+        ++q;
+    }
+    return TT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tt_last_error(void) { return g_err.c_str(); }
+
+size_t tt_workspace_size(const tt_grid* grid, int32_t nsrc, const tt_opts* opts, int32_t which) {
+    if (check_grid(grid) || nsrc < 1 || which < 0 || which > 3) return 0;
+    tt::Geo G = make_geo(grid, tile_k_of(opts));
+    tt::Plan P;
+    fill_plan(P, G, nsrc);
+    return layout(G, nsrc, P.nslots, which).total;
+}
+
+int tt_source_params(const tt_grid* grid, const double* s, const double* xi, const double* eta, int32_t nsrc,
+                     const double* src_pos, double* src_par, void* stream) {
+    g_err.clear();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (nsrc < 0) return fail(TT_EINVAL, "nsrc < 0");
+    if (nsrc == 0) return TT_OK;
+    if ((rc = check_ptrs({s, xi, eta, src_pos, src_par}))) return rc;
+    tt::Geo G = make_geo(grid, kDefaultTileK);
+    tt::launch_source_params(G, s, xi, eta, src_pos, src_par, nsrc, (hipStream_t)stream);
+    TT_HIP(hipGetLastError());
+    return TT_OK;
+}
+
+int tt_forward(const tt_grid* grid, const double* s, const double* xi, const double* eta, int32_t nsrc,
+               const double* src_pos, const double* src_par, const double* tau_init, const tt_opts* opts, double* tau,
+               int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    int rc = check_grid(grid);
+    if (rc || (rc = check_opts(opts))) return rc;
+    if (nsrc < 0) return fail(TT_EINVAL, "nsrc < 0");
+    if (nsrc == 0) return TT_OK;
+    if (nsrc > 65535) return fail(TT_EINVAL, "nsrc > 65535");
+    if ((rc = check_ptrs({s, xi, eta, src_pos, src_par, tau, status, ws}))) return rc;
+    tt::Geo G = make_geo(grid, tile_k_of(opts));
+    tt::Plan P;
+    fill_plan(P, G, nsrc);
+    Layout L = layout(G, nsrc, P.nslots, 0);
+    if (ws_bytes < L.total) return fail(TT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    bind_workspace(P, ws, L);
+    P.kappa = opts->kappa;
+    P.tol = opts->tol;
+    P.max_iter = opts->max_iter;
+    hipStream_t st = (hipStream_t)stream;
+    tt::launch_tables(P, st);
+    tt::launch_src_setup(P, src_pos, src_par, st);
+    tt::SweepArgs a = tt::make_args(P, s, xi, eta, tau, status);
+    tt::launch_fwd_init(P, a, tau_init, st);
+    TT_HIP(hipGetLastError());
+    return run_iterations(P, st, [&]() { tt::launch_fwd_iteration(P, a, st); });
+}
+
+int tt_sample(const tt_grid* grid, int32_t nsrc, const double* src_pos, const double* src_par, const double* tau,
+              int32_t nrec, const double* rec_pos, double* T_rec, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (nsrc < 0 || nrec < 0) return fail(TT_EINVAL, "negative count");
+    if (nsrc == 0 || nrec == 0) return TT_OK;
+    if ((rc = check_ptrs({src_pos, src_par, tau, rec_pos, T_rec, ws}))) return rc;
+    tt::Geo G = make_geo(grid, kDefaultTileK);
+    tt::Plan P;
+    fill_plan(P, G, nsrc);
+    Layout L = layout(G, nsrc, P.nslots, 2);
+    if (ws_bytes < L.total) return fail(TT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    bind_workspace(P, ws, L);
+    hipStream_t st = (hipStream_t)stream;
+    tt::launch_tables(P, st);
+    tt::launch_src_setup(P, src_pos, src_par, st);
+    tt::launch_sample(P, tau, nrec, rec_pos, T_rec, st);
+    TT_HIP(hipGetLastError());
+    return TT_OK;
+}
+
+int tt_misfit(int32_t nsrc, int32_t nrec, const double* T_rec, const double* T_obs, const double* w, int32_t npair,
+              const int32_t* pairs, const double* wpair, double alpha, double beta, double* R, double* chi,
+              void* stream) {
+    g_err.clear();
+    if (nsrc < 0 || nrec < 0 || npair < 0) return fail(TT_EINVAL, "negative count");
+    int rc = check_ptrs({T_rec, T_obs, R, chi});
+    if (rc) return rc;
+    if (npair > 0 && !pairs) return fail(TT_EINVAL, "pairs is NULL with npair > 0");
+    if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(TT_EINVAL, "alpha/beta not finite");
+    tt::launch_misfit(nsrc, nrec, T_rec, T_obs, w, npair, pairs, wpair, alpha, beta, R, chi, (hipStream_t)stream);
+    TT_HIP(hipGetLastError());
+    return TT_OK;
+}
+
+int tt_adjoint(const tt_grid* grid, const double* s, const double* xi, const double* eta, int32_t nsrc,
+               const double* src_pos, const double* src_par, const double* tau, int32_t nrec, const double* rec_pos,
+               const double* R, const tt_opts* opts, double* lam, int32_t* status, void* ws, size_t ws_bytes,
+               void* stream) {
+    g_err.clear();
+    int rc = check_grid(grid);
+    if (rc || (rc = check_opts(opts))) return rc;
+    if (nsrc < 0 || nrec < 0) return fail(TT_EINVAL, "negative count");
+    if (nsrc == 0) return TT_OK;
+    if (nsrc > 65535) return fail(TT_EINVAL, "nsrc > 65535");
+    if ((rc = check_ptrs({s, xi, eta, src_pos, src_par, tau, lam, status, ws}))) return rc;
+    if (nrec > 0 && (!rec_pos || !R)) return fail(TT_EINVAL, "rec_pos/R NULL with nrec > 0");
+    tt::Geo G = make_geo(grid, tile_k_of(opts));
+    tt::Plan P;
+    fill_plan(P, G, nsrc);
+    Layout L = layout(G, nsrc, P.nslots, 1);
+    if (ws_bytes < L.total) return fail(TT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    bind_workspace(P, ws, L);
+    P.kappa = opts->kappa;
+    P.tol = opts->tol;
+    P.max_iter = opts->max_iter;
+    hipStream_t st = (hipStream_t)stream;
+    tt::launch_tables(P, st);
+    tt::launch_src_setup(P, src_pos, src_par, st);
+    tt::SweepArgs a = tt::make_args(P, s, xi, eta, lam, status);
+    tt::launch_adj_init(P, a, tau, nrec, rec_pos, R, st);
+    TT_HIP(hipGetLastError());
+    return run_iterations(P, st, [&]() { tt::launch_adj_iteration(P, a, st); });
+}
+
+int tt_kernel(const tt_grid* grid, const double* s, const double* xi, const double* eta, int32_t nsrc,
+              const double* src_pos, const double* src_par, const double* tau, const double* lam, double* grad,
+              int32_t accumulate, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (nsrc < 0) return fail(TT_EINVAL, "nsrc < 0");
+    if ((rc = check_ptrs({s, xi, eta, grad}))) return rc;
+    if (nsrc > 0 && (rc = check_ptrs({src_pos, src_par, tau, lam, ws}))) return rc;
+    tt::Geo G = make_geo(grid, kDefaultTileK);
+    tt::Plan P;
+    fill_plan(P, G, nsrc > 0 ? nsrc : 1);
+    P.nsrc = nsrc;
+    Layout L = layout(G, nsrc > 0 ? nsrc : 1, P.nslots, 3);
+    if (nsrc > 0 && ws_bytes < L.total) return fail(TT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    hipStream_t st = (hipStream_t)stream;
+    if (nsrc > 0) {
+        bind_workspace(P, ws, L);
+        tt::launch_tables(P, st);
+        tt::launch_src_setup(P, src_pos, src_par, st);
+    }
+    tt::launch_kernel_accum(P, xi, eta, tau, lam, grad, accumulate, st);
+    TT_HIP(hipGetLastError());
+    return TT_OK;
+}
+
+}  // extern "C"

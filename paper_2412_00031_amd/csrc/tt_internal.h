@@ -1,0 +1,239 @@
+// tt_internal.h -- library-private types and device helpers of libtt.
+//
+// Numerics (Chen et al., TomoATT, arXiv 2412.00031; Sec. 2.1 Eq. (4), Sec. 3.1):
+//   T = T0 * tau with T0 = s0 sqrt(d^T M0^{-1} d), d = x - x_s in the source's
+//   local (r^, theta^, phi^) frame; scaled gradient p = (dT/dr, dT/dtheta / r,
+//   dT/dphi / (r cos theta)); Lax-Friedrichs update of the factored equation
+//   with viscosity sigma_a = kappa T0 g_a.  Everything in FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "tt.h"
+
+namespace tt {
+
+constexpr int kBI = 8;        // column block of one wave: 8 x 8 (i, j) columns
+constexpr int kBJ = 8;
+constexpr int kWave = 64;
+constexpr int kBndThreads = 256;
+
+// Kernel-argument copy of the grid.
+struct Geo {
+    int n[3];          // nodes per axis
+    int m[3];          // interior nodes per axis (n - 2)
+    int coord;         // 0 Cartesian, 1 spherical
+    int nt[3];         // tiles per axis in sweep-relative coordinates
+    int tk;            // k-extent of a tile
+    int ntiles;        // nt0 * nt1 * nt2
+    long long N;       // n0 * n1 * n2
+    long long si, sj;  // strides of axes 0 and 1 (axis 2 has stride 1)
+    long long NB;      // boundary nodes
+    double o[3], h[3], inv2h[3], invh[3];
+};
+
+// Per-source constants, produced on the device by k_src_setup.
+struct Src {
+    double Xs[3];      // source position in the embedding (spherical) or (z,y,x)
+    double E[9];       // rows: source-frame unit vectors r^_s, theta^_s, phi^_s
+    double mi11, mi12, mi22;  // lower-right block of M0^{-1}
+    double s0;
+    int fb[3];         // base corner of the fixed cell
+    int pad;
+};
+
+// Per-axis tables, built on the device by k_tables into the caller's workspace.
+//   tab0[i]  = r (spherical) or z (Cartesian)
+//   tab1[j]  = (cos theta, sin theta) (spherical) or (y, 0) (Cartesian)
+//   tab2[k]  = (cos phi, sin phi) (spherical) or (x, 0) (Cartesian)
+struct Tabs {
+    const double* t0;
+    const double2* t1;
+    const double2* t2;
+};
+
+// Lane-constant geometry of an (i, j) column.
+struct Col {
+    double x0;         // r or z
+    double ct, st;     // cos/sin latitude (spherical), y in ct (Cartesian)
+    double rct, rst;   // r cos theta, r sin theta
+    double g1, g2;     // scaled-gradient factors of axes 1, 2 (g0 = 1)
+};
+
+__device__ __forceinline__ Col make_col(const Geo& G, const Tabs& T, int i, int j) {
+    Col c;
+    c.x0 = T.t0[i];
+    double2 a1 = T.t1[j];
+    c.ct = a1.x;
+    c.st = a1.y;
+    if (G.coord == 1) {
+        c.rct = c.x0 * c.ct;
+        c.rst = c.x0 * c.st;
+        c.g1 = 1.0 / c.x0;
+        c.g2 = 1.0 / c.rct;
+    } else {
+        c.rct = c.rst = 0.0;
+        c.g1 = c.g2 = 1.0;
+    }
+    return c;
+}
+
+__device__ __forceinline__ bool in_fixed(const Src& S, int i, int j, int k) {
+    return (unsigned)(i - S.fb[0]) <= 1u && (unsigned)(j - S.fb[1]) <= 1u && (unsigned)(k - S.fb[2]) <= 1u;
+}
+
+// T0 and its scaled gradient t at a node of column c with axis-2 table value
+// (c2, s2) = (cos phi, sin phi) or (x, 0).
+template <int COORD>
+__device__ __forceinline__ void factor(const Src& S, const Col& c, double c2, double s2, double& T0,
+                                       double t[3]) {
+    double d0, d1, d2;
+    double er0 = 0, er1 = 0, er2 = 0, et0 = 0, et1 = 0, et2 = 0;
+    if (COORD == 1) {
+        double D0 = c.rct * c2 - S.Xs[0];
+        double D1 = c.rct * s2 - S.Xs[1];
+        double D2 = c.rst - S.Xs[2];
+        d0 = D0 * S.E[0] + D1 * S.E[1] + D2 * S.E[2];
+        d1 = D0 * S.E[3] + D1 * S.E[4] + D2 * S.E[5];
+        d2 = D0 * S.E[6] + D1 * S.E[7] + D2 * S.E[8];
+        er0 = c.ct * c2; er1 = c.ct * s2; er2 = c.st;
+        et0 = -c.st * c2; et1 = -c.st * s2; et2 = c.ct;
+    } else {
+        d0 = c.x0 - S.Xs[0];
+        d1 = c.ct - S.Xs[1];
+        d2 = c2 - S.Xs[2];
+    }
+    double m0 = d0;
+    double m1 = S.mi11 * d1 + S.mi12 * d2;
+    double m2 = S.mi12 * d1 + S.mi22 * d2;
+    double Q = d0 * m0 + d1 * m1 + d2 * m2;
+    if (!(Q > 0.0)) {
+        T0 = 0.0;
+        t[0] = t[1] = t[2] = 0.0;
+        return;
+    }
+    double sq = sqrt(Q);
+    T0 = S.s0 * sq;
+    double f = S.s0 / sq;
+    if (COORD == 1) {
+        double G0 = f * (m0 * S.E[0] + m1 * S.E[3] + m2 * S.E[6]);
+        double G1 = f * (m0 * S.E[1] + m1 * S.E[4] + m2 * S.E[7]);
+        double G2 = f * (m0 * S.E[2] + m1 * S.E[5] + m2 * S.E[8]);
+        t[0] = G0 * er0 + G1 * er1 + G2 * er2;
+        t[1] = G0 * et0 + G1 * et1 + G2 * et2;
+        t[2] = -G0 * s2 + G1 * c2;
+    } else {
+        t[0] = f * m0;
+        t[1] = f * m1;
+        t[2] = f * m2;
+    }
+}
+
+// Local state of the factored Hamiltonian at an interior node: P, M P, H.
+struct Loc {
+    double T0, t[3], P[3], MP[3], H;
+};
+
+template <int COORD>
+__device__ __forceinline__ void local_state(const Geo& G, const Src& S, const Col& c, double c2, double s2,
+                                            double xi, double eta, double tx, double up0, double dn0,
+                                            double up1, double dn1, double up2, double dn2, Loc& L) {
+    // up_a = tau(x - e_a), dn_a = tau(x + e_a) in absolute axis directions
+    factor<COORD>(S, c, c2, s2, L.T0, L.t);
+    double q0 = (dn0 - up0) * G.inv2h[0];
+    double q1 = c.g1 * (dn1 - up1) * G.inv2h[1];
+    double q2 = c.g2 * (dn2 - up2) * G.inv2h[2];
+    L.P[0] = L.T0 * q0 + tx * L.t[0];
+    L.P[1] = L.T0 * q1 + tx * L.t[1];
+    L.P[2] = L.T0 * q2 + tx * L.t[2];
+    L.MP[0] = L.P[0];
+    L.MP[1] = (1.0 - 2.0 * xi) * L.P[1] + 2.0 * eta * L.P[2];
+    L.MP[2] = 2.0 * eta * L.P[1] + (1.0 + 2.0 * xi) * L.P[2];
+    L.H = sqrt(L.P[0] * L.MP[0] + L.P[1] * L.MP[1] + L.P[2] * L.MP[2]);
+}
+
+// Lax-Friedrichs update: the tau(x) that zeroes
+//   G_x = H(q, tau_old(x)) - sum_a sigma_a (dn_a - 2 tau(x) + up_a) / (2 h_a) - s(x).
+template <int COORD>
+__device__ __forceinline__ double lf_update(const Geo& G, const Src& S, const Col& c, double c2, double s2,
+                                            double kappa, double sx, double xi, double eta, double tx,
+                                            double up0, double dn0, double up1, double dn1, double up2,
+                                            double dn2) {
+    Loc L;
+    local_state<COORD>(G, S, c, c2, s2, xi, eta, tx, up0, dn0, up1, dn1, up2, dn2, L);
+    double kT = kappa * L.T0;
+    double num = sx - L.H +
+                 kT * ((up0 + dn0) * G.inv2h[0] + c.g1 * (up1 + dn1) * G.inv2h[1] +
+                       c.g2 * (up2 + dn2) * G.inv2h[2]);
+    double den = kT * (G.invh[0] + c.g1 * G.invh[1] + c.g2 * G.invh[2]);
+    return num / den;
+}
+
+// ----- state of one batched solve (host side) -----
+struct Plan {
+    Geo G;
+    Tabs T;
+    int nsrc = 0;
+    int nplanes = 0;          // tile-planes per sweep
+    int max_plane_tiles = 0;  // largest tile-plane
+    int nbblocks = 0;         // boundary-pass blocks per source
+    int nslots = 0;           // partial-sum slots per source per iteration
+    double kappa = 1.0, tol = 1e-6;
+    int max_iter = 1;
+    // workspace views
+    Src* src = nullptr;
+    double* tab0 = nullptr;
+    double2* tab1 = nullptr;
+    double2* tab2 = nullptr;
+    int* active = nullptr;
+    int* iter = nullptr;
+    int* counter = nullptr;
+    double* part = nullptr;
+    double* part2 = nullptr;
+    double* coef = nullptr;   // adjoint: [nsrc][N][8]
+    double* bnd_in = nullptr; // adjoint: [nsrc][NB]
+    std::vector<int> plane_count;
+};
+
+// Kernel-argument bundle of the sweep kernels.
+struct SweepArgs {
+    Geo G;
+    Tabs T;
+    const double *s, *xi, *eta;
+    const Src* src;
+    double* field;          // tau or lambda [nsrc][N]
+    const double* coef;     // adjoint coefficients [nsrc][N][8]
+    const double* bnd_in;   // adjoint face couplings [nsrc][NB]
+    int* active;
+    int* iter;
+    int32_t* status;
+    double* part;
+    double* part2;
+    int* counter;
+    int nslots, nbblocks, nsrc, max_iter;
+    double kappa, tol;
+};
+
+SweepArgs make_args(const Plan& P, const double* s, const double* xi, const double* eta, double* field,
+                    int32_t* status);
+void launch_tables(const Plan& P, hipStream_t st);
+void launch_src_setup(const Plan& P, const double* src_pos, const double* src_par, hipStream_t st);
+void launch_source_params(const Geo& G, const double* s, const double* xi, const double* eta,
+                          const double* src_pos, double* src_par, int nsrc, hipStream_t st);
+void launch_fwd_init(const Plan& P, const SweepArgs& a, const double* tau_init, hipStream_t st);
+void launch_fwd_iteration(const Plan& P, const SweepArgs& a, hipStream_t st);
+void launch_adj_init(const Plan& P, const SweepArgs& a, const double* tau, int nrec, const double* rec_pos,
+                     const double* R, hipStream_t st);
+void launch_adj_iteration(const Plan& P, const SweepArgs& a, hipStream_t st);
+void launch_sample(const Plan& P, const double* tau, int nrec, const double* rec_pos, double* out,
+                   hipStream_t st);
+void launch_misfit(int nsrc, int nrec, const double* T, const double* Tobs, const double* w, int npair,
+                   const int32_t* pairs, const double* wpair, double alpha, double beta, double* R,
+                   double* chi, hipStream_t st);
+void launch_kernel_accum(const Plan& P, const double* xi, const double* eta, const double* tau,
+                         const double* lam, double* grad, int accumulate, hipStream_t st);
+
+}  // namespace tt

@@ -1,0 +1,846 @@
+// tt_kernels.hip -- CDNA4 (gfx950) kernels of libtt.
+//
+// Sweep schedule.  One directional sweep must visit the interior nodes in an
+// order where x - sigma_a e_a precedes x on every axis a (the Gauss-Seidel
+// order of fast sweeping, Sec. 3.1).  The stencil touches only axis neighbours
+// and boundary nodes are not written during a sweep, so every such order yields
+// the same numbers as the lexicographic one; the hyperplane-stepping idea of
+// Sec. 3.4 (nodes with i'+j'+k' = L are independent) is used in this form:
+//   - the interior is cut into tiles of 8 x 8 (i, j) columns x tk nodes along k
+//     (sweep-relative coordinates, ragged last tiles);
+//   - tiles with the same TI'+TJ'+TK' form a tile-plane; one launch processes
+//     one tile-plane of every active source (grid.y = source);
+//   - inside a tile one 64-lane wave owns the 8 x 8 columns; at step t lane
+//     (li, lj) updates k' = k0' + t - li - lj, i.e. the tile is walked along its
+//     own hyperplanes; the neighbours in i and j come from the adjacent lanes'
+//     registers (ds_bpermute shuffles), the neighbour in k from the lane's own
+//     previous result, and tile-face neighbours from global memory (finished by
+//     an earlier launch, or still untouched in this sweep).
+// Each sweep is followed by a boundary pass (one thread per boundary node), and
+// each iteration by a finalize kernel that forms the convergence measure from
+// per-tile partial sums in a fixed order (bitwise reproducible run to run).
+#include <hip/hip_runtime.h>
+
+#include "tt_internal.h"
+
+namespace tt {
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ int cell_base(const Geo& G, int a, double x) {
+    double u = (x - G.o[a]) / G.h[a];
+    double fl = floor(u);
+    if (fl < 0.0) return 0;
+    if (fl > (double)(G.n[a] - 2)) return G.n[a] - 2;
+    return (int)fl;
+}
+
+__device__ __forceinline__ long long nidx(const Geo& G, int i, int j, int k) {
+    return (long long)i * G.si + (long long)j * G.sj + k;
+}
+
+// boundary node number b in [0, NB) -> (i, j, k); slabs i = 0 and n0-1 are full,
+// slabs in between contribute the ring j in {0, n1-1} or k in {0, n2-1}.
+__device__ __forceinline__ void bnd_decode(const Geo& G, long long b, int& i, int& j, int& k) {
+    const long long plane = (long long)G.n[1] * G.n[2];
+    const long long ring = 2LL * G.n[2] + 2LL * (G.n[1] - 2);
+    if (b < plane) {
+        i = 0; j = (int)(b / G.n[2]); k = (int)(b % G.n[2]);
+        return;
+    }
+    b -= plane;
+    if (b >= (long long)(G.n[0] - 2) * ring) {
+        b -= (long long)(G.n[0] - 2) * ring;
+        i = G.n[0] - 1; j = (int)(b / G.n[2]); k = (int)(b % G.n[2]);
+        return;
+    }
+    i = 1 + (int)(b / ring);
+    long long r = b % ring;
+    if (r < G.n[2]) { j = 0; k = (int)r; return; }
+    if (r < 2LL * G.n[2]) { j = G.n[1] - 1; k = (int)(r - G.n[2]); return; }
+    r -= 2LL * G.n[2];
+    j = 1 + (int)(r >> 1);
+    k = (r & 1) ? G.n[2] - 1 : 0;
+}
+
+// inverse of bnd_decode
+__device__ __forceinline__ long long bnd_encode(const Geo& G, int i, int j, int k) {
+    const long long plane = (long long)G.n[1] * G.n[2];
+    const long long ring = 2LL * G.n[2] + 2LL * (G.n[1] - 2);
+    if (i == 0) return (long long)j * G.n[2] + k;
+    if (i == G.n[0] - 1) return plane + (long long)(G.n[0] - 2) * ring + (long long)j * G.n[2] + k;
+    long long base = plane + (long long)(i - 1) * ring;
+    if (j == 0) return base + k;
+    if (j == G.n[1] - 1) return base + G.n[2] + k;
+    return base + 2LL * G.n[2] + 2LL * (j - 1) + (k == 0 ? 0 : 1);
+}
+
+__device__ __forceinline__ bool on_bnd(const Geo& G, int a, int idx) { return idx == 0 || idx == G.n[a] - 1; }
+
+__device__ __forceinline__ int astar_of(const Geo& G, const int p[3]) {
+    int as = -1;
+    for (int a = 0; a < 3; ++a)
+        if (on_bnd(G, a, p[a])) as = a;
+    return as;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// fixed-order sum over a 256-thread block (result valid in thread 0)
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return r;
+}
+
+// tile (TI', TJ', TK') number b of tile-plane p (TI'+TJ'+TK' = p), ordered by
+// TI' then TJ'
+__device__ __forceinline__ void tile_decode(const Geo& G, int p, int b, int& TI, int& TJ, int& TK) {
+    const int lo = max(0, p - (G.nt[1] - 1) - (G.nt[2] - 1));
+    const int hi = min(G.nt[0] - 1, p);
+    TI = lo; TJ = 0; TK = 0;
+    for (int ti = lo; ti <= hi; ++ti) {
+        const int r = p - ti;
+        const int jlo = max(0, r - (G.nt[2] - 1)), jhi = min(G.nt[1] - 1, r);
+        const int cnt = jhi - jlo + 1;
+        if (cnt <= 0) continue;
+        if (b < cnt) {
+            TI = ti; TJ = jlo + b; TK = r - TJ;
+            return;
+        }
+        b -= cnt;
+    }
+}
+
+// ---------------------------------------------------------------- set-up
+__global__ void k_tables(Geo G, double* __restrict__ t0, double2* __restrict__ t1, double2* __restrict__ t2) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < G.n[0]) t0[q] = G.o[0] + (double)q * G.h[0];
+    if (q < G.n[1]) {
+        double v = G.o[1] + (double)q * G.h[1];
+        t1[q] = G.coord == 1 ? make_double2(cos(v), sin(v)) : make_double2(v, 0.0);
+    }
+    if (q < G.n[2]) {
+        double v = G.o[2] + (double)q * G.h[2];
+        t2[q] = G.coord == 1 ? make_double2(cos(v), sin(v)) : make_double2(v, 0.0);
+    }
+}
+
+__global__ void k_src_setup(Geo G, const double* __restrict__ pos, const double* __restrict__ par,
+                            Src* __restrict__ out, int nsrc) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nsrc) return;
+    Src S;
+    const double p0 = pos[3 * q], p1 = pos[3 * q + 1], p2 = pos[3 * q + 2];
+    if (G.coord == 1) {
+        const double ct = cos(p1), st = sin(p1), cp = cos(p2), sp = sin(p2);
+        S.E[0] = ct * cp; S.E[1] = ct * sp; S.E[2] = st;
+        S.E[3] = -st * cp; S.E[4] = -st * sp; S.E[5] = ct;
+        S.E[6] = -sp; S.E[7] = cp; S.E[8] = 0.0;
+        S.Xs[0] = p0 * S.E[0]; S.Xs[1] = p0 * S.E[1]; S.Xs[2] = p0 * S.E[2];
+    } else {
+        for (int a = 0; a < 9; ++a) S.E[a] = (a % 4 == 0) ? 1.0 : 0.0;
+        S.Xs[0] = p0; S.Xs[1] = p1; S.Xs[2] = p2;
+    }
+    const double xi0 = par[3 * q + 1], eta0 = par[3 * q + 2];
+    const double b = 1.0 - 2.0 * xi0, c = 1.0 + 2.0 * xi0, f = 2.0 * eta0;
+    const double det = b * c - f * f;
+    S.mi11 = c / det; S.mi12 = -f / det; S.mi22 = b / det;
+    S.s0 = par[3 * q];
+    S.fb[0] = cell_base(G, 0, p0);
+    S.fb[1] = cell_base(G, 1, p1);
+    S.fb[2] = cell_base(G, 2, p2);
+    S.pad = 0;
+    out[q] = S;
+}
+
+// trilinear cell and weights at a continuous position (clamped to the grid)
+struct Tri {
+    int b[3];
+    double f[3];
+};
+
+__device__ __forceinline__ Tri tri_of(const Geo& G, double p0, double p1, double p2) {
+    Tri t;
+    const double p[3] = {p0, p1, p2};
+    for (int a = 0; a < 3; ++a) {
+        t.b[a] = cell_base(G, a, p[a]);
+        const double f = (p[a] - G.o[a]) / G.h[a] - (double)t.b[a];
+        t.f[a] = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+    }
+    return t;
+}
+
+__device__ __forceinline__ double tri_w(const Tri& t, int c0, int c1, int c2) {
+    return (c0 ? t.f[0] : 1.0 - t.f[0]) * (c1 ? t.f[1] : 1.0 - t.f[1]) * (c2 ? t.f[2] : 1.0 - t.f[2]);
+}
+
+__global__ void k_source_params(Geo G, const double* __restrict__ s, const double* __restrict__ xi,
+                                const double* __restrict__ eta, const double* __restrict__ pos,
+                                double* __restrict__ par, int nsrc) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nsrc) return;
+    const Tri t = tri_of(G, pos[3 * q], pos[3 * q + 1], pos[3 * q + 2]);
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int c0 = 0; c0 < 2; ++c0)
+        for (int c1 = 0; c1 < 2; ++c1)
+            for (int c2 = 0; c2 < 2; ++c2) {
+                const double w = tri_w(t, c0, c1, c2);
+                const long long x = nidx(G, t.b[0] + c0, t.b[1] + c1, t.b[2] + c2);
+                a += w * s[x]; b += w * xi[x]; c += w * eta[x];
+            }
+    par[3 * q] = a; par[3 * q + 1] = b; par[3 * q + 2] = c;
+}
+
+__global__ void k_fill(double* __restrict__ p, long long n, double v) {
+    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+         x += (long long)gridDim.x * blockDim.x)
+        p[x] = v;
+}
+
+// initialise a solve: field = init (or v0), fixed nodes = vfix; flags and counters
+__global__ void k_solve_init(SweepArgs a, const double* __restrict__ init, double v0, double vfix) {
+    const int src = blockIdx.y;
+    const Src S = a.src[src];
+    double* f = a.field + (long long)src * a.G.N;
+    const double* ti = init ? init + (long long)src * a.G.N : nullptr;
+    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < a.G.N;
+         x += (long long)gridDim.x * blockDim.x) {
+        const int k = (int)(x % a.G.n[2]);
+        const long long q = x / a.G.n[2];
+        const int j = (int)(q % a.G.n[1]), i = (int)(q / a.G.n[1]);
+        f[x] = in_fixed(S, i, j, k) ? vfix : (ti ? ti[x] : v0);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.active[src] = 1;
+        a.iter[src] = 0;
+        a.status[src] = 0;
+        if (src == 0) *a.counter = a.nsrc;
+    }
+}
+
+// --------------------------------------------------------- forward sweep
+template <int COORD>
+__global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int dir, int plane) {
+    const int src = blockIdx.y;
+    if (!a.active[src]) return;
+    const Geo& G = a.G;
+    int TI, TJ, TK;
+    tile_decode(G, plane, blockIdx.x, TI, TJ, TK);
+    const int lane = threadIdx.x, li = lane >> 3, lj = lane & 7;
+    const int s0 = (dir & 4) ? -1 : 1, s1 = (dir & 2) ? -1 : 1, s2 = (dir & 1) ? -1 : 1;
+    const int ext_i = min(kBI, G.m[0] - TI * kBI), ext_j = min(kBJ, G.m[1] - TJ * kBJ);
+    const int k0p = TK * G.tk, k1p = min(k0p + G.tk, G.m[2]);
+    const bool colv = li < ext_i && lj < ext_j;
+    const int ip = TI * kBI + (colv ? li : 0), jp = TJ * kBJ + (colv ? lj : 0);
+    const int i = s0 > 0 ? 1 + ip : G.n[0] - 2 - ip;
+    const int j = s1 > 0 ? 1 + jp : G.n[1] - 2 - jp;
+    const Src S = a.src[src];
+    const Col c = make_col(G, a.T, i, j);
+    double* __restrict__ fld = a.field + (long long)src * G.N;
+    const long long col = nidx(G, i, j, 0);
+    const long long di = s0 * G.si, dj = s1 * G.sj;
+    const bool fcol = (unsigned)(i - S.fb[0]) <= 1u && (unsigned)(j - S.fb[1]) <= 1u;
+    const int nsteps = (k1p - k0p) + ext_i - 1 + ext_j - 1;
+    const int kp0 = k0p - li - lj;               // this lane's k' at step 0
+    const int kbase = s2 > 0 ? 1 : G.n[2] - 2;   // absolute k = kbase + s2 * k'
+
+    double cur = 0.0, ahead = 0.0, prev = 0.0, eps = 0.0;
+    if (colv && kp0 >= k0p && kp0 < k1p) cur = fld[col + kbase + s2 * kp0];
+    if (colv && kp0 + 1 >= k0p && kp0 + 1 <= k1p) ahead = fld[col + kbase + s2 * (kp0 + 1)];
+
+    for (int t = 0; t < nsteps; ++t) {
+        const int kp = kp0 + t;
+        const bool valid = colv && kp >= k0p && kp < k1p;
+        // new values upstream in i/j were produced by the neighbour lanes one
+        // step ago; old values downstream are the neighbour lanes' look-ahead
+        double up_i = __shfl(prev, lane - 8, 64);
+        double up_j = __shfl(prev, lane - 1, 64);
+        double dn_i = __shfl(ahead, lane + 8, 64);
+        double dn_j = __shfl(ahead, lane + 1, 64);
+        if (valid) {
+            const int ka = kbase + s2 * kp;
+            const long long x = col + ka;
+            if (li == 0) up_i = fld[x - di];
+            if (lj == 0) up_j = fld[x - dj];
+            if (li == ext_i - 1) dn_i = fld[x + di];
+            if (lj == ext_j - 1) dn_j = fld[x + dj];
+            const double up_k = (kp > k0p) ? prev : fld[x - s2];
+            double nv = cur;
+            if (!(fcol && (unsigned)(ka - S.fb[2]) <= 1u)) {
+                const double m0 = s0 > 0 ? up_i : dn_i, p0 = s0 > 0 ? dn_i : up_i;
+                const double m1 = s1 > 0 ? up_j : dn_j, p1 = s1 > 0 ? dn_j : up_j;
+                const double m2 = s2 > 0 ? up_k : ahead, p2 = s2 > 0 ? ahead : up_k;
+                const double2 t2 = a.T.t2[ka];
+                nv = lf_update<COORD>(G, S, c, t2.x, t2.y, a.kappa, a.s[x], a.xi[x], a.eta[x], cur, m0, p0, m1,
+                                      p1, m2, p2);
+                fld[x] = nv;
+                eps += fabs(nv - cur);
+            }
+            prev = nv;
+        }
+        cur = ahead;
+        const int kn = kp + 2;
+        ahead = (colv && kn >= k0p && kn <= k1p) ? fld[col + kbase + s2 * kn] : 0.0;
+    }
+    eps = wave_sum(eps);
+    if (lane == 0) {
+        const int tile_id = (TI * G.nt[1] + TJ) * G.nt[2] + TK;
+        a.part[(long long)src * a.nslots + dir * G.ntiles + tile_id] = eps;
+    }
+}
+
+// Value of node p once the boundary pass is done: interior and fixed nodes as
+// stored; a boundary node extrapolates linearly along its largest boundary
+// axis from the two inward nodes, which have one boundary axis fewer.
+template <int BUDGET>
+__device__ __forceinline__ double fwd_bval(const Geo& G, const Src& S, const double* f, int i, int j, int k) {
+    const int p[3] = {i, j, k};
+    const int as = astar_of(G, p);
+    if constexpr (BUDGET == 0) {
+        return f[nidx(G, i, j, k)];
+    } else {
+        if (as < 0 || in_fixed(S, i, j, k)) return f[nidx(G, i, j, k)];
+        const int nu = (p[as] == 0) ? 1 : -1;
+        int q1[3] = {i, j, k}, q2[3] = {i, j, k};
+        q1[as] += nu;
+        q2[as] += 2 * nu;
+        const double v1 = fwd_bval<BUDGET - 1>(G, S, f, q1[0], q1[1], q1[2]);
+        const double v2 = fwd_bval<BUDGET - 1>(G, S, f, q2[0], q2[1], q2[2]);
+        return 2.0 * v1 - v2;
+    }
+}
+
+__global__ void __launch_bounds__(kBndThreads) k_fwd_bnd(SweepArgs a, int dir) {
+    __shared__ double sh[4];
+    const int src = blockIdx.y;
+    if (!a.active[src]) return;
+    const Geo& G = a.G;
+    const Src S = a.src[src];
+    double* fld = a.field + (long long)src * G.N;
+    const long long b = (long long)blockIdx.x * kBndThreads + threadIdx.x;
+    double d = 0.0;
+    if (b < G.NB) {
+        int i, j, k;
+        bnd_decode(G, b, i, j, k);
+        if (!in_fixed(S, i, j, k)) {
+            const double nv = fwd_bval<3>(G, S, fld, i, j, k);
+            const long long x = nidx(G, i, j, k);
+            d = fabs(nv - fld[x]);
+            fld[x] = nv;
+        }
+    }
+    d = block_sum256(d, sh);
+    if (threadIdx.x == 0) a.part[(long long)src * a.nslots + 8 * G.ntiles + dir * a.nbblocks + blockIdx.x] = d;
+}
+
+__device__ __forceinline__ double fixed_sum(const double* p, int cnt, double* sh) {
+    double v = 0.0;
+    for (int q = threadIdx.x; q < cnt; q += blockDim.x) v += p[q];
+    return block_sum256(v, sh);
+}
+
+__device__ __forceinline__ void finish_iteration(const SweepArgs& a, int src, double eps) {
+    const int it = a.iter[src] + 1;
+    a.iter[src] = it;
+    if (eps < a.tol) {
+        a.status[src] = it;
+        a.active[src] = 0;
+        atomicSub(a.counter, 1);
+    } else if (it >= a.max_iter) {
+        a.status[src] = -it;
+        a.active[src] = 0;
+        atomicSub(a.counter, 1);
+    } else {
+        a.status[src] = -it;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fwd_finalize(SweepArgs a) {
+    __shared__ double sh[4];
+    const int src = blockIdx.x;
+    if (!a.active[src]) return;
+    const double tot = fixed_sum(a.part + (long long)src * a.nslots, a.nslots, sh);
+    if (threadIdx.x == 0) finish_iteration(a, src, tot / (double)a.G.N);
+}
+
+// --------------------------------------------------------- adjoint solve
+// Local state at an arbitrary interior node, loading what it needs.
+template <int COORD>
+__device__ __forceinline__ void state_at(const Geo& G, const Tabs& T, const Src& S, const double* __restrict__ tau,
+                                         const double* __restrict__ xi, const double* __restrict__ eta, int i,
+                                         int j, int k, Col& c, Loc& L) {
+    c = make_col(G, T, i, j);
+    const long long x = nidx(G, i, j, k);
+    const double2 t2 = T.t2[k];
+    local_state<COORD>(G, S, c, t2.x, t2.y, xi[x], eta[x], tau[x], tau[x - G.si], tau[x + G.si], tau[x - G.sj],
+                       tau[x + G.sj], tau[x - 1], tau[x + 1], L);
+}
+
+__device__ __forceinline__ double g_of(const Col& c, int a) { return a == 0 ? 1.0 : (a == 1 ? c.g1 : c.g2); }
+
+// J_{x, x + dirn e_a} of an interior non-fixed row x (dirn = +1 or -1):
+//   alpha_a - beta_a or -alpha_a - beta_a with alpha_a = T0 g_a (MP)_a / (2 h_a H),
+//   beta_a = kappa T0 g_a / (2 h_a).
+__device__ __forceinline__ double row_off(const Geo& G, const Col& c, const Loc& L, double kappa, int a, int dirn) {
+    const double ga = g_of(c, a);
+    const double alpha = L.T0 * ga * L.MP[a] / (2.0 * G.h[a] * L.H);
+    const double beta = kappa * L.T0 * ga / (2.0 * G.h[a]);
+    return dirn > 0 ? alpha - beta : -alpha - beta;
+}
+
+// Coefficients of the transposed system at every node of every source:
+// coef[x] = {in+_0, in-_0, in+_1, in-_1, in+_2, in-_2, J_xx, rhs} with
+// in+-_a = J_{x +- e_a, x}, the coefficient of lambda(x +- e_a) in the column
+// equation of x (zero unless x is interior and not fixed); bnd_in[b] = J_{x, b}
+// for each face node b and its interior neighbour x (zero when x is fixed).
+template <int COORD>
+__global__ void __launch_bounds__(256) k_adj_coef(SweepArgs a, const double* __restrict__ tau_all,
+                                                  double* __restrict__ coef_all, double* __restrict__ bnd_all) {
+    const Geo& G = a.G;
+    const int src = blockIdx.y;
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= G.N) return;
+    const Src S = a.src[src];
+    const double* tau = tau_all + (long long)src * G.N;
+    double* cf = coef_all + ((long long)src * G.N + x) * 8;
+    const int k = (int)(x % G.n[2]);
+    const long long q = x / G.n[2];
+    const int j = (int)(q % G.n[1]), i = (int)(q / G.n[1]);
+    double out[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const bool interior = i > 0 && i < G.n[0] - 1 && j > 0 && j < G.n[1] - 1 && k > 0 && k < G.n[2] - 1;
+    if (interior && !in_fixed(S, i, j, k)) {
+        Col c;
+        Loc L;
+        state_at<COORD>(G, a.T, S, tau, a.xi, a.eta, i, j, k, c, L);
+        double diag = (L.t[0] * L.MP[0] + L.t[1] * L.MP[1] + L.t[2] * L.MP[2]) / L.H;
+        for (int ax = 0; ax < 3; ++ax) diag += 2.0 * (a.kappa * L.T0 * g_of(c, ax) / (2.0 * G.h[ax]));
+        out[6] = diag;
+        for (int ax = 0; ax < 3; ++ax) {
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                const int dirn = sgn == 0 ? 1 : -1;
+                int y[3] = {i, j, k};
+                y[ax] += dirn;
+                double v = 0.0;
+                if (!in_fixed(S, y[0], y[1], y[2])) {
+                    if (on_bnd(G, ax, y[ax])) {
+                        v = -2.0;  // the face row of y extrapolates through x
+                    } else {
+                        Col cy;
+                        Loc Ly;
+                        state_at<COORD>(G, a.T, S, tau, a.xi, a.eta, y[0], y[1], y[2], cy, Ly);
+                        v = row_off(G, cy, Ly, a.kappa, ax, -dirn);
+                    }
+                }
+                out[2 * ax + sgn] = v;
+                if (on_bnd(G, ax, y[ax]))
+                    bnd_all[(long long)src * G.NB + bnd_encode(G, y[0], y[1], y[2])] =
+                        row_off(G, c, L, a.kappa, ax, dirn);
+            }
+        }
+    }
+    for (int q2 = 0; q2 < 8; ++q2) cf[q2] = out[q2];
+}
+
+// d chi / d tau = sum_m R_m w_c T0(c), added in receiver order (one thread per
+// source: deterministic)
+template <int COORD>
+__global__ void k_adj_rhs(SweepArgs a, double* __restrict__ coef_all, int nrec, const double* __restrict__ rec,
+                          const double* __restrict__ R) {
+    const int src = blockIdx.x * blockDim.x + threadIdx.x;
+    if (src >= a.nsrc) return;
+    const Geo& G = a.G;
+    const Src S = a.src[src];
+    double* cf = coef_all + (long long)src * G.N * 8;
+    for (int m = 0; m < nrec; ++m) {
+        const Tri t = tri_of(G, rec[3 * m], rec[3 * m + 1], rec[3 * m + 2]);
+        const double r = R[(long long)src * nrec + m];
+        for (int c0 = 0; c0 < 2; ++c0)
+            for (int c1 = 0; c1 < 2; ++c1)
+                for (int c2 = 0; c2 < 2; ++c2) {
+                    const int i = t.b[0] + c0, j = t.b[1] + c1, k = t.b[2] + c2;
+                    const Col c = make_col(G, a.T, i, j);
+                    const double2 t2 = a.T.t2[k];
+                    double T0, tt[3];
+                    factor<COORD>(S, c, t2.x, t2.y, T0, tt);
+                    cf[nidx(G, i, j, k) * 8 + 7] += r * tri_w(t, c0, c1, c2) * T0;
+                }
+    }
+}
+
+template <int COORD>
+__global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int dir, int plane) {
+    const int src = blockIdx.y;
+    if (!a.active[src]) return;
+    const Geo& G = a.G;
+    int TI, TJ, TK;
+    tile_decode(G, plane, blockIdx.x, TI, TJ, TK);
+    const int lane = threadIdx.x, li = lane >> 3, lj = lane & 7;
+    const int s0 = (dir & 4) ? -1 : 1, s1 = (dir & 2) ? -1 : 1, s2 = (dir & 1) ? -1 : 1;
+    const int ext_i = min(kBI, G.m[0] - TI * kBI), ext_j = min(kBJ, G.m[1] - TJ * kBJ);
+    const int k0p = TK * G.tk, k1p = min(k0p + G.tk, G.m[2]);
+    const bool colv = li < ext_i && lj < ext_j;
+    const int ip = TI * kBI + (colv ? li : 0), jp = TJ * kBJ + (colv ? lj : 0);
+    const int i = s0 > 0 ? 1 + ip : G.n[0] - 2 - ip;
+    const int j = s1 > 0 ? 1 + jp : G.n[1] - 2 - jp;
+    const Src S = a.src[src];
+    double* __restrict__ fld = a.field + (long long)src * G.N;
+    const double* __restrict__ cf = a.coef + (long long)src * G.N * 8;
+    const long long col = nidx(G, i, j, 0);
+    const long long di = s0 * G.si, dj = s1 * G.sj;
+    const bool fcol = (unsigned)(i - S.fb[0]) <= 1u && (unsigned)(j - S.fb[1]) <= 1u;
+    const int nsteps = (k1p - k0p) + ext_i - 1 + ext_j - 1;
+    const int kp0 = k0p - li - lj;
+    const int kbase = s2 > 0 ? 1 : G.n[2] - 2;
+    const bool last = (dir == 7);
+
+    double cur = 0.0, ahead = 0.0, prev = 0.0, dsum = 0.0, asum = 0.0;
+    if (colv && kp0 >= k0p && kp0 < k1p) cur = fld[col + kbase + s2 * kp0];
+    if (colv && kp0 + 1 >= k0p && kp0 + 1 <= k1p) ahead = fld[col + kbase + s2 * (kp0 + 1)];
+
+    for (int t = 0; t < nsteps; ++t) {
+        const int kp = kp0 + t;
+        const bool valid = colv && kp >= k0p && kp < k1p;
+        double up_i = __shfl(prev, lane - 8, 64);
+        double up_j = __shfl(prev, lane - 1, 64);
+        double dn_i = __shfl(ahead, lane + 8, 64);
+        double dn_j = __shfl(ahead, lane + 1, 64);
+        if (valid) {
+            const int ka = kbase + s2 * kp;
+            const long long x = col + ka;
+            if (li == 0) up_i = fld[x - di];
+            if (lj == 0) up_j = fld[x - dj];
+            if (li == ext_i - 1) dn_i = fld[x + di];
+            if (lj == ext_j - 1) dn_j = fld[x + dj];
+            const double up_k = (kp > k0p) ? prev : fld[x - s2];
+            double nv = cur;
+            if (!(fcol && (unsigned)(ka - S.fb[2]) <= 1u)) {
+                const double m0 = s0 > 0 ? up_i : dn_i, p0 = s0 > 0 ? dn_i : up_i;
+                const double m1 = s1 > 0 ? up_j : dn_j, p1 = s1 > 0 ? dn_j : up_j;
+                const double m2 = s2 > 0 ? up_k : ahead, p2 = s2 > 0 ? ahead : up_k;
+                const double* r = cf + x * 8;
+                double acc = r[7];
+                acc -= r[0] * p0;
+                acc -= r[1] * m0;
+                // face rows that extrapolate through x from distance 2 (coefficient +1)
+                if (i == 2 && !in_fixed(S, 0, j, ka)) acc -= fld[nidx(G, 0, j, ka)];
+                if (i == G.n[0] - 3 && !in_fixed(S, G.n[0] - 1, j, ka)) acc -= fld[nidx(G, G.n[0] - 1, j, ka)];
+                acc -= r[2] * p1;
+                acc -= r[3] * m1;
+                if (j == 2 && !in_fixed(S, i, 0, ka)) acc -= fld[nidx(G, i, 0, ka)];
+                if (j == G.n[1] - 3 && !in_fixed(S, i, G.n[1] - 1, ka)) acc -= fld[nidx(G, i, G.n[1] - 1, ka)];
+                acc -= r[4] * p2;
+                acc -= r[5] * m2;
+                if (ka == 2 && !in_fixed(S, i, j, 0)) acc -= fld[nidx(G, i, j, 0)];
+                if (ka == G.n[2] - 3 && !in_fixed(S, i, j, G.n[2] - 1)) acc -= fld[nidx(G, i, j, G.n[2] - 1)];
+                nv = acc / r[6];
+                fld[x] = nv;
+                dsum += fabs(nv - cur);
+                if (last) asum += fabs(nv);
+            }
+            prev = nv;
+        }
+        cur = ahead;
+        const int kn = kp + 2;
+        ahead = (colv && kn >= k0p && kn <= k1p) ? fld[col + kbase + s2 * kn] : 0.0;
+    }
+    dsum = wave_sum(dsum);
+    asum = wave_sum(asum);
+    if (lane == 0) {
+        const int tile_id = (TI * G.nt[1] + TJ) * G.nt[2] + TK;
+        a.part[(long long)src * a.nslots + dir * G.ntiles + tile_id] = dsum;
+        if (last) a.part2[(long long)src * a.nslots + tile_id] = asum;
+    }
+}
+
+// Transposed boundary pass: lambda_b = rhs_b - sum_{rows r != b} J_{r, b} lambda_r.
+// The rows that reference a boundary node b are its interior neighbour (face
+// nodes only, coefficient bnd_in[b]) and boundary rows b' extrapolating through
+// b along an axis a' above a*(b) (coefficient -2 at distance 1, +1 at distance
+// 2); lambda(b') is evaluated in place (a* grows strictly: depth <= 3).
+template <int BUDGET>
+__device__ double adj_bval(const Geo& G, const Src& S, const double* lam, const double* cf, const double* bin, int i,
+                           int j, int k) {
+    const int p[3] = {i, j, k};
+    const int as = astar_of(G, p);
+    double acc = cf[nidx(G, i, j, k) * 8 + 7];
+    const int nb = (int)on_bnd(G, 0, i) + (int)on_bnd(G, 1, j) + (int)on_bnd(G, 2, k);
+    if (nb == 1) {
+        const int nu = (p[as] == 0) ? 1 : -1;
+        int x[3] = {i, j, k};
+        x[as] += nu;
+        acc -= bin[bnd_encode(G, i, j, k)] * lam[nidx(G, x[0], x[1], x[2])];
+    }
+    if constexpr (BUDGET > 0) {
+        for (int ap = as + 1; ap < 3; ++ap) {
+            const int id = p[ap];
+            if (on_bnd(G, ap, id)) continue;
+            for (int side = 0; side < 2; ++side) {
+                const int dist = side == 0 ? id : (G.n[ap] - 1 - id);
+                if (dist != 1 && dist != 2) continue;
+                int q[3] = {i, j, k};
+                q[ap] = side == 0 ? 0 : G.n[ap] - 1;
+                if (in_fixed(S, q[0], q[1], q[2])) continue;
+                const double cv = dist == 1 ? -2.0 : 1.0;
+                acc -= cv * adj_bval<BUDGET - 1>(G, S, lam, cf, bin, q[0], q[1], q[2]);
+            }
+        }
+    }
+    return acc;
+}
+
+__global__ void __launch_bounds__(kBndThreads) k_adj_bnd(SweepArgs a, int dir) {
+    __shared__ double sh[4];
+    const int src = blockIdx.y;
+    if (!a.active[src]) return;
+    const Geo& G = a.G;
+    const Src S = a.src[src];
+    double* lam = a.field + (long long)src * G.N;
+    const double* cf = a.coef + (long long)src * G.N * 8;
+    const double* bin = a.bnd_in + (long long)src * G.NB;
+    const long long b = (long long)blockIdx.x * kBndThreads + threadIdx.x;
+    double d = 0.0, av = 0.0;
+    if (b < G.NB) {
+        int i, j, k;
+        bnd_decode(G, b, i, j, k);
+        if (!in_fixed(S, i, j, k)) {
+            const double nv = adj_bval<2>(G, S, lam, cf, bin, i, j, k);
+            const long long x = nidx(G, i, j, k);
+            d = fabs(nv - lam[x]);
+            av = fabs(nv);
+            lam[x] = nv;
+        }
+    }
+    d = block_sum256(d, sh);
+    const double as = (dir == 7) ? block_sum256(av, sh) : 0.0;
+    if (threadIdx.x == 0) {
+        a.part[(long long)src * a.nslots + 8 * G.ntiles + dir * a.nbblocks + blockIdx.x] = d;
+        if (dir == 7) a.part2[(long long)src * a.nslots + G.ntiles + blockIdx.x] = as;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_adj_finalize(SweepArgs a) {
+    __shared__ double sh[4];
+    const int src = blockIdx.x;
+    if (!a.active[src]) return;
+    const double dtot = fixed_sum(a.part + (long long)src * a.nslots, a.nslots, sh);
+    const double atot = fixed_sum(a.part2 + (long long)src * a.nslots, a.G.ntiles + a.nbblocks, sh);
+    if (threadIdx.x == 0) finish_iteration(a, src, dtot / (atot > 1e-300 ? atot : 1e-300));
+}
+
+// --------------------------------------------------------- sampling etc.
+template <int COORD>
+__global__ void k_sample(Geo G, Tabs T, const Src* __restrict__ srcs, int nsrc, const double* __restrict__ tau_all,
+                         int nrec, const double* __restrict__ rec, double* __restrict__ out) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long long)nsrc * nrec) return;
+    const int src = (int)(q / nrec), m = (int)(q % nrec);
+    const Src S = srcs[src];
+    const double* tau = tau_all + (long long)src * G.N;
+    const Tri t = tri_of(G, rec[3 * m], rec[3 * m + 1], rec[3 * m + 2]);
+    double acc = 0.0;
+    for (int c0 = 0; c0 < 2; ++c0)
+        for (int c1 = 0; c1 < 2; ++c1)
+            for (int c2 = 0; c2 < 2; ++c2) {
+                const int i = t.b[0] + c0, j = t.b[1] + c1, k = t.b[2] + c2;
+                const Col c = make_col(G, T, i, j);
+                const double2 t2 = T.t2[k];
+                double T0, tt[3];
+                factor<COORD>(S, c, t2.x, t2.y, T0, tt);
+                acc += tri_w(t, c0, c1, c2) * T0 * tau[nidx(G, i, j, k)];
+            }
+    out[q] = acc;
+}
+
+__global__ void __launch_bounds__(256) k_misfit(int nsrc, int nrec, const double* __restrict__ T,
+                                                const double* __restrict__ Tobs, const double* __restrict__ w,
+                                                int npair, const int32_t* __restrict__ pairs,
+                                                const double* __restrict__ wpair, double alpha, double beta,
+                                                double* __restrict__ R, double* __restrict__ chi) {
+    __shared__ double sh[4];
+    double part = 0.0;
+    for (int q = threadIdx.x; q < nsrc; q += blockDim.x) {
+        const long long base = (long long)q * nrec;
+        for (int m = 0; m < nrec; ++m) {
+            const double ww = w ? w[base + m] : 1.0;
+            const double r = T[base + m] - Tobs[base + m];
+            part += alpha * 0.5 * ww * r * r;
+            R[base + m] = alpha * ww * r;
+        }
+        for (int p = 0; p < npair; ++p) {
+            const int m = pairs[2 * p], i = pairs[2 * p + 1];
+            const double ww = wpair ? wpair[(long long)q * npair + p] : 1.0;
+            const double r = (T[base + m] - T[base + i]) - (Tobs[base + m] - Tobs[base + i]);
+            part += beta * 0.5 * ww * r * r;
+            R[base + m] += beta * ww * r;
+            R[base + i] -= beta * ww * r;
+        }
+    }
+    const double tot = block_sum256(part, sh);
+    if (threadIdx.x == 0) *chi = tot;
+}
+
+template <int COORD>
+__global__ void __launch_bounds__(256) k_kernel_accum(Geo G, Tabs T, const Src* __restrict__ srcs, int nsrc,
+                                                      const double* __restrict__ xi, const double* __restrict__ eta,
+                                                      const double* __restrict__ tau_all,
+                                                      const double* __restrict__ lam_all, double* __restrict__ grad,
+                                                      int accumulate) {
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= G.N) return;
+    const int k = (int)(x % G.n[2]);
+    const long long q = x / G.n[2];
+    const int j = (int)(q % G.n[1]), i = (int)(q / G.n[1]);
+    double gs = 0.0, gx = 0.0, ge = 0.0;
+    const bool interior = i > 0 && i < G.n[0] - 1 && j > 0 && j < G.n[1] - 1 && k > 0 && k < G.n[2] - 1;
+    if (interior) {
+        for (int n = 0; n < nsrc; ++n) {
+            const Src S = srcs[n];
+            if (in_fixed(S, i, j, k)) continue;
+            const double l = lam_all[(long long)n * G.N + x];
+            Col c;
+            Loc L;
+            state_at<COORD>(G, T, S, tau_all + (long long)n * G.N, xi, eta, i, j, k, c, L);
+            gs += l;
+            gx += l * (L.P[1] * L.P[1] - L.P[2] * L.P[2]) / L.H;
+            ge += -2.0 * l * L.P[1] * L.P[2] / L.H;
+        }
+    }
+    if (accumulate) {
+        grad[x] += gs; grad[G.N + x] += gx; grad[2 * G.N + x] += ge;
+    } else {
+        grad[x] = gs; grad[G.N + x] = gx; grad[2 * G.N + x] = ge;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+SweepArgs make_args(const Plan& P, const double* s, const double* xi, const double* eta, double* field,
+                    int32_t* status) {
+    SweepArgs a;
+    a.G = P.G;
+    a.T = P.T;
+    a.s = s; a.xi = xi; a.eta = eta;
+    a.src = P.src;
+    a.field = field;
+    a.coef = P.coef;
+    a.bnd_in = P.bnd_in;
+    a.active = P.active;
+    a.iter = P.iter;
+    a.status = status;
+    a.part = P.part;
+    a.part2 = P.part2;
+    a.counter = P.counter;
+    a.nslots = P.nslots;
+    a.nbblocks = P.nbblocks;
+    a.nsrc = P.nsrc;
+    a.max_iter = P.max_iter;
+    a.kappa = P.kappa;
+    a.tol = P.tol;
+    return a;
+}
+
+void launch_tables(const Plan& P, hipStream_t st) {
+    int n = P.G.n[0];
+    if (P.G.n[1] > n) n = P.G.n[1];
+    if (P.G.n[2] > n) n = P.G.n[2];
+    hipLaunchKernelGGL(k_tables, dim3(blocks_for(n, 64)), dim3(64), 0, st, P.G, P.tab0, P.tab1, P.tab2);
+}
+
+void launch_src_setup(const Plan& P, const double* pos, const double* par, hipStream_t st) {
+    hipLaunchKernelGGL(k_src_setup, dim3(blocks_for(P.nsrc, 64)), dim3(64), 0, st, P.G, pos, par, P.src, P.nsrc);
+}
+
+void launch_source_params(const Geo& G, const double* s, const double* xi, const double* eta, const double* pos,
+                          double* par, int nsrc, hipStream_t st) {
+    hipLaunchKernelGGL(k_source_params, dim3(blocks_for(nsrc, 64)), dim3(64), 0, st, G, s, xi, eta, pos, par, nsrc);
+}
+
+static unsigned fill_blocks(long long n) {
+    unsigned nb = blocks_for(n, 256);
+    return nb > 2048 ? 2048 : (nb == 0 ? 1 : nb);
+}
+
+void launch_fwd_init(const Plan& P, const SweepArgs& a, const double* tau_init, hipStream_t st) {
+    hipLaunchKernelGGL(k_solve_init, dim3(fill_blocks(P.G.N), P.nsrc), dim3(256), 0, st, a, tau_init, 1.0, 1.0);
+}
+
+void launch_fwd_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
+    for (int d = 0; d < 8; ++d) {
+        for (int p = 0; p < P.nplanes; ++p) {
+            const dim3 grid(P.plane_count[p], P.nsrc);
+            if (P.G.coord == 1)
+                hipLaunchKernelGGL(k_fwd_sweep<1>, grid, dim3(64), 0, st, a, d, p);
+            else
+                hipLaunchKernelGGL(k_fwd_sweep<0>, grid, dim3(64), 0, st, a, d, p);
+        }
+        hipLaunchKernelGGL(k_fwd_bnd, dim3(P.nbblocks, P.nsrc), dim3(kBndThreads), 0, st, a, d);
+    }
+    hipLaunchKernelGGL(k_fwd_finalize, dim3(P.nsrc), dim3(256), 0, st, a);
+}
+
+void launch_adj_init(const Plan& P, const SweepArgs& a, const double* tau, int nrec, const double* rec,
+                     const double* R, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill, dim3(fill_blocks(P.G.NB * P.nsrc)), dim3(256), 0, st, P.bnd_in, P.G.NB * P.nsrc, 0.0);
+    const dim3 grid(blocks_for(P.G.N, 256), P.nsrc);
+    if (P.G.coord == 1) {
+        hipLaunchKernelGGL(k_adj_coef<1>, grid, dim3(256), 0, st, a, tau, P.coef, P.bnd_in);
+        hipLaunchKernelGGL(k_adj_rhs<1>, dim3(blocks_for(P.nsrc, 64)), dim3(64), 0, st, a, P.coef, nrec, rec, R);
+    } else {
+        hipLaunchKernelGGL(k_adj_coef<0>, grid, dim3(256), 0, st, a, tau, P.coef, P.bnd_in);
+        hipLaunchKernelGGL(k_adj_rhs<0>, dim3(blocks_for(P.nsrc, 64)), dim3(64), 0, st, a, P.coef, nrec, rec, R);
+    }
+    hipLaunchKernelGGL(k_solve_init, dim3(fill_blocks(P.G.N), P.nsrc), dim3(256), 0, st, a, nullptr, 0.0, 0.0);
+}
+
+void launch_adj_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
+    for (int d = 0; d < 8; ++d) {
+        for (int p = 0; p < P.nplanes; ++p) {
+            const dim3 grid(P.plane_count[p], P.nsrc);
+            if (P.G.coord == 1)
+                hipLaunchKernelGGL(k_adj_sweep<1>, grid, dim3(64), 0, st, a, d, p);
+            else
+                hipLaunchKernelGGL(k_adj_sweep<0>, grid, dim3(64), 0, st, a, d, p);
+        }
+        hipLaunchKernelGGL(k_adj_bnd, dim3(P.nbblocks, P.nsrc), dim3(kBndThreads), 0, st, a, d);
+    }
+    hipLaunchKernelGGL(k_adj_finalize, dim3(P.nsrc), dim3(256), 0, st, a);
+}
+
+void launch_sample(const Plan& P, const double* tau, int nrec, const double* rec, double* out, hipStream_t st) {
+    const long long tot = (long long)P.nsrc * nrec;
+    if (tot == 0) return;
+    if (P.G.coord == 1)
+        hipLaunchKernelGGL(k_sample<1>, dim3(blocks_for(tot, 256)), dim3(256), 0, st, P.G, P.T, P.src, P.nsrc, tau,
+                           nrec, rec, out);
+    else
+        hipLaunchKernelGGL(k_sample<0>, dim3(blocks_for(tot, 256)), dim3(256), 0, st, P.G, P.T, P.src, P.nsrc, tau,
+                           nrec, rec, out);
+}
+
+void launch_misfit(int nsrc, int nrec, const double* T, const double* Tobs, const double* w, int npair,
+                   const int32_t* pairs, const double* wpair, double alpha, double beta, double* R, double* chi,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(k_misfit, dim3(1), dim3(256), 0, st, nsrc, nrec, T, Tobs, w, npair, pairs, wpair, alpha, beta,
+                       R, chi);
+}
+
+void launch_kernel_accum(const Plan& P, const double* xi, const double* eta, const double* tau, const double* lam,
+                         double* grad, int accumulate, hipStream_t st) {
+    if (P.G.coord == 1)
+        hipLaunchKernelGGL(k_kernel_accum<1>, dim3(blocks_for(P.G.N, 256)), dim3(256), 0, st, P.G, P.T, P.src,
+                           P.nsrc, xi, eta, tau, lam, grad, accumulate);
+    else
+        hipLaunchKernelGGL(k_kernel_accum<0>, dim3(blocks_for(P.G.N, 256)), dim3(256), 0, st, P.G, P.T, P.src,
+                           P.nsrc, xi, eta, tau, lam, grad, accumulate);
+}
+
+}  // namespace tt

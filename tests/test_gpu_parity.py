@@ -1,0 +1,205 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Both sides start from the same seeded inputs (paper_2412_00031_amd.workloads)
+and run their own pipeline: source constants, forward solve, receiver
+sampling, misfit/adjoint sources, adjoint solve, kernels.  Tolerances: tau and
+T at receivers 1e-12 (normwise relative), adjoint fields and kernels 1e-10,
+and identical iteration counts (the GPU visits the same Gauss-Seidel
+dependencies as the lexicographic oracle, so only rounding differs).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from conftest import rel_inf
+from paper_2412_00031_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_TAU = 1e-12
+TOL_ADJ = 1e-10
+
+
+def _dev(torch, a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device="cuda")
+
+
+def oracle_path(wl, tol, max_iter, R=None, T_obs=None, adj_tol=None, max_iter_adj=None, tau_init=None,
+                nsrc=None):
+    g, s, xi, eta = wl["grid"], wl["s"], wl["xi"], wl["eta"]
+    src = wl["src"][:nsrc] if nsrc else wl["src"]
+    rec = wl["rec"]
+    par = O.source_params(g, s, xi, eta, src)
+    taus, its, Ts = [], [], []
+    for q in range(len(src)):
+        ti = None if tau_init is None else tau_init[q]
+        tau, it, conv, _ = O.forward(g, s, xi, eta, src[q], par[q], wl["kappa"], tol, max_iter, tau_init=ti)
+        taus.append(tau)
+        its.append(it if conv else -it)
+        Ts.append(O.sample(g, src[q], par[q], tau, rec))
+    T = np.stack(Ts)
+    chi = None
+    if R is None:
+        chi, R = O.misfit(T, T_obs, pairs=wl.get("pairs"))
+    lams, ita = [], []
+    grad = np.zeros((3,) + tuple(g["n"]))
+    for q in range(len(src)):
+        rhs = O.adjoint_rhs(g, src[q], par[q], rec, R[q])
+        lam, it, conv, _ = O.adjoint(g, s, xi, eta, src[q], par[q], wl["kappa"], taus[q], rhs,
+                                     adj_tol or tol, max_iter_adj or max_iter)
+        lams.append(lam)
+        ita.append(it if conv else -it)
+        O.kernel(g, s, xi, eta, src[q], par[q], wl["kappa"], taus[q], lam, grad)
+    return dict(par=par, tau=np.stack(taus), it_f=np.array(its), T=T, chi=chi, R=R, lam=np.stack(lams),
+                it_a=np.array(ita), grad=grad)
+
+
+def gpu_path(torch, wl, tol, max_iter, R=None, T_obs=None, adj_tol=None, max_iter_adj=None, tile_k=0,
+             tau_init=None, nsrc=None):
+    from paper_2412_00031_amd import api
+    g = wl["grid"]
+    s, xi, eta = (_dev(torch, wl[k]) for k in ("s", "xi", "eta"))
+    src = _dev(torch, wl["src"][:nsrc] if nsrc else wl["src"])
+    rec = _dev(torch, wl["rec"])
+    par = api.source_params(g, s, xi, eta, src)
+    ti = None if tau_init is None else _dev(torch, tau_init)
+    tau, st_f = api.forward(g, s, xi, eta, src, par, tol, max_iter, wl["kappa"], tau_init=ti, tile_k=tile_k)
+    T = api.sample(g, src, par, tau, rec)
+    chi = None
+    if R is None:
+        pairs = None if wl.get("pairs") is None else _dev(torch, wl["pairs"], torch.int32)
+        chi, Rd = api.misfit(T, _dev(torch, T_obs), pairs=pairs)
+        chi = float(chi.item())
+    else:
+        Rd = _dev(torch, R)
+    lam, st_a = api.adjoint(g, s, xi, eta, src, par, tau, rec, Rd, adj_tol or tol, max_iter_adj or max_iter,
+                            wl["kappa"], tile_k=tile_k)
+    grad = api.kernel(g, s, xi, eta, src, par, tau, lam)
+    torch.cuda.synchronize()
+    c = lambda t: t.cpu().numpy()
+    return dict(par=c(par), tau=c(tau), it_f=c(st_f), T=c(T), chi=chi, R=c(Rd), lam=c(lam), it_a=c(st_a),
+                grad=c(grad))
+
+
+def assert_parity(gp, op, check_grad=True):
+    assert np.array_equal(gp["it_f"], op["it_f"]), (gp["it_f"], op["it_f"])
+    assert rel_inf(gp["par"], op["par"]) <= 1e-15
+    assert rel_inf(gp["tau"], op["tau"]) <= TOL_TAU, rel_inf(gp["tau"], op["tau"])
+    assert rel_inf(gp["T"], op["T"]) <= TOL_TAU, rel_inf(gp["T"], op["T"])
+    assert np.array_equal(gp["it_a"], op["it_a"]), (gp["it_a"], op["it_a"])
+    for q in range(len(op["lam"])):
+        assert rel_inf(gp["lam"][q], op["lam"][q]) <= TOL_ADJ, (q, rel_inf(gp["lam"][q], op["lam"][q]))
+    if check_grad:
+        for c in range(3):
+            if np.abs(op["grad"][c]).max() > 0:
+                assert rel_inf(gp["grad"][c], op["grad"][c]) <= TOL_ADJ, (c, rel_inf(gp["grad"][c], op["grad"][c]))
+
+
+def test_cartesian41_full_path(torch_cuda):
+    wl = W.cartesian41()
+    op = oracle_path(wl, wl["tol"], 400, R=wl["R"])
+    gp = gpu_path(torch_cuda, wl, wl["tol"], 400, R=wl["R"])
+    assert op["it_f"][0] > 1 and op["it_a"][0] > 1
+    assert_parity(gp, op)
+
+
+def test_small_spherical_several_tiles(torch_cuda):
+    wl = W.small_spherical(n=(13, 14, 15), nsrc=3)
+    op = oracle_path(wl, 1e-11, 400, R=wl["R"])
+    for tk in (0, 4):
+        gp = gpu_path(torch_cuda, wl, 1e-11, 400, R=wl["R"], tile_k=tk)
+        assert_parity(gp, op)
+
+
+def test_tile_shapes_bitwise(torch_cuda):
+    """Any tile shape visits the same dependencies: results are bit-identical."""
+    wl = W.small_spherical(n=(21, 19, 23), nsrc=2, seed=11)
+    ref = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=1000)
+    for tk in (1, 3, 5, 8, 32):
+        gp = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=tk)
+        for key in ("tau", "lam", "grad", "it_f", "it_a", "T"):
+            assert np.array_equal(gp[key], ref[key]), (tk, key)
+
+
+def test_misfit_with_pairs(torch_cuda):
+    from paper_2412_00031_amd import api
+    rng = np.random.default_rng(5)
+    nsrc, nrec, npair = 7, 40, 150
+    T = rng.uniform(1, 20, (nsrc, nrec))
+    Tobs = T + rng.normal(0, 0.2, T.shape)
+    w = rng.uniform(0.5, 1.5, T.shape)
+    pairs = W.random_pairs(nrec, npair, rng)
+    wpair = rng.uniform(0.5, 2.0, (nsrc, npair))
+    chi_o, R_o = O.misfit(T, Tobs, w, pairs, wpair, alpha=0.7, beta=1.3)
+    chi_g, R_g = api.misfit(_dev(torch_cuda, T), _dev(torch_cuda, Tobs), _dev(torch_cuda, w),
+                            _dev(torch_cuda, pairs, torch_cuda.int32), _dev(torch_cuda, wpair), 0.7, 1.3)
+    assert abs(chi_g.item() - chi_o) <= 1e-13 * abs(chi_o)
+    assert rel_inf(R_g.cpu().numpy(), R_o) <= 1e-14
+
+
+def test_misfit_path_with_pairs_spherical(torch_cuda):
+    wl = W.small_spherical(n=(12, 13, 17), nsrc=2, nrec=12, seed=21)
+    rng = np.random.default_rng(22)
+    wl["pairs"] = W.random_pairs(len(wl["rec"]), 20, rng)
+    T_obs = W.straight_line_times(wl["grid"], wl["src"], wl["rec"], 6.3)
+    op = oracle_path(wl, 1e-11, 300, T_obs=T_obs)
+    gp = gpu_path(torch_cuda, wl, 1e-11, 300, T_obs=T_obs)
+    assert abs(gp["chi"] - op["chi"]) <= 1e-12 * abs(op["chi"])
+    assert rel_inf(gp["R"], op["R"]) <= 1e-11
+    assert_parity(gp, op)
+
+
+def test_truncated_iterations_report_nonconvergence(torch_cuda):
+    wl = W.small_spherical(n=(16, 15, 14), nsrc=2, seed=3)
+    op = oracle_path(wl, 1e-14, 3, R=wl["R"], max_iter_adj=2)
+    gp = gpu_path(torch_cuda, wl, 1e-14, 3, R=wl["R"], max_iter_adj=2)
+    assert list(op["it_f"]) == [-3, -3] and list(op["it_a"]) == [-2, -2]
+    assert_parity(gp, op)
+
+
+def test_warm_start_parity(torch_cuda):
+    wl = W.small_spherical(n=(14, 14, 14), nsrc=2, seed=9)
+    rng = np.random.default_rng(10)
+    tau0 = 1.0 + 0.02 * rng.standard_normal((2,) + tuple(wl["grid"]["n"]))
+    op = oracle_path(wl, 1e-11, 300, R=wl["R"], tau_init=tau0)
+    gp = gpu_path(torch_cuda, wl, 1e-11, 300, R=wl["R"], tau_init=tau0)
+    assert_parity(gp, op)
+
+
+def test_fixed_cell_touching_boundary_and_on_node(torch_cuda):
+    wl = W.small_spherical(n=(10, 11, 12), nsrc=3, seed=4)
+    g = wl["grid"]
+    ax = W.axes(g)
+    src = wl["src"].copy()
+    src[0] = [ax[0][-1] - 0.3 * g["h"][0], ax[1][0] + 0.2 * g["h"][1], ax[2][5]]      # cell at the surface/corner
+    src[1] = [ax[0][4], ax[1][6], ax[2][7]]                                            # exactly on a node
+    src[2] = [ax[0][0] + 0.5 * g["h"][0], ax[1][-1] - 0.1 * g["h"][1], ax[2][-1]]     # far corner
+    wl["src"] = src
+    op = oracle_path(wl, 1e-11, 300, R=wl["R"])
+    gp = gpu_path(torch_cuda, wl, 1e-11, 300, R=wl["R"])
+    assert_parity(gp, op)
+
+
+def test_minimal_grid_and_cartesian_anisotropic(torch_cuda):
+    rng = np.random.default_rng(8)
+    for n in ((4, 4, 4), (4, 6, 5), (9, 4, 7)):
+        g = W.cartesian_grid(1, 1.0)
+        g["n"] = n
+        s = 1.0 / rng.uniform(5.0, 7.0, n)
+        xi = rng.uniform(-0.05, 0.05, n)
+        eta = rng.uniform(-0.05, 0.05, n)
+        L = [(v - 1) * 1.0 for v in n]
+        src = np.array([[rng.uniform(0, L[0]), rng.uniform(0, L[1]), rng.uniform(0, L[2])]])
+        rec = np.array([[0.0, rng.uniform(0, L[1]), rng.uniform(0, L[2])] for _ in range(3)])
+        wl = dict(grid=g, s=s, xi=xi, eta=eta, src=src, rec=rec, R=rng.normal(0, 0.1, (1, 3)), kappa=1.12)
+        op = oracle_path(wl, 1e-12, 300, R=wl["R"])
+        gp = gpu_path(torch_cuda, wl, 1e-12, 300, R=wl["R"])
+        assert_parity(gp, op)
+
+
+@pytest.mark.slow
+def test_sph61_two_sources(torch_cuda):
+    wl = W.sph61(nsrc=32)
+    op = oracle_path(wl, wl["tol"], 300, R=wl["R"][:2], nsrc=2)
+    gp = gpu_path(torch_cuda, wl, wl["tol"], 300, R=wl["R"][:2], nsrc=2)
+    assert_parity(gp, op)
