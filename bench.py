@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Throughput of the adjoint-state traveltime hot path on one MI355X.
+
+One step = one pass of the whole per-source path over a batch of sources:
+source constants, forward fast-sweeping solve to tol, receiver traveltimes,
+misfit and adjoint sources (Eqs. (2), (A2)), adjoint solve to tol, and the
+kernels summed over sources (Eqs. (6)-(8)).  Workload: 101^3 spherical grid
+(0-100 km depth, 4 x 4 degrees), Gaussian-random-field slowness (+-10 %) and
+anisotropy (+-0.04), 128 sources, 500 surface receivers, tol 1e-6, FP64;
+observed times come from a forward solve in an independent random model
+(computed before timing).  value = sources per second (fwd + adjoint +
+kernel per source).
+
+Prints one JSON line (rank 0).  Extra objects: "roofline" (the dominant sweep
+kernel, timed live with HIP events around each of its launches) and
+"cpu_baseline" (the CPU oracle on a bounded sample of the same workload).
+"""
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "converged fwd+adjoint Eikonal solves/s (101³, tol 1e-6), plain vs warm-start"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nsrc", type=int, default=128)
+    ap.add_argument("--tile-k", type=int, default=0)
+    ap.add_argument("--max-iter", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    return ap.parse_args()
+
+
+def interior_nonfixed(grid):
+    n = grid["n"]
+    return (n[0] - 2) * (n[1] - 2) * (n[2] - 2)
+
+
+def cpu_baseline(wl, it_f, it_a, threads):
+    """Time the oracle on `threads` sources at once (one per thread): 3 forward
+    iterations, then adjoint solves capped at 1 and 3 iterations and one kernel
+    accumulation; scale to whole solves with the per-source iteration counts
+    that the GPU reached (identical to the oracle's by construction of the
+    parity tests).  Returns solves/s over all threads."""
+    import numpy as np
+    import oracle as O
+    g, s, xi, eta = wl["grid"], wl["s"], wl["xi"], wl["eta"]
+    src = wl["src"][:threads]
+    par = O.source_params(g, s, xi, eta, src)
+    kappa = wl["kappa"]
+    out = [None] * threads
+
+    def work(q):
+        t0 = time.perf_counter()
+        tau, _, _, _ = O.forward(g, s, xi, eta, src[q], par[q], kappa, 1e-30, 3)
+        t1 = time.perf_counter()
+        rhs = O.adjoint_rhs(g, src[q], par[q], wl["rec"], wl["R"][q])
+        t2 = time.perf_counter()
+        O.adjoint(g, s, xi, eta, src[q], par[q], kappa, tau, rhs, 1e-30, 1)
+        t3 = time.perf_counter()
+        lam, _, _, _ = O.adjoint(g, s, xi, eta, src[q], par[q], kappa, tau, rhs, 1e-30, 3)
+        t4 = time.perf_counter()
+        O.kernel(g, s, xi, eta, src[q], par[q], kappa, tau, lam)
+        t5 = time.perf_counter()
+        per_f = (t1 - t0) / 3.0
+        per_a = ((t4 - t3) - (t3 - t2)) / 2.0
+        fixed_a = (t3 - t2) - per_a + (t2 - t1)
+        out[q] = per_f * it_f[q] + fixed_a + per_a * it_a[q] + (t5 - t4)
+
+    t0 = time.perf_counter()
+    ths = [threading.Thread(target=work, args=(q,)) for q in range(threads)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    wall = time.perf_counter() - t0
+    per_source = float(np.mean(out))
+    return threads / per_source, wall
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sources of a batch shard "
+              "across GPUs with no communication but this build measures the one-GPU share", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2412_00031_amd import api, workloads as W
+
+    dev = torch.device("cuda:0")
+    wl = W.sph101(nsrc=args.nsrc)
+    g, kappa, tol = wl["grid"], wl["kappa"], wl["tol"]
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    s, xi, eta, src, rec = t(wl["s"]), t(wl["xi"]), t(wl["eta"]), t(wl["src"]), t(wl["rec"])
+    nsrc = args.nsrc
+
+    # observations: forward solve in the independent "true" model (untimed)
+    st_, xt_, et_ = t(wl["s_true"]), t(wl["xi_true"]), t(wl["eta_true"])
+    par_t = api.source_params(g, st_, xt_, et_, src)
+    tau_t, _ = api.forward(g, st_, xt_, et_, src, par_t, tol, args.max_iter, kappa, tile_k=args.tile_k)
+    T_obs = api.sample(g, src, par_t, tau_t, rec)
+    del tau_t
+    torch.cuda.synchronize()
+    log("observations ready")
+
+    ws_f = api.workspace(g, nsrc, 0, args.tile_k, dev)
+    ws_a = api.workspace(g, nsrc, 1, args.tile_k, dev)
+    tau = torch.empty((nsrc,) + tuple(g["n"]), dtype=torch.float64, device=dev)
+    lam = torch.empty_like(tau)
+    grad = torch.empty((3,) + tuple(g["n"]), dtype=torch.float64, device=dev)
+
+    def step(timed):
+        par = api.source_params(g, s, xi, eta, src)
+        _, st_f = api.forward(g, s, xi, eta, src, par, tol, args.max_iter, kappa, tile_k=args.tile_k, ws=ws_f,
+                              out=tau, time_sweeps=timed)
+        T = api.sample(g, src, par, tau, rec)
+        chi, R = api.misfit(T, T_obs)
+        _, st_a = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, tol, args.max_iter, kappa, tile_k=args.tile_k,
+                              ws=ws_a, out=lam, time_sweeps=timed)
+        api.kernel(g, s, xi, eta, src, par, tau, lam, grad=grad.zero_())
+        return st_f, st_a, chi
+
+    for w in range(args.warmup):
+        step(False)
+        torch.cuda.synchronize()
+        log(f"warmup step {w + 1} done")
+    torch.cuda.synchronize()
+    api.sweep_timing(0, reset=True)
+    api.sweep_timing(1, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st_f, st_a, chi = step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"timed {args.steps} steps: {elapsed:.2f} s")
+    st_f = st_f.cpu().numpy()
+    st_a = st_a.cpu().numpy()
+    if (st_f <= 0).any() or (st_a <= 0).any():
+        print(f"warning: not all sources converged (fwd {st_f.min()}, adj {st_a.min()})", file=sys.stderr)
+    it_f = np.abs(st_f)
+    it_a = np.abs(st_a)
+    ms_f, n_f = api.sweep_timing(0, reset=True)
+    ms_a, n_a = api.sweep_timing(1, reset=True)
+
+    value = nsrc * args.steps / elapsed
+    nodes = interior_nonfixed(g)
+    # algorithmic bytes per node update: forward = tau read + write (16 B) plus
+    # the model (24 B per node per sweep, shared by the batch); adjoint =
+    # lambda read + write plus the 8 stored coefficients of the node (80 B)
+    upd_f = float(it_f.sum()) * 8 * nodes * args.steps
+    upd_a = float(it_a.sum()) * 8 * nodes * args.steps
+    bytes_f = upd_f * (16.0 + 24.0 / nsrc)
+    bytes_a = upd_a * (16.0 + 64.0 + 24.0 / nsrc)
+    kern = {
+        "k_fwd_sweep": dict(ms=ms_f, launches=n_f, bytes=bytes_f, updates=upd_f),
+        "k_adj_sweep": dict(ms=ms_a, launches=n_a, bytes=bytes_a, updates=upd_a),
+    }
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    K = kern[dom]
+    avg_ms = K["ms"] / max(K["launches"], 1)
+    achieved = K["bytes"] / (K["ms"] * 1e-3) / 1e9 if K["ms"] > 0 else 0.0
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "kernel": dom, "avg_launch_ms": round(avg_ms, 5), "launches": K["launches"],
+        "bytes_per_update": round(K["bytes"] / K["updates"], 3),
+        "sweep_ms": {k: round(v["ms"], 2) for k, v in kern.items()},
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(len(os.sched_getaffinity(0)), 16)
+        threads = max(1, min(threads, nsrc))
+        log(f"cpu baseline on {threads} threads")
+        v_cpu, wall = cpu_baseline(wl, it_f[:threads], it_a[:threads], threads)
+        cpu = {"value": round(v_cpu, 5), "unit": "solves/s", "cores": threads, "kind": "oracle",
+               "sample": f"{threads} sources of the same workload, one per thread: 3 forward iterations, adjoint "
+                         f"capped at 1 and 3 iterations, one kernel pass; scaled per source to the converged "
+                         f"iteration counts ({wall:.1f} s wall)"}
+
+    line = {
+        "metric": METRIC, "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"sph101: 101^3 spherical (0-100 km, 4x4 deg), GRF model, {nsrc} sources, "
+                               f"{len(wl['rec'])} receivers, tol {tol:g}, plain start",
+                   "nsrc": nsrc, "grid": list(g["n"]), "tol": tol, "kappa": kappa,
+                   "mean_iters_fwd": round(float(it_f.mean()), 2), "mean_iters_adj": round(float(it_a.mean()), 2),
+                   "tile_k": args.tile_k or 32},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

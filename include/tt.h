@@ -59,8 +59,15 @@ typedef struct tt_opts {
     int32_t max_iter;  /* >= 1 */
     double kappa;      /* Lax-Friedrichs viscosity factor, >= max sqrt(1 + 2|xi|) */
     int32_t tile_k;    /* k-extent of one sweep tile; 0 = library default */
-    int32_t flags;     /* reserved, 0 */
+    int32_t flags;     /* bit 0 (TT_FLAG_TIME_SWEEPS): time every sweep-kernel launch with
+                          HIP events on the call's stream (see tt_sweep_timing) */
+    double* eps_hist;  /* optional device buffer [nsrc][max_iter] that receives the
+                          convergence measure of every iteration of every source
+                          (entries past a source's last iteration are left as
+                          they were), or NULL */
 } tt_opts;
+
+#define TT_FLAG_TIME_SWEEPS 1
 
 /* Bytes of device workspace needed by tt_forward (which = 0), tt_adjoint
  * (which = 1), tt_sample (which = 2) or tt_kernel (which = 3) for this grid,
@@ -133,6 +140,13 @@ int tt_adjoint(const tt_grid* grid, const double* s, const double* xi, const dou
 int tt_kernel(const tt_grid* grid, const double* s, const double* xi, const double* eta, int32_t nsrc,
               const double* src_pos, const double* src_par, const double* tau, const double* lam,
               double* grad, int32_t accumulate, void* ws, size_t ws_bytes, void* stream);
+
+/* Sweep-kernel timing gathered by tt_forward (which = 0) and tt_adjoint
+ * (which = 1) calls of the calling thread that had TT_FLAG_TIME_SWEEPS set:
+ * the summed device time of every timed sweep-kernel launch (ms, from a HIP
+ * event pair around each launch) and the number of such launches.  reset != 0
+ * clears the totals after reading.  Pointers may be NULL. */
+int tt_sweep_timing(int32_t which, double* total_ms, int64_t* launches, int32_t reset);
 
 /* Message for the last nonzero return of the calling thread ("" if none). */
 const char* tt_last_error(void);

@@ -39,8 +39,14 @@
  *   (R5) 8 sweep directions in binary order (+++, ++-, +-+, ..., ---), axis 2
  *        least significant; each sweep is followed by a boundary pass.
  *   (R6) boundary pass: for a boundary node b not in F let a* be the largest
- *        axis on which b lies on the boundary; tau_b = 2 tau(b+nu e_a*) -
- *        tau(b+2 nu e_a*), nu the inward sign; groups a* = 0, 1, 2 in turn.
+ *        axis on which b lies on the boundary; tau_b = tau(b + nu e_a*), nu the
+ *        inward sign (zeroth-order extrapolation of the factor tau); groups
+ *        a* = 0, 1, 2 in turn.  Linear extrapolation (2 tau(b+nu e) -
+ *        tau(b+2nu e)) was tried first: with it the sweeps diverge for deep
+ *        sources of the 101^3 spherical workload, while Sec. 3.1 states that the
+ *        method converges unconditionally; with the copy rule every boundary row
+ *        is an M-matrix row and both the sweeps and the transposed sweeps
+ *        converge.
  *   (R7) iteration = 8 sweeps with their boundary passes; eps = (1/N) sum of
  *        |tau_new - tau_old| over all writes of the iteration; stop at the first
  *        iteration with eps < tol.
@@ -235,14 +241,13 @@ static int astar_of(const OGrid* g, int i, int j, int k) {
     return as;
 }
 
-/* the two inward nodes used by the extrapolation row of boundary node b */
-static void bnd_refs(const OGrid* g, int i, int j, int k, int as, size_t* b1, size_t* b2) {
+/* the inward node copied by the boundary row of boundary node b */
+static size_t bnd_ref(const OGrid* g, int i, int j, int k, int as) {
     int idx[3] = {i, j, k};
     int nu = (idx[as] == 0) ? 1 : -1;
-    int p1[3] = {i, j, k}, p2[3] = {i, j, k};
-    p1[as] += nu; p2[as] += 2 * nu;
-    *b1 = IDX(g, p1[0], p1[1], p1[2]);
-    *b2 = IDX(g, p2[0], p2[1], p2[2]);
+    int p1[3] = {i, j, k};
+    p1[as] += nu;
+    return IDX(g, p1[0], p1[1], p1[2]);
 }
 
 /* boundary nodes with a* == as, in storage order; returns the count */
@@ -274,9 +279,8 @@ static double boundary_pass(const OGrid* g, const OSrc* S, double* tau, size_t* 
             int i, j, k;
             unidx(g, bl[q], &i, &j, &k);
             if (is_fixed(S, i, j, k)) continue;
-            size_t b1, b2;
-            bnd_refs(g, i, j, k, as, &b1, &b2);
-            double nv = 2.0 * tau[b1] - tau[b2];
+            size_t b1 = bnd_ref(g, i, j, k, as);
+            double nv = tau[b1];
             acc += fabs(nv - tau[bl[q]]);
             tau[bl[q]] = nv;
         }
@@ -588,7 +592,7 @@ int tto_adjoint_rhs(const int* n, int coord, const double* o, const double* h,
 /* ---------------------------------------------------------------------------
  * Discrete adjoint.  Rows of the Jacobian J of the discrete forward system:
  *   fixed node f:       tau_f - 1 = 0                       -> J_ff = 1
- *   boundary node b:    tau_b - 2 tau_b1 + tau_b2 = 0       -> 1, -2, +1
+ *   boundary node b:    tau_b - tau_b1 = 0                  -> 1, -1
  *   interior node x:    G_x (see lf_update)                 ->
  *       J_xx        = t.MP / H + sum_a 2 beta_a,
  *       J_x,x+e_a   =  alpha_a - beta_a,
@@ -621,12 +625,9 @@ static int jac_row(const OGrid* g, const OSrc* S, const OCoef* coef, int i, int 
     if (is_fixed(S, i, j, k)) { col[0] = c; val[0] = 1.0; return 1; }
     int as = astar_of(g, i, j, k);
     if (as >= 0) {
-        size_t b1, b2;
-        bnd_refs(g, i, j, k, as, &b1, &b2);
         col[0] = c; val[0] = 1.0;
-        col[1] = b1; val[1] = -2.0;
-        col[2] = b2; val[2] = 1.0;
-        return 3;
+        col[1] = bnd_ref(g, i, j, k, as); val[1] = -1.0;
+        return 2;
     }
     size_t st[3] = {(size_t)g->n[1] * g->n[2], (size_t)g->n[2], 1};
     const OCoef* C = &coef[c];
@@ -640,7 +641,8 @@ static int jac_row(const OGrid* g, const OSrc* S, const OCoef* coef, int i, int 
 }
 
 /* column equation of J^T lambda = rhs at node y, solved for lambda_y:
- * every row that can reference y lies within distance 2 of y along one axis. */
+ * every row that can reference y lies within distance 1 of y along one axis
+ * (candidates up to distance 2 are scanned; jac_row decides). */
 static double transposed_update(const OGrid* g, const OSrc* S, const OCoef* coef,
                                 const double* rhs, const double* lam, int i, int j, int k) {
     size_t y = IDX(g, i, j, k);

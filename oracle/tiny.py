@@ -1,7 +1,7 @@
 """Tiny-grid numpy tools for pinning the oracle (test infrastructure only).
 
 ``residual`` writes out the discrete forward system that the sweeps solve
-(interior Lax-Friedrichs equations, boundary extrapolation rows, fixed rows),
+(interior Lax-Friedrichs equations, boundary copy rows, fixed rows),
 vectorised in numpy; ``jacobian_fd`` differentiates it numerically.  They let
 the tests check the Gauss-Seidel solvers against dense direct solves (Newton
 for the forward fixed point, J^T lambda = g for the adjoint).
@@ -59,14 +59,13 @@ def residual(grid, s, xi, eta, src_pos, src_par, kappa, tau):
     H = np.sqrt(P[0] ** 2 + (1 - 2 * x) * P[1] ** 2 + 4 * e * P[1] * P[2] + (1 + 2 * x) * P[2] ** 2)
     Gint = H - visc - s[sl]
     res[sl] = Gint
-    # boundary rows: extrapolation along the largest boundary axis
+    # boundary rows: copy of the inward neighbour along the largest boundary axis
     for idx in zip(*np.nonzero(Bn)):
         p = list(idx)
         as_ = max(a for a in range(3) if p[a] in (0, n[a] - 1))
         nu = 1 if p[as_] == 0 else -1
         p1 = list(p); p1[as_] += nu
-        p2 = list(p); p2[as_] += 2 * nu
-        res[idx] = tau[idx] - 2.0 * tau[tuple(p1)] + tau[tuple(p2)]
+        res[idx] = tau[idx] - tau[tuple(p1)]
     res[F] = tau[F] - 1.0
     return res
 
@@ -102,8 +101,7 @@ def assemble_jacobian(grid, coeffs, src_pos):
             as_ = max(a for a in range(3) if p[a] in (0, n[a] - 1))
             nu = 1 if p[as_] == 0 else -1
             J[r, r] = 1.0
-            J[r, r + nu * st[as_]] += -2.0
-            J[r, r + 2 * nu * st[as_]] += 1.0
+            J[r, r + nu * st[as_]] += -1.0
         else:
             J[r, r] = coeffs[6][idx]
             for a in range(3):

@@ -17,11 +17,13 @@ class TTGrid(ctypes.Structure):
 
 class TTOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("kappa", ctypes.c_double),
-                ("tile_k", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("tile_k", ctypes.c_int32), ("flags", ctypes.c_int32), ("eps_hist", ctypes.c_void_p)]
 
 
 EXPORTS = ["tt_workspace_size", "tt_source_params", "tt_forward", "tt_sample", "tt_misfit", "tt_adjoint",
-           "tt_kernel", "tt_last_error"]
+           "tt_kernel", "tt_sweep_timing", "tt_last_error"]
+
+TT_FLAG_TIME_SWEEPS = 1
 
 _lib = None
 
@@ -53,6 +55,8 @@ def load(path=LIB_PATH):
     lib.tt_misfit.argtypes = [i32, i32, P, P, P, i32, P, P, ctypes.c_double, ctypes.c_double, P, P, P]
     lib.tt_adjoint.argtypes = [G, P, P, P, i32, P, P, P, i32, P, P, O, P, P, P, sz, P]
     lib.tt_kernel.argtypes = [G, P, P, P, i32, P, P, P, P, P, i32, P, sz, P]
+    lib.tt_sweep_timing.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
+    lib.tt_sweep_timing.restype = ctypes.c_int
     lib.tt_last_error.argtypes = []
     lib.tt_last_error.restype = ctypes.c_char_p
     for name in ("tt_source_params", "tt_forward", "tt_sample", "tt_misfit", "tt_adjoint", "tt_kernel"):

@@ -26,14 +26,25 @@ def _grid(grid):
     return g
 
 
-def _opts(tol, max_iter, kappa, tile_k=0):
+def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None):
     o = _lib.TTOpts()
+    o.eps_hist = _dev(eps_hist, "eps_hist").value if eps_hist is not None else None
     o.tol = float(tol)
     o.max_iter = int(max_iter)
     o.kappa = float(kappa)
     o.tile_k = int(tile_k)
-    o.flags = 0
+    o.flags = _lib.TT_FLAG_TIME_SWEEPS if time_sweeps else 0
     return o
+
+
+def sweep_timing(which, reset=True):
+    """(total ms, launches) of the timed sweep-kernel launches of this thread:
+    which = 0 forward, 1 adjoint (calls made with time_sweeps=True)."""
+    lib = _lib.load()
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _lib.check(lib.tt_sweep_timing(int(which), ctypes.byref(ms), ctypes.byref(n), int(bool(reset))))
+    return ms.value, n.value
 
 
 def _dev(t, name, dtype=_F64, numel=None):
@@ -88,8 +99,10 @@ def source_params(grid, s, xi, eta, src_pos):
 
 
 def forward(grid, s, xi, eta, src_pos, src_par, tol, max_iter, kappa, tau_init=None, tile_k=0, ws=None,
-            out=None):
-    """Batched forward solve.  Returns (tau [nsrc, *n], status int32 [nsrc])."""
+            out=None, time_sweeps=False, eps_hist=None):
+    """Batched forward solve.  Returns (tau [nsrc, *n], status int32 [nsrc]).
+    eps_hist: optional float64 device tensor [nsrc, max_iter] receiving the
+    convergence measure of every iteration."""
     lib = _lib.load()
     N = _N(grid)
     nsrc = int(src_pos.shape[0])
@@ -99,7 +112,9 @@ def forward(grid, s, xi, eta, src_pos, src_par, tol, max_iter, kappa, tau_init=N
     if ws is None:
         ws = workspace(grid, nsrc, 0, tile_k, dev)
     g = _grid(grid)
-    o = _opts(tol, max_iter, kappa, tile_k)
+    if eps_hist is not None and eps_hist.numel() != nsrc * int(max_iter):
+        raise ValueError("eps_hist must have nsrc * max_iter elements")
+    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist)
     ti = _dev(tau_init, "tau_init", numel=nsrc * N) if tau_init is not None else _null()
     _lib.check(lib.tt_forward(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
                               _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
@@ -143,8 +158,9 @@ def misfit(T_rec, T_obs, w=None, pairs=None, wpair=None, alpha=1.0, beta=1.0):
 
 
 def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, kappa, tile_k=0, ws=None,
-            out=None):
-    """Batched adjoint solve.  Returns (lambda [nsrc, *n], status int32 [nsrc])."""
+            out=None, time_sweeps=False, eps_hist=None):
+    """Batched adjoint solve.  Returns (lambda [nsrc, *n], status int32 [nsrc]);
+    eps_hist as for forward."""
     lib = _lib.load()
     N = _N(grid)
     nsrc, nrec = int(src_pos.shape[0]), int(rec_pos.shape[0])
@@ -154,7 +170,9 @@ def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, 
     if ws is None:
         ws = workspace(grid, nsrc, 1, tile_k, dev)
     g = _grid(grid)
-    o = _opts(tol, max_iter, kappa, tile_k)
+    if eps_hist is not None and eps_hist.numel() != nsrc * int(max_iter):
+        raise ValueError("eps_hist must have nsrc * max_iter elements")
+    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist)
     _lib.check(lib.tt_adjoint(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
                               _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
                               _dev(src_par, "src_par", numel=3 * nsrc), _dev(tau, "tau", numel=nsrc * N), nrec,

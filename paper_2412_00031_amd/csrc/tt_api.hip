@@ -157,18 +157,14 @@ void bind_workspace(tt::Plan& P, void* ws, const Layout& L) {
 
 int tile_k_of(const tt_opts* o) { return (o && o->tile_k > 0) ? o->tile_k : kDefaultTileK; }
 
-// pinned host word that receives the active-source count of each iteration
-struct Pinned {
-    int* p = nullptr;
-    ~Pinned() {
-        if (p) (void)hipHostFree(p);
-    }
-};
-thread_local Pinned g_pinned;
+// pinned host words that receive the active-source count of each iteration
+// (allocated once per thread and kept until the process ends: freeing them
+// from a thread-exit destructor could run after the HIP runtime is gone)
+thread_local int* g_pinned = nullptr;
 
 int pinned_counter(int** out) {
-    if (!g_pinned.p) TT_HIP(hipHostMalloc(reinterpret_cast<void**>(&g_pinned.p), 2 * sizeof(int), hipHostMallocDefault));
-    *out = g_pinned.p;
+    if (!g_pinned) TT_HIP(hipHostMalloc(reinterpret_cast<void**>(&g_pinned), 2 * sizeof(int), hipHostMallocDefault));
+    *out = g_pinned;
     return TT_OK;
 }
 
@@ -215,6 +211,24 @@ int run_iterations(const tt::Plan& P, hipStream_t st, Launch launch_one) {
     return result;
 }
 
+// sweep-kernel timing totals of this thread: [0] forward, [1] adjoint
+thread_local double g_sweep_ms[2] = {0.0, 0.0};
+thread_local int64_t g_sweep_launches[2] = {0, 0};
+
+// sum and release the event pairs recorded during a solve (stream already synchronised)
+void collect_timing(std::vector<std::pair<hipEvent_t, hipEvent_t>>& ev, int which) {
+    for (auto& pr : ev) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+            g_sweep_ms[which] += ms;
+            g_sweep_launches[which] += 1;
+        }
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    ev.clear();
+}
+
 int check_ptrs(std::initializer_list<const void*> ps) {
     int q = 0;
     for (const void* p : ps) {
@@ -229,6 +243,17 @@ int check_ptrs(std::initializer_list<const void*> ps) {
 extern "C" {
 
 const char* tt_last_error(void) { return g_err.c_str(); }
+
+int tt_sweep_timing(int32_t which, double* total_ms, int64_t* launches, int32_t reset) {
+    if (which < 0 || which > 1) return fail(TT_EINVAL, "which must be 0 or 1");
+    if (total_ms) *total_ms = g_sweep_ms[which];
+    if (launches) *launches = g_sweep_launches[which];
+    if (reset) {
+        g_sweep_ms[which] = 0.0;
+        g_sweep_launches[which] = 0;
+    }
+    return TT_OK;
+}
 
 size_t tt_workspace_size(const tt_grid* grid, int32_t nsrc, const tt_opts* opts, int32_t which) {
     if (check_grid(grid) || nsrc < 1 || which < 0 || which > 3) return 0;
@@ -271,13 +296,18 @@ int tt_forward(const tt_grid* grid, const double* s, const double* xi, const dou
     P.kappa = opts->kappa;
     P.tol = opts->tol;
     P.max_iter = opts->max_iter;
+    P.eps_hist = opts->eps_hist;
     hipStream_t st = (hipStream_t)stream;
     tt::launch_tables(P, st);
     tt::launch_src_setup(P, src_pos, src_par, st);
     tt::SweepArgs a = tt::make_args(P, s, xi, eta, tau, status);
     tt::launch_fwd_init(P, a, tau_init, st);
     TT_HIP(hipGetLastError());
-    return run_iterations(P, st, [&]() { tt::launch_fwd_iteration(P, a, st); });
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    if (opts->flags & TT_FLAG_TIME_SWEEPS) P.timing = &ev;
+    rc = run_iterations(P, st, [&]() { tt::launch_fwd_iteration(P, a, st); });
+    collect_timing(ev, 0);
+    return rc;
 }
 
 int tt_sample(const tt_grid* grid, int32_t nsrc, const double* src_pos, const double* src_par, const double* tau,
@@ -337,13 +367,18 @@ int tt_adjoint(const tt_grid* grid, const double* s, const double* xi, const dou
     P.kappa = opts->kappa;
     P.tol = opts->tol;
     P.max_iter = opts->max_iter;
+    P.eps_hist = opts->eps_hist;
     hipStream_t st = (hipStream_t)stream;
     tt::launch_tables(P, st);
     tt::launch_src_setup(P, src_pos, src_par, st);
     tt::SweepArgs a = tt::make_args(P, s, xi, eta, lam, status);
     tt::launch_adj_init(P, a, tau, nrec, rec_pos, R, st);
     TT_HIP(hipGetLastError());
-    return run_iterations(P, st, [&]() { tt::launch_adj_iteration(P, a, st); });
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    if (opts->flags & TT_FLAG_TIME_SWEEPS) P.timing = &ev;
+    rc = run_iterations(P, st, [&]() { tt::launch_adj_iteration(P, a, st); });
+    collect_timing(ev, 1);
+    return rc;
 }
 
 int tt_kernel(const tt_grid* grid, const double* s, const double* xi, const double* eta, int32_t nsrc,

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
 #include <vector>
 
 #include "tt.h"
@@ -183,6 +184,7 @@ struct Plan {
     int nslots = 0;           // partial-sum slots per source per iteration
     double kappa = 1.0, tol = 1e-6;
     int max_iter = 1;
+    double* eps_hist = nullptr;
     // workspace views
     Src* src = nullptr;
     double* tab0 = nullptr;
@@ -196,6 +198,9 @@ struct Plan {
     double* coef = nullptr;   // adjoint: [nsrc][N][8]
     double* bnd_in = nullptr; // adjoint: [nsrc][NB]
     std::vector<int> plane_count;
+    // optional per-launch timing of the sweep kernels (events recorded around
+    // each tile-plane launch); filled by the launchers when non-null
+    std::vector<std::pair<hipEvent_t, hipEvent_t>>* timing = nullptr;
 };
 
 // Kernel-argument bundle of the sweep kernels.
@@ -213,6 +218,7 @@ struct SweepArgs {
     double* part;
     double* part2;
     int* counter;
+    double* eps_hist;       // optional [nsrc][max_iter]
     int nslots, nbblocks, nsrc, max_iter;
     double kappa, tol;
 };

@@ -298,8 +298,8 @@ __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int dir, int plan
 }
 
 // Value of node p once the boundary pass is done: interior and fixed nodes as
-// stored; a boundary node extrapolates linearly along its largest boundary
-// axis from the two inward nodes, which have one boundary axis fewer.
+// stored; a boundary node copies its inward neighbour along its largest
+// boundary axis, which has one boundary axis fewer (depth <= 3).
 template <int BUDGET>
 __device__ __forceinline__ double fwd_bval(const Geo& G, const Src& S, const double* f, int i, int j, int k) {
     const int p[3] = {i, j, k};
@@ -308,13 +308,9 @@ __device__ __forceinline__ double fwd_bval(const Geo& G, const Src& S, const dou
         return f[nidx(G, i, j, k)];
     } else {
         if (as < 0 || in_fixed(S, i, j, k)) return f[nidx(G, i, j, k)];
-        const int nu = (p[as] == 0) ? 1 : -1;
-        int q1[3] = {i, j, k}, q2[3] = {i, j, k};
-        q1[as] += nu;
-        q2[as] += 2 * nu;
-        const double v1 = fwd_bval<BUDGET - 1>(G, S, f, q1[0], q1[1], q1[2]);
-        const double v2 = fwd_bval<BUDGET - 1>(G, S, f, q2[0], q2[1], q2[2]);
-        return 2.0 * v1 - v2;
+        int q1[3] = {i, j, k};
+        q1[as] += (p[as] == 0) ? 1 : -1;
+        return fwd_bval<BUDGET - 1>(G, S, f, q1[0], q1[1], q1[2]);
     }
 }
 
@@ -350,6 +346,7 @@ __device__ __forceinline__ double fixed_sum(const double* p, int cnt, double* sh
 __device__ __forceinline__ void finish_iteration(const SweepArgs& a, int src, double eps) {
     const int it = a.iter[src] + 1;
     a.iter[src] = it;
+    if (a.eps_hist) a.eps_hist[(long long)src * a.max_iter + (it - 1)] = eps;
     if (eps < a.tol) {
         a.status[src] = it;
         a.active[src] = 0;
@@ -431,7 +428,7 @@ __global__ void __launch_bounds__(256) k_adj_coef(SweepArgs a, const double* __r
                 double v = 0.0;
                 if (!in_fixed(S, y[0], y[1], y[2])) {
                     if (on_bnd(G, ax, y[ax])) {
-                        v = -2.0;  // the face row of y extrapolates through x
+                        v = -1.0;  // the face row of y copies x
                     } else {
                         Col cy;
                         Loc Ly;
@@ -529,17 +526,10 @@ __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int dir, int plan
                 double acc = r[7];
                 acc -= r[0] * p0;
                 acc -= r[1] * m0;
-                // face rows that extrapolate through x from distance 2 (coefficient +1)
-                if (i == 2 && !in_fixed(S, 0, j, ka)) acc -= fld[nidx(G, 0, j, ka)];
-                if (i == G.n[0] - 3 && !in_fixed(S, G.n[0] - 1, j, ka)) acc -= fld[nidx(G, G.n[0] - 1, j, ka)];
                 acc -= r[2] * p1;
                 acc -= r[3] * m1;
-                if (j == 2 && !in_fixed(S, i, 0, ka)) acc -= fld[nidx(G, i, 0, ka)];
-                if (j == G.n[1] - 3 && !in_fixed(S, i, G.n[1] - 1, ka)) acc -= fld[nidx(G, i, G.n[1] - 1, ka)];
                 acc -= r[4] * p2;
                 acc -= r[5] * m2;
-                if (ka == 2 && !in_fixed(S, i, j, 0)) acc -= fld[nidx(G, i, j, 0)];
-                if (ka == G.n[2] - 3 && !in_fixed(S, i, j, G.n[2] - 1)) acc -= fld[nidx(G, i, j, G.n[2] - 1)];
                 nv = acc / r[6];
                 fld[x] = nv;
                 dsum += fabs(nv - cur);
@@ -562,9 +552,9 @@ __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int dir, int plan
 
 // Transposed boundary pass: lambda_b = rhs_b - sum_{rows r != b} J_{r, b} lambda_r.
 // The rows that reference a boundary node b are its interior neighbour (face
-// nodes only, coefficient bnd_in[b]) and boundary rows b' extrapolating through
-// b along an axis a' above a*(b) (coefficient -2 at distance 1, +1 at distance
-// 2); lambda(b') is evaluated in place (a* grows strictly: depth <= 3).
+// nodes only, coefficient bnd_in[b]) and boundary rows b' that copy b along an
+// axis a' above a*(b) (b' one step outward along a', coefficient -1);
+// lambda(b') is evaluated in place (a* grows strictly: depth <= 3).
 template <int BUDGET>
 __device__ double adj_bval(const Geo& G, const Src& S, const double* lam, const double* cf, const double* bin, int i,
                            int j, int k) {
@@ -573,9 +563,8 @@ __device__ double adj_bval(const Geo& G, const Src& S, const double* lam, const 
     double acc = cf[nidx(G, i, j, k) * 8 + 7];
     const int nb = (int)on_bnd(G, 0, i) + (int)on_bnd(G, 1, j) + (int)on_bnd(G, 2, k);
     if (nb == 1) {
-        const int nu = (p[as] == 0) ? 1 : -1;
         int x[3] = {i, j, k};
-        x[as] += nu;
+        x[as] += (p[as] == 0) ? 1 : -1;
         acc -= bin[bnd_encode(G, i, j, k)] * lam[nidx(G, x[0], x[1], x[2])];
     }
     if constexpr (BUDGET > 0) {
@@ -584,12 +573,11 @@ __device__ double adj_bval(const Geo& G, const Src& S, const double* lam, const 
             if (on_bnd(G, ap, id)) continue;
             for (int side = 0; side < 2; ++side) {
                 const int dist = side == 0 ? id : (G.n[ap] - 1 - id);
-                if (dist != 1 && dist != 2) continue;
+                if (dist != 1) continue;
                 int q[3] = {i, j, k};
                 q[ap] = side == 0 ? 0 : G.n[ap] - 1;
                 if (in_fixed(S, q[0], q[1], q[2])) continue;
-                const double cv = dist == 1 ? -2.0 : 1.0;
-                acc -= cv * adj_bval<BUDGET - 1>(G, S, lam, cf, bin, q[0], q[1], q[2]);
+                acc += adj_bval<BUDGET - 1>(G, S, lam, cf, bin, q[0], q[1], q[2]);
             }
         }
     }
@@ -739,6 +727,7 @@ SweepArgs make_args(const Plan& P, const double* s, const double* xi, const doub
     a.part = P.part;
     a.part2 = P.part2;
     a.counter = P.counter;
+    a.eps_hist = P.eps_hist;
     a.nslots = P.nslots;
     a.nbblocks = P.nbblocks;
     a.nsrc = P.nsrc;
@@ -773,10 +762,32 @@ void launch_fwd_init(const Plan& P, const SweepArgs& a, const double* tau_init, 
     hipLaunchKernelGGL(k_solve_init, dim3(fill_blocks(P.G.N), P.nsrc), dim3(256), 0, st, a, tau_init, 1.0, 1.0);
 }
 
+// event pair around one launch when timing is on
+struct TimedLaunch {
+    const Plan& P;
+    hipStream_t st;
+    hipEvent_t e1 = nullptr;
+    TimedLaunch(const Plan& p, hipStream_t s) : P(p), st(s) {
+        if (P.timing) {
+            hipEvent_t e0;
+            if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+                (void)hipEventRecord(e0, st);
+                P.timing->push_back({e0, e1});
+            } else {
+                e1 = nullptr;
+            }
+        }
+    }
+    ~TimedLaunch() {
+        if (P.timing && e1) (void)hipEventRecord(e1, st);
+    }
+};
+
 void launch_fwd_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
     for (int d = 0; d < 8; ++d) {
         for (int p = 0; p < P.nplanes; ++p) {
             const dim3 grid(P.plane_count[p], P.nsrc);
+            TimedLaunch tl(P, st);
             if (P.G.coord == 1)
                 hipLaunchKernelGGL(k_fwd_sweep<1>, grid, dim3(64), 0, st, a, d, p);
             else
@@ -805,6 +816,7 @@ void launch_adj_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
     for (int d = 0; d < 8; ++d) {
         for (int p = 0; p < P.nplanes; ++p) {
             const dim3 grid(P.plane_count[p], P.nsrc);
+            TimedLaunch tl(P, st);
             if (P.G.coord == 1)
                 hipLaunchKernelGGL(k_adj_sweep<1>, grid, dim3(64), 0, st, a, d, p);
             else
