@@ -43,7 +43,33 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="MiB of a plain device-to-device copy run first (counter calibration)")
     return ap.parse_args()
+
+
+def measured_traffic(kernel, updates_per_launch, default_tiles):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (bytes per node update, calibrated against a plain copy), or None
+    when the kernel source changed since the counters were taken or the tile
+    shape differs from the one measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sweeps_sph101_pmc.md")
+    src = os.path.join(ROOT, "paper_2412_00031_amd", "csrc", "tt_kernels.hip")
+    if not default_tiles or not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith(("|", "`", "#")):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    try:
+        per_update = float(vals[f"{kernel} read_bytes_per_update"]) + float(vals[f"{kernel} write_bytes_per_update"])
+    except KeyError:
+        return None
+    return per_update * updates_per_launch
 
 
 def interior_nonfixed(grid):
@@ -104,6 +130,15 @@ def main():
     from paper_2412_00031_amd import api, workloads as W
 
     dev = torch.device("cuda:0")
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 8
+        xa = torch.ones(n, dtype=torch.float64, device=dev)
+        xb = torch.empty_like(xa)
+        torch.cuda.synchronize()
+        xb.copy_(xa)
+        torch.cuda.synchronize()
+        del xa, xb
+        log(f"copy probe: {args.copy_probe} MiB read + {args.copy_probe} MiB written")
     wl = W.sph101(nsrc=args.nsrc)
     g, kappa, tol = wl["grid"], wl["kappa"], wl["tol"]
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
@@ -160,7 +195,7 @@ def main():
     ms_a, n_a = api.sweep_timing(1, reset=True)
 
     value = nsrc * args.steps / elapsed
-    nodes = interior_nonfixed(g)
+    nodes = interior_nonfixed(g) - 8
     # algorithmic bytes per node update: forward = tau read + write (16 B) plus
     # the model (24 B per node per sweep, shared by the batch); adjoint =
     # lambda read + write plus the 8 stored coefficients of the node (80 B)
@@ -176,9 +211,11 @@ def main():
     K = kern[dom]
     avg_ms = K["ms"] / max(K["launches"], 1)
     achieved = K["bytes"] / (K["ms"] * 1e-3) / 1e9 if K["ms"] > 0 else 0.0
+    traffic = measured_traffic(dom, K["updates"] / max(K["launches"], 1), args.tile_k == 0)
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None if traffic is None else round(traffic),
+        "algorithmic_bytes_per_launch": round(K["bytes"] / max(K["launches"], 1)),
         "kernel": dom, "avg_launch_ms": round(avg_ms, 5), "launches": K["launches"],
         "bytes_per_update": round(K["bytes"] / K["updates"], 3),
         "sweep_ms": {k: round(v["ms"], 2) for k, v in kern.items()},
@@ -203,7 +240,7 @@ def main():
                                f"{len(wl['rec'])} receivers, tol {tol:g}, plain start",
                    "nsrc": nsrc, "grid": list(g["n"]), "tol": tol, "kappa": kappa,
                    "mean_iters_fwd": round(float(it_f.mean()), 2), "mean_iters_adj": round(float(it_a.mean()), 2),
-                   "tile_k": args.tile_k or 32},
+                   "tile_k": args.tile_k or "default (fwd 16, adj 48)"},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

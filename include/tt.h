@@ -58,7 +58,8 @@ typedef struct tt_opts {
     double tol;        /* stop at the first iteration whose convergence measure is < tol */
     int32_t max_iter;  /* >= 1 */
     double kappa;      /* Lax-Friedrichs viscosity factor, >= max sqrt(1 + 2|xi|) */
-    int32_t tile_k;    /* k-extent of one sweep tile; 0 = library default */
+    int32_t tile_k;    /* k-extent of one sweep tile, 1..62; 0 = library default
+                          (16 for tt_forward, 48 for tt_adjoint) */
     int32_t flags;     /* bit 0 (TT_FLAG_TIME_SWEEPS): time every sweep-kernel launch with
                           HIP events on the call's stream (see tt_sweep_timing) */
     double* eps_hist;  /* optional device buffer [nsrc][max_iter] that receives the

@@ -31,7 +31,12 @@ int fail(int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(TT_EHIP, "%s: %s", #call, hipGetErrorString(e_));   \
     } while (0)
 
+// default tile k-extents (the forward update is long, so shorter tiles with
+// more parallel tiles per plane win; the adjoint step is short, so longer
+// tiles amortise the staging better); measured on the 101^3 spherical batch
 constexpr int kDefaultTileK = 32;
+constexpr int kDefaultTileKFwd = 16;
+constexpr int kDefaultTileKAdj = 48;
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -60,7 +65,8 @@ int check_opts(const tt_opts* o) {
     if (!(o->tol > 0.0)) return fail(TT_EINVAL, "opts.tol must be > 0");
     if (o->max_iter < 1) return fail(TT_EINVAL, "opts.max_iter must be >= 1");
     if (!(o->kappa > 0.0) || !std::isfinite(o->kappa)) return fail(TT_EINVAL, "opts.kappa must be > 0");
-    if (o->tile_k < 0) return fail(TT_EINVAL, "opts.tile_k must be >= 0");
+    if (o->tile_k < 0 || o->tile_k > tt::kMaxTileK)
+        return fail(TT_EINVAL, "opts.tile_k must be in [0, %d]", tt::kMaxTileK);
     return TT_OK;
 }
 
@@ -85,16 +91,18 @@ tt::Geo make_geo(const tt_grid* g, int tk) {
     G.si = (long long)G.n[1] * G.n[2];
     G.sj = G.n[2];
     G.NB = G.N - (long long)G.m[0] * G.m[1] * G.m[2];
+    G.W = G.n[1] + G.n[2] - 1;
+    G.S = (long long)G.n[0] * G.W * G.n[1];
     return G;
 }
 
 // Workspace layout (each region 256-byte aligned):
 //   Src[nsrc] | tab0[n0] | tab1[n1] | tab2[n2] | active[nsrc] | iter[nsrc] | counter |
-//   part[nsrc*nslots] | part2[nsrc*nslots] (adjoint) | coef[nsrc*N*8] (adjoint) |
-//   bnd_in[nsrc*NB] (adjoint)
+//   part[nsrc*nslots] | model[2*S*4] (forward) | part2[nsrc*nslots] (adjoint) |
+//   coef[nsrc*2*S*8] (adjoint) | bnd_in[nsrc*NB] (adjoint)
 struct Layout {
     size_t off_src, off_t0, off_t1, off_t2, off_active, off_iter, off_counter, off_part, off_part2, off_coef,
-        off_bnd, total;
+        off_bnd, off_model, total;
 };
 
 Layout layout(const tt::Geo& G, int nsrc, int nslots, int which) {
@@ -111,12 +119,16 @@ Layout layout(const tt::Geo& G, int nsrc, int nslots, int which) {
     L.off_part2 = o;
     L.off_coef = o;
     L.off_bnd = o;
+    L.off_model = o;
     if (which == 0 || which == 1) {
         L.off_part = o; o = align_up(o + sizeof(double) * (size_t)nsrc * nslots);
     }
+    if (which == 0) {
+        L.off_model = o; o = align_up(o + sizeof(double) * 4 * 2 * (size_t)G.S);
+    }
     if (which == 1) {
         L.off_part2 = o; o = align_up(o + sizeof(double) * (size_t)nsrc * nslots);
-        L.off_coef = o; o = align_up(o + sizeof(double) * 8 * (size_t)nsrc * (size_t)G.N);
+        L.off_coef = o; o = align_up(o + sizeof(double) * 8 * 2 * (size_t)nsrc * (size_t)G.S);
         L.off_bnd = o; o = align_up(o + sizeof(double) * (size_t)nsrc * (size_t)G.NB);
     }
     L.total = o;
@@ -150,12 +162,17 @@ void bind_workspace(tt::Plan& P, void* ws, const Layout& L) {
     P.part2 = reinterpret_cast<double*>(b + L.off_part2);
     P.coef = reinterpret_cast<double*>(b + L.off_coef);
     P.bnd_in = reinterpret_cast<double*>(b + L.off_bnd);
+    P.model = reinterpret_cast<double*>(b + L.off_model);
     P.T.t0 = P.tab0;
     P.T.t1 = P.tab1;
     P.T.t2 = P.tab2;
 }
 
-int tile_k_of(const tt_opts* o) { return (o && o->tile_k > 0) ? o->tile_k : kDefaultTileK; }
+int tile_k_of(const tt_opts* o, int which) {
+    int tk = (o && o->tile_k > 0) ? o->tile_k
+                                  : (which == 0 ? kDefaultTileKFwd : (which == 1 ? kDefaultTileKAdj : kDefaultTileK));
+    return tk > tt::kMaxTileK ? tt::kMaxTileK : tk;
+}
 
 // pinned host words that receive the active-source count of each iteration
 // (allocated once per thread and kept until the process ends: freeing them
@@ -257,7 +274,7 @@ int tt_sweep_timing(int32_t which, double* total_ms, int64_t* launches, int32_t 
 
 size_t tt_workspace_size(const tt_grid* grid, int32_t nsrc, const tt_opts* opts, int32_t which) {
     if (check_grid(grid) || nsrc < 1 || which < 0 || which > 3) return 0;
-    tt::Geo G = make_geo(grid, tile_k_of(opts));
+    tt::Geo G = make_geo(grid, tile_k_of(opts, which));
     tt::Plan P;
     fill_plan(P, G, nsrc);
     return layout(G, nsrc, P.nslots, which).total;
@@ -287,9 +304,10 @@ int tt_forward(const tt_grid* grid, const double* s, const double* xi, const dou
     if (nsrc == 0) return TT_OK;
     if (nsrc > 65535) return fail(TT_EINVAL, "nsrc > 65535");
     if ((rc = check_ptrs({s, xi, eta, src_pos, src_par, tau, status, ws}))) return rc;
-    tt::Geo G = make_geo(grid, tile_k_of(opts));
+    tt::Geo G = make_geo(grid, tile_k_of(opts, 0));
     tt::Plan P;
     fill_plan(P, G, nsrc);
+    if (P.max_plane_tiles > 65535) return fail(TT_EINVAL, "too many tiles per tile-plane; raise opts.tile_k");
     Layout L = layout(G, nsrc, P.nslots, 0);
     if (ws_bytes < L.total) return fail(TT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
     bind_workspace(P, ws, L);
@@ -301,7 +319,7 @@ int tt_forward(const tt_grid* grid, const double* s, const double* xi, const dou
     tt::launch_tables(P, st);
     tt::launch_src_setup(P, src_pos, src_par, st);
     tt::SweepArgs a = tt::make_args(P, s, xi, eta, tau, status);
-    tt::launch_fwd_init(P, a, tau_init, st);
+    tt::launch_fwd_init(P, a, tau_init, s, xi, eta, st);
     TT_HIP(hipGetLastError());
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     if (opts->flags & TT_FLAG_TIME_SWEEPS) P.timing = &ev;
@@ -358,9 +376,10 @@ int tt_adjoint(const tt_grid* grid, const double* s, const double* xi, const dou
     if (nsrc > 65535) return fail(TT_EINVAL, "nsrc > 65535");
     if ((rc = check_ptrs({s, xi, eta, src_pos, src_par, tau, lam, status, ws}))) return rc;
     if (nrec > 0 && (!rec_pos || !R)) return fail(TT_EINVAL, "rec_pos/R NULL with nrec > 0");
-    tt::Geo G = make_geo(grid, tile_k_of(opts));
+    tt::Geo G = make_geo(grid, tile_k_of(opts, 1));
     tt::Plan P;
     fill_plan(P, G, nsrc);
+    if (P.max_plane_tiles > 65535) return fail(TT_EINVAL, "too many tiles per tile-plane; raise opts.tile_k");
     Layout L = layout(G, nsrc, P.nslots, 1);
     if (ws_bytes < L.total) return fail(TT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
     bind_workspace(P, ws, L);

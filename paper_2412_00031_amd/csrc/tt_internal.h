@@ -21,6 +21,7 @@ constexpr int kBI = 8;        // column block of one wave: 8 x 8 (i, j) columns
 constexpr int kBJ = 8;
 constexpr int kWave = 64;
 constexpr int kBndThreads = 256;
+constexpr int kMaxTileK = 62;  // k-extent of a sweep tile; the staged column (tk + 2) fits one wave
 
 // Kernel-argument copy of the grid.
 struct Geo {
@@ -33,6 +34,8 @@ struct Geo {
     long long N;       // n0 * n1 * n2
     long long si, sj;  // strides of axes 0 and 1 (axis 2 has stride 1)
     long long NB;      // boundary nodes
+    int W;             // n1 + n2 - 1: width of the row-coalesced layouts
+    long long S;       // records per row-coalesced layout: n0 * W * n1
     double o[3], h[3], inv2h[3], invh[3];
 };
 
@@ -195,7 +198,8 @@ struct Plan {
     int* counter = nullptr;
     double* part = nullptr;
     double* part2 = nullptr;
-    double* coef = nullptr;   // adjoint: [nsrc][N][8]
+    double* coef = nullptr;   // adjoint: [nsrc][2][S][8] (row-coalesced layouts)
+    double* model = nullptr;  // forward: [2][S][4] = (s, xi, eta, 0) (row-coalesced layouts)
     double* bnd_in = nullptr; // adjoint: [nsrc][NB]
     std::vector<int> plane_count;
     // optional per-launch timing of the sweep kernels (events recorded around
@@ -210,7 +214,8 @@ struct SweepArgs {
     const double *s, *xi, *eta;
     const Src* src;
     double* field;          // tau or lambda [nsrc][N]
-    const double* coef;     // adjoint coefficients [nsrc][N][8]
+    const double* coef;     // adjoint coefficients [nsrc][2][S][8]
+    const double* model;    // forward model records [2][S][4]
     const double* bnd_in;   // adjoint face couplings [nsrc][NB]
     int* active;
     int* iter;
@@ -229,7 +234,8 @@ void launch_tables(const Plan& P, hipStream_t st);
 void launch_src_setup(const Plan& P, const double* src_pos, const double* src_par, hipStream_t st);
 void launch_source_params(const Geo& G, const double* s, const double* xi, const double* eta,
                           const double* src_pos, double* src_par, int nsrc, hipStream_t st);
-void launch_fwd_init(const Plan& P, const SweepArgs& a, const double* tau_init, hipStream_t st);
+void launch_fwd_init(const Plan& P, const SweepArgs& a, const double* tau_init, const double* s, const double* xi,
+                     const double* eta, hipStream_t st);
 void launch_fwd_iteration(const Plan& P, const SweepArgs& a, hipStream_t st);
 void launch_adj_init(const Plan& P, const SweepArgs& a, const double* tau, int nrec, const double* rec_pos,
                      const double* R, hipStream_t st);

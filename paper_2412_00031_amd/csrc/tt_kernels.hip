@@ -9,13 +9,19 @@
 //   - the interior is cut into tiles of 8 x 8 (i, j) columns x tk nodes along k
 //     (sweep-relative coordinates, ragged last tiles);
 //   - tiles with the same TI'+TJ'+TK' form a tile-plane; one launch processes
-//     one tile-plane of every active source (grid.y = source);
-//   - inside a tile one 64-lane wave owns the 8 x 8 columns; at step t lane
-//     (li, lj) updates k' = k0' + t - li - lj, i.e. the tile is walked along its
-//     own hyperplanes; the neighbours in i and j come from the adjacent lanes'
-//     registers (ds_bpermute shuffles), the neighbour in k from the lane's own
-//     previous result, and tile-face neighbours from global memory (finished by
-//     an earlier launch, or still untouched in this sweep).
+//     one tile-plane of every active source.  grid.x is the source, so
+//     consecutive workgroups are one tile of consecutive sources: workgroups
+//     are dealt to the 8 XCDs round-robin, hence every tile of a source runs
+//     on the same XCD (its field stays in that XCD's L2) and the sources that
+//     share an XCD read the same model lines;
+//   - inside a tile one 64-lane wave owns the 8 x 8 columns; the tile and its
+//     one-node halo are staged in LDS with contiguous column loads, then at
+//     step t lane (li, lj) updates k' = k0' + t - li - lj (the tile is walked
+//     along its own hyperplanes) reading and writing LDS only, and the tile is
+//     written back with contiguous column stores;
+//   - per-node records (model, adjoint coefficients) are read from
+//     row-coalesced layouts in which the 8 lanes of a tile row find their
+//     records side by side on every step.
 // Each sweep is followed by a boundary pass (one thread per boundary node), and
 // each iteration by a finalize kernel that forms the convergence measure from
 // per-tile partial sums in a fixed order (bitwise reproducible run to run).
@@ -75,6 +81,17 @@ __device__ __forceinline__ long long bnd_encode(const Geo& G, int i, int j, int 
 }
 
 __device__ __forceinline__ bool on_bnd(const Geo& G, int a, int idx) { return idx == 0 || idx == G.n[a] - 1; }
+
+// Row-coalesced record layouts.  On a sweep hyperplane the 8 lanes of one
+// tile row (fixed i, consecutive j) satisfy j + rho k = const with
+// rho = sigma_1 sigma_2, so records stored as [i][w = j + rho k][j] put those 8
+// lanes' records next to each other.  fam 0: rho = +1, fam 1: rho = -1.
+__device__ __forceinline__ int sweep_family(int dir) { return ((dir >> 1) ^ dir) & 1; }
+
+__device__ __forceinline__ long long skew_idx(const Geo& G, int fam, int i, int j, int k) {
+    const int w = fam == 0 ? j + k : j - k + (G.n[2] - 1);
+    return ((long long)i * G.W + w) * G.n[1] + j;
+}
 
 __device__ __forceinline__ int astar_of(const Geo& G, const int p[3]) {
     int as = -1;
@@ -226,74 +243,218 @@ __global__ void k_solve_init(SweepArgs a, const double* __restrict__ init, doubl
     }
 }
 
-// --------------------------------------------------------- forward sweep
+// --------------------------------------------------------- sweep tiles
+// Lane-constant context of one tile of one source in one directional sweep.
+struct TileCtx {
+    int TI, TJ, TK, lane, li, lj, s0, s1, s2, ext_i, ext_j, k0p, k1p, kp0, kbase, nsteps;
+    bool colv, fcol;
+    int i, j;
+    long long col, di, dj;
+};
+
+__device__ __forceinline__ TileCtx tile_ctx(const Geo& G, const Src& S, int dir, int plane) {
+    TileCtx c;
+    tile_decode(G, plane, blockIdx.y, c.TI, c.TJ, c.TK);
+    c.lane = threadIdx.x;
+    c.li = c.lane >> 3;
+    c.lj = c.lane & 7;
+    c.s0 = (dir & 4) ? -1 : 1;
+    c.s1 = (dir & 2) ? -1 : 1;
+    c.s2 = (dir & 1) ? -1 : 1;
+    c.ext_i = min(kBI, G.m[0] - c.TI * kBI);
+    c.ext_j = min(kBJ, G.m[1] - c.TJ * kBJ);
+    c.k0p = c.TK * G.tk;
+    c.k1p = min(c.k0p + G.tk, G.m[2]);
+    c.colv = c.li < c.ext_i && c.lj < c.ext_j;
+    const int ip = c.TI * kBI + (c.colv ? c.li : 0), jp = c.TJ * kBJ + (c.colv ? c.lj : 0);
+    c.i = c.s0 > 0 ? 1 + ip : G.n[0] - 2 - ip;
+    c.j = c.s1 > 0 ? 1 + jp : G.n[1] - 2 - jp;
+    c.col = nidx(G, c.i, c.j, 0);
+    c.di = c.s0 * G.si;
+    c.dj = c.s1 * G.sj;
+    c.fcol = (unsigned)(c.i - S.fb[0]) <= 1u && (unsigned)(c.j - S.fb[1]) <= 1u;
+    c.nsteps = (c.k1p - c.k0p) + c.ext_i - 1 + c.ext_j - 1;
+    c.kp0 = c.k0p - c.li - c.lj;               // this lane's k' at step 0
+    c.kbase = c.s2 > 0 ? 1 : G.n[2] - 2;       // absolute k = kbase + s2 * k'
+    return c;
+}
+
+// Staged tile: the (8+2) x (8+2) columns of the tile and its i/j halo, each
+// with the k'-range [k0'-1, k1'] (tk + 2 values), in LDS as [ci][cj][kk]
+// (ci = li + 1, cj = lj + 1, kk = k' - k0' + 1).  Everything a step reads from
+// the field is staged (upstream tiles are finished, downstream ones untouched),
+// so the march touches LDS only; the tile is loaded and written back with
+// contiguous column segments.
+constexpr int kTC = kBI + 2;
+
+__device__ __forceinline__ int stage_abs(const Geo& G, int a, int T, int sgn, int ci) {
+    const int p = T * kBI + ci - 1;  // sweep-relative coordinate, -1 .. ext
+    return sgn > 0 ? 1 + p : G.n[a] - 2 - p;
+}
+
+// Staging covers the tile's columns as one flat list of (column, k) elements
+// spread over all 64 lanes.  Loads are issued unconditionally from addresses
+// that are always valid (clamped), kStageBatch at a time, and only the LDS
+// writes are predicated: a load inside a divergent branch would make the
+// compiler wait for it before the branch joins, serialising the staging.
+constexpr int kStageBatch = 16;
+
+__device__ __forceinline__ void stage_tile(const Geo& G, const TileCtx& c, const double* __restrict__ fld,
+                                           double* lds, int L) {
+    const int Lk = c.k1p - c.k0p + 2;                 // staged k entries per column
+    const int nj = c.ext_j + 2, ncol = (c.ext_i + 2) * nj;
+    const int total = ncol * Lk;
+    int col = c.lane / Lk, kk = c.lane - col * Lk;    // element e = lane + 64 r
+    const int dcol = 64 / Lk, dkk = 64 - dcol * Lk;
+    for (int e0 = 0; e0 < total; e0 += 64 * kStageBatch) {
+        double v[kStageBatch];
+        int ci_[kStageBatch], cj_[kStageBatch], kk_[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int cc = min(col, ncol - 1);
+            const int ci = cc / nj, cj = cc - ci * nj;
+            ci_[u] = ci;
+            cj_[u] = cj;
+            kk_[u] = col < ncol ? kk : -1;
+            const int ka = c.kbase + c.s2 * (c.k0p - 1 + kk);
+            v[u] = fld[nidx(G, stage_abs(G, 0, c.TI, c.s0, ci), stage_abs(G, 1, c.TJ, c.s1, cj), ka)];
+            col += dcol;
+            kk += dkk;
+            if (kk >= Lk) {
+                kk -= Lk;
+                ++col;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u)
+            if (kk_[u] >= 0) lds[(ci_[u] * kTC + cj_[u]) * L + kk_[u]] = v[u];
+    }
+}
+
+__device__ __forceinline__ void unstage_tile(const Geo& G, const TileCtx& c, double* __restrict__ fld,
+                                             const double* lds, int L) {
+    const int ek = c.k1p - c.k0p;
+    const int n = c.ext_i * c.ext_j, total = n * ek;
+    int col = c.lane / ek, kk = c.lane - col * ek;    // kk = k' - k0' here (0 .. ek-1)
+    const int dcol = 64 / ek, dkk = 64 - dcol * ek;
+    for (int e0 = 0; e0 < total; e0 += 64 * kStageBatch) {
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            if (col < n) {
+                const int li = col / c.ext_j, lj = col - li * c.ext_j;
+                const int ka = c.kbase + c.s2 * (c.k0p + kk);
+                fld[nidx(G, stage_abs(G, 0, c.TI, c.s0, li + 1), stage_abs(G, 1, c.TJ, c.s1, lj + 1), ka)] =
+                    lds[((li + 1) * kTC + lj + 1) * L + kk + 1];
+            }
+            col += dcol;
+            kk += dkk;
+            if (kk >= ek) {
+                kk -= ek;
+                ++col;
+            }
+        }
+    }
+}
+
+// The per-node records a step needs (model, table) are loaded kPre steps
+// ahead into a ring slot indexed by the wave-uniform step number.
+constexpr int kPre = 3;       // forward: steps are long (the full update)
+constexpr int kPreAdj = 6;    // adjoint: short steps, so look further ahead
+
+struct FwdSlot {
+    double sx, xi, eta, c2, s2;
+};
+
+// unconditional: k' is clamped into the tile, so the address is always valid
+__device__ __forceinline__ void fwd_fetch(const SweepArgs& a, const TileCtx& c, const double* __restrict__ mdl,
+                                          int fam, int t, FwdSlot& r) {
+    const int kp = min(max(c.kp0 + t, c.k0p), c.k1p - 1);
+    const int ka = c.kbase + c.s2 * kp;
+    const double2* m = reinterpret_cast<const double2*>(mdl + skew_idx(a.G, fam, c.i, c.j, ka) * 4);
+    const double2 m0 = m[0], m1 = m[1];
+    r.sx = m0.x;
+    r.xi = m0.y;
+    r.eta = m1.x;
+    const double2 t2 = a.T.t2[ka];
+    r.c2 = t2.x;
+    r.s2 = t2.y;
+}
+
 template <int COORD>
 __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int dir, int plane) {
-    const int src = blockIdx.y;
+    extern __shared__ double lds[];
+    const int src = blockIdx.x;
     if (!a.active[src]) return;
     const Geo& G = a.G;
-    int TI, TJ, TK;
-    tile_decode(G, plane, blockIdx.x, TI, TJ, TK);
-    const int lane = threadIdx.x, li = lane >> 3, lj = lane & 7;
-    const int s0 = (dir & 4) ? -1 : 1, s1 = (dir & 2) ? -1 : 1, s2 = (dir & 1) ? -1 : 1;
-    const int ext_i = min(kBI, G.m[0] - TI * kBI), ext_j = min(kBJ, G.m[1] - TJ * kBJ);
-    const int k0p = TK * G.tk, k1p = min(k0p + G.tk, G.m[2]);
-    const bool colv = li < ext_i && lj < ext_j;
-    const int ip = TI * kBI + (colv ? li : 0), jp = TJ * kBJ + (colv ? lj : 0);
-    const int i = s0 > 0 ? 1 + ip : G.n[0] - 2 - ip;
-    const int j = s1 > 0 ? 1 + jp : G.n[1] - 2 - jp;
     const Src S = a.src[src];
-    const Col c = make_col(G, a.T, i, j);
+    const TileCtx c = tile_ctx(G, S, dir, plane);
+    const Col cl = make_col(G, a.T, c.i, c.j);
     double* __restrict__ fld = a.field + (long long)src * G.N;
-    const long long col = nidx(G, i, j, 0);
-    const long long di = s0 * G.si, dj = s1 * G.sj;
-    const bool fcol = (unsigned)(i - S.fb[0]) <= 1u && (unsigned)(j - S.fb[1]) <= 1u;
-    const int nsteps = (k1p - k0p) + ext_i - 1 + ext_j - 1;
-    const int kp0 = k0p - li - lj;               // this lane's k' at step 0
-    const int kbase = s2 > 0 ? 1 : G.n[2] - 2;   // absolute k = kbase + s2 * k'
+    const int fam = sweep_family(dir);
+    const double* __restrict__ mdl = a.model + (long long)fam * G.S * 4;
+    const int L = G.tk + 2;
 
-    double cur = 0.0, ahead = 0.0, prev = 0.0, eps = 0.0;
-    if (colv && kp0 >= k0p && kp0 < k1p) cur = fld[col + kbase + s2 * kp0];
-    if (colv && kp0 + 1 >= k0p && kp0 + 1 <= k1p) ahead = fld[col + kbase + s2 * (kp0 + 1)];
+    FwdSlot ring[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) fwd_fetch(a, c, mdl, fam, u, ring[u]);
+    stage_tile(G, c, fld, lds, L);
+    __syncthreads();
 
-    for (int t = 0; t < nsteps; ++t) {
-        const int kp = kp0 + t;
-        const bool valid = colv && kp >= k0p && kp < k1p;
-        // new values upstream in i/j were produced by the neighbour lanes one
-        // step ago; old values downstream are the neighbour lanes' look-ahead
-        double up_i = __shfl(prev, lane - 8, 64);
-        double up_j = __shfl(prev, lane - 1, 64);
-        double dn_i = __shfl(ahead, lane + 8, 64);
-        double dn_j = __shfl(ahead, lane + 1, 64);
-        if (valid) {
-            const int ka = kbase + s2 * kp;
-            const long long x = col + ka;
-            if (li == 0) up_i = fld[x - di];
-            if (lj == 0) up_j = fld[x - dj];
-            if (li == ext_i - 1) dn_i = fld[x + di];
-            if (lj == ext_j - 1) dn_j = fld[x + dj];
-            const double up_k = (kp > k0p) ? prev : fld[x - s2];
-            double nv = cur;
-            if (!(fcol && (unsigned)(ka - S.fb[2]) <= 1u)) {
-                const double m0 = s0 > 0 ? up_i : dn_i, p0 = s0 > 0 ? dn_i : up_i;
-                const double m1 = s1 > 0 ? up_j : dn_j, p1 = s1 > 0 ? dn_j : up_j;
-                const double m2 = s2 > 0 ? up_k : ahead, p2 = s2 > 0 ? ahead : up_k;
-                const double2 t2 = a.T.t2[ka];
-                nv = lf_update<COORD>(G, S, c, t2.x, t2.y, a.kappa, a.s[x], a.xi[x], a.eta[x], cur, m0, p0, m1,
-                                      p1, m2, p2);
-                fld[x] = nv;
-                eps += fabs(nv - cur);
+    const int own = ((c.li + 1) * kTC + c.lj + 1) * L;
+    const int oim = own - kTC * L, oip = own + kTC * L;  // column upstream / downstream in sweep i
+    double eps = 0.0;
+    // the step count is padded to a multiple of kPre: no branch encloses a load
+    for (int t0 = 0; t0 < c.nsteps; t0 += kPre) {
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const int t = t0 + u;
+            {
+                FwdSlot& r = ring[u];
+                const int kp = c.kp0 + t;
+                if (c.colv && kp >= c.k0p && kp < c.k1p) {
+                    const int kk = kp - c.k0p + 1;
+                    const int ka = c.kbase + c.s2 * kp;
+                    if (!(c.fcol && (unsigned)(ka - S.fb[2]) <= 1u)) {
+                        // sweep-relative neighbours: "up" = already updated this sweep
+                        const double cur = lds[own + kk];
+                        const double up_i = lds[oim + kk], dn_i = lds[oip + kk];
+                        const double up_j = lds[own - L + kk], dn_j = lds[own + L + kk];
+                        const double up_k = lds[own + kk - 1], dn_k = lds[own + kk + 1];
+                        const double m0 = c.s0 > 0 ? up_i : dn_i, p0 = c.s0 > 0 ? dn_i : up_i;
+                        const double m1 = c.s1 > 0 ? up_j : dn_j, p1 = c.s1 > 0 ? dn_j : up_j;
+                        const double m2 = c.s2 > 0 ? up_k : dn_k, p2 = c.s2 > 0 ? dn_k : up_k;
+                        const double nv = lf_update<COORD>(G, S, cl, r.c2, r.s2, a.kappa, r.sx, r.xi, r.eta, cur, m0,
+                                                           p0, m1, p1, m2, p2);
+                        lds[own + kk] = nv;
+                        eps += fabs(nv - cur);
+                    }
+                }
+                fwd_fetch(a, c, mdl, fam, t + kPre, r);
             }
-            prev = nv;
         }
-        cur = ahead;
-        const int kn = kp + 2;
-        ahead = (colv && kn >= k0p && kn <= k1p) ? fld[col + kbase + s2 * kn] : 0.0;
     }
+    __syncthreads();
+    unstage_tile(G, c, fld, lds, L);
     eps = wave_sum(eps);
-    if (lane == 0) {
-        const int tile_id = (TI * G.nt[1] + TJ) * G.nt[2] + TK;
+    if (c.lane == 0) {
+        const int tile_id = (c.TI * G.nt[1] + c.TJ) * G.nt[2] + c.TK;
         a.part[(long long)src * a.nslots + dir * G.ntiles + tile_id] = eps;
+    }
+}
+
+// model records (s, xi, eta, 0) in both row-coalesced layouts
+__global__ void k_model_records(Geo G, const double* __restrict__ s, const double* __restrict__ xi,
+                                const double* __restrict__ eta, double* __restrict__ out) {
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= G.N) return;
+    const int k = (int)(x % G.n[2]);
+    const long long q = x / G.n[2];
+    const int j = (int)(q % G.n[1]), i = (int)(q / G.n[1]);
+    const double2 v0 = make_double2(s[x], xi[x]), v1 = make_double2(eta[x], 0.0);
+    for (int f = 0; f < 2; ++f) {
+        double2* o = reinterpret_cast<double2*>(out + ((long long)f * G.S + skew_idx(G, f, i, j, k)) * 4);
+        o[0] = v0;
+        o[1] = v1;
     }
 }
 
@@ -393,8 +554,9 @@ __device__ __forceinline__ double row_off(const Geo& G, const Col& c, const Loc&
     return dirn > 0 ? alpha - beta : -alpha - beta;
 }
 
-// Coefficients of the transposed system at every node of every source:
-// coef[x] = {in+_0, in-_0, in+_1, in-_1, in+_2, in-_2, J_xx, rhs} with
+// Coefficients of the transposed system at every node of every source, stored
+// in both row-coalesced layouts: record {in+_0, in-_0, in+_1, in-_1, in+_2,
+// in-_2, J_xx, rhs} with
 // in+-_a = J_{x +- e_a, x}, the coefficient of lambda(x +- e_a) in the column
 // equation of x (zero unless x is interior and not fixed); bnd_in[b] = J_{x, b}
 // for each face node b and its interior neighbour x (zero when x is fixed).
@@ -407,7 +569,6 @@ __global__ void __launch_bounds__(256) k_adj_coef(SweepArgs a, const double* __r
     if (x >= G.N) return;
     const Src S = a.src[src];
     const double* tau = tau_all + (long long)src * G.N;
-    double* cf = coef_all + ((long long)src * G.N + x) * 8;
     const int k = (int)(x % G.n[2]);
     const long long q = x / G.n[2];
     const int j = (int)(q % G.n[1]), i = (int)(q / G.n[1]);
@@ -443,7 +604,11 @@ __global__ void __launch_bounds__(256) k_adj_coef(SweepArgs a, const double* __r
             }
         }
     }
-    for (int q2 = 0; q2 < 8; ++q2) cf[q2] = out[q2];
+    for (int f = 0; f < 2; ++f) {
+        double2* cf = reinterpret_cast<double2*>(coef_all + (((long long)src * 2 + f) * G.S + skew_idx(G, f, i, j, k)) * 8);
+#pragma unroll
+        for (int q2 = 0; q2 < 4; ++q2) cf[q2] = make_double2(out[2 * q2], out[2 * q2 + 1]);
+    }
 }
 
 // d chi / d tau = sum_m R_m w_c T0(c), added in receiver order (one thread per
@@ -455,7 +620,7 @@ __global__ void k_adj_rhs(SweepArgs a, double* __restrict__ coef_all, int nrec, 
     if (src >= a.nsrc) return;
     const Geo& G = a.G;
     const Src S = a.src[src];
-    double* cf = coef_all + (long long)src * G.N * 8;
+    double* cf = coef_all + (long long)src * 2 * G.S * 8;
     for (int m = 0; m < nrec; ++m) {
         const Tri t = tri_of(G, rec[3 * m], rec[3 * m + 1], rec[3 * m + 2]);
         const double r = R[(long long)src * nrec + m];
@@ -467,84 +632,95 @@ __global__ void k_adj_rhs(SweepArgs a, double* __restrict__ coef_all, int nrec, 
                     const double2 t2 = a.T.t2[k];
                     double T0, tt[3];
                     factor<COORD>(S, c, t2.x, t2.y, T0, tt);
-                    cf[nidx(G, i, j, k) * 8 + 7] += r * tri_w(t, c0, c1, c2) * T0;
+                    const double v = r * tri_w(t, c0, c1, c2) * T0;
+                    cf[skew_idx(G, 0, i, j, k) * 8 + 7] += v;
+                    cf[(G.S + skew_idx(G, 1, i, j, k)) * 8 + 7] += v;
                 }
+    }
+}
+
+struct AdjSlot {
+    double r[8];  // coefficient record of the node at k'
+};
+
+__device__ __forceinline__ void adj_fetch(const Geo& G, const TileCtx& c, const double* __restrict__ cf, int fam,
+                                          int t, AdjSlot& r) {
+    const int kp = min(max(c.kp0 + t, c.k0p), c.k1p - 1);
+    const int ka = c.kbase + c.s2 * kp;
+    const double2* rc = reinterpret_cast<const double2*>(cf + skew_idx(G, fam, c.i, c.j, ka) * 8);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double2 v = rc[q];
+        r.r[2 * q] = v.x;
+        r.r[2 * q + 1] = v.y;
     }
 }
 
 template <int COORD>
 __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int dir, int plane) {
-    const int src = blockIdx.y;
+    extern __shared__ double lds[];
+    const int src = blockIdx.x;
     if (!a.active[src]) return;
     const Geo& G = a.G;
-    int TI, TJ, TK;
-    tile_decode(G, plane, blockIdx.x, TI, TJ, TK);
-    const int lane = threadIdx.x, li = lane >> 3, lj = lane & 7;
-    const int s0 = (dir & 4) ? -1 : 1, s1 = (dir & 2) ? -1 : 1, s2 = (dir & 1) ? -1 : 1;
-    const int ext_i = min(kBI, G.m[0] - TI * kBI), ext_j = min(kBJ, G.m[1] - TJ * kBJ);
-    const int k0p = TK * G.tk, k1p = min(k0p + G.tk, G.m[2]);
-    const bool colv = li < ext_i && lj < ext_j;
-    const int ip = TI * kBI + (colv ? li : 0), jp = TJ * kBJ + (colv ? lj : 0);
-    const int i = s0 > 0 ? 1 + ip : G.n[0] - 2 - ip;
-    const int j = s1 > 0 ? 1 + jp : G.n[1] - 2 - jp;
     const Src S = a.src[src];
+    const TileCtx c = tile_ctx(G, S, dir, plane);
     double* __restrict__ fld = a.field + (long long)src * G.N;
-    const double* __restrict__ cf = a.coef + (long long)src * G.N * 8;
-    const long long col = nidx(G, i, j, 0);
-    const long long di = s0 * G.si, dj = s1 * G.sj;
-    const bool fcol = (unsigned)(i - S.fb[0]) <= 1u && (unsigned)(j - S.fb[1]) <= 1u;
-    const int nsteps = (k1p - k0p) + ext_i - 1 + ext_j - 1;
-    const int kp0 = k0p - li - lj;
-    const int kbase = s2 > 0 ? 1 : G.n[2] - 2;
+    const int fam = sweep_family(dir);
+    const double* __restrict__ cf = a.coef + ((long long)src * 2 + fam) * G.S * 8;
     const bool last = (dir == 7);
+    const int L = G.tk + 2;
 
-    double cur = 0.0, ahead = 0.0, prev = 0.0, dsum = 0.0, asum = 0.0;
-    if (colv && kp0 >= k0p && kp0 < k1p) cur = fld[col + kbase + s2 * kp0];
-    if (colv && kp0 + 1 >= k0p && kp0 + 1 <= k1p) ahead = fld[col + kbase + s2 * (kp0 + 1)];
+    AdjSlot ring[kPreAdj];
+#pragma unroll
+    for (int u = 0; u < kPreAdj; ++u) adj_fetch(G, c, cf, fam, u, ring[u]);
+    stage_tile(G, c, fld, lds, L);
+    __syncthreads();
 
-    for (int t = 0; t < nsteps; ++t) {
-        const int kp = kp0 + t;
-        const bool valid = colv && kp >= k0p && kp < k1p;
-        double up_i = __shfl(prev, lane - 8, 64);
-        double up_j = __shfl(prev, lane - 1, 64);
-        double dn_i = __shfl(ahead, lane + 8, 64);
-        double dn_j = __shfl(ahead, lane + 1, 64);
-        if (valid) {
-            const int ka = kbase + s2 * kp;
-            const long long x = col + ka;
-            if (li == 0) up_i = fld[x - di];
-            if (lj == 0) up_j = fld[x - dj];
-            if (li == ext_i - 1) dn_i = fld[x + di];
-            if (lj == ext_j - 1) dn_j = fld[x + dj];
-            const double up_k = (kp > k0p) ? prev : fld[x - s2];
-            double nv = cur;
-            if (!(fcol && (unsigned)(ka - S.fb[2]) <= 1u)) {
-                const double m0 = s0 > 0 ? up_i : dn_i, p0 = s0 > 0 ? dn_i : up_i;
-                const double m1 = s1 > 0 ? up_j : dn_j, p1 = s1 > 0 ? dn_j : up_j;
-                const double m2 = s2 > 0 ? up_k : ahead, p2 = s2 > 0 ? ahead : up_k;
-                const double* r = cf + x * 8;
-                double acc = r[7];
-                acc -= r[0] * p0;
-                acc -= r[1] * m0;
-                acc -= r[2] * p1;
-                acc -= r[3] * m1;
-                acc -= r[4] * p2;
-                acc -= r[5] * m2;
-                nv = acc / r[6];
-                fld[x] = nv;
-                dsum += fabs(nv - cur);
-                if (last) asum += fabs(nv);
+    const int own = ((c.li + 1) * kTC + c.lj + 1) * L;
+    const int oim = own - kTC * L, oip = own + kTC * L;
+    double dsum = 0.0, asum = 0.0;
+    // the step count is padded to a multiple of kPreAdj: no branch encloses a load
+    for (int t0 = 0; t0 < c.nsteps; t0 += kPreAdj) {
+#pragma unroll
+        for (int u = 0; u < kPreAdj; ++u) {
+            const int t = t0 + u;
+            {
+                AdjSlot& r = ring[u];
+                const int kp = c.kp0 + t;
+                if (c.colv && kp >= c.k0p && kp < c.k1p) {
+                    const int kk = kp - c.k0p + 1;
+                    const int ka = c.kbase + c.s2 * kp;
+                    if (!(c.fcol && (unsigned)(ka - S.fb[2]) <= 1u)) {
+                        const double cur = lds[own + kk];
+                        const double up_i = lds[oim + kk], dn_i = lds[oip + kk];
+                        const double up_j = lds[own - L + kk], dn_j = lds[own + L + kk];
+                        const double up_k = lds[own + kk - 1], dn_k = lds[own + kk + 1];
+                        const double m0 = c.s0 > 0 ? up_i : dn_i, p0 = c.s0 > 0 ? dn_i : up_i;
+                        const double m1 = c.s1 > 0 ? up_j : dn_j, p1 = c.s1 > 0 ? dn_j : up_j;
+                        const double m2 = c.s2 > 0 ? up_k : dn_k, p2 = c.s2 > 0 ? dn_k : up_k;
+                        double acc = r.r[7];
+                        acc -= r.r[0] * p0;
+                        acc -= r.r[1] * m0;
+                        acc -= r.r[2] * p1;
+                        acc -= r.r[3] * m1;
+                        acc -= r.r[4] * p2;
+                        acc -= r.r[5] * m2;
+                        const double nv = acc / r.r[6];
+                        lds[own + kk] = nv;
+                        dsum += fabs(nv - cur);
+                        if (last) asum += fabs(nv);
+                    }
+                }
+                adj_fetch(G, c, cf, fam, t + kPreAdj, r);
             }
-            prev = nv;
         }
-        cur = ahead;
-        const int kn = kp + 2;
-        ahead = (colv && kn >= k0p && kn <= k1p) ? fld[col + kbase + s2 * kn] : 0.0;
     }
+    __syncthreads();
+    unstage_tile(G, c, fld, lds, L);
     dsum = wave_sum(dsum);
     asum = wave_sum(asum);
-    if (lane == 0) {
-        const int tile_id = (TI * G.nt[1] + TJ) * G.nt[2] + TK;
+    if (c.lane == 0) {
+        const int tile_id = (c.TI * G.nt[1] + c.TJ) * G.nt[2] + c.TK;
         a.part[(long long)src * a.nslots + dir * G.ntiles + tile_id] = dsum;
         if (last) a.part2[(long long)src * a.nslots + tile_id] = asum;
     }
@@ -560,7 +736,7 @@ __device__ double adj_bval(const Geo& G, const Src& S, const double* lam, const 
                            int j, int k) {
     const int p[3] = {i, j, k};
     const int as = astar_of(G, p);
-    double acc = cf[nidx(G, i, j, k) * 8 + 7];
+    double acc = cf[skew_idx(G, 0, i, j, k) * 8 + 7];
     const int nb = (int)on_bnd(G, 0, i) + (int)on_bnd(G, 1, j) + (int)on_bnd(G, 2, k);
     if (nb == 1) {
         int x[3] = {i, j, k};
@@ -591,7 +767,7 @@ __global__ void __launch_bounds__(kBndThreads) k_adj_bnd(SweepArgs a, int dir) {
     const Geo& G = a.G;
     const Src S = a.src[src];
     double* lam = a.field + (long long)src * G.N;
-    const double* cf = a.coef + (long long)src * G.N * 8;
+    const double* cf = a.coef + (long long)src * 2 * G.S * 8;
     const double* bin = a.bnd_in + (long long)src * G.NB;
     const long long b = (long long)blockIdx.x * kBndThreads + threadIdx.x;
     double d = 0.0, av = 0.0;
@@ -720,6 +896,7 @@ SweepArgs make_args(const Plan& P, const double* s, const double* xi, const doub
     a.src = P.src;
     a.field = field;
     a.coef = P.coef;
+    a.model = P.model;
     a.bnd_in = P.bnd_in;
     a.active = P.active;
     a.iter = P.iter;
@@ -758,9 +935,13 @@ static unsigned fill_blocks(long long n) {
     return nb > 2048 ? 2048 : (nb == 0 ? 1 : nb);
 }
 
-void launch_fwd_init(const Plan& P, const SweepArgs& a, const double* tau_init, hipStream_t st) {
+void launch_fwd_init(const Plan& P, const SweepArgs& a, const double* tau_init, const double* s, const double* xi,
+                     const double* eta, hipStream_t st) {
+    hipLaunchKernelGGL(k_model_records, dim3(blocks_for(P.G.N, 256)), dim3(256), 0, st, P.G, s, xi, eta, P.model);
     hipLaunchKernelGGL(k_solve_init, dim3(fill_blocks(P.G.N), P.nsrc), dim3(256), 0, st, a, tau_init, 1.0, 1.0);
 }
+
+static size_t tile_lds_bytes(const Geo& G) { return sizeof(double) * kTC * kTC * (size_t)(G.tk + 2); }
 
 // event pair around one launch when timing is on
 struct TimedLaunch {
@@ -786,12 +967,12 @@ struct TimedLaunch {
 void launch_fwd_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
     for (int d = 0; d < 8; ++d) {
         for (int p = 0; p < P.nplanes; ++p) {
-            const dim3 grid(P.plane_count[p], P.nsrc);
+            const dim3 grid(P.nsrc, P.plane_count[p]);
             TimedLaunch tl(P, st);
             if (P.G.coord == 1)
-                hipLaunchKernelGGL(k_fwd_sweep<1>, grid, dim3(64), 0, st, a, d, p);
+                hipLaunchKernelGGL(k_fwd_sweep<1>, grid, dim3(64), tile_lds_bytes(P.G), st, a, d, p);
             else
-                hipLaunchKernelGGL(k_fwd_sweep<0>, grid, dim3(64), 0, st, a, d, p);
+                hipLaunchKernelGGL(k_fwd_sweep<0>, grid, dim3(64), tile_lds_bytes(P.G), st, a, d, p);
         }
         hipLaunchKernelGGL(k_fwd_bnd, dim3(P.nbblocks, P.nsrc), dim3(kBndThreads), 0, st, a, d);
     }
@@ -815,12 +996,12 @@ void launch_adj_init(const Plan& P, const SweepArgs& a, const double* tau, int n
 void launch_adj_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
     for (int d = 0; d < 8; ++d) {
         for (int p = 0; p < P.nplanes; ++p) {
-            const dim3 grid(P.plane_count[p], P.nsrc);
+            const dim3 grid(P.nsrc, P.plane_count[p]);
             TimedLaunch tl(P, st);
             if (P.G.coord == 1)
-                hipLaunchKernelGGL(k_adj_sweep<1>, grid, dim3(64), 0, st, a, d, p);
+                hipLaunchKernelGGL(k_adj_sweep<1>, grid, dim3(64), tile_lds_bytes(P.G), st, a, d, p);
             else
-                hipLaunchKernelGGL(k_adj_sweep<0>, grid, dim3(64), 0, st, a, d, p);
+                hipLaunchKernelGGL(k_adj_sweep<0>, grid, dim3(64), tile_lds_bytes(P.G), st, a, d, p);
         }
         hipLaunchKernelGGL(k_adj_bnd, dim3(P.nbblocks, P.nsrc), dim3(kBndThreads), 0, st, a, d);
     }

@@ -114,11 +114,30 @@ def test_small_spherical_several_tiles(torch_cuda):
 def test_tile_shapes_bitwise(torch_cuda):
     """Any tile shape visits the same dependencies: results are bit-identical."""
     wl = W.small_spherical(n=(21, 19, 23), nsrc=2, seed=11)
-    ref = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=1000)
-    for tk in (1, 3, 5, 8, 32):
+    ref = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=62)
+    for tk in (1, 3, 5, 8, 21, 32):
         gp = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=tk)
         for key in ("tau", "lam", "grad", "it_f", "it_a", "T"):
             assert np.array_equal(gp[key], ref[key]), (tk, key)
+
+
+def test_invalid_arguments_rejected(torch_cuda):
+    from paper_2412_00031_amd import api, _lib
+    wl = W.small_spherical(n=(6, 6, 6), nsrc=1)
+    g = wl["grid"]
+    s, xi, eta, src = (_dev(torch_cuda, wl[k]) for k in ("s", "xi", "eta", "src"))
+    par = api.source_params(g, s, xi, eta, src)
+    for kw in (dict(tile_k=63), dict(tile_k=-1)):
+        with pytest.raises(_lib.TTError):
+            api.forward(g, s, xi, eta, src, par, 1e-6, 10, 1.05, ws=torch_cuda.empty(1 << 20, dtype=torch_cuda.uint8,
+                                                                                     device="cuda"), **kw)
+    with pytest.raises(_lib.TTError):
+        api.forward(g, s, xi, eta, src, par, 0.0, 10, 1.05)
+    with pytest.raises(_lib.TTError):
+        api.forward(g, s, xi, eta, src, par, 1e-6, 0, 1.05)
+    bad = dict(g, n=(3, 6, 6))
+    with pytest.raises((_lib.TTError, ValueError)):
+        api.forward(bad, s[:108], xi[:108], eta[:108], src, par, 1e-6, 10, 1.05)
 
 
 def test_misfit_with_pairs(torch_cuda):
