@@ -12,7 +12,8 @@ observed times come from a forward solve in an independent random model
 kernel per source).
 
 Prints one JSON line (rank 0).  Extra objects: "roofline" (the dominant sweep
-kernel, timed live with HIP events around each of its launches) and
+kernel, timed live with HIP event pairs around the back-to-back launches of
+each directional sweep, on the library's stream) and
 "cpu_baseline" (the CPU oracle on a bounded sample of the same workload).
 """
 import argparse
@@ -39,7 +40,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nsrc", type=int, default=128)
-    ap.add_argument("--tile-k", type=int, default=0)
+    ap.add_argument("--tile-k", type=int, default=0, help="tile depth for both solves (0: autotune)")
+    ap.add_argument("--no-autotune", action="store_true", help="use the library's default tile depths")
+    ap.add_argument("--graph", action="store_true", help="replay each iteration from a captured hipGraph")
+    ap.add_argument("--no-sweep-timing", action="store_true",
+                    help="skip the per-launch sweep events (roofline then unmeasured)")
     ap.add_argument("--max-iter", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
@@ -154,20 +159,29 @@ def main():
     torch.cuda.synchronize()
     log("observations ready")
 
-    ws_f = api.workspace(g, nsrc, 0, args.tile_k, dev)
-    ws_a = api.workspace(g, nsrc, 1, args.tile_k, dev)
+    tk_f = tk_a = args.tile_k
+    tuned = None
+    if args.tile_k == 0 and not args.no_autotune:
+        from paper_2412_00031_amd import autotune
+        par0 = api.source_params(g, s, xi, eta, src)
+        R0 = torch.zeros((nsrc, len(wl["rec"])), dtype=torch.float64, device=dev)
+        tuned = autotune.tune(g, s, xi, eta, src, par0, kappa, rec, R0, log=log)
+        tk_f, tk_a = tuned["fwd"], tuned["adj"]
+        log(f"tile depths: forward {tk_f}, adjoint {tk_a}")
+    ws_f = api.workspace(g, nsrc, 0, tk_f, dev)
+    ws_a = api.workspace(g, nsrc, 1, tk_a, dev)
     tau = torch.empty((nsrc,) + tuple(g["n"]), dtype=torch.float64, device=dev)
     lam = torch.empty_like(tau)
     grad = torch.empty((3,) + tuple(g["n"]), dtype=torch.float64, device=dev)
 
     def step(timed):
         par = api.source_params(g, s, xi, eta, src)
-        _, st_f = api.forward(g, s, xi, eta, src, par, tol, args.max_iter, kappa, tile_k=args.tile_k, ws=ws_f,
-                              out=tau, time_sweeps=timed)
+        _, st_f = api.forward(g, s, xi, eta, src, par, tol, args.max_iter, kappa, tile_k=tk_f, ws=ws_f,
+                              out=tau, time_sweeps=timed, graph=args.graph)
         T = api.sample(g, src, par, tau, rec)
         chi, R = api.misfit(T, T_obs)
-        _, st_a = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, tol, args.max_iter, kappa, tile_k=args.tile_k,
-                              ws=ws_a, out=lam, time_sweeps=timed)
+        _, st_a = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, tol, args.max_iter, kappa, tile_k=tk_a,
+                              ws=ws_a, out=lam, time_sweeps=timed, graph=args.graph)
         api.kernel(g, s, xi, eta, src, par, tau, lam, grad=grad.zero_())
         return st_f, st_a, chi
 
@@ -181,7 +195,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        st_f, st_a, chi = step(True)
+        st_f, st_a, chi = step(not args.no_sweep_timing)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     log(f"timed {args.steps} steps: {elapsed:.2f} s")
@@ -211,7 +225,8 @@ def main():
     K = kern[dom]
     avg_ms = K["ms"] / max(K["launches"], 1)
     achieved = K["bytes"] / (K["ms"] * 1e-3) / 1e9 if K["ms"] > 0 else 0.0
-    traffic = measured_traffic(dom, K["updates"] / max(K["launches"], 1), args.tile_k == 0)
+    traffic = measured_traffic(dom, K["updates"] / max(K["launches"], 1),
+                               (tk_f, tk_a) == (16, 48) or (args.tile_k == 0 and args.no_autotune))
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None if traffic is None else round(traffic),
@@ -240,7 +255,9 @@ def main():
                                f"{len(wl['rec'])} receivers, tol {tol:g}, plain start",
                    "nsrc": nsrc, "grid": list(g["n"]), "tol": tol, "kappa": kappa,
                    "mean_iters_fwd": round(float(it_f.mean()), 2), "mean_iters_adj": round(float(it_a.mean()), 2),
-                   "tile_k": args.tile_k or "default (fwd 16, adj 48)"},
+                   "tile_k": {"fwd": tk_f or 16, "adj": tk_a or 48,
+                              "chosen_by": "autotune" if tuned else ("fixed" if args.tile_k else "default")},
+                   "graph": bool(args.graph)},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -60,8 +60,9 @@ typedef struct tt_opts {
     double kappa;      /* Lax-Friedrichs viscosity factor, >= max sqrt(1 + 2|xi|) */
     int32_t tile_k;    /* k-extent of one sweep tile, 1..62; 0 = library default
                           (16 for tt_forward, 48 for tt_adjoint) */
-    int32_t flags;     /* bit 0 (TT_FLAG_TIME_SWEEPS): time every sweep-kernel launch with
-                          HIP events on the call's stream (see tt_sweep_timing) */
+    int32_t flags;     /* bit 0 (TT_FLAG_TIME_SWEEPS): time the sweep kernels with a HIP
+                          event pair around the tile-plane launches of every
+                          directional sweep on the call's stream (tt_sweep_timing) */
     double* eps_hist;  /* optional device buffer [nsrc][max_iter] that receives the
                           convergence measure of every iteration of every source
                           (entries past a source's last iteration are left as
@@ -69,6 +70,10 @@ typedef struct tt_opts {
 } tt_opts;
 
 #define TT_FLAG_TIME_SWEEPS 1
+/* bit 1: capture one iteration (every sweep, boundary and convergence launch)
+ * as a hipGraph once per call and replay it each iteration.  Ignored when
+ * TT_FLAG_TIME_SWEEPS is set (per-launch events are recorded eagerly). */
+#define TT_FLAG_GRAPH 2
 
 /* Bytes of device workspace needed by tt_forward (which = 0), tt_adjoint
  * (which = 1), tt_sample (which = 2) or tt_kernel (which = 3) for this grid,
@@ -144,9 +149,10 @@ int tt_kernel(const tt_grid* grid, const double* s, const double* xi, const doub
 
 /* Sweep-kernel timing gathered by tt_forward (which = 0) and tt_adjoint
  * (which = 1) calls of the calling thread that had TT_FLAG_TIME_SWEEPS set:
- * the summed device time of every timed sweep-kernel launch (ms, from a HIP
- * event pair around each launch) and the number of such launches.  reset != 0
- * clears the totals after reading.  Pointers may be NULL. */
+ * the summed device time of the timed sweeps (ms, HIP event pairs around the
+ * back-to-back tile-plane launches of each directional sweep) and the number
+ * of sweep-kernel launches they contain.  reset != 0 clears the totals after
+ * reading.  Pointers may be NULL. */
 int tt_sweep_timing(int32_t which, double* total_ms, int64_t* launches, int32_t reset);
 
 /* Message for the last nonzero return of the calling thread ("" if none). */

@@ -24,6 +24,7 @@ EXPORTS = ["tt_workspace_size", "tt_source_params", "tt_forward", "tt_sample", "
            "tt_kernel", "tt_sweep_timing", "tt_last_error"]
 
 TT_FLAG_TIME_SWEEPS = 1
+TT_FLAG_GRAPH = 2
 
 _lib = None
 

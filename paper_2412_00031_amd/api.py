@@ -26,14 +26,14 @@ def _grid(grid):
     return g
 
 
-def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None):
+def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None, graph=False):
     o = _lib.TTOpts()
     o.eps_hist = _dev(eps_hist, "eps_hist").value if eps_hist is not None else None
     o.tol = float(tol)
     o.max_iter = int(max_iter)
     o.kappa = float(kappa)
     o.tile_k = int(tile_k)
-    o.flags = _lib.TT_FLAG_TIME_SWEEPS if time_sweeps else 0
+    o.flags = (_lib.TT_FLAG_TIME_SWEEPS if time_sweeps else 0) | (_lib.TT_FLAG_GRAPH if graph else 0)
     return o
 
 
@@ -99,7 +99,7 @@ def source_params(grid, s, xi, eta, src_pos):
 
 
 def forward(grid, s, xi, eta, src_pos, src_par, tol, max_iter, kappa, tau_init=None, tile_k=0, ws=None,
-            out=None, time_sweeps=False, eps_hist=None):
+            out=None, time_sweeps=False, eps_hist=None, graph=False):
     """Batched forward solve.  Returns (tau [nsrc, *n], status int32 [nsrc]).
     eps_hist: optional float64 device tensor [nsrc, max_iter] receiving the
     convergence measure of every iteration."""
@@ -114,7 +114,7 @@ def forward(grid, s, xi, eta, src_pos, src_par, tol, max_iter, kappa, tau_init=N
     g = _grid(grid)
     if eps_hist is not None and eps_hist.numel() != nsrc * int(max_iter):
         raise ValueError("eps_hist must have nsrc * max_iter elements")
-    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist)
+    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph)
     ti = _dev(tau_init, "tau_init", numel=nsrc * N) if tau_init is not None else _null()
     _lib.check(lib.tt_forward(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
                               _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
@@ -158,7 +158,7 @@ def misfit(T_rec, T_obs, w=None, pairs=None, wpair=None, alpha=1.0, beta=1.0):
 
 
 def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, kappa, tile_k=0, ws=None,
-            out=None, time_sweeps=False, eps_hist=None):
+            out=None, time_sweeps=False, eps_hist=None, graph=False):
     """Batched adjoint solve.  Returns (lambda [nsrc, *n], status int32 [nsrc]);
     eps_hist as for forward."""
     lib = _lib.load()
@@ -172,7 +172,7 @@ def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, 
     g = _grid(grid)
     if eps_hist is not None and eps_hist.numel() != nsrc * int(max_iter):
         raise ValueError("eps_hist must have nsrc * max_iter elements")
-    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist)
+    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph)
     _lib.check(lib.tt_adjoint(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
                               _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
                               _dev(src_par, "src_par", numel=3 * nsrc), _dev(tau, "tau", numel=nsrc * N), nrec,

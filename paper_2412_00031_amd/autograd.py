@@ -1,0 +1,53 @@
+"""Differentiable traveltime misfit: chi(s, xi, eta) as a torch.autograd.Function.
+
+Forward: batched fast-sweeping solve (Sec. 2.1 step 1), receiver traveltimes
+and the misfit chi = alpha chi_t + beta chi_cs (Eqs. (1)-(3)).  Backward: the
+adjoint solve at the adjoint sources R = d chi / d T (Eq. (5), (A2)-(A3)) and
+the kernels (Eqs. (6)-(8)) scaled by the incoming gradient.  Both passes run
+in libtt through the C ABI; this module only routes tensors.
+
+The source constants s0, xi0, eta0 of the factorisation are not
+differentiated: pass them in ``problem["src_par"]`` to hold them fixed (for
+finite-difference checks), or let the forward take them from the model.
+"""
+import torch
+
+from . import api
+
+
+class EikonalMisfit(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, s, xi, eta, problem):
+        g = problem["grid"]
+        src, rec, T_obs = problem["src"], problem["rec"], problem["T_obs"]
+        tol, max_iter, kappa = problem["tol"], problem.get("max_iter", 2000), problem["kappa"]
+        par = problem.get("src_par")
+        if par is None:
+            par = api.source_params(g, s.detach(), xi.detach(), eta.detach(), src)
+        tau, st = api.forward(g, s.detach(), xi.detach(), eta.detach(), src, par, tol, max_iter, kappa,
+                              tile_k=problem.get("tile_k_fwd", 0))
+        T = api.sample(g, src, par, tau, rec)
+        chi, R = api.misfit(T, T_obs, problem.get("w"), problem.get("pairs"), problem.get("wpair"),
+                            problem.get("alpha", 1.0), problem.get("beta", 1.0))
+        ctx.save_for_backward(s.detach(), xi.detach(), eta.detach(), tau, R, par)
+        ctx.problem = problem
+        ctx.status_fwd = st
+        return chi
+
+    @staticmethod
+    def backward(ctx, grad_chi):
+        s, xi, eta, tau, R, par = ctx.saved_tensors
+        p = ctx.problem
+        g = p["grid"]
+        lam, st = api.adjoint(g, s, xi, eta, p["src"], par, tau, p["rec"], R, p.get("adj_tol", p["tol"]),
+                              p.get("max_iter", 2000), p["kappa"], tile_k=p.get("tile_k_adj", 0))
+        grad = api.kernel(g, s, xi, eta, p["src"], par, tau, lam)
+        grad = grad * grad_chi.to(grad.dtype)
+        return grad[0], grad[1], grad[2], None
+
+
+def misfit(s, xi, eta, problem):
+    """chi(s, xi, eta) for the sources, receivers and observations in
+    ``problem`` (keys: grid, src, rec, T_obs, tol, kappa, optional max_iter,
+    adj_tol, src_par, w, pairs, wpair, alpha, beta, tile_k_fwd, tile_k_adj)."""
+    return EikonalMisfit.apply(s, xi, eta, problem)

@@ -1,0 +1,94 @@
+"""Autotuner for the sweep tile depth (tile_k) of the forward and adjoint solves.
+
+For a grid and source count it times a few iterations of each solve for every
+candidate tile depth (summed device time of the sweep-kernel launches, from the
+library's per-launch HIP events) and keeps the fastest.  Any tile depth gives
+bit-identical results, so the choice affects speed only.  Choices are cached in
+a JSON file keyed by (kind, coordinates, grid shape, source count); the file is
+``$TT_TUNE_CACHE`` or ``~/.cache/paper_2412_00031_amd/tiles.json``.
+"""
+import json
+import os
+
+import torch
+
+from . import api
+
+CANDIDATES = (8, 12, 16, 20, 24, 32, 40, 48, 62)
+
+
+def cache_path():
+    p = os.environ.get("TT_TUNE_CACHE")
+    if p:
+        return p
+    return os.path.join(os.path.expanduser("~"), ".cache", "paper_2412_00031_amd", "tiles.json")
+
+
+def _key(kind, grid, nsrc):
+    n = "x".join(str(int(v)) for v in grid["n"])
+    return f"{kind}:{int(grid['coord'])}:{n}:{int(nsrc)}"
+
+
+def _load():
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(d):
+    p = cache_path()
+    try:
+        os.makedirs(os.path.dirname(p), exist_ok=True)
+        tmp = p + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+        os.replace(tmp, p)
+    except OSError:
+        pass
+
+
+def _time_fwd(grid, s, xi, eta, src, par, kappa, tk, iters):
+    api.sweep_timing(0, reset=True)
+    api.forward(grid, s, xi, eta, src, par, 1e-300, iters, kappa, tile_k=tk, time_sweeps=True)
+    torch.cuda.synchronize()
+    ms, n = api.sweep_timing(0, reset=True)
+    return ms
+
+
+def _time_adj(grid, s, xi, eta, src, par, tau, rec, R, kappa, tk, iters):
+    api.sweep_timing(1, reset=True)
+    api.adjoint(grid, s, xi, eta, src, par, tau, rec, R, 1e-300, iters, kappa, tile_k=tk, time_sweeps=True)
+    torch.cuda.synchronize()
+    ms, n = api.sweep_timing(1, reset=True)
+    return ms
+
+
+def tune(grid, s, xi, eta, src, par, kappa, rec, R, iters=2, candidates=CANDIDATES, use_cache=True, log=None):
+    """Return {"fwd": tile_k, "adj": tile_k} for this grid and batch size."""
+    nsrc = int(src.shape[0])
+    cache = _load() if use_cache else {}
+    kf, ka = _key("fwd", grid, nsrc), _key("adj", grid, nsrc)
+    if use_cache and kf in cache and ka in cache:
+        return {"fwd": int(cache[kf]["tile_k"]), "adj": int(cache[ka]["tile_k"]), "cached": True}
+    m2 = int(grid["n"][2]) - 2
+    cands = sorted({min(c, m2, 62) for c in candidates})
+    tau, _ = api.forward(grid, s, xi, eta, src, par, 1e-300, iters, kappa)
+    res = {}
+    for kind in ("fwd", "adj"):
+        best, best_ms, times = None, None, {}
+        for tk in cands:
+            ms = min((_time_fwd(grid, s, xi, eta, src, par, kappa, tk, iters) if kind == "fwd" else
+                      _time_adj(grid, s, xi, eta, src, par, tau, rec, R, kappa, tk, iters)) for _ in range(2))
+            times[tk] = round(ms, 3)
+            if best_ms is None or ms < best_ms:
+                best, best_ms = tk, ms
+        res[kind] = best
+        cache[_key(kind, grid, nsrc)] = {"tile_k": best, "ms": times}
+        if log:
+            log(f"autotune {kind}: tile_k {best} ({times})")
+    if use_cache:
+        _store(cache)
+    res["cached"] = False
+    return res

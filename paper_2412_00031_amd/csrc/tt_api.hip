@@ -188,11 +188,32 @@ int pinned_counter(int** out) {
 // Enqueue iterations until no source is active.  The count of active sources
 // after iteration k is copied to pinned host memory; the host waits for it
 // while iteration k+1 is already queued, so the device never idles on the poll.
+// stream used only to capture graphs (capture is not allowed on the legacy
+// default stream); nothing runs on it
+thread_local hipStream_t g_capture_stream = nullptr;
+
+// Capture one iteration into an executable graph.
 template <typename Launch>
-int run_iterations(const tt::Plan& P, hipStream_t st, Launch launch_one) {
+int capture_iteration(Launch launch_one, hipGraphExec_t* exec) {
+    if (!g_capture_stream) TT_HIP(hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    TT_HIP(hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal));
+    launch_one(g_capture_stream);
+    hipError_t e = hipStreamEndCapture(g_capture_stream, &graph);
+    if (e != hipSuccess) return fail(TT_EHIP, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(TT_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+    return TT_OK;
+}
+
+template <typename Launch>
+int run_iterations(const tt::Plan& P, hipStream_t st, bool use_graph, Launch launch_one) {
     int* host = nullptr;
     int rc = pinned_counter(&host);
     if (rc) return rc;
+    hipGraphExec_t exec = nullptr;
+    if (use_graph && (rc = capture_iteration(launch_one, &exec))) return rc;
     hipEvent_t ev[2];
     TT_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     TT_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -200,7 +221,15 @@ int run_iterations(const tt::Plan& P, hipStream_t st, Launch launch_one) {
     int result = TT_OK;
     for (;;) {
         if (issued < P.max_iter) {
-            launch_one();
+            if (exec) {
+                hipError_t e = hipGraphLaunch(exec, st);
+                if (e != hipSuccess) {
+                    result = fail(TT_EHIP, "graph launch: %s", hipGetErrorString(e));
+                    break;
+                }
+            } else {
+                launch_one(st);
+            }
             hipError_t e = hipMemcpyAsync(&host[issued & 1], P.counter, sizeof(int), hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipEventRecord(ev[issued & 1], st);
             if (e != hipSuccess) {
@@ -225,6 +254,7 @@ int run_iterations(const tt::Plan& P, hipStream_t st, Launch launch_one) {
     if (e != hipSuccess && result == TT_OK) result = fail(TT_EHIP, "kernel launch: %s", hipGetErrorString(e));
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
+    if (exec) (void)hipGraphExecDestroy(exec);
     return result;
 }
 
@@ -233,15 +263,15 @@ thread_local double g_sweep_ms[2] = {0.0, 0.0};
 thread_local int64_t g_sweep_launches[2] = {0, 0};
 
 // sum and release the event pairs recorded during a solve (stream already synchronised)
-void collect_timing(std::vector<std::pair<hipEvent_t, hipEvent_t>>& ev, int which) {
+void collect_timing(std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>>& ev, int which) {
     for (auto& pr : ev) {
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+        if (hipEventElapsedTime(&ms, pr.first.first, pr.first.second) == hipSuccess) {
             g_sweep_ms[which] += ms;
-            g_sweep_launches[which] += 1;
+            g_sweep_launches[which] += pr.second;
         }
-        (void)hipEventDestroy(pr.first);
-        (void)hipEventDestroy(pr.second);
+        (void)hipEventDestroy(pr.first.first);
+        (void)hipEventDestroy(pr.first.second);
     }
     ev.clear();
 }
@@ -321,9 +351,10 @@ int tt_forward(const tt_grid* grid, const double* s, const double* xi, const dou
     tt::SweepArgs a = tt::make_args(P, s, xi, eta, tau, status);
     tt::launch_fwd_init(P, a, tau_init, s, xi, eta, st);
     TT_HIP(hipGetLastError());
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
     if (opts->flags & TT_FLAG_TIME_SWEEPS) P.timing = &ev;
-    rc = run_iterations(P, st, [&]() { tt::launch_fwd_iteration(P, a, st); });
+    const bool graph = (opts->flags & TT_FLAG_GRAPH) && !(opts->flags & TT_FLAG_TIME_SWEEPS);
+    rc = run_iterations(P, st, graph, [&](hipStream_t s_) { tt::launch_fwd_iteration(P, a, s_); });
     collect_timing(ev, 0);
     return rc;
 }
@@ -393,9 +424,10 @@ int tt_adjoint(const tt_grid* grid, const double* s, const double* xi, const dou
     tt::SweepArgs a = tt::make_args(P, s, xi, eta, lam, status);
     tt::launch_adj_init(P, a, tau, nrec, rec_pos, R, st);
     TT_HIP(hipGetLastError());
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
     if (opts->flags & TT_FLAG_TIME_SWEEPS) P.timing = &ev;
-    rc = run_iterations(P, st, [&]() { tt::launch_adj_iteration(P, a, st); });
+    const bool graph = (opts->flags & TT_FLAG_GRAPH) && !(opts->flags & TT_FLAG_TIME_SWEEPS);
+    rc = run_iterations(P, st, graph, [&](hipStream_t s_) { tt::launch_adj_iteration(P, a, s_); });
     collect_timing(ev, 1);
     return rc;
 }

@@ -202,9 +202,9 @@ struct Plan {
     double* model = nullptr;  // forward: [2][S][4] = (s, xi, eta, 0) (row-coalesced layouts)
     double* bnd_in = nullptr; // adjoint: [nsrc][NB]
     std::vector<int> plane_count;
-    // optional per-launch timing of the sweep kernels (events recorded around
-    // each tile-plane launch); filled by the launchers when non-null
-    std::vector<std::pair<hipEvent_t, hipEvent_t>>* timing = nullptr;
+    // optional timing of the sweep kernels: an event pair around the
+    // tile-plane launches of each directional sweep, with the launch count
+    std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>>* timing = nullptr;
 };
 
 // Kernel-argument bundle of the sweep kernels.

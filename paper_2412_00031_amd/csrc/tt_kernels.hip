@@ -943,17 +943,18 @@ void launch_fwd_init(const Plan& P, const SweepArgs& a, const double* tau_init, 
 
 static size_t tile_lds_bytes(const Geo& G) { return sizeof(double) * kTC * kTC * (size_t)(G.tk + 2); }
 
-// event pair around one launch when timing is on
+// Event pair around the tile-plane launches of one directional sweep when
+// timing is on; the launch count of the group is recorded with it.
 struct TimedLaunch {
     const Plan& P;
     hipStream_t st;
     hipEvent_t e1 = nullptr;
-    TimedLaunch(const Plan& p, hipStream_t s) : P(p), st(s) {
+    TimedLaunch(const Plan& p, hipStream_t s, int launches) : P(p), st(s) {
         if (P.timing) {
             hipEvent_t e0;
             if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
                 (void)hipEventRecord(e0, st);
-                P.timing->push_back({e0, e1});
+                P.timing->push_back({{e0, e1}, launches});
             } else {
                 e1 = nullptr;
             }
@@ -966,13 +967,15 @@ struct TimedLaunch {
 
 void launch_fwd_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
     for (int d = 0; d < 8; ++d) {
+        {
+        TimedLaunch tl(P, st, P.nplanes);
         for (int p = 0; p < P.nplanes; ++p) {
             const dim3 grid(P.nsrc, P.plane_count[p]);
-            TimedLaunch tl(P, st);
             if (P.G.coord == 1)
                 hipLaunchKernelGGL(k_fwd_sweep<1>, grid, dim3(64), tile_lds_bytes(P.G), st, a, d, p);
             else
                 hipLaunchKernelGGL(k_fwd_sweep<0>, grid, dim3(64), tile_lds_bytes(P.G), st, a, d, p);
+        }
         }
         hipLaunchKernelGGL(k_fwd_bnd, dim3(P.nbblocks, P.nsrc), dim3(kBndThreads), 0, st, a, d);
     }
@@ -995,13 +998,15 @@ void launch_adj_init(const Plan& P, const SweepArgs& a, const double* tau, int n
 
 void launch_adj_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
     for (int d = 0; d < 8; ++d) {
+        {
+        TimedLaunch tl(P, st, P.nplanes);
         for (int p = 0; p < P.nplanes; ++p) {
             const dim3 grid(P.nsrc, P.plane_count[p]);
-            TimedLaunch tl(P, st);
             if (P.G.coord == 1)
                 hipLaunchKernelGGL(k_adj_sweep<1>, grid, dim3(64), tile_lds_bytes(P.G), st, a, d, p);
             else
                 hipLaunchKernelGGL(k_adj_sweep<0>, grid, dim3(64), tile_lds_bytes(P.G), st, a, d, p);
+        }
         }
         hipLaunchKernelGGL(k_adj_bnd, dim3(P.nbblocks, P.nsrc), dim3(kBndThreads), 0, st, a, d);
     }

@@ -1,0 +1,77 @@
+"""The autograd.Function's backward (adjoint solve + kernels) against central
+finite differences of its forward (solve + sampling + misfit), on the GPU.
+
+Source constants are held fixed (passed in), as the derivative defines them.
+"""
+import numpy as np
+import pytest
+
+from paper_2412_00031_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(torch, a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device="cuda")
+
+
+def _problem(torch, wl, nsrc, T_obs, tol, pairs=None):
+    from paper_2412_00031_amd import api
+    s, xi, eta = (_dev(torch, wl[k]) for k in ("s", "xi", "eta"))
+    src = _dev(torch, wl["src"][:nsrc])
+    par = api.source_params(wl["grid"], s, xi, eta, src)
+    prob = dict(grid=wl["grid"], src=src, rec=_dev(torch, wl["rec"]), T_obs=_dev(torch, T_obs[:nsrc]), tol=tol,
+                adj_tol=tol, kappa=wl["kappa"], max_iter=5000, src_par=par)
+    if pairs is not None:
+        prob["pairs"] = _dev(torch, pairs, torch.int32)
+    return s, xi, eta, prob
+
+
+def _fd_check(torch, wl, nsrc, ncell, seed, tol, steps=(2e-6, 2e-5, 2e-5), pairs=None, rtol=2e-5):
+    from paper_2412_00031_amd.autograd import misfit
+    T_obs = W.straight_line_times(wl["grid"], wl["src"], wl["rec"], 6.4)
+    s, xi, eta, prob = _problem(torch, wl, nsrc, T_obs, tol, pairs)
+    m = [s.clone().requires_grad_(True), xi.clone().requires_grad_(True), eta.clone().requires_grad_(True)]
+    chi = misfit(m[0], m[1], m[2], prob)
+    chi.backward()
+    grads = [p.grad.cpu().numpy() for p in m]
+    n = tuple(wl["grid"]["n"])
+    rng = np.random.default_rng(seed)
+    fixed = []
+    for q in range(nsrc):
+        # cells away from the fixed cells of the sources
+        from oracle import fixed_base
+        fixed.append(fixed_base(wl["grid"], wl["src"][q]))
+    cells = []
+    while len(cells) < ncell:
+        c = tuple(int(rng.integers(1, n[a] - 1)) for a in range(3))
+        if any(all(fb[a] - 1 <= c[a] <= fb[a] + 2 for a in range(3)) for fb in fixed):
+            continue
+        cells.append(c)
+    base = [s, xi, eta]
+    for t, c in enumerate(cells):
+        p = t % 3
+        h = steps[p]
+        vals = []
+        for sgn in (1, -1):
+            pert = [b.clone() for b in base]
+            pert[p][c] += sgn * h
+            with torch.no_grad():
+                vals.append(float(misfit(pert[0], pert[1], pert[2], prob)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        gmax = np.abs(grads[p]).max()
+        assert abs(fd - grads[p][c]) <= rtol * abs(fd) + 1e-6 * gmax, (p, c, fd, grads[p][c])
+
+
+def test_autograd_matches_fd_small_spherical(torch_cuda):
+    wl = W.small_spherical(n=(14, 15, 16), nsrc=3, nrec=12, seed=41, aniso=0.05)
+    pairs = W.random_pairs(12, 10, np.random.default_rng(3))
+    _fd_check(torch_cuda, wl, 3, 16, 7, 1e-15, pairs=pairs)
+
+
+@pytest.mark.slow
+def test_autograd_matches_fd_101(torch_cuda):
+    """101^3 spherical GRF model: central differences at 16 random cells
+    (s, xi, eta in turn) on a subset of 4 sources."""
+    wl = W.sph101(with_true=False)
+    _fd_check(torch_cuda, wl, 4, 16, 11, 1e-13, steps=(2e-5, 2e-4, 2e-4), rtol=1e-4)
