@@ -100,14 +100,24 @@ def init_params(rng, ch=CH, in_ch=IN_CH):
     return P
 
 
-def forward(P, x):
-    """x [D, H, W, IN_CH] (D, H, W multiples of 8) -> (y [D, H, W], cache)."""
+def _ident(a):
+    return a
+
+
+def forward(P, x, q=None):
+    """x [D, H, W, IN_CH] (D, H, W multiples of 8) -> (y [D, H, W], cache).
+
+    q (default: identity) is applied to the 3^3 convolution weights and to every
+    stored activation (each convolution's ReLU output and each up-sampling's
+    output); passing a rounding function evaluates the same network with those
+    tensors held in a narrower storage format, the rest in float64."""
+    q = q or _ident
     c = {}
     def cr(name, inp):
         c[name + ".in"] = inp
-        z = conv3(inp, P[name + ".W"], P[name + ".b"])
+        z = conv3(inp, q(P[name + ".W"]), P[name + ".b"])
         c[name + ".z"] = z
-        return relu(z)
+        return q(relu(z))
     e1 = cr("e1b", cr("e1a", x))
     p1 = pool(e1); c["p1.in"] = e1
     e2 = cr("e2b", cr("e2a", p1))
@@ -116,60 +126,66 @@ def forward(P, x):
     p3 = pool(e3); c["p3.in"] = e3
     bn = cr("bnb", cr("bna", p3))
     c["u3.in"] = bn
-    u3 = up(bn, P["u3.W"], P["u3.b"])
+    u3 = q(up(bn, P["u3.W"], P["u3.b"]))
     d3 = cr("d3b", cr("d3a", np.concatenate([u3, e3], axis=3)))
     c["u2.in"] = d3
-    u2 = up(d3, P["u2.W"], P["u2.b"])
+    u2 = q(up(d3, P["u2.W"], P["u2.b"]))
     d2 = cr("d2b", cr("d2a", np.concatenate([u2, e2], axis=3)))
     c["u1.in"] = d2
-    u1 = up(d2, P["u1.W"], P["u1.b"])
+    u1 = q(up(d2, P["u1.W"], P["u1.b"]))
     d1 = cr("d1b", cr("d1a", np.concatenate([u1, e1], axis=3)))
     c["head.in"] = d1
     y = (d1 @ P["head.W"])[..., 0] + P["head.b"][0]
     return y, c
 
 
-def backward(P, c, gy):
-    """Gradients of sum(gy * forward(P, x)[0]) for every parameter."""
+def backward(P, c, gy, q=None):
+    """Gradients of sum(gy * forward(P, x)[0]) for every parameter.
+
+    q (default: identity), as in forward, is applied to the 3^3 convolution
+    weights and to every stored activation gradient (the head's and each
+    layer's input gradient, and the skip + pooled gradient sums)."""
+    q = q or _ident
     G = {}
     d1 = c["head.in"]
     G["head.W"] = np.einsum("zyxi,zyx->i", d1, gy)[:, None]
     G["head.b"] = np.array([gy.sum()])
-    g = gy[..., None] * P["head.W"][:, 0]
+    g = q(gy[..., None] * P["head.W"][:, 0])
 
     def crb(name, g_out):
         gz = g_out * (c[name + ".z"] > 0)
-        gx, G[name + ".W"], G[name + ".b"] = conv3_backward(c[name + ".in"], P[name + ".W"], gz)
-        return gx
+        gx, G[name + ".W"], G[name + ".b"] = conv3_backward(c[name + ".in"], q(P[name + ".W"]), gz)
+        return q(gx)
 
     g = crb("d1a", crb("d1b", g))
     c1 = P["u1.W"].shape[2]
     g_u1, g_e1_skip = g[..., :c1], g[..., c1:]
     g_d2, G["u1.W"], G["u1.b"] = up_backward(c["u1.in"], P["u1.W"], g_u1)
-    g = crb("d2a", crb("d2b", g_d2))
+    g = crb("d2a", crb("d2b", q(g_d2)))
     c2 = P["u2.W"].shape[2]
     g_u2, g_e2_skip = g[..., :c2], g[..., c2:]
     g_d3, G["u2.W"], G["u2.b"] = up_backward(c["u2.in"], P["u2.W"], g_u2)
-    g = crb("d3a", crb("d3b", g_d3))
+    g = crb("d3a", crb("d3b", q(g_d3)))
     c3 = P["u3.W"].shape[2]
     g_u3, g_e3_skip = g[..., :c3], g[..., c3:]
     g_bn, G["u3.W"], G["u3.b"] = up_backward(c["u3.in"], P["u3.W"], g_u3)
-    g = crb("bna", crb("bnb", g_bn))
-    g = pool_backward(c["p3.in"], g) + g_e3_skip
+    g = crb("bna", crb("bnb", q(g_bn)))
+    g = q(pool_backward(c["p3.in"], g) + g_e3_skip)
     g = crb("e3a", crb("e3b", g))
-    g = pool_backward(c["p2.in"], g) + g_e2_skip
+    g = q(pool_backward(c["p2.in"], g) + g_e2_skip)
     g = crb("e2a", crb("e2b", g))
-    g = pool_backward(c["p1.in"], g) + g_e1_skip
+    g = q(pool_backward(c["p1.in"], g) + g_e1_skip)
     crb("e1a", crb("e1b", g))
     return G
 
 
 def mse(y, t, mask=None):
-    """(loss, d loss / d y) for loss = mean over masked points of (y - t)^2."""
+    """(loss, d loss / d y) for the weighted mean sum m (y - t)^2 / max(sum m, 1)
+    (m = mask, 1 if None; a 0/1 mask gives the mean over the masked points)."""
     m = np.ones_like(y) if mask is None else mask.astype(np.float64)
     n = max(m.sum(), 1.0)
-    r = (y - t) * m
-    return float((r * r).sum() / n), 2.0 * r / n
+    r = y - t
+    return float((m * r * r).sum() / n), 2.0 * m * r / n
 
 
 def adam(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):

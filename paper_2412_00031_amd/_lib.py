@@ -23,6 +23,23 @@ class TTOpts(ctypes.Structure):
 EXPORTS = ["tt_workspace_size", "tt_source_params", "tt_forward", "tt_sample", "tt_misfit", "tt_adjoint",
            "tt_kernel", "tt_sweep_timing", "tt_last_error"]
 
+NN_EXPORTS = ["nn_to_bf16", "nn_from_bf16", "nn_conv3_pack", "nn_conv3_fwd", "nn_conv3_wgrad_work", "nn_conv3_wgrad",
+              "nn_relu_mask", "nn_pool_fwd", "nn_pool_bwd", "nn_up_fwd", "nn_up_wgrad_work", "nn_up_bwd",
+              "nn_head_fwd", "nn_head_work", "nn_head_bwd", "nn_mse", "nn_adam", "nn_unet_nparams", "nn_unet_nfrag",
+              "nn_unet_workspace", "nn_unet_pack", "nn_unet_forward", "nn_unet_backward", "nn_warm_features",
+              "nn_warm_target", "nn_warm_init"]
+
+# constants of include/nn.h
+NN_FEAT_S = 5.0
+NN_FEAT_A = 25.0
+NN_FEAT_D = 0.01
+NN_TARGET_SCALE = 10.0
+NN_MSE_LOSS_FLOATS = 2 + 2 * 1024
+
+
+class NNUnetCfg(ctypes.Structure):
+    _fields_ = [("ch", ctypes.c_int32 * 4), ("in_ch", ctypes.c_int32)]
+
 TT_FLAG_TIME_SWEEPS = 1
 TT_FLAG_GRAPH = 2
 
@@ -62,6 +79,7 @@ def load(path=LIB_PATH):
     lib.tt_last_error.restype = ctypes.c_char_p
     for name in ("tt_source_params", "tt_forward", "tt_sample", "tt_misfit", "tt_adjoint", "tt_kernel"):
         getattr(lib, name).restype = ctypes.c_int
+    _declare_nn(lib)
     _lib = lib
     return lib
 
@@ -75,3 +93,53 @@ class TTError(RuntimeError):
 def check(rc):
     if rc != TT_OK:
         raise TTError(rc, load().tt_last_error().decode())
+
+
+def _declare_nn(lib):
+    P = ctypes.c_void_p
+    G = ctypes.POINTER(TTGrid)
+    C = ctypes.POINTER(NNUnetCfg)
+    i = ctypes.c_int
+    i64 = ctypes.c_int64
+    sz = ctypes.c_size_t
+    f = ctypes.c_float
+    sig = {
+        "nn_to_bf16": [P, i64, P, P],
+        "nn_from_bf16": [P, i64, P, P],
+        "nn_conv3_pack": [P, i, i, i, P, P],
+        "nn_conv3_fwd": [P, i, i, i, i, i, i, i, P, P, i, i, P, i, i, P],
+        "nn_conv3_wgrad": [P, i, i, i, i, i, i, i, P, i, i, i, P, P, P, sz, P],
+        "nn_relu_mask": [P, P, i64, i, i, i, P, i, i, P],
+        "nn_pool_fwd": [P, i, i, i, i, i, i, i, P, P],
+        "nn_pool_bwd": [P, P, i, i, i, i, i, i, i, P, i, P],
+        "nn_up_fwd": [P, i, i, i, i, i, P, P, i, P, i, i, P],
+        "nn_up_bwd": [P, P, i, i, i, i, i, i, i, i, P, P, P, P, P, sz, P],
+        "nn_head_fwd": [P, i64, i, P, P, P, P],
+        "nn_head_bwd": [P, P, i64, i, P, P, P, P, P, sz, P],
+        "nn_mse": [P, P, P, i64, P, P, P],
+        "nn_adam": [P, P, P, P, i64, i, f, f, f, f, P],
+        "nn_unet_pack": [C, P, P, P],
+        "nn_unet_forward": [C, P, P, P, i, i, i, i, P, P, sz, i, P],
+        "nn_unet_backward": [C, P, P, P, P, i, i, i, i, P, P, sz, P],
+        "nn_warm_features": [G, P, P, P, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                             ctypes.c_int32, P, P],
+        "nn_warm_target": [G, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P,
+                           P],
+        "nn_warm_init": [G, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    sizes = {
+        "nn_conv3_wgrad_work": [i, i, i, i, i, i],
+        "nn_up_wgrad_work": [i, i, i, i, i, i],
+        "nn_head_work": [i64, i],
+        "nn_unet_nparams": [C],
+        "nn_unet_nfrag": [C],
+        "nn_unet_workspace": [C, i, i, i, i, i],
+    }
+    for name, args in sizes.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = sz

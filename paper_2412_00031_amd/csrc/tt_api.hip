@@ -12,9 +12,10 @@
 #include "tt_internal.h"
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
+namespace tt {
 int fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -24,6 +25,10 @@ int fail(int code, const char* fmt, ...) {
     g_err = buf;
     return code;
 }
+}  // namespace tt
+
+namespace {
+using tt::fail;
 
 #define TT_HIP(call)                                                                          \
     do {                                                                                      \

@@ -17,6 +17,9 @@
 
 namespace tt {
 
+// Record a printf-style message for tt_last_error() and return `code`.
+int fail(int code, const char* fmt, ...);
+
 constexpr int kBI = 8;        // column block of one wave: 8 x 8 (i, j) columns
 constexpr int kBJ = 8;
 constexpr int kWave = 64;

@@ -1,0 +1,63 @@
+"""The C-ABI library loads without a GPU and exports every function that
+include/*.h declares (no compute calls)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+INCLUDE = os.path.join(ROOT, "include")
+
+
+def declared_functions():
+    names = set()
+    for fn in sorted(os.listdir(INCLUDE)):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(INCLUDE, fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        text = re.sub(r"#[^\n]*", "", text)
+        for m in re.finditer(r"\b(?:int|size_t|void|const\s+char\s*\*)\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def libpath():
+    from paper_2412_00031_amd import _lib, build
+    if not os.path.exists(_lib.LIB_PATH):
+        build.build()
+    return _lib.LIB_PATH
+
+
+def test_headers_declare_the_entry_points():
+    names = declared_functions()
+    for n in ("tt_forward", "tt_adjoint", "tt_kernel", "tt_sample", "tt_misfit", "tt_workspace_size",
+              "tt_last_error", "nn_unet_forward", "nn_unet_backward", "nn_warm_init"):
+        assert n in names, n
+
+
+def test_library_exports_every_declared_symbol(libpath):
+    lib = ctypes.CDLL(libpath)
+    missing = [n for n in sorted(declared_functions()) if not hasattr(lib, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", libpath], capture_output=True, text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    assert declared_functions() <= exported
+
+
+def test_binding_declares_every_header_symbol():
+    from paper_2412_00031_amd import _lib
+    assert declared_functions() == set(_lib.EXPORTS) | set(_lib.NN_EXPORTS)
+
+
+def test_last_error_without_gpu(libpath):
+    """A host-checked argument error is reported without touching a device."""
+    from paper_2412_00031_amd import _lib
+    lib = _lib.load(libpath)
+    rc = lib.tt_misfit(0, 1, None, None, None, 0, None, None, 1.0, 1.0, None, None, None)
+    assert rc == _lib.TT_EINVAL
+    assert lib.tt_last_error().decode()

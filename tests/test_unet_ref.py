@@ -75,6 +75,11 @@ def test_mse_and_adam_first_step():
     e = 1e-7
     y2 = y.copy(); y2[1, 2, 3] += e
     assert abs((U.mse(y2, t, mask)[0] - loss) / e - g[1, 2, 3]) < 1e-5
+    w = rng.random((4, 4, 4))  # fractional weights
+    lw, gw = U.mse(y, t, w)
+    assert abs(lw - (w * (y - t) ** 2).sum() / w.sum()) < 1e-14
+    y2 = y.copy(); y2[2, 0, 1] += e
+    assert abs((U.mse(y2, t, w)[0] - lw) / e - gw[2, 0, 1]) < 1e-5
     p, gg = rng.standard_normal(5), rng.standard_normal(5)
     p1, m1, v1 = U.adam(p, gg, np.zeros(5), np.zeros(5), 1, 1e-3)
     assert np.allclose(p1, p - 1e-3 * gg / (np.abs(gg) + 1e-8), rtol=1e-12, atol=1e-15)
