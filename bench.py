@@ -2,14 +2,17 @@
 """Throughput of the adjoint-state traveltime hot path on one MI355X.
 
 One step = one pass of the whole per-source path over a batch of sources:
-source constants, forward fast-sweeping solve to tol, receiver traveltimes,
+source constants, (warm start: features, U-Net inference, interpolation to
+the initial tau), forward fast-sweeping solve to tol, receiver traveltimes,
 misfit and adjoint sources (Eqs. (2), (A2)), adjoint solve to tol, and the
 kernels summed over sources (Eqs. (6)-(8)).  Workload: 101^3 spherical grid
 (0-100 km depth, 4 x 4 degrees), Gaussian-random-field slowness (+-10 %) and
 anisotropy (+-0.04), 128 sources, 500 surface receivers, tol 1e-6, FP64;
 observed times come from a forward solve in an independent random model
-(computed before timing).  value = sources per second (fwd + adjoint +
-kernel per source).
+(computed before timing).  The plain path (tau = 1 start) and the warm-started
+path run the same steps back to back; value = sources per second (fwd +
+adjoint + kernel per source) of the warm-started path, with the plain path's
+figures in "plain".
 
 Prints one JSON line (rank 0).  Extra objects: "roofline" (the dominant sweep
 kernel, timed live with HIP event pairs around the back-to-back launches of
@@ -41,6 +44,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nsrc", type=int, default=128)
     ap.add_argument("--tile-k", type=int, default=0, help="tile depth for both solves (0: autotune)")
+    ap.add_argument("--tile-k-fwd", type=int, default=0, help="forward tile depth (overrides --tile-k/autotune)")
+    ap.add_argument("--tile-k-adj", type=int, default=0, help="adjoint tile depth (overrides --tile-k/autotune)")
     ap.add_argument("--no-autotune", action="store_true", help="use the library's default tile depths")
     ap.add_argument("--graph", action="store_true", help="replay each iteration from a captured hipGraph")
     ap.add_argument("--no-sweep-timing", action="store_true",
@@ -50,18 +55,21 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB of a plain device-to-device copy run first (counter calibration)")
+    ap.add_argument("--start", choices=("both", "plain", "warm"), default="both",
+                    help="which forward start to time (both: plain, then warm-started)")
+    ap.add_argument("--weights", default=None, help="U-Net weights (.npz) of the warm start")
     return ap.parse_args()
 
 
-def measured_traffic(kernel, updates_per_launch, default_tiles):
+def measured_traffic(kernel, updates_per_launch, tiles):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (bytes per node update, calibrated against a plain copy), or None
     when the kernel source changed since the counters were taken or the tile
-    shape differs from the one measured."""
+    depths (forward, adjoint) differ from the ones measured."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "sweeps_sph101_pmc.md")
     src = os.path.join(ROOT, "paper_2412_00031_amd", "csrc", "tt_kernels.hip")
-    if not default_tiles or not os.path.exists(path):
+    if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
@@ -69,6 +77,8 @@ def measured_traffic(kernel, updates_per_launch, default_tiles):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    if (vals.get("tile_k_fwd"), vals.get("tile_k_adj")) != (str(tiles[0]), str(tiles[1])):
         return None
     try:
         per_update = float(vals[f"{kernel} read_bytes_per_update"]) + float(vals[f"{kernel} write_bytes_per_update"])
@@ -159,14 +169,15 @@ def main():
     torch.cuda.synchronize()
     log("observations ready")
 
-    tk_f = tk_a = args.tile_k
+    tk_f = args.tile_k_fwd or args.tile_k
+    tk_a = args.tile_k_adj or args.tile_k
     tuned = None
-    if args.tile_k == 0 and not args.no_autotune:
+    if (tk_f == 0 or tk_a == 0) and not args.no_autotune:
         from paper_2412_00031_amd import autotune
         par0 = api.source_params(g, s, xi, eta, src)
         R0 = torch.zeros((nsrc, len(wl["rec"])), dtype=torch.float64, device=dev)
         tuned = autotune.tune(g, s, xi, eta, src, par0, kappa, rec, R0, log=log)
-        tk_f, tk_a = tuned["fwd"], tuned["adj"]
+        tk_f, tk_a = tk_f or tuned["fwd"], tk_a or tuned["adj"]
         log(f"tile depths: forward {tk_f}, adjoint {tk_a}")
     ws_f = api.workspace(g, nsrc, 0, tk_f, dev)
     ws_a = api.workspace(g, nsrc, 1, tk_a, dev)
@@ -174,10 +185,24 @@ def main():
     lam = torch.empty_like(tau)
     grad = torch.empty((3,) + tuple(g["n"]), dtype=torch.float64, device=dev)
 
-    def step(timed):
+    warm = None
+    if args.start != "plain":
+        from paper_2412_00031_amd.warmstart import WEIGHTS, UNet, WarmStart
+        wpath = args.weights or WEIGHTS
+        if os.path.exists(wpath):
+            warm = WarmStart(UNet.load(wpath, dev), g)
+            init_buf = torch.empty((nsrc, tau[0].numel()), dtype=torch.float64, device=dev)
+            log(f"warm start: {wpath}")
+        elif args.start == "warm":
+            sys.exit(f"no warm-start weights at {wpath}")
+        else:
+            log(f"no warm-start weights at {wpath}: timing the plain path only")
+
+    def step(timed, use_warm):
         par = api.source_params(g, s, xi, eta, src)
-        _, st_f = api.forward(g, s, xi, eta, src, par, tol, args.max_iter, kappa, tile_k=tk_f, ws=ws_f,
-                              out=tau, time_sweeps=timed, graph=args.graph)
+        init = warm.predict(s, xi, eta, src, par, out=init_buf) if use_warm else None
+        _, st_f = api.forward(g, s, xi, eta, src, par, tol, args.max_iter, kappa, tau_init=init, tile_k=tk_f,
+                              ws=ws_f, out=tau, time_sweeps=timed, graph=args.graph)
         T = api.sample(g, src, par, tau, rec)
         chi, R = api.misfit(T, T_obs)
         _, st_a = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, tol, args.max_iter, kappa, tile_k=tk_a,
@@ -185,28 +210,43 @@ def main():
         api.kernel(g, s, xi, eta, src, par, tau, lam, grad=grad.zero_())
         return st_f, st_a, chi
 
-    for w in range(args.warmup):
-        step(False)
+    def run(use_warm):
+        name = "warm" if use_warm else "plain"
+        for w in range(args.warmup):
+            step(False, use_warm)
+            torch.cuda.synchronize()
+            log(f"{name}: warmup step {w + 1} done")
         torch.cuda.synchronize()
-        log(f"warmup step {w + 1} done")
-    torch.cuda.synchronize()
-    api.sweep_timing(0, reset=True)
-    api.sweep_timing(1, reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st_f, st_a, chi = step(not args.no_sweep_timing)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    log(f"timed {args.steps} steps: {elapsed:.2f} s")
-    st_f = st_f.cpu().numpy()
-    st_a = st_a.cpu().numpy()
-    if (st_f <= 0).any() or (st_a <= 0).any():
-        print(f"warning: not all sources converged (fwd {st_f.min()}, adj {st_a.min()})", file=sys.stderr)
-    it_f = np.abs(st_f)
-    it_a = np.abs(st_a)
-    ms_f, n_f = api.sweep_timing(0, reset=True)
-    ms_a, n_a = api.sweep_timing(1, reset=True)
+        api.sweep_timing(0, reset=True)
+        api.sweep_timing(1, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            st_f, st_a, chi = step(not args.no_sweep_timing, use_warm)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        log(f"{name}: timed {args.steps} steps: {elapsed:.2f} s")
+        st_f = st_f.cpu().numpy()
+        st_a = st_a.cpu().numpy()
+        if (st_f <= 0).any() or (st_a <= 0).any():
+            print(f"warning: not all sources converged (fwd {st_f.min()}, adj {st_a.min()})", file=sys.stderr)
+        return dict(elapsed=elapsed, it_f=np.abs(st_f), it_a=np.abs(st_a), chi=float(chi),
+                    sweep=(api.sweep_timing(0, reset=True), api.sweep_timing(1, reset=True)))
+
+    runs = {}
+    if args.start in ("both", "plain") or warm is None:
+        runs["plain"] = run(False)
+    if warm is not None:
+        runs["warm"] = run(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            warm.predict(s, xi, eta, src, api.source_params(g, s, xi, eta, src), out=init_buf)
+        torch.cuda.synchronize()
+        runs["warm"]["predict_ms"] = (time.perf_counter() - t0) / 3 * 1e3
+    main_run = runs["warm"] if warm is not None else runs["plain"]
+    elapsed, it_f, it_a = main_run["elapsed"], main_run["it_f"], main_run["it_a"]
+    (ms_f, n_f), (ms_a, n_a) = main_run["sweep"]
 
     value = nsrc * args.steps / elapsed
     nodes = interior_nonfixed(g) - 8
@@ -225,8 +265,7 @@ def main():
     K = kern[dom]
     avg_ms = K["ms"] / max(K["launches"], 1)
     achieved = K["bytes"] / (K["ms"] * 1e-3) / 1e9 if K["ms"] > 0 else 0.0
-    traffic = measured_traffic(dom, K["updates"] / max(K["launches"], 1),
-                               (tk_f, tk_a) == (16, 48) or (args.tile_k == 0 and args.no_autotune))
+    traffic = measured_traffic(dom, K["updates"] / max(K["launches"], 1), (tk_f or 16, tk_a or 48))
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None if traffic is None else round(traffic),
@@ -247,16 +286,24 @@ def main():
                          f"capped at 1 and 3 iterations, one kernel pass; scaled per source to the converged "
                          f"iteration counts ({wall:.1f} s wall)"}
 
+    def summary(r):
+        return {"value": round(nsrc * args.steps / r["elapsed"], 4), "ms_per_step": round(1e3 * r["elapsed"] / args.steps, 2),
+                "mean_iters_fwd": round(float(r["it_f"].mean()), 2), "mean_iters_adj": round(float(r["it_a"].mean()), 2),
+                "chi": r["chi"]}
+
+    start = "warm start (U-Net prediction, plain sweeps to the same tol)" if warm is not None else "plain start"
     line = {
         "metric": METRIC, "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 2), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "plain": summary(runs["plain"]) if "plain" in runs else None,
+        "warm": dict(summary(runs["warm"]), predict_ms=round(runs["warm"]["predict_ms"], 2)) if "warm" in runs else None,
         "config": {"workload": f"sph101: 101^3 spherical (0-100 km, 4x4 deg), GRF model, {nsrc} sources, "
-                               f"{len(wl['rec'])} receivers, tol {tol:g}, plain start",
+                               f"{len(wl['rec'])} receivers, tol {tol:g}, {start}",
                    "nsrc": nsrc, "grid": list(g["n"]), "tol": tol, "kappa": kappa,
                    "mean_iters_fwd": round(float(it_f.mean()), 2), "mean_iters_adj": round(float(it_a.mean()), 2),
                    "tile_k": {"fwd": tk_f or 16, "adj": tk_a or 48,
-                              "chosen_by": "autotune" if tuned else ("fixed" if args.tile_k else "default")},
+                              "chosen_by": "autotune" if tuned else ("fixed" if (tk_f or tk_a) else "default")},
                    "graph": bool(args.graph)},
         "roofline": roofline, "cpu_baseline": cpu,
     }

@@ -45,6 +45,12 @@ extern "C" {
 #define NN_FEAT_D 0.01
 #define NN_TARGET_SCALE 10.0
 
+/* Range of the initial tau that nn_warm_init hands to the solver: a
+ * prediction outside it is clamped (a NaN becomes 1), so that a poor network
+ * costs iterations only. */
+#define NN_TAU_INIT_MIN 0.25
+#define NN_TAU_INIT_MAX 4.0
+
 /* Scratch of nn_mse: loss holds 2 + 2 * NN_MSE_MAX_BLOCKS floats. */
 #define NN_MSE_MAX_BLOCKS 1024
 #define NN_MSE_LOSS_FLOATS (2 + 2 * NN_MSE_MAX_BLOCKS)
@@ -168,7 +174,8 @@ int nn_unet_backward(const nn_unet_cfg* cfg, const float* params, const uint16_t
  * nn_warm_target: target [nsrc][D][H][W] = (tau - 1) * NN_TARGET_SCALE at the
  *   coarse nodes of tau [nsrc][N], 0 outside; mask (may be NULL) 1 inside, 0 outside.
  * nn_warm_init: tau_init [nsrc][N] = 1 + pred / NN_TARGET_SCALE, interpolated
- *   trilinearly from the coarse nodes (held constant past the last one). */
+ *   trilinearly from the coarse nodes (held constant past the last one) and
+ *   clamped to [NN_TAU_INIT_MIN, NN_TAU_INIT_MAX]. */
 int nn_warm_features(const tt_grid* grid, const double* s, const double* xi, const double* eta, int32_t nsrc,
                      const double* src_pos, const double* src_par, int32_t stride, int32_t D, int32_t H, int32_t W,
                      uint16_t* feat, void* stream);

@@ -606,7 +606,8 @@ __global__ void k_warm_target(WarmGrid G, const double* __restrict__ tau, int st
     }
 }
 
-// tau_init = 1 + pred / NN_TARGET_SCALE, trilinear from the coarse nodes
+// tau_init = 1 + pred / NN_TARGET_SCALE, trilinear from the coarse nodes,
+// clamped to [NN_TAU_INIT_MIN, NN_TAU_INIT_MAX] (NaN -> 1)
 __global__ void k_warm_init(WarmGrid G, const float* __restrict__ pred, int stride, int D, int H, int W,
                             double* __restrict__ tau) {
     const int q = blockIdx.y;
@@ -637,7 +638,12 @@ __global__ void k_warm_init(WarmGrid G, const float* __restrict__ pred, int stri
             const int zz = a ? c1[0] : c0[0], yy = b ? c1[1] : c0[1], xx = d ? c1[2] : c0[2];
             v += w * (double)pr[((long long)zz * H + yy) * W + xx];
         }
-        tau[q * N + x] = 1.0 + v / NN_TARGET_SCALE;
+        double t = 1.0 + v / NN_TARGET_SCALE;
+        if (t != t)
+            t = 1.0;
+        else
+            t = fmin(fmax(t, NN_TAU_INIT_MIN), NN_TAU_INIT_MAX);
+        tau[q * N + x] = t;
     }
 }
 
