@@ -67,7 +67,16 @@ typedef struct tt_opts {
                           convergence measure of every iteration of every source
                           (entries past a source's last iteration are left as
                           they were), or NULL */
+    int32_t groups;    /* the sources are split into this many contiguous groups,
+                          each iterated on its own stream so that the groups'
+                          tile-plane launches run concurrently (fewer idle units
+                          at the narrow ends of every sweep and in the
+                          convergence tail); 0 = automatic (nsrc / 32, at most
+                          4); 1 when TT_FLAG_TIME_SWEEPS is set.  Results do not
+                          depend on it. */
 } tt_opts;
+
+#define TT_MAX_GROUPS 8
 
 #define TT_FLAG_TIME_SWEEPS 1
 /* bit 1: capture one iteration (every sweep, boundary and convergence launch)

@@ -17,7 +17,8 @@ class TTGrid(ctypes.Structure):
 
 class TTOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("kappa", ctypes.c_double),
-                ("tile_k", ctypes.c_int32), ("flags", ctypes.c_int32), ("eps_hist", ctypes.c_void_p)]
+                ("tile_k", ctypes.c_int32), ("flags", ctypes.c_int32), ("eps_hist", ctypes.c_void_p),
+                ("groups", ctypes.c_int32)]
 
 
 EXPORTS = ["tt_workspace_size", "tt_source_params", "tt_forward", "tt_sample", "tt_misfit", "tt_adjoint",
@@ -42,6 +43,7 @@ class NNUnetCfg(ctypes.Structure):
 
 TT_FLAG_TIME_SWEEPS = 1
 TT_FLAG_GRAPH = 2
+TT_MAX_GROUPS = 8
 
 _lib = None
 

@@ -26,8 +26,9 @@ def _grid(grid):
     return g
 
 
-def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None, graph=False):
+def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None, graph=False, groups=0):
     o = _lib.TTOpts()
+    o.groups = int(groups)
     o.eps_hist = _dev(eps_hist, "eps_hist").value if eps_hist is not None else None
     o.tol = float(tol)
     o.max_iter = int(max_iter)
@@ -74,11 +75,13 @@ def _N(grid):
     return int(n[0]) * int(n[1]) * int(n[2])
 
 
-def workspace(grid, nsrc, which, tile_k=0, device=None):
-    """Device workspace (uint8 tensor) for forward (0), adjoint (1), sample (2), kernel (3)."""
+def workspace(grid, nsrc, which, tile_k=0, device=None, groups=0, time_sweeps=False):
+    """Device workspace (uint8 tensor) for forward (0), adjoint (1), sample (2), kernel (3);
+    groups / time_sweeps as for the solve that will use it (its size depends on
+    the number of source groups)."""
     lib = _lib.load()
     g = _grid(grid)
-    o = _opts(1e-6, 1, 1.0, tile_k)
+    o = _opts(1e-6, 1, 1.0, tile_k, time_sweeps=time_sweeps, groups=groups)
     nbytes = lib.tt_workspace_size(ctypes.byref(g), int(nsrc), ctypes.byref(o), int(which))
     if nbytes == 0:
         raise ValueError("invalid grid or source count for the workspace")
@@ -99,10 +102,11 @@ def source_params(grid, s, xi, eta, src_pos):
 
 
 def forward(grid, s, xi, eta, src_pos, src_par, tol, max_iter, kappa, tau_init=None, tile_k=0, ws=None,
-            out=None, time_sweeps=False, eps_hist=None, graph=False):
+            out=None, time_sweeps=False, eps_hist=None, graph=False, groups=0):
     """Batched forward solve.  Returns (tau [nsrc, *n], status int32 [nsrc]).
     eps_hist: optional float64 device tensor [nsrc, max_iter] receiving the
-    convergence measure of every iteration."""
+    convergence measure of every iteration.  groups: concurrently iterated
+    source groups (0 = library default; results do not depend on it)."""
     lib = _lib.load()
     N = _N(grid)
     nsrc = int(src_pos.shape[0])
@@ -110,11 +114,11 @@ def forward(grid, s, xi, eta, src_pos, src_par, tol, max_iter, kappa, tau_init=N
     tau = out if out is not None else torch.empty((nsrc,) + tuple(int(v) for v in grid["n"]), dtype=_F64, device=dev)
     status = torch.zeros(nsrc, dtype=torch.int32, device=dev)
     if ws is None:
-        ws = workspace(grid, nsrc, 0, tile_k, dev)
+        ws = workspace(grid, nsrc, 0, tile_k, dev, groups, time_sweeps)
     g = _grid(grid)
     if eps_hist is not None and eps_hist.numel() != nsrc * int(max_iter):
         raise ValueError("eps_hist must have nsrc * max_iter elements")
-    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph)
+    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph, groups)
     ti = _dev(tau_init, "tau_init", numel=nsrc * N) if tau_init is not None else _null()
     _lib.check(lib.tt_forward(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
                               _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
@@ -158,9 +162,9 @@ def misfit(T_rec, T_obs, w=None, pairs=None, wpair=None, alpha=1.0, beta=1.0):
 
 
 def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, kappa, tile_k=0, ws=None,
-            out=None, time_sweeps=False, eps_hist=None, graph=False):
+            out=None, time_sweeps=False, eps_hist=None, graph=False, groups=0):
     """Batched adjoint solve.  Returns (lambda [nsrc, *n], status int32 [nsrc]);
-    eps_hist as for forward."""
+    eps_hist and groups as for forward."""
     lib = _lib.load()
     N = _N(grid)
     nsrc, nrec = int(src_pos.shape[0]), int(rec_pos.shape[0])
@@ -168,11 +172,11 @@ def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, 
     lam = out if out is not None else torch.empty((nsrc,) + tuple(int(v) for v in grid["n"]), dtype=_F64, device=dev)
     status = torch.zeros(nsrc, dtype=torch.int32, device=dev)
     if ws is None:
-        ws = workspace(grid, nsrc, 1, tile_k, dev)
+        ws = workspace(grid, nsrc, 1, tile_k, dev, groups, time_sweeps)
     g = _grid(grid)
     if eps_hist is not None and eps_hist.numel() != nsrc * int(max_iter):
         raise ValueError("eps_hist must have nsrc * max_iter elements")
-    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph)
+    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph, groups)
     _lib.check(lib.tt_adjoint(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
                               _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
                               _dev(src_par, "src_par", numel=3 * nsrc), _dev(tau, "tau", numel=nsrc * N), nrec,

@@ -54,6 +54,9 @@ int check_grid(const tt_grid* g) {
         if (!(g->h[a] > 0.0) || !std::isfinite(g->h[a])) return fail(TT_EINVAL, "grid.h[%d] must be > 0", a);
         if (!std::isfinite(g->o[a])) return fail(TT_EINVAL, "grid.o[%d] not finite", a);
     }
+    // per-node records are addressed with 32-bit indices: n0 (n1 + n2 - 1) n1 < 2^31
+    if ((double)g->n[0] * (g->n[1] + g->n[2] - 1) * g->n[1] >= 2147483647.0)
+        return fail(TT_EINVAL, "grid too large: n0 * (n1 + n2 - 1) * n1 must stay below 2^31");
     if (g->coord == 1) {
         double rmin = g->o[0];
         if (!(rmin > 0.0)) return fail(TT_EINVAL, "spherical grid needs r > 0");
@@ -72,8 +75,25 @@ int check_opts(const tt_opts* o) {
     if (!(o->kappa > 0.0) || !std::isfinite(o->kappa)) return fail(TT_EINVAL, "opts.kappa must be > 0");
     if (o->tile_k < 0 || o->tile_k > tt::kMaxTileK)
         return fail(TT_EINVAL, "opts.tile_k must be in [0, %d]", tt::kMaxTileK);
+    if (o->groups < 0 || o->groups > TT_MAX_GROUPS)
+        return fail(TT_EINVAL, "opts.groups must be in [0, %d]", TT_MAX_GROUPS);
     return TT_OK;
 }
+
+// number of concurrently iterated source groups of a solve
+int groups_of(const tt_opts* o, int nsrc) {
+    int g;
+    if (o && (o->flags & TT_FLAG_TIME_SWEEPS))
+        g = 1;
+    else if (o && o->groups > 0)
+        g = o->groups;
+    else
+        g = nsrc / 32 < 1 ? 1 : (nsrc / 32 > 4 ? 4 : nsrc / 32);
+    return g > nsrc ? nsrc : g;
+}
+
+// first source of group q of G
+int group_begin(int nsrc, int G, int q) { return (int)(((long long)nsrc * q) / G); }
 
 tt::Geo make_geo(const tt_grid* g, int tk) {
     tt::Geo G;
@@ -185,8 +205,29 @@ int tile_k_of(const tt_opts* o, int which) {
 thread_local int* g_pinned = nullptr;
 
 int pinned_counter(int** out) {
-    if (!g_pinned) TT_HIP(hipHostMalloc(reinterpret_cast<void**>(&g_pinned), 2 * sizeof(int), hipHostMallocDefault));
+    if (!g_pinned)
+        TT_HIP(hipHostMalloc(reinterpret_cast<void**>(&g_pinned), 2 * TT_MAX_GROUPS * sizeof(int),
+                             hipHostMallocDefault));
     *out = g_pinned;
+    return TT_OK;
+}
+
+// per-thread, per-device streams of groups 1.. (group 0 runs on the caller's
+// stream); created on first use with default priority and kept
+constexpr int kMaxDevices = 64;
+thread_local hipStream_t g_group_streams[kMaxDevices][TT_MAX_GROUPS] = {};
+
+int group_stream(int q, hipStream_t caller, hipStream_t* out) {
+    if (q == 0) {
+        *out = caller;
+        return TT_OK;
+    }
+    int dev = 0;
+    TT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(TT_EINVAL, "device index %d out of range", dev);
+    hipStream_t& s = g_group_streams[dev][q];
+    if (!s) TT_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    *out = s;
     return TT_OK;
 }
 
@@ -212,55 +253,132 @@ int capture_iteration(Launch launch_one, hipGraphExec_t* exec) {
     return TT_OK;
 }
 
+// One group of a batched solve: its plan, kernel arguments and stream.
+struct Group {
+    tt::Plan P;
+    tt::SweepArgs a;
+    hipStream_t st = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int issued = 0;
+    bool done = false;
+};
+
+// Enqueue iterations of every group on its own stream until no source of any
+// group is active.  Each group's count of active sources after iteration k is
+// copied to pinned host memory; the host waits for it while iteration k+1 of
+// every group is already queued, so no stream idles on the poll.
 template <typename Launch>
-int run_iterations(const tt::Plan& P, hipStream_t st, bool use_graph, Launch launch_one) {
+int run_iterations(std::vector<Group>& gs, bool use_graph, Launch launch_one) {
     int* host = nullptr;
     int rc = pinned_counter(&host);
     if (rc) return rc;
-    hipGraphExec_t exec = nullptr;
-    if (use_graph && (rc = capture_iteration(launch_one, &exec))) return rc;
-    hipEvent_t ev[2];
-    TT_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    TT_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-    int issued = 0;
     int result = TT_OK;
-    for (;;) {
-        if (issued < P.max_iter) {
-            if (exec) {
-                hipError_t e = hipGraphLaunch(exec, st);
-                if (e != hipSuccess) {
-                    result = fail(TT_EHIP, "graph launch: %s", hipGetErrorString(e));
-                    break;
-                }
-            } else {
-                launch_one(st);
-            }
-            hipError_t e = hipMemcpyAsync(&host[issued & 1], P.counter, sizeof(int), hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipEventRecord(ev[issued & 1], st);
-            if (e != hipSuccess) {
-                result = fail(TT_EHIP, "iteration enqueue: %s", hipGetErrorString(e));
-                break;
-            }
-            ++issued;
-        }
-        // wait for the previous iteration's count (or the last one when no more can be issued)
-        const int wait_for = (issued < P.max_iter) ? issued - 2 : issued - 1;
-        if (wait_for < 0) continue;
-        hipError_t e = hipEventSynchronize(ev[wait_for & 1]);
-        if (e != hipSuccess) {
-            result = fail(TT_EHIP, "iteration wait: %s", hipGetErrorString(e));
+    for (auto& g : gs) {
+        if (use_graph && (rc = capture_iteration([&](hipStream_t s_) { launch_one(g, s_); }, &g.exec))) {
+            result = rc;
             break;
         }
-        if (host[wait_for & 1] == 0 || wait_for == P.max_iter - 1) break;
+        if (hipEventCreateWithFlags(&g.ev[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&g.ev[1], hipEventDisableTiming) != hipSuccess) {
+            result = fail(TT_EHIP, "event create failed");
+            break;
+        }
     }
-    hipError_t e = hipStreamSynchronize(st);
-    if (e != hipSuccess && result == TT_OK) result = fail(TT_EHIP, "stream sync: %s", hipGetErrorString(e));
-    e = hipGetLastError();
+    while (result == TT_OK) {
+        for (size_t q = 0; q < gs.size() && result == TT_OK; ++q) {
+            Group& g = gs[q];
+            if (g.done || g.issued >= g.P.max_iter) continue;
+            if (g.exec) {
+                hipError_t e = hipGraphLaunch(g.exec, g.st);
+                if (e != hipSuccess) result = fail(TT_EHIP, "graph launch: %s", hipGetErrorString(e));
+            } else {
+                launch_one(g, g.st);
+            }
+            int* slot = &host[2 * q + (g.issued & 1)];
+            hipError_t e = hipMemcpyAsync(slot, g.P.counter, sizeof(int), hipMemcpyDeviceToHost, g.st);
+            if (e == hipSuccess) e = hipEventRecord(g.ev[g.issued & 1], g.st);
+            if (e != hipSuccess && result == TT_OK) result = fail(TT_EHIP, "iteration enqueue: %s", hipGetErrorString(e));
+            ++g.issued;
+        }
+        bool pending = false;
+        for (size_t q = 0; q < gs.size() && result == TT_OK; ++q) {
+            Group& g = gs[q];
+            if (g.done) continue;
+            // wait for the previous iteration's count (or the last one when no more can be issued)
+            const int wait_for = (g.issued < g.P.max_iter) ? g.issued - 2 : g.issued - 1;
+            if (wait_for < 0) {
+                pending = true;
+                continue;
+            }
+            hipError_t e = hipEventSynchronize(g.ev[wait_for & 1]);
+            if (e != hipSuccess) {
+                result = fail(TT_EHIP, "iteration wait: %s", hipGetErrorString(e));
+                break;
+            }
+            if (host[2 * q + (wait_for & 1)] == 0 || wait_for == g.P.max_iter - 1)
+                g.done = true;
+            else
+                pending = true;
+        }
+        if (!pending) break;
+    }
+    for (auto& g : gs) {
+        hipError_t e = hipStreamSynchronize(g.st);
+        if (e != hipSuccess && result == TT_OK) result = fail(TT_EHIP, "stream sync: %s", hipGetErrorString(e));
+        if (g.ev[0]) (void)hipEventDestroy(g.ev[0]);
+        if (g.ev[1]) (void)hipEventDestroy(g.ev[1]);
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    }
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess && result == TT_OK) result = fail(TT_EHIP, "kernel launch: %s", hipGetErrorString(e));
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
-    if (exec) (void)hipGraphExecDestroy(exec);
     return result;
+}
+
+// Workspace bytes of a solve split into `groups` groups (one region per group).
+size_t grouped_total(const tt::Geo& G, int nsrc, int groups, int which) {
+    size_t total = 0;
+    for (int q = 0; q < groups; ++q) {
+        const int n = group_begin(nsrc, groups, q + 1) - group_begin(nsrc, groups, q);
+        tt::Plan P;
+        fill_plan(P, G, n);
+        total += layout(G, n, P.nslots, which).total;
+    }
+    return total;
+}
+
+// Plans of the groups of a solve, bound to consecutive workspace regions, with
+// their streams made to wait for the work already queued on the caller's stream.
+int make_groups(const tt::Geo& G, int nsrc, int groups, int which, void* ws, size_t ws_bytes, const tt_opts* opts,
+                hipStream_t caller, std::vector<Group>& gs) {
+    const size_t need = grouped_total(G, nsrc, groups, which);
+    if (ws_bytes < need) return fail(TT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    hipEvent_t fork = nullptr;
+    if (groups > 1) {
+        TT_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        TT_HIP(hipEventRecord(fork, caller));
+    }
+    gs.resize(groups);
+    char* base = static_cast<char*>(ws);
+    int rc = TT_OK;
+    for (int q = 0; q < groups && rc == TT_OK; ++q) {
+        Group& g = gs[q];
+        const int n = group_begin(nsrc, groups, q + 1) - group_begin(nsrc, groups, q);
+        fill_plan(g.P, G, n);
+        Layout L = layout(G, n, g.P.nslots, which);
+        bind_workspace(g.P, base, L);
+        base += L.total;
+        g.P.kappa = opts->kappa;
+        g.P.tol = opts->tol;
+        g.P.max_iter = opts->max_iter;
+        rc = group_stream(q, caller, &g.st);
+        if (rc == TT_OK && q > 0) {
+            hipError_t e = hipStreamWaitEvent(g.st, fork, 0);
+            if (e != hipSuccess) rc = fail(TT_EHIP, "stream wait: %s", hipGetErrorString(e));
+        }
+    }
+    if (fork) (void)hipEventDestroy(fork);
+    return rc;
 }
 
 // sweep-kernel timing totals of this thread: [0] forward, [1] adjoint
@@ -309,10 +427,9 @@ int tt_sweep_timing(int32_t which, double* total_ms, int64_t* launches, int32_t 
 
 size_t tt_workspace_size(const tt_grid* grid, int32_t nsrc, const tt_opts* opts, int32_t which) {
     if (check_grid(grid) || nsrc < 1 || which < 0 || which > 3) return 0;
+    if (opts && (opts->groups < 0 || opts->groups > TT_MAX_GROUPS)) return 0;
     tt::Geo G = make_geo(grid, tile_k_of(opts, which));
-    tt::Plan P;
-    fill_plan(P, G, nsrc);
-    return layout(G, nsrc, P.nslots, which).total;
+    return grouped_total(G, nsrc, which <= 1 ? groups_of(opts, nsrc) : 1, which);
 }
 
 int tt_source_params(const tt_grid* grid, const double* s, const double* xi, const double* eta, int32_t nsrc,
@@ -340,26 +457,29 @@ int tt_forward(const tt_grid* grid, const double* s, const double* xi, const dou
     if (nsrc > 65535) return fail(TT_EINVAL, "nsrc > 65535");
     if ((rc = check_ptrs({s, xi, eta, src_pos, src_par, tau, status, ws}))) return rc;
     tt::Geo G = make_geo(grid, tile_k_of(opts, 0));
-    tt::Plan P;
-    fill_plan(P, G, nsrc);
-    if (P.max_plane_tiles > 65535) return fail(TT_EINVAL, "too many tiles per tile-plane; raise opts.tile_k");
-    Layout L = layout(G, nsrc, P.nslots, 0);
-    if (ws_bytes < L.total) return fail(TT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
-    bind_workspace(P, ws, L);
-    P.kappa = opts->kappa;
-    P.tol = opts->tol;
-    P.max_iter = opts->max_iter;
-    P.eps_hist = opts->eps_hist;
-    hipStream_t st = (hipStream_t)stream;
-    tt::launch_tables(P, st);
-    tt::launch_src_setup(P, src_pos, src_par, st);
-    tt::SweepArgs a = tt::make_args(P, s, xi, eta, tau, status);
-    tt::launch_fwd_init(P, a, tau_init, s, xi, eta, st);
-    TT_HIP(hipGetLastError());
+    {
+        tt::Plan P;
+        fill_plan(P, G, 1);
+        if (P.max_plane_tiles > 65535) return fail(TT_EINVAL, "too many tiles per tile-plane; raise opts.tile_k");
+    }
+    const int groups = groups_of(opts, nsrc);
+    hipStream_t caller = (hipStream_t)stream;
+    std::vector<Group> gs;
+    if ((rc = make_groups(G, nsrc, groups, 0, ws, ws_bytes, opts, caller, gs))) return rc;
     std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
-    if (opts->flags & TT_FLAG_TIME_SWEEPS) P.timing = &ev;
+    for (int q = 0; q < groups; ++q) {
+        Group& g = gs[q];
+        const int q0 = group_begin(nsrc, groups, q);
+        g.P.eps_hist = opts->eps_hist ? opts->eps_hist + (long long)q0 * opts->max_iter : nullptr;
+        if (opts->flags & TT_FLAG_TIME_SWEEPS) g.P.timing = &ev;
+        tt::launch_tables(g.P, g.st);
+        tt::launch_src_setup(g.P, src_pos + 3LL * q0, src_par + 3LL * q0, g.st);
+        g.a = tt::make_args(g.P, s, xi, eta, tau + (long long)q0 * G.N, status + q0);
+        tt::launch_fwd_init(g.P, g.a, tau_init ? tau_init + (long long)q0 * G.N : nullptr, s, xi, eta, g.st);
+    }
+    TT_HIP(hipGetLastError());
     const bool graph = (opts->flags & TT_FLAG_GRAPH) && !(opts->flags & TT_FLAG_TIME_SWEEPS);
-    rc = run_iterations(P, st, graph, [&](hipStream_t s_) { tt::launch_fwd_iteration(P, a, s_); });
+    rc = run_iterations(gs, graph, [&](Group& g, hipStream_t s_) { tt::launch_fwd_iteration(g.P, g.a, s_); });
     collect_timing(ev, 0);
     return rc;
 }
@@ -413,26 +533,30 @@ int tt_adjoint(const tt_grid* grid, const double* s, const double* xi, const dou
     if ((rc = check_ptrs({s, xi, eta, src_pos, src_par, tau, lam, status, ws}))) return rc;
     if (nrec > 0 && (!rec_pos || !R)) return fail(TT_EINVAL, "rec_pos/R NULL with nrec > 0");
     tt::Geo G = make_geo(grid, tile_k_of(opts, 1));
-    tt::Plan P;
-    fill_plan(P, G, nsrc);
-    if (P.max_plane_tiles > 65535) return fail(TT_EINVAL, "too many tiles per tile-plane; raise opts.tile_k");
-    Layout L = layout(G, nsrc, P.nslots, 1);
-    if (ws_bytes < L.total) return fail(TT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
-    bind_workspace(P, ws, L);
-    P.kappa = opts->kappa;
-    P.tol = opts->tol;
-    P.max_iter = opts->max_iter;
-    P.eps_hist = opts->eps_hist;
-    hipStream_t st = (hipStream_t)stream;
-    tt::launch_tables(P, st);
-    tt::launch_src_setup(P, src_pos, src_par, st);
-    tt::SweepArgs a = tt::make_args(P, s, xi, eta, lam, status);
-    tt::launch_adj_init(P, a, tau, nrec, rec_pos, R, st);
-    TT_HIP(hipGetLastError());
+    {
+        tt::Plan P;
+        fill_plan(P, G, 1);
+        if (P.max_plane_tiles > 65535) return fail(TT_EINVAL, "too many tiles per tile-plane; raise opts.tile_k");
+    }
+    const int groups = groups_of(opts, nsrc);
+    hipStream_t caller = (hipStream_t)stream;
+    std::vector<Group> gs;
+    if ((rc = make_groups(G, nsrc, groups, 1, ws, ws_bytes, opts, caller, gs))) return rc;
     std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
-    if (opts->flags & TT_FLAG_TIME_SWEEPS) P.timing = &ev;
+    for (int q = 0; q < groups; ++q) {
+        Group& g = gs[q];
+        const int q0 = group_begin(nsrc, groups, q);
+        g.P.eps_hist = opts->eps_hist ? opts->eps_hist + (long long)q0 * opts->max_iter : nullptr;
+        if (opts->flags & TT_FLAG_TIME_SWEEPS) g.P.timing = &ev;
+        tt::launch_tables(g.P, g.st);
+        tt::launch_src_setup(g.P, src_pos + 3LL * q0, src_par + 3LL * q0, g.st);
+        g.a = tt::make_args(g.P, s, xi, eta, lam + (long long)q0 * G.N, status + q0);
+        tt::launch_adj_init(g.P, g.a, tau + (long long)q0 * G.N, nrec, rec_pos, R ? R + (long long)q0 * nrec : nullptr,
+                            g.st);
+    }
+    TT_HIP(hipGetLastError());
     const bool graph = (opts->flags & TT_FLAG_GRAPH) && !(opts->flags & TT_FLAG_TIME_SWEEPS);
-    rc = run_iterations(P, st, graph, [&](hipStream_t s_) { tt::launch_adj_iteration(P, a, s_); });
+    rc = run_iterations(gs, graph, [&](Group& g, hipStream_t s_) { tt::launch_adj_iteration(g.P, g.a, s_); });
     collect_timing(ev, 1);
     return rc;
 }

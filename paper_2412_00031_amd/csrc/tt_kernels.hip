@@ -27,6 +27,8 @@
 // per-tile partial sums in a fixed order (bitwise reproducible run to run).
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "tt_internal.h"
 
 namespace tt {
@@ -86,7 +88,6 @@ __device__ __forceinline__ bool on_bnd(const Geo& G, int a, int idx) { return id
 // tile row (fixed i, consecutive j) satisfy j + rho k = const with
 // rho = sigma_1 sigma_2, so records stored as [i][w = j + rho k][j] put those 8
 // lanes' records next to each other.  fam 0: rho = +1, fam 1: rho = -1.
-__device__ __forceinline__ int sweep_family(int dir) { return ((dir >> 1) ^ dir) & 1; }
 
 __device__ __forceinline__ long long skew_idx(const Geo& G, int fam, int i, int j, int k) {
     const int w = fam == 0 ? j + k : j - k + (G.n[2] - 1);
@@ -244,38 +245,49 @@ __global__ void k_solve_init(SweepArgs a, const double* __restrict__ init, doubl
 }
 
 // --------------------------------------------------------- sweep tiles
-// Lane-constant context of one tile of one source in one directional sweep.
-struct TileCtx {
-    int TI, TJ, TK, lane, li, lj, s0, s1, s2, ext_i, ext_j, k0p, k1p, kp0, kbase, nsteps;
-    bool colv, fcol;
-    int i, j;
-    long long col, di, dj;
+// Lane-constant context of one tile of one source in directional sweep DIR
+// (signs s_a = -1 where bit 2 - a of DIR is set; compile-time, so every
+// sign-dependent index folds to adds).
+template <int DIR>
+struct Dir {
+    static constexpr int s0 = (DIR & 4) ? -1 : 1;
+    static constexpr int s1 = (DIR & 2) ? -1 : 1;
+    static constexpr int s2 = (DIR & 1) ? -1 : 1;
+    static constexpr int fam = ((DIR >> 1) ^ DIR) & 1;  // row-coalesced layout of this sweep
 };
 
-__device__ __forceinline__ TileCtx tile_ctx(const Geo& G, const Src& S, int dir, int plane) {
+struct TileCtx {
+    int TI, TJ, TK, lane, li, lj, ext_i, ext_j, k0p, k1p, kp0, kbase, nsteps;
+    bool colv, fcol;
+    int i, j;
+    int rbase, rstep;  // record index of this lane's column at k' = 0, and its change per k'
+};
+
+template <int DIR>
+__device__ __forceinline__ TileCtx tile_ctx(const Geo& G, const Src& S, int plane) {
+    using D = Dir<DIR>;
     TileCtx c;
     tile_decode(G, plane, blockIdx.y, c.TI, c.TJ, c.TK);
     c.lane = threadIdx.x;
     c.li = c.lane >> 3;
     c.lj = c.lane & 7;
-    c.s0 = (dir & 4) ? -1 : 1;
-    c.s1 = (dir & 2) ? -1 : 1;
-    c.s2 = (dir & 1) ? -1 : 1;
     c.ext_i = min(kBI, G.m[0] - c.TI * kBI);
     c.ext_j = min(kBJ, G.m[1] - c.TJ * kBJ);
     c.k0p = c.TK * G.tk;
     c.k1p = min(c.k0p + G.tk, G.m[2]);
     c.colv = c.li < c.ext_i && c.lj < c.ext_j;
     const int ip = c.TI * kBI + (c.colv ? c.li : 0), jp = c.TJ * kBJ + (c.colv ? c.lj : 0);
-    c.i = c.s0 > 0 ? 1 + ip : G.n[0] - 2 - ip;
-    c.j = c.s1 > 0 ? 1 + jp : G.n[1] - 2 - jp;
-    c.col = nidx(G, c.i, c.j, 0);
-    c.di = c.s0 * G.si;
-    c.dj = c.s1 * G.sj;
+    c.i = D::s0 > 0 ? 1 + ip : G.n[0] - 2 - ip;
+    c.j = D::s1 > 0 ? 1 + jp : G.n[1] - 2 - jp;
     c.fcol = (unsigned)(c.i - S.fb[0]) <= 1u && (unsigned)(c.j - S.fb[1]) <= 1u;
     c.nsteps = (c.k1p - c.k0p) + c.ext_i - 1 + c.ext_j - 1;
     c.kp0 = c.k0p - c.li - c.lj;               // this lane's k' at step 0
-    c.kbase = c.s2 > 0 ? 1 : G.n[2] - 2;       // absolute k = kbase + s2 * k'
+    c.kbase = D::s2 > 0 ? 1 : G.n[2] - 2;      // absolute k = kbase + s2 * k'
+    // record index ((i W + w) n1 + j) with w = j + k (family 0) or j - k + n2 - 1
+    // (family 1), k = kbase + s2 k': linear in k' with slope s1 n1 in both families
+    const int w0 = D::fam == 0 ? c.j + c.kbase : c.j - c.kbase + G.n[2] - 1;
+    c.rbase = (c.i * G.W + w0) * G.n[1] + c.j;
+    c.rstep = D::s1 * G.n[1];
     return c;
 }
 
@@ -287,37 +299,102 @@ __device__ __forceinline__ TileCtx tile_ctx(const Geo& G, const Src& S, int dir,
 // contiguous column segments.
 constexpr int kTC = kBI + 2;
 
-__device__ __forceinline__ int stage_abs(const Geo& G, int a, int T, int sgn, int ci) {
-    const int p = T * kBI + ci - 1;  // sweep-relative coordinate, -1 .. ext
-    return sgn > 0 ? 1 + p : G.n[a] - 2 - p;
-}
-
 // Staging covers the tile's columns as one flat list of (column, k) elements
-// spread over all 64 lanes.  Loads are issued unconditionally from addresses
-// that are always valid (clamped), kStageBatch at a time, and only the LDS
-// writes are predicated: a load inside a divergent branch would make the
-// compiler wait for it before the branch joins, serialising the staging.
+// spread over all 64 lanes; each lane walks its elements with running indices
+// (no division or multiplication per element).  Loads are issued
+// unconditionally from addresses that are always valid (clamped), kStageBatch
+// at a time, and only the LDS writes are predicated: a load inside a
+// divergent branch would make the compiler wait for it before the branch
+// joins, serialising the staging.
 constexpr int kStageBatch = 16;
 
-__device__ __forceinline__ void stage_tile(const Geo& G, const TileCtx& c, const double* __restrict__ fld,
+// Absolute index along axis a of staged column/row ci (0 = upstream halo):
+// origin + sgn * ci.
+template <int SGN>
+__device__ __forceinline__ int stage_origin(const Geo& G, int a, int T) {
+    return SGN > 0 ? T * kBI : G.n[a] - 1 - T * kBI;
+}
+
+template <int DIR>
+__device__ __forceinline__ void stage_tile_incr(const Geo& G, const TileCtx& c, const double* __restrict__ fld,
                                            double* lds, int L) {
+    using D = Dir<DIR>;
     const int Lk = c.k1p - c.k0p + 2;                 // staged k entries per column
     const int nj = c.ext_j + 2, ncol = (c.ext_i + 2) * nj;
     const int total = ncol * Lk;
-    int col = c.lane / Lk, kk = c.lane - col * Lk;    // element e = lane + 64 r
+    const long long si = D::s0 * G.si, sj = D::s1 * G.sj;
+    const long long base = nidx(G, stage_origin<D::s0>(G, 0, c.TI), stage_origin<D::s1>(G, 1, c.TJ),
+                                c.kbase + D::s2 * (c.k0p - 1));
+    // element e = lane + 64 r  <->  column col = e / Lk = ci nj + cj, kk = e % Lk
+    int col = c.lane / Lk, kk = c.lane - col * Lk;
+    int ci = col / nj, cj = col - ci * nj;
+    long long goff = ci * si + cj * sj + D::s2 * kk;  // field offset from base
+    int loff = (ci * kTC + cj) * L + kk;              // LDS offset
+    const int dcol = 64 / Lk, dkk = 64 - dcol * Lk;
+    const long long g_step = dcol * sj + D::s2 * dkk, g_kwrap = sj - D::s2 * Lk, g_jwrap = si - nj * sj;
+    const int l_step = dcol * L + dkk, l_kwrap = L - Lk, l_jwrap = (kTC - nj) * L;
+    for (int e0 = 0; e0 < total; e0 += 64 * kStageBatch) {
+        double v[kStageBatch];
+        int lo[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const bool ok = col < ncol;
+            v[u] = fld[base + (ok ? goff : 0)];
+            lo[u] = ok ? loff : -1;
+            col += dcol;
+            cj += dcol;
+            kk += dkk;
+            goff += g_step;
+            loff += l_step;
+            const bool kw = kk >= Lk;  // selects, not branches
+            kk -= kw ? Lk : 0;
+            col += kw;
+            cj += kw;
+            goff += kw ? g_kwrap : 0;
+            loff += kw ? l_kwrap : 0;
+            if (dcol < nj) {  // wave-uniform: at most one row wrap
+                const bool jw = cj >= nj;
+                cj -= jw ? nj : 0;
+                goff += jw ? g_jwrap : 0;
+                loff += jw ? l_jwrap : 0;
+            } else {
+                while (cj >= nj) {
+                    cj -= nj;
+                    goff += g_jwrap;
+                    loff += l_jwrap;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u)
+            if (lo[u] >= 0) lds[lo[u]] = v[u];
+    }
+}
+
+// Same staging with each element's column decoded by division: fewer live
+// scalar values than the running-index form (the forward kernel, short of
+// scalar registers, spills with that form), more vector registers.
+template <int DIR>
+__device__ __forceinline__ void stage_tile_div(const Geo& G, const TileCtx& c, const double* __restrict__ fld,
+                                               double* lds, int L) {
+    using D = Dir<DIR>;
+    const int Lk = c.k1p - c.k0p + 2;
+    const int nj = c.ext_j + 2, ncol = (c.ext_i + 2) * nj;
+    const int total = ncol * Lk;
+    const long long si = D::s0 * G.si, sj = D::s1 * G.sj;
+    const long long base = nidx(G, stage_origin<D::s0>(G, 0, c.TI), stage_origin<D::s1>(G, 1, c.TJ),
+                                c.kbase + D::s2 * (c.k0p - 1));
+    int col = c.lane / Lk, kk = c.lane - col * Lk;
     const int dcol = 64 / Lk, dkk = 64 - dcol * Lk;
     for (int e0 = 0; e0 < total; e0 += 64 * kStageBatch) {
         double v[kStageBatch];
-        int ci_[kStageBatch], cj_[kStageBatch], kk_[kStageBatch];
+        int lo[kStageBatch];
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u) {
             const int cc = min(col, ncol - 1);
             const int ci = cc / nj, cj = cc - ci * nj;
-            ci_[u] = ci;
-            cj_[u] = cj;
-            kk_[u] = col < ncol ? kk : -1;
-            const int ka = c.kbase + c.s2 * (c.k0p - 1 + kk);
-            v[u] = fld[nidx(G, stage_abs(G, 0, c.TI, c.s0, ci), stage_abs(G, 1, c.TJ, c.s1, cj), ka)];
+            v[u] = fld[base + ci * si + cj * sj + D::s2 * kk];
+            lo[u] = col < ncol ? (ci * kTC + cj) * L + kk : -1;
             col += dcol;
             kk += dkk;
             if (kk >= Lk) {
@@ -327,30 +404,53 @@ __device__ __forceinline__ void stage_tile(const Geo& G, const TileCtx& c, const
         }
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u)
-            if (kk_[u] >= 0) lds[(ci_[u] * kTC + cj_[u]) * L + kk_[u]] = v[u];
+            if (lo[u] >= 0) lds[lo[u]] = v[u];
     }
 }
 
+template <int DIR>
 __device__ __forceinline__ void unstage_tile(const Geo& G, const TileCtx& c, double* __restrict__ fld,
                                              const double* lds, int L) {
+    using D = Dir<DIR>;
     const int ek = c.k1p - c.k0p;
-    const int n = c.ext_i * c.ext_j, total = n * ek;
-    int col = c.lane / ek, kk = c.lane - col * ek;    // kk = k' - k0' here (0 .. ek-1)
+    const int nj = c.ext_j, n = c.ext_i * nj, total = n * ek;
+    const long long si = D::s0 * G.si, sj = D::s1 * G.sj;
+    const long long base = nidx(G, stage_origin<D::s0>(G, 0, c.TI) + D::s0, stage_origin<D::s1>(G, 1, c.TJ) + D::s1,
+                                c.kbase + D::s2 * c.k0p);
+    // element e <-> column col = e / ek = li nj + lj, kk = e % ek (kk = k' - k0')
+    int col = c.lane / ek, kk = c.lane - col * ek;
+    int li = col / nj, lj = col - li * nj;
+    long long goff = li * si + lj * sj + D::s2 * kk;
+    int loff = ((li + 1) * kTC + lj + 1) * L + kk + 1;
     const int dcol = 64 / ek, dkk = 64 - dcol * ek;
+    const long long g_step = dcol * sj + D::s2 * dkk, g_kwrap = sj - D::s2 * ek, g_jwrap = si - nj * sj;
+    const int l_step = dcol * L + dkk, l_kwrap = L - ek, l_jwrap = (kTC - nj) * L;
     for (int e0 = 0; e0 < total; e0 += 64 * kStageBatch) {
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u) {
-            if (col < n) {
-                const int li = col / c.ext_j, lj = col - li * c.ext_j;
-                const int ka = c.kbase + c.s2 * (c.k0p + kk);
-                fld[nidx(G, stage_abs(G, 0, c.TI, c.s0, li + 1), stage_abs(G, 1, c.TJ, c.s1, lj + 1), ka)] =
-                    lds[((li + 1) * kTC + lj + 1) * L + kk + 1];
-            }
+            if (col < n) fld[base + goff] = lds[loff];
             col += dcol;
+            lj += dcol;
             kk += dkk;
-            if (kk >= ek) {
-                kk -= ek;
-                ++col;
+            goff += g_step;
+            loff += l_step;
+            const bool kw = kk >= ek;
+            kk -= kw ? ek : 0;
+            col += kw;
+            lj += kw;
+            goff += kw ? g_kwrap : 0;
+            loff += kw ? l_kwrap : 0;
+            if (dcol < nj) {
+                const bool jw = lj >= nj;
+                lj -= jw ? nj : 0;
+                goff += jw ? g_jwrap : 0;
+                loff += jw ? l_jwrap : 0;
+            } else {
+                while (lj >= nj) {
+                    lj -= nj;
+                    goff += g_jwrap;
+                    loff += l_jwrap;
+                }
             }
         }
     }
@@ -366,38 +466,39 @@ struct FwdSlot {
 };
 
 // unconditional: k' is clamped into the tile, so the address is always valid
-__device__ __forceinline__ void fwd_fetch(const SweepArgs& a, const TileCtx& c, const double* __restrict__ mdl,
-                                          int fam, int t, FwdSlot& r) {
+template <int DIR>
+__device__ __forceinline__ void fwd_fetch(const TileCtx& c, const double* __restrict__ mdl,
+                                          const double2* __restrict__ t2, int t, FwdSlot& r) {
     const int kp = min(max(c.kp0 + t, c.k0p), c.k1p - 1);
-    const int ka = c.kbase + c.s2 * kp;
-    const double2* m = reinterpret_cast<const double2*>(mdl + skew_idx(a.G, fam, c.i, c.j, ka) * 4);
+    const double2* m = reinterpret_cast<const double2*>(mdl + (c.rbase + c.rstep * kp) * 4LL);
     const double2 m0 = m[0], m1 = m[1];
     r.sx = m0.x;
     r.xi = m0.y;
     r.eta = m1.x;
-    const double2 t2 = a.T.t2[ka];
-    r.c2 = t2.x;
-    r.s2 = t2.y;
+    const double2 tv = t2[c.kbase + Dir<DIR>::s2 * kp];
+    r.c2 = tv.x;
+    r.s2 = tv.y;
 }
 
-template <int COORD>
-__global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int dir, int plane) {
+template <int COORD, int DIR>
+__global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane) {
+    using D = Dir<DIR>;
     extern __shared__ double lds[];
     const int src = blockIdx.x;
     if (!a.active[src]) return;
     const Geo& G = a.G;
     const Src S = a.src[src];
-    const TileCtx c = tile_ctx(G, S, dir, plane);
+    const TileCtx c = tile_ctx<DIR>(G, S, plane);
     const Col cl = make_col(G, a.T, c.i, c.j);
     double* __restrict__ fld = a.field + (long long)src * G.N;
-    const int fam = sweep_family(dir);
-    const double* __restrict__ mdl = a.model + (long long)fam * G.S * 4;
+    const double* __restrict__ mdl = a.model + (long long)D::fam * G.S * 4;
+    const double2* __restrict__ t2 = a.T.t2;
     const int L = G.tk + 2;
 
     FwdSlot ring[kPre];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) fwd_fetch(a, c, mdl, fam, u, ring[u]);
-    stage_tile(G, c, fld, lds, L);
+    for (int u = 0; u < kPre; ++u) fwd_fetch<DIR>(c, mdl, t2, u, ring[u]);
+    stage_tile_div<DIR>(G, c, fld, lds, L);
     __syncthreads();
 
     const int own = ((c.li + 1) * kTC + c.lj + 1) * L;
@@ -413,32 +514,32 @@ __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int dir, int plan
                 const int kp = c.kp0 + t;
                 if (c.colv && kp >= c.k0p && kp < c.k1p) {
                     const int kk = kp - c.k0p + 1;
-                    const int ka = c.kbase + c.s2 * kp;
+                    const int ka = c.kbase + D::s2 * kp;
                     if (!(c.fcol && (unsigned)(ka - S.fb[2]) <= 1u)) {
                         // sweep-relative neighbours: "up" = already updated this sweep
                         const double cur = lds[own + kk];
                         const double up_i = lds[oim + kk], dn_i = lds[oip + kk];
                         const double up_j = lds[own - L + kk], dn_j = lds[own + L + kk];
                         const double up_k = lds[own + kk - 1], dn_k = lds[own + kk + 1];
-                        const double m0 = c.s0 > 0 ? up_i : dn_i, p0 = c.s0 > 0 ? dn_i : up_i;
-                        const double m1 = c.s1 > 0 ? up_j : dn_j, p1 = c.s1 > 0 ? dn_j : up_j;
-                        const double m2 = c.s2 > 0 ? up_k : dn_k, p2 = c.s2 > 0 ? dn_k : up_k;
+                        const double m0 = D::s0 > 0 ? up_i : dn_i, p0 = D::s0 > 0 ? dn_i : up_i;
+                        const double m1 = D::s1 > 0 ? up_j : dn_j, p1 = D::s1 > 0 ? dn_j : up_j;
+                        const double m2 = D::s2 > 0 ? up_k : dn_k, p2 = D::s2 > 0 ? dn_k : up_k;
                         const double nv = lf_update<COORD>(G, S, cl, r.c2, r.s2, a.kappa, r.sx, r.xi, r.eta, cur, m0,
                                                            p0, m1, p1, m2, p2);
                         lds[own + kk] = nv;
                         eps += fabs(nv - cur);
                     }
                 }
-                fwd_fetch(a, c, mdl, fam, t + kPre, r);
+                fwd_fetch<DIR>(c, mdl, t2, t + kPre, r);
             }
         }
     }
     __syncthreads();
-    unstage_tile(G, c, fld, lds, L);
+    unstage_tile<DIR>(G, c, fld, lds, L);
     eps = wave_sum(eps);
     if (c.lane == 0) {
         const int tile_id = (c.TI * G.nt[1] + c.TJ) * G.nt[2] + c.TK;
-        a.part[(long long)src * a.nslots + dir * G.ntiles + tile_id] = eps;
+        a.part[(long long)src * a.nslots + DIR * G.ntiles + tile_id] = eps;
     }
 }
 
@@ -643,11 +744,10 @@ struct AdjSlot {
     double r[8];  // coefficient record of the node at k'
 };
 
-__device__ __forceinline__ void adj_fetch(const Geo& G, const TileCtx& c, const double* __restrict__ cf, int fam,
-                                          int t, AdjSlot& r) {
+template <int DIR>
+__device__ __forceinline__ void adj_fetch(const TileCtx& c, const double* __restrict__ cf, int t, AdjSlot& r) {
     const int kp = min(max(c.kp0 + t, c.k0p), c.k1p - 1);
-    const int ka = c.kbase + c.s2 * kp;
-    const double2* rc = reinterpret_cast<const double2*>(cf + skew_idx(G, fam, c.i, c.j, ka) * 8);
+    const double2* rc = reinterpret_cast<const double2*>(cf + (c.rbase + c.rstep * kp) * 8LL);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const double2 v = rc[q];
@@ -656,24 +756,24 @@ __device__ __forceinline__ void adj_fetch(const Geo& G, const TileCtx& c, const 
     }
 }
 
-template <int COORD>
-__global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int dir, int plane) {
+template <int COORD, int DIR>
+__global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane) {
+    using D = Dir<DIR>;
     extern __shared__ double lds[];
     const int src = blockIdx.x;
     if (!a.active[src]) return;
     const Geo& G = a.G;
     const Src S = a.src[src];
-    const TileCtx c = tile_ctx(G, S, dir, plane);
+    const TileCtx c = tile_ctx<DIR>(G, S, plane);
     double* __restrict__ fld = a.field + (long long)src * G.N;
-    const int fam = sweep_family(dir);
-    const double* __restrict__ cf = a.coef + ((long long)src * 2 + fam) * G.S * 8;
-    const bool last = (dir == 7);
+    const double* __restrict__ cf = a.coef + ((long long)src * 2 + D::fam) * G.S * 8;
+    constexpr bool last = (DIR == 7);
     const int L = G.tk + 2;
 
     AdjSlot ring[kPreAdj];
 #pragma unroll
-    for (int u = 0; u < kPreAdj; ++u) adj_fetch(G, c, cf, fam, u, ring[u]);
-    stage_tile(G, c, fld, lds, L);
+    for (int u = 0; u < kPreAdj; ++u) adj_fetch<DIR>(c, cf, u, ring[u]);
+    stage_tile_incr<DIR>(G, c, fld, lds, L);
     __syncthreads();
 
     const int own = ((c.li + 1) * kTC + c.lj + 1) * L;
@@ -689,15 +789,15 @@ __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int dir, int plan
                 const int kp = c.kp0 + t;
                 if (c.colv && kp >= c.k0p && kp < c.k1p) {
                     const int kk = kp - c.k0p + 1;
-                    const int ka = c.kbase + c.s2 * kp;
+                    const int ka = c.kbase + D::s2 * kp;
                     if (!(c.fcol && (unsigned)(ka - S.fb[2]) <= 1u)) {
                         const double cur = lds[own + kk];
                         const double up_i = lds[oim + kk], dn_i = lds[oip + kk];
                         const double up_j = lds[own - L + kk], dn_j = lds[own + L + kk];
                         const double up_k = lds[own + kk - 1], dn_k = lds[own + kk + 1];
-                        const double m0 = c.s0 > 0 ? up_i : dn_i, p0 = c.s0 > 0 ? dn_i : up_i;
-                        const double m1 = c.s1 > 0 ? up_j : dn_j, p1 = c.s1 > 0 ? dn_j : up_j;
-                        const double m2 = c.s2 > 0 ? up_k : dn_k, p2 = c.s2 > 0 ? dn_k : up_k;
+                        const double m0 = D::s0 > 0 ? up_i : dn_i, p0 = D::s0 > 0 ? dn_i : up_i;
+                        const double m1 = D::s1 > 0 ? up_j : dn_j, p1 = D::s1 > 0 ? dn_j : up_j;
+                        const double m2 = D::s2 > 0 ? up_k : dn_k, p2 = D::s2 > 0 ? dn_k : up_k;
                         double acc = r.r[7];
                         acc -= r.r[0] * p0;
                         acc -= r.r[1] * m0;
@@ -711,17 +811,17 @@ __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int dir, int plan
                         if (last) asum += fabs(nv);
                     }
                 }
-                adj_fetch(G, c, cf, fam, t + kPreAdj, r);
+                adj_fetch<DIR>(c, cf, t + kPreAdj, r);
             }
         }
     }
     __syncthreads();
-    unstage_tile(G, c, fld, lds, L);
+    unstage_tile<DIR>(G, c, fld, lds, L);
     dsum = wave_sum(dsum);
     asum = wave_sum(asum);
     if (c.lane == 0) {
         const int tile_id = (c.TI * G.nt[1] + c.TJ) * G.nt[2] + c.TK;
-        a.part[(long long)src * a.nslots + dir * G.ntiles + tile_id] = dsum;
+        a.part[(long long)src * a.nslots + DIR * G.ntiles + tile_id] = dsum;
         if (last) a.part2[(long long)src * a.nslots + tile_id] = asum;
     }
 }
@@ -965,17 +1065,38 @@ struct TimedLaunch {
     }
 };
 
+// Sweep kernels are instantiated per coordinate system and direction.
+typedef void (*SweepFn)(SweepArgs, int);
+
+template <int COORD, int... DS>
+constexpr SweepFn pick_fwd(int d, std::integer_sequence<int, DS...>) {
+    SweepFn t[] = {k_fwd_sweep<COORD, DS>...};
+    return t[d];
+}
+
+template <int COORD, int... DS>
+constexpr SweepFn pick_adj(int d, std::integer_sequence<int, DS...>) {
+    SweepFn t[] = {k_adj_sweep<COORD, DS>...};
+    return t[d];
+}
+
+SweepFn fwd_sweep_fn(int coord, int d) {
+    return coord == 1 ? pick_fwd<1>(d, std::make_integer_sequence<int, 8>{})
+                      : pick_fwd<0>(d, std::make_integer_sequence<int, 8>{});
+}
+
+SweepFn adj_sweep_fn(int coord, int d) {
+    return coord == 1 ? pick_adj<1>(d, std::make_integer_sequence<int, 8>{})
+                      : pick_adj<0>(d, std::make_integer_sequence<int, 8>{});
+}
+
 void launch_fwd_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
     for (int d = 0; d < 8; ++d) {
         {
         TimedLaunch tl(P, st, P.nplanes);
-        for (int p = 0; p < P.nplanes; ++p) {
-            const dim3 grid(P.nsrc, P.plane_count[p]);
-            if (P.G.coord == 1)
-                hipLaunchKernelGGL(k_fwd_sweep<1>, grid, dim3(64), tile_lds_bytes(P.G), st, a, d, p);
-            else
-                hipLaunchKernelGGL(k_fwd_sweep<0>, grid, dim3(64), tile_lds_bytes(P.G), st, a, d, p);
-        }
+        const SweepFn fn = fwd_sweep_fn(P.G.coord, d);
+        for (int p = 0; p < P.nplanes; ++p)
+            hipLaunchKernelGGL(fn, dim3(P.nsrc, P.plane_count[p]), dim3(64), tile_lds_bytes(P.G), st, a, p);
         }
         hipLaunchKernelGGL(k_fwd_bnd, dim3(P.nbblocks, P.nsrc), dim3(kBndThreads), 0, st, a, d);
     }
@@ -1000,13 +1121,9 @@ void launch_adj_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
     for (int d = 0; d < 8; ++d) {
         {
         TimedLaunch tl(P, st, P.nplanes);
-        for (int p = 0; p < P.nplanes; ++p) {
-            const dim3 grid(P.nsrc, P.plane_count[p]);
-            if (P.G.coord == 1)
-                hipLaunchKernelGGL(k_adj_sweep<1>, grid, dim3(64), tile_lds_bytes(P.G), st, a, d, p);
-            else
-                hipLaunchKernelGGL(k_adj_sweep<0>, grid, dim3(64), tile_lds_bytes(P.G), st, a, d, p);
-        }
+        const SweepFn fn = adj_sweep_fn(P.G.coord, d);
+        for (int p = 0; p < P.nplanes; ++p)
+            hipLaunchKernelGGL(fn, dim3(P.nsrc, P.plane_count[p]), dim3(64), tile_lds_bytes(P.G), st, a, p);
         }
         hipLaunchKernelGGL(k_adj_bnd, dim3(P.nbblocks, P.nsrc), dim3(kBndThreads), 0, st, a, d);
     }
