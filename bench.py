@@ -167,7 +167,8 @@ def main():
     # observations: forward solve in the independent "true" model (untimed)
     st_, xt_, et_ = t(wl["s_true"]), t(wl["xi_true"]), t(wl["eta_true"])
     par_t = api.source_params(g, st_, xt_, et_, src)
-    tau_t, _ = api.forward(g, st_, xt_, et_, src, par_t, tol, args.max_iter, kappa, tile_k=args.tile_k)
+    tau_t, _ = api.forward(g, st_, xt_, et_, src, par_t, tol, args.max_iter, kappa, tile_k=args.tile_k,
+                           groups=args.groups)
     T_obs = api.sample(g, src, par_t, tau_t, rec)
     del tau_t
     torch.cuda.synchronize()
