@@ -194,6 +194,19 @@ def node_volume(grid):
     return V
 
 
+def kernel_density(grid, s, dens, grad, eps, zeta):
+    """(K [3, n], Kd [n]): paper kernels K_s, K_xi, K_eta of the summed discrete
+    gradients grad [3, n], normalised by the kernel density Kd made from dens,
+    the summed s-gradient of the R = 1 adjoint fields (Eqs. (18)-(19)); see
+    oracle.c."""
+    n, coord, o, h = _grid_args(grid)
+    K = np.zeros((3,) + _shape(grid))
+    Kd = np.zeros(_shape(grid))
+    lib().tto_kernel_density(_i(n), coord, _d(o), _d(h), _d(_f64(s)), _d(_f64(dens)), _d(_f64(grad)),
+                             ctypes.c_double(eps), ctypes.c_double(zeta), _d(K), _d(Kd))
+    return K, Kd
+
+
 def solve_source(grid, s, xi, eta, src_pos, src_par, kappa, rec_pos, T_obs=None, R=None,
                  tol=1e-6, adj_tol=None, max_iter=2000, w=None):
     """Forward + sample + (misfit) + adjoint + kernel for one source (chi_t only).

@@ -57,6 +57,9 @@
  *        directions; after each sweep a transposed boundary pass in reverse group
  *        order (a* = 2, 1, 0); lambda = 0 on F (the fixed rows couple to nothing).
  *        eps = sum|d lambda| / max(sum|lambda|, 1e-300).
+ *   (R11) kernel density (Eqs. (18)-(19)): the adjoint field of Eq. (5) is
+ *        P = (d chi / d s) / (s V) with V the trapezoidal node volume, since
+ *        K_s = s (d chi / d s) / V (Eq. (9)) and K_s = P s^2.
  */
 #include <math.h>
 #include <stddef.h>
@@ -828,4 +831,34 @@ void tto_node_volume(const int* n, int coord, const double* o, const double* h, 
                 if (k == 0 || k == g.n[2] - 1) v *= 0.5;
                 V[IDX(&g, i, j, k)] = v;
             }
+}
+
+/* Kernel-density normalisation (Eqs. (18)-(19)).
+ * The density of the event kernels is the adjoint field P_hat of Eq. (5) with
+ * every adjoint source R = 1, summed over sources.  In this discretisation the
+ * s-gradient of a source's misfit is its adjoint field at the interior
+ * non-fixed nodes (zero elsewhere: the model enters only the interior
+ * equations), and K_s = s (d chi / d s) / V (Eq. (9)) with K_s = P s^2, so
+ * P = (d chi / d s) / (s V).  Given dens = the s-gradient summed over sources of
+ * the R = 1 adjoint fields, and grad [3][N] = the summed discrete gradients of
+ * the misfit, per node x:
+ *   Kd(x)   = dens(x) / (s(x) V(x))
+ *   K_s(x)  = s(x) grad_s(x) / V(x) / (Kd(x) + eps)^zeta
+ *   K_xi(x) = grad_xi(x) / V(x) / (Kd(x) + eps)^zeta,  K_eta likewise. */
+void tto_kernel_density(const int* n, int coord, const double* o, const double* h, const double* s,
+                        const double* dens, const double* grad, double eps, double zeta, double* K, double* Kd) {
+    OGrid g;
+    grid_init(&g, n, coord, o, h);
+    const long N = (long)g.n[0] * g.n[1] * g.n[2];
+    double* V = (double*)malloc(sizeof(double) * (size_t)N);
+    tto_node_volume(n, coord, o, h, V);
+    for (long x = 0; x < N; ++x) {
+        const double d = dens[x] / (s[x] * V[x]);
+        const double w = pow(d + eps, zeta);
+        Kd[x] = d;
+        K[x] = s[x] * grad[x] / V[x] / w;
+        K[N + x] = grad[N + x] / V[x] / w;
+        K[2 * N + x] = grad[2 * N + x] / V[x] / w;
+    }
+    free(V);
 }

@@ -381,3 +381,49 @@ def test_mirror_symmetry():
     tau, it, conv, _ = O.forward(g, s, xi, eta, src, par, 1.1, 1e-14, 2000)
     assert conv
     assert np.abs(tau - tau[:, :, ::-1]).max() < 1e-11
+
+
+# ------------------------------------------------- kernel-density normalisation
+def test_node_volume_integrates_domain():
+    """Sum of the trapezoidal node volumes: exact for a Cartesian box; second
+    order against the closed-form volume of a spherical sector,
+    (r1^3 - r0^3)/3 (sin th1 - sin th0)(ph1 - ph0)."""
+    g = W.cartesian_grid(11, 0.7)
+    assert abs(O.node_volume(g).sum() - 7.0 ** 3) < 1e-12 * 7.0 ** 3
+    errs = []
+    for n in (11, 21, 41):
+        g = W.spherical_grid(n, 40.0, 3.0)
+        ax = W.axes(g)
+        exact = ((ax[0][-1] ** 3 - ax[0][0] ** 3) / 3.0 * (math.sin(ax[1][-1]) - math.sin(ax[1][0]))
+                 * (ax[2][-1] - ax[2][0]))
+        errs.append(abs(O.node_volume(g).sum() - exact) / exact)
+    assert errs[0] < 1e-3 and errs[1] < errs[0] / 3.5 and errs[2] < errs[1] / 3.5, errs
+
+
+def test_kernel_density_properties(tiny_case):
+    """Density adjoint (every R = 1): nonnegative (J^T is an M-matrix: positive
+    diagonal, non-positive couplings), linear in R, nonzero at every interior
+    node reached from a receiver; normalising the R = 1 kernel K_s = P s^2 by its
+    own density (zeta = 1, eps = 0) leaves s^2; zeta = 0 is the plain conversion
+    K_s = s grad / V, K_xi = grad_xi / V."""
+    wl, src, par, tau = tiny_case
+    g, s, xi, eta, rec = wl["grid"], wl["s"], wl["xi"], wl["eta"], wl["rec"]
+    ones = np.ones(len(rec))
+    lam1, _, conv, _ = O.adjoint(g, s, xi, eta, src, par, wl["kappa"], tau, O.adjoint_rhs(g, src, par, rec, ones),
+                                 1e-15, 5000)
+    lam2, _, _, _ = O.adjoint(g, s, xi, eta, src, par, wl["kappa"], tau,
+                              O.adjoint_rhs(g, src, par, rec, 2.0 * ones), 1e-15, 5000)
+    assert conv
+    assert lam1.min() >= -1e-13 * lam1.max() and lam1.max() > 0
+    d1 = O.kernel(g, s, xi, eta, src, par, wl["kappa"], tau, lam1)
+    d2 = O.kernel(g, s, xi, eta, src, par, wl["kappa"], tau, lam2)
+    K, Kd = O.kernel_density(g, s, d1[0], d1, 0.0, 1.0)
+    _, Kd2 = O.kernel_density(g, s, d2[0], d1, 0.0, 1.0)
+    assert Kd.min() >= -1e-13 * Kd.max()
+    assert np.allclose(Kd2, 2.0 * Kd, rtol=1e-9, atol=1e-300)
+    live = Kd > 1e-10 * Kd.max()
+    assert live[1:-1, 1:-1, 1:-1].mean() > 0.9
+    assert np.allclose(K[0][live], (s * s)[live], rtol=1e-12)
+    K0, _ = O.kernel_density(g, s, d1[0], d1, 0.3, 0.0)
+    V = O.node_volume(g)
+    assert np.allclose(K0[0], s * d1[0] / V, rtol=1e-13) and np.allclose(K0[1], d1[1] / V, rtol=1e-13)
