@@ -156,6 +156,22 @@ int tt_kernel(const tt_grid* grid, const double* s, const double* xi, const doub
               const double* src_pos, const double* src_par, const double* tau, const double* lam,
               double* grad, int32_t accumulate, void* ws, size_t ws_bytes, void* stream);
 
+/* Kernel-density normalisation (Eqs. (18)-(19)).  The density of the event
+ * kernels is the adjoint field of Eq. (5) with every adjoint source R = 1,
+ * summed over sources: run tt_adjoint with R = 1 and tt_kernel on its fields,
+ * and pass the s-gradient row of the result as dens [N].  With V the
+ * trapezoidal node volume (r^2 cos(theta) dr dtheta dphi in spherical
+ * coordinates, halved once per boundary axis), and since
+ * K_s = s (d chi / d s) / V (Eq. (9)) and K_s = P s^2, per node:
+ *   Kd   = dens / (s V)                                  (Eq. (19))
+ *   K[0] = s grad[0] / V / (Kd + eps)^zeta   (K_s)        (Eq. (18))
+ *   K[1] = grad[1] / V / (Kd + eps)^zeta     (K_xi),  K[2] likewise (K_eta).
+ * grad [3][N] are the summed discrete gradients of the misfit (tt_kernel);
+ * K [3][N] out; Kd [N] out (may be NULL).  eps >= 0, zeta finite (eps > 0 when
+ * zeta is not an integer and Kd can be 0).  Asynchronous on stream. */
+int tt_kernel_density(const tt_grid* grid, const double* s, const double* dens, const double* grad, double eps,
+                      double zeta, double* K, double* Kd, void* stream);
+
 /* Sweep-kernel timing gathered by tt_forward (which = 0) and tt_adjoint
  * (which = 1) calls of the calling thread that had TT_FLAG_TIME_SWEEPS set:
  * the summed device time of the timed sweeps (ms, HIP event pairs around the

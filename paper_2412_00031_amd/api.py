@@ -204,3 +204,19 @@ def kernel(grid, s, xi, eta, src_pos, src_par, tau, lam, grad=None, ws=None):
                              _dev(lam, "lam", numel=nsrc * N), _dev(grad, "grad", numel=3 * N), int(acc),
                              _dev(ws, "ws", torch.uint8), ws.numel(), _stream(dev)))
     return grad
+
+
+def kernel_density(grid, s, dens, grad, eps, zeta):
+    """Kernel-density normalisation (Eqs. (18)-(19)): returns (K [3, *n], Kd [*n])
+    from dens (s-gradient row of tt_kernel over the R = 1 adjoint fields) and the
+    summed misfit gradients grad [3, *n]."""
+    lib = _lib.load()
+    N = _N(grid)
+    dev = s.device
+    K = torch.empty((3,) + tuple(int(v) for v in grid["n"]), dtype=_F64, device=dev)
+    Kd = torch.empty(tuple(int(v) for v in grid["n"]), dtype=_F64, device=dev)
+    g = _grid(grid)
+    _lib.check(lib.tt_kernel_density(ctypes.byref(g), _dev(s, "s", numel=N), _dev(dens, "dens", numel=N),
+                                     _dev(grad, "grad", numel=3 * N), float(eps), float(zeta), _dev(K, "K"),
+                                     _dev(Kd, "Kd"), _stream(dev)))
+    return K, Kd

@@ -587,4 +587,18 @@ int tt_kernel(const tt_grid* grid, const double* s, const double* xi, const doub
     return TT_OK;
 }
 
+int tt_kernel_density(const tt_grid* grid, const double* s, const double* dens, const double* grad, double eps,
+                      double zeta, double* K, double* Kd, void* stream) {
+    g_err.clear();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if ((rc = check_ptrs({s, dens, grad, K}))) return rc;
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(TT_EINVAL, "eps must be finite and >= 0");
+    if (!std::isfinite(zeta)) return fail(TT_EINVAL, "zeta must be finite");
+    tt::Geo G = make_geo(grid, kDefaultTileK);
+    tt::launch_kernel_density(G, s, dens, grad, eps, zeta, K, Kd, (hipStream_t)stream);
+    TT_HIP(hipGetLastError());
+    return TT_OK;
+}
+
 }  // extern "C"

@@ -1148,6 +1148,40 @@ void launch_misfit(int nsrc, int nrec, const double* T, const double* Tobs, cons
                        R, chi);
 }
 
+// Kernel-density normalisation (Eqs. (18)-(19)), one thread per node:
+// Kd = dens / (s V), K = (s grad_s, grad_xi, grad_eta) / V / (Kd + eps)^zeta with
+// V the trapezoidal node volume.
+__global__ void k_kernel_density(Geo G, const double* __restrict__ s, const double* __restrict__ dens,
+                                 const double* __restrict__ grad, double eps, double zeta, double* __restrict__ K,
+                                 double* __restrict__ Kd) {
+    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < G.N;
+         x += (long long)gridDim.x * blockDim.x) {
+        const int k = (int)(x % G.n[2]);
+        const long long q = x / G.n[2];
+        const int j = (int)(q % G.n[1]), i = (int)(q / G.n[1]);
+        double v = G.h[0] * G.h[1] * G.h[2];
+        if (G.coord == 1) {
+            const double r = G.o[0] + i * G.h[0];
+            v *= r * r * cos(G.o[1] + j * G.h[1]);
+        }
+        if (i == 0 || i == G.n[0] - 1) v *= 0.5;
+        if (j == 0 || j == G.n[1] - 1) v *= 0.5;
+        if (k == 0 || k == G.n[2] - 1) v *= 0.5;
+        const double d = dens[x] / (s[x] * v);
+        const double w = pow(d + eps, zeta);
+        if (Kd) Kd[x] = d;
+        K[x] = s[x] * grad[x] / v / w;
+        K[G.N + x] = grad[G.N + x] / v / w;
+        K[2 * G.N + x] = grad[2 * G.N + x] / v / w;
+    }
+}
+
+void launch_kernel_density(const Geo& G, const double* s, const double* dens, const double* grad, double eps,
+                           double zeta, double* K, double* Kd, hipStream_t st) {
+    hipLaunchKernelGGL(k_kernel_density, dim3(fill_blocks(G.N)), dim3(256), 0, st, G, s, dens, grad, eps, zeta, K,
+                       Kd);
+}
+
 void launch_kernel_accum(const Plan& P, const double* xi, const double* eta, const double* tau, const double* lam,
                          double* grad, int accumulate, hipStream_t st) {
     if (P.G.coord == 1)

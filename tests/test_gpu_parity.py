@@ -172,6 +172,51 @@ def test_source_groups_bitwise(torch_cuda):
     assert rel_inf(ref[0], o["tau"]) <= TOL_TAU and rel_inf(ref[3], o["lam"]) <= TOL_ADJ
 
 
+@pytest.mark.parametrize("zeta,eps_rel", [(0.5, 1e-3), (1.0, 0.0), (0.0, 0.1)])
+def test_kernel_density_parity(torch_cuda, zeta, eps_rel):
+    """Kernel-density normalisation (Eqs. (18)-(19)) through the C ABI: the
+    density adjoint (every R = 1) and the data adjoint on the GPU, Kd and the
+    normalised kernels against the oracle's own chain, to the adjoint
+    tolerance; Kd >= 0 and, for zeta = 1 and eps = 0, the density kernel
+    normalised by itself is s^2."""
+    from paper_2412_00031_amd import api
+    wl = W.small_spherical(n=(13, 14, 15), nsrc=3, nrec=9, seed=29)
+    g, kap = wl["grid"], wl["kappa"]
+    s, xi, eta, src, rec, R = (_dev(torch_cuda, wl[k]) for k in ("s", "xi", "eta", "src", "rec", "R"))
+    par = api.source_params(g, s, xi, eta, src)
+    tau, _ = api.forward(g, s, xi, eta, src, par, 1e-13, 1000, kap)
+    lam, _ = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, 1e-13, 1000, kap)
+    grad = api.kernel(g, s, xi, eta, src, par, tau, lam)
+    ones = torch_cuda.ones_like(R)
+    lam1, _ = api.adjoint(g, s, xi, eta, src, par, tau, rec, ones, 1e-13, 1000, kap)
+    dens = api.kernel(g, s, xi, eta, src, par, tau, lam1)[0].contiguous()
+    o = oracle_path(wl, 1e-13, 1000, R=wl["R"])
+    od = np.zeros((3,) + tuple(g["n"]))
+    for q in range(3):
+        rhs = O.adjoint_rhs(g, wl["src"][q], o["par"][q], wl["rec"], np.ones(len(wl["rec"])))
+        l1, _, conv, _ = O.adjoint(g, wl["s"], wl["xi"], wl["eta"], wl["src"][q], o["par"][q], kap, o["tau"][q], rhs,
+                                   1e-13, 1000)
+        assert conv
+        O.kernel(g, wl["s"], wl["xi"], wl["eta"], wl["src"][q], o["par"][q], kap, o["tau"][q], l1, od)
+    _, Kd_o = O.kernel_density(g, wl["s"], od[0], o["grad"], 0.0, 0.0)
+    eps = eps_rel * Kd_o.max()
+    K_o, Kd_o = O.kernel_density(g, wl["s"], od[0], o["grad"], eps, zeta)
+    K, Kd = api.kernel_density(g, s, dens, grad, eps, zeta)
+    K, Kd = K.cpu().numpy(), Kd.cpu().numpy()
+    assert Kd.min() >= -1e-13 * Kd.max()
+    assert rel_inf(Kd, Kd_o) <= TOL_ADJ
+    fin = np.isfinite(K_o).all(axis=0)
+    if eps == 0.0 and zeta > 0.0:  # K / Kd^zeta is ill-conditioned where Kd underflows towards 0
+        fin &= Kd_o > 1e-8 * Kd_o.max()
+    assert fin[1:-1, 1:-1, 1:-1].mean() > 0.8
+    for c in range(3):
+        assert rel_inf(K[c][fin], K_o[c][fin]) <= TOL_ADJ, c
+    if zeta == 1.0 and eps == 0.0:
+        Ks_self, _ = api.kernel_density(g, s, dens, api.kernel(g, s, xi, eta, src, par, tau, lam1), 0.0, 1.0)
+        live = Kd > 1e-10 * Kd.max()
+        assert np.allclose(Ks_self[0].cpu().numpy()[live], wl["s"][live] ** 2, rtol=1e-12)
+
+
 def test_invalid_arguments_rejected(torch_cuda):
     from paper_2412_00031_amd import api, _lib
     wl = W.small_spherical(n=(6, 6, 6), nsrc=1)
