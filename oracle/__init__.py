@@ -207,6 +207,40 @@ def kernel_density(grid, s, dens, grad, eps, zeta):
     return K, Kd
 
 
+def _mg_args(inv_grids):
+    m = np.array([[len(c) for c in axes] for axes in inv_grids], dtype=np.int32).reshape(-1)
+    coords = np.concatenate([np.asarray(c, dtype=np.float64) for axes in inv_grids for c in axes])
+    sizes = [int(np.prod([len(c) for c in axes])) for axes in inv_grids]
+    return m, coords, sizes
+
+
+def mg_project(grid, inv_grids, K):
+    """d chi / d C (Eq. (17)) for inversion grids inv_grids = [(r, th, ph), ...]
+    (ascending coordinate arrays): list of [3, m0, m1, m2] arrays, one per grid."""
+    n, coord, o, h = _grid_args(grid)
+    m, coords, sizes = _mg_args(inv_grids)
+    out = np.zeros(3 * sum(sizes))
+    lib().tto_mg_project(_i(n), coord, _d(o), _d(h), len(inv_grids), m.ctypes.data_as(_I), _d(coords),
+                         _d(_f64(K)), _d(out))
+    res, off = [], 0
+    for axes, sz in zip(inv_grids, sizes):
+        res.append(out[off:off + 3 * sz].reshape((3,) + tuple(len(c) for c in axes)))
+        off += 3 * sz
+    return res
+
+
+def mg_expand(grid, inv_grids, C):
+    """Fields [3, n] = sum over grids and basis functions of C B (Eq. (15));
+    C: list of [3, m0, m1, m2] arrays, one per grid."""
+    n, coord, o, h = _grid_args(grid)
+    m, coords, sizes = _mg_args(inv_grids)
+    Cf = np.concatenate([np.asarray(c, dtype=np.float64).reshape(-1) for c in C])
+    field = np.zeros((3,) + _shape(grid))
+    lib().tto_mg_expand(_i(n), coord, _d(o), _d(h), len(inv_grids), m.ctypes.data_as(_I), _d(coords), _d(Cf),
+                        _d(field))
+    return field
+
+
 def solve_source(grid, s, xi, eta, src_pos, src_par, kappa, rec_pos, T_obs=None, R=None,
                  tol=1e-6, adj_tol=None, max_iter=2000, w=None):
     """Forward + sample + (misfit) + adjoint + kernel for one source (chi_t only).

@@ -60,6 +60,9 @@
  *   (R11) kernel density (Eqs. (18)-(19)): the adjoint field of Eq. (5) is
  *        P = (d chi / d s) / (s V) with V the trapezoidal node volume, since
  *        K_s = s (d chi / d s) / V (Eq. (9)) and K_s = P s^2.
+ *   (R12) multiple-grid basis (Eqs. (11)-(17)): tents vanish outside each
+ *        inversion grid's range; the integral of Eq. (17) is the node
+ *        quadrature sum_x K B V; the s-coefficients perturb ds / s (Eq. (9)).
  */
 #include <math.h>
 #include <stddef.h>
@@ -861,4 +864,102 @@ void tto_kernel_density(const int* n, int coord, const double* o, const double* 
         K[2 * N + x] = grad[2 * N + x] / V[x] / w;
     }
     free(V);
+}
+
+/* Multiple-grid parameterisation (Eqs. (11)-(17)).
+ * H inversion grids; grid h has ascending node coordinates c_a^h[0..m_a-1] on
+ * each axis a (r, theta, phi or z, y, x).  One-dimensional tent functions
+ * (Eqs. (12)-(14)): node i is (x - c[i-1]) / (c[i] - c[i-1]) on [c[i-1], c[i]]
+ * (i > 0), (c[i+1] - x) / (c[i+1] - c[i]) on [c[i], c[i+1]] (i < m - 1), and 0
+ * elsewhere, in particular outside [c[0], c[m-1]].  B_l^h = u_i v_j w_k / H
+ * (Eq. (11)); the coefficient index l of the paper is stored as [i][j][k]
+ * (k fastest), grid after grid.  Coordinates of all grids are concatenated:
+ * grid h's r, theta, phi arrays in turn; m holds m_a^h as [H][3]. */
+static double tent(const double* c, int m, int i, double x) {
+    if (i > 0 && x >= c[i - 1] && x <= c[i]) return (x - c[i - 1]) / (c[i] - c[i - 1]);
+    if (i < m - 1 && x >= c[i] && x <= c[i + 1]) return (c[i + 1] - x) / (c[i + 1] - c[i]);
+    if (m == 1 && x == c[0]) return 1.0;
+    return 0.0;
+}
+
+/* Projection of kernels onto the basis (Eq. (17)), by node quadrature:
+ * out[h][p][i][j][k] = sum_x K[p](x) B_(i,j,k)^h(x) V(x), p = s, xi, eta. */
+void tto_mg_project(const int* n, int coord, const double* o, const double* h, int H, const int* m,
+                    const double* coords, const double* K, double* out) {
+    OGrid g;
+    grid_init(&g, n, coord, o, h);
+    const long N = (long)g.N;
+    double* V = (double*)malloc(sizeof(double) * (size_t)N);
+    tto_node_volume(n, coord, o, h, V);
+    const double* cg = coords;
+    double* og = out;
+    for (int q = 0; q < H; ++q) {
+        const int* mq = m + 3 * q;
+        const double *c0 = cg, *c1 = cg + mq[0], *c2 = cg + mq[0] + mq[1];
+        const long M = (long)mq[0] * mq[1] * mq[2];
+        for (long e = 0; e < 3 * M; ++e) og[e] = 0.0;
+        for (int ci = 0; ci < mq[0]; ++ci)
+            for (int cj = 0; cj < mq[1]; ++cj)
+                for (int ck = 0; ck < mq[2]; ++ck) {
+                    double acc[3] = {0.0, 0.0, 0.0};
+                    for (int i = 0; i < g.n[0]; ++i) {
+                        const double u = tent(c0, mq[0], ci, cval(&g, 0, i));
+                        if (u == 0.0) continue;
+                        for (int j = 0; j < g.n[1]; ++j) {
+                            const double v = tent(c1, mq[1], cj, cval(&g, 1, j));
+                            if (v == 0.0) continue;
+                            for (int k = 0; k < g.n[2]; ++k) {
+                                const double w = tent(c2, mq[2], ck, cval(&g, 2, k));
+                                if (w == 0.0) continue;
+                                const long x = IDX(&g, i, j, k);
+                                const double b = u * v * w / H * V[x];
+                                for (int p = 0; p < 3; ++p) acc[p] += K[p * N + x] * b;
+                            }
+                        }
+                    }
+                    const long l = ((long)ci * mq[1] + cj) * mq[2] + ck;
+                    for (int p = 0; p < 3; ++p) og[p * M + l] = acc[p];
+                }
+        cg += mq[0] + mq[1] + mq[2];
+        og += 3 * M;
+    }
+    free(V);
+}
+
+/* Expansion of coefficients into fields (Eq. (15)):
+ * field[p](x) = sum_h sum_(i,j,k) C[h][p][i][j][k] B_(i,j,k)^h(x). */
+void tto_mg_expand(const int* n, int coord, const double* o, const double* h, int H, const int* m,
+                   const double* coords, const double* C, double* field) {
+    OGrid g;
+    grid_init(&g, n, coord, o, h);
+    const long N = (long)g.N;
+    for (long e = 0; e < 3 * N; ++e) field[e] = 0.0;
+    const double* cg = coords;
+    const double* Cg = C;
+    for (int q = 0; q < H; ++q) {
+        const int* mq = m + 3 * q;
+        const double *c0 = cg, *c1 = cg + mq[0], *c2 = cg + mq[0] + mq[1];
+        const long M = (long)mq[0] * mq[1] * mq[2];
+        for (int i = 0; i < g.n[0]; ++i)
+            for (int j = 0; j < g.n[1]; ++j)
+                for (int k = 0; k < g.n[2]; ++k) {
+                    const long x = IDX(&g, i, j, k);
+                    for (int ci = 0; ci < mq[0]; ++ci) {
+                        const double u = tent(c0, mq[0], ci, cval(&g, 0, i));
+                        if (u == 0.0) continue;
+                        for (int cj = 0; cj < mq[1]; ++cj) {
+                            const double v = tent(c1, mq[1], cj, cval(&g, 1, j));
+                            if (v == 0.0) continue;
+                            for (int ck = 0; ck < mq[2]; ++ck) {
+                                const double w = tent(c2, mq[2], ck, cval(&g, 2, k));
+                                if (w == 0.0) continue;
+                                const long l = ((long)ci * mq[1] + cj) * mq[2] + ck;
+                                for (int p = 0; p < 3; ++p) field[p * N + x] += Cg[p * M + l] * u * v * w / H;
+                            }
+                        }
+                    }
+                }
+        cg += mq[0] + mq[1] + mq[2];
+        Cg += 3 * M;
+    }
 }

@@ -427,3 +427,96 @@ def test_kernel_density_properties(tiny_case):
     K0, _ = O.kernel_density(g, s, d1[0], d1, 0.3, 0.0)
     V = O.node_volume(g)
     assert np.allclose(K0[0], s * d1[0] / V, rtol=1e-13) and np.allclose(K0[1], d1[1] / V, rtol=1e-13)
+
+
+# ------------------------------------------------ multiple-grid parameterisation
+def _inv_grids(g, seed):
+    """Two staggered inversion grids covering the forward grid, with uneven
+    spacing and a margin past its ends."""
+    rng = np.random.default_rng(seed)
+    ax = W.axes(g)
+    grids = []
+    for q, m in enumerate(((4, 3, 5), (5, 4, 4))):
+        axes = []
+        for a in range(3):
+            lo, hi = ax[a][0], ax[a][-1]
+            span = hi - lo
+            c = np.sort(lo + span * np.concatenate([[-0.05 - 0.1 * q], rng.uniform(0.1, 0.9, m[a] - 2),
+                                                     [1.05 + 0.1 * q]]))
+            axes.append(c)
+        grids.append(tuple(axes))
+    return grids
+
+
+def test_multigrid_basis_partition_and_linear_reproduction():
+    """Eqs. (11)-(15): the tents of each grid sum to 1 (so H grids with the 1/H
+    factor sum to 1), and expanding the values of a linear function at the
+    inversion nodes reproduces it at every forward node (tents interpolate
+    linearly along each axis)."""
+    wl = W.small_spherical(n=(9, 10, 11), seed=3)
+    g = wl["grid"]
+    inv = _inv_grids(g, 5)
+    ones = [np.ones((3,) + tuple(len(c) for c in axes)) for axes in inv]
+    assert np.allclose(O.mg_expand(g, inv, ones), 1.0, rtol=0, atol=1e-14)
+    ax = W.axes(g)
+    A, B, Cc = np.meshgrid(ax[0], ax[1], ax[2], indexing="ij")
+    lin = lambda r, t, p: 0.3 + 0.02 * (r - ax[0][0]) - 7.0 * t + 4.0 * p
+    coef = []
+    for axes in inv:
+        R_, T_, P_ = np.meshgrid(*axes, indexing="ij")
+        coef.append(np.stack([lin(R_, T_, P_), 2.0 * lin(R_, T_, P_), -lin(R_, T_, P_)]))
+    f = O.mg_expand(g, inv, coef)
+    ref = lin(A, B, Cc)
+    assert np.allclose(f[0], ref, rtol=1e-12, atol=1e-12) and np.allclose(f[1], 2.0 * ref, rtol=1e-12, atol=1e-12)
+    assert np.allclose(f[2], -ref, rtol=1e-12, atol=1e-12)
+
+
+def test_multigrid_projection_is_transpose_of_expansion():
+    """sum_l P_l(K) C_l = sum_x K(x) V(x) expand(C)(x): the projection of Eq. (17)
+    is the adjoint of the expansion of Eq. (15) under the node quadrature."""
+    wl = W.small_spherical(n=(7, 9, 8), seed=4)
+    g = wl["grid"]
+    inv = _inv_grids(g, 9)
+    rng = np.random.default_rng(1)
+    K = rng.standard_normal((3,) + tuple(g["n"]))
+    C = [rng.standard_normal((3,) + tuple(len(c) for c in axes)) for axes in inv]
+    P = O.mg_project(g, inv, K)
+    lhs = sum(float((p * c).sum()) for p, c in zip(P, C))
+    rhs = float((K * O.node_volume(g)[None] * O.mg_expand(g, inv, C)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs))
+
+
+def test_multigrid_gradient_matches_finite_differences():
+    """Eq. (16): with the model perturbation ds / s = sum C B (Eq. (15)), the
+    projected kernel d chi / d C_s (Eq. (17), from K_s = s grad / V) equals
+    central differences of the misfit in the coefficients; likewise for xi."""
+    wl = W.small_spherical(n=(8, 9, 10), nsrc=1, seed=17, nrec=7, aniso=0.05)
+    g, s, xi, eta = wl["grid"], wl["s"], wl["xi"], wl["eta"]
+    src = wl["src"][0]
+    par = O.source_params(g, s, xi, eta, src)[0]
+    T_obs = W.straight_line_times(g, src[None, :], wl["rec"], 6.4)[0]
+    tau, it, conv, _ = O.forward(g, s, xi, eta, src, par, wl["kappa"], 1e-16, 3000)
+    T = O.sample(g, src, par, tau, wl["rec"])
+    chi, R = O.misfit(T[None, :], T_obs[None, :])
+    lam, _, _, _ = O.adjoint(g, s, xi, eta, src, par, wl["kappa"], tau, O.adjoint_rhs(g, src, par, wl["rec"], R[0]),
+                             1e-16, 5000)
+    grad = O.kernel(g, s, xi, eta, src, par, wl["kappa"], tau, lam)
+    K, _ = O.kernel_density(g, s, grad[0], grad, 1.0, 0.0)
+    inv = _inv_grids(g, 2)
+    P = O.mg_project(g, inv, K)
+    rng = np.random.default_rng(8)
+    shapes = [tuple(len(c) for c in axes) for axes in inv]
+    for p, step in ((0, 1e-6), (1, 1e-5)):
+        for _ in range(3):
+            h_ = int(rng.integers(0, 2))
+            l = tuple(int(rng.integers(1, m - 1)) for m in shapes[h_])
+            C = [np.zeros((3,) + sh) for sh in shapes]
+            C[h_][(p,) + l] = 1.0
+            d = O.mg_expand(g, inv, C)[p]
+            vals = []
+            for sg in (1, -1):
+                m = [s.copy(), xi.copy(), eta.copy()]
+                m[p] = m[p] * (1.0 + sg * step * d) if p == 0 else m[p] + sg * step * d
+                vals.append(_chi_of_model(wl, src, par, m, T_obs, None))
+            fd = (vals[0] - vals[1]) / (2 * step)
+            assert abs(fd - P[h_][(p,) + l]) <= 1e-6 * abs(fd) + 1e-9 * np.abs(P[h_][p]).max(), (p, l, fd, P[h_][(p,) + l])
