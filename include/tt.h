@@ -172,6 +172,27 @@ int tt_kernel(const tt_grid* grid, const double* s, const double* xi, const doub
 int tt_kernel_density(const tt_grid* grid, const double* s, const double* dens, const double* grad, double eps,
                       double zeta, double* K, double* Kd, void* stream);
 
+/* Multiple-grid parameterisation (Eqs. (11)-(17)).  H inversion grids; grid q
+ * has m[3q + a] (>= 1) strictly ascending node coordinates on axis a (r km,
+ * latitude, longitude rad; or z, y, x km), concatenated in coords (device,
+ * grid after grid, axes in turn).  Basis B = u v w / H with the tents of
+ * Eqs. (12)-(14), which vanish outside each grid's coordinate range.
+ * Coefficients and projections are stored per grid as [3][m0][m1][m2] (k
+ * fastest; the paper's index l = i + m0 j + m0 m1 k names the same entries),
+ * grids in turn; the three rows are the s, xi, eta parameters.  m is a host
+ * array; every other pointer is device memory.
+ *
+ * tt_mg_project: out = d chi / d C (Eq. (17)) from the kernels K [3][N] (e.g.
+ *   tt_kernel_density), by node quadrature: out = sum_x K(x) B(x) V(x).  With
+ *   ds / s = sum C B (s row) and dxi = sum C B, d eta likewise (Eq. (15)), this
+ *   is the gradient of Eq. (16).  One wave per inversion node, deterministic.
+ * tt_mg_expand: field [3][N] = sum over grids and nodes of C B (Eq. (15)),
+ *   overwritten.  Asynchronous on stream. */
+int tt_mg_project(const tt_grid* grid, int32_t H, const int32_t* m, const double* coords, const double* K,
+                  double* out, void* stream);
+int tt_mg_expand(const tt_grid* grid, int32_t H, const int32_t* m, const double* coords, const double* C,
+                 double* field, void* stream);
+
 /* Sweep-kernel timing gathered by tt_forward (which = 0) and tt_adjoint
  * (which = 1) calls of the calling thread that had TT_FLAG_TIME_SWEEPS set:
  * the summed device time of the timed sweeps (ms, HIP event pairs around the

@@ -220,3 +220,45 @@ def kernel_density(grid, s, dens, grad, eps, zeta):
                                      _dev(grad, "grad", numel=3 * N), float(eps), float(zeta), _dev(K, "K"),
                                      _dev(Kd, "Kd"), _stream(dev)))
     return K, Kd
+
+
+def _mg_args(inv_grids, device):
+    """(m host int32 array, coords device tensor, per-grid sizes) of inversion
+    grids given as [(r, theta, phi), ...] ascending coordinate sequences."""
+    sizes = [tuple(len(c) for c in axes) for axes in inv_grids]
+    m = (ctypes.c_int32 * (3 * len(inv_grids)))(*[v for sz in sizes for v in sz])
+    flat = [float(v) for axes in inv_grids for c in axes for v in (c.tolist() if hasattr(c, "tolist") else c)]
+    coords = torch.tensor(flat, dtype=_F64, device=device)
+    return m, coords, sizes
+
+
+def mg_project(grid, inv_grids, K):
+    """d chi / d C (Eq. (17)) on each inversion grid: list of [3, m0, m1, m2] tensors."""
+    lib = _lib.load()
+    dev = K.device
+    m, coords, sizes = _mg_args(inv_grids, dev)
+    total = sum(3 * a * b * c for a, b, c in sizes)
+    out = torch.empty(total, dtype=_F64, device=dev)
+    g = _grid(grid)
+    _lib.check(lib.tt_mg_project(ctypes.byref(g), len(inv_grids), m, _dev(coords, "coords"),
+                                 _dev(K, "K", numel=3 * _N(grid)), _dev(out, "out"), _stream(dev)))
+    res, off = [], 0
+    for sz in sizes:
+        n = 3 * sz[0] * sz[1] * sz[2]
+        res.append(out[off:off + n].view((3,) + sz))
+        off += n
+    return res
+
+
+def mg_expand(grid, inv_grids, C):
+    """Fields [3, *n] = sum of C B over the inversion grids (Eq. (15)); C is a
+    list of [3, m0, m1, m2] tensors."""
+    lib = _lib.load()
+    dev = C[0].device
+    m, coords, sizes = _mg_args(inv_grids, dev)
+    Cf = torch.cat([c.reshape(-1) for c in C]).contiguous()
+    field = torch.empty((3,) + tuple(int(v) for v in grid["n"]), dtype=_F64, device=dev)
+    g = _grid(grid)
+    _lib.check(lib.tt_mg_expand(ctypes.byref(g), len(inv_grids), m, _dev(coords, "coords"), _dev(Cf, "C"),
+                                _dev(field, "field"), _stream(dev)))
+    return field

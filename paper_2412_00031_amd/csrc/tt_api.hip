@@ -601,4 +601,39 @@ int tt_kernel_density(const tt_grid* grid, const double* s, const double* dens, 
     return TT_OK;
 }
 
+static int check_mg(int H, const int32_t* m, const double* coords) {
+    if (H < 1) return fail(TT_EINVAL, "H must be >= 1");
+    if (!m || !coords) return fail(TT_EINVAL, "m and coords must not be NULL");
+    for (int q = 0; q < 3 * H; ++q)
+        if (m[q] < 1 || m[q] > 1 << 20) return fail(TT_EINVAL, "inversion grid size m[%d] = %d out of range", q, m[q]);
+    for (int q = 0; q < H; ++q)
+        if ((long long)m[3 * q] * m[3 * q + 1] * m[3 * q + 2] > 0x7fffffffLL)
+            return fail(TT_EINVAL, "inversion grid %d too large", q);
+    return TT_OK;
+}
+
+int tt_mg_project(const tt_grid* grid, int32_t H, const int32_t* m, const double* coords, const double* K,
+                  double* out, void* stream) {
+    g_err.clear();
+    int rc = check_grid(grid);
+    if (rc || (rc = check_mg(H, m, coords))) return rc;
+    if ((rc = check_ptrs({K, out}))) return rc;
+    tt::Geo G = make_geo(grid, kDefaultTileK);
+    tt::launch_mg_project(G, H, m, coords, K, out, (hipStream_t)stream);
+    TT_HIP(hipGetLastError());
+    return TT_OK;
+}
+
+int tt_mg_expand(const tt_grid* grid, int32_t H, const int32_t* m, const double* coords, const double* C,
+                 double* field, void* stream) {
+    g_err.clear();
+    int rc = check_grid(grid);
+    if (rc || (rc = check_mg(H, m, coords))) return rc;
+    if ((rc = check_ptrs({C, field}))) return rc;
+    tt::Geo G = make_geo(grid, kDefaultTileK);
+    tt::launch_mg_expand(G, H, m, coords, C, field, (hipStream_t)stream);
+    TT_HIP(hipGetLastError());
+    return TT_OK;
+}
+
 }  // extern "C"

@@ -1148,6 +1148,120 @@ void launch_misfit(int nsrc, int nrec, const double* T, const double* Tobs, cons
                        R, chi);
 }
 
+// ------------------------------------------- multiple-grid parameterisation
+// One-dimensional tent of inversion node i (ascending coordinates c[0..m-1])
+// at x (Eqs. (12)-(14)); zero outside [c[0], c[m-1]].
+__device__ __forceinline__ double mg_tent(const double* c, int m, int i, double x) {
+    if (i > 0 && x >= c[i - 1] && x <= c[i]) return (x - c[i - 1]) / (c[i] - c[i - 1]);
+    if (i < m - 1 && x >= c[i] && x <= c[i + 1]) return (c[i + 1] - x) / (c[i + 1] - c[i]);
+    if (m == 1 && x == c[0]) return 1.0;
+    return 0.0;
+}
+
+// Trapezoidal node volume (r^2 cos(theta) dr dtheta dphi in spherical
+// coordinates, halved once per boundary axis).
+__device__ __forceinline__ double node_volume(const Geo& G, int i, int j, int k) {
+    double v = G.h[0] * G.h[1] * G.h[2];
+    if (G.coord == 1) {
+        const double r = G.o[0] + i * G.h[0];
+        v *= r * r * cos(G.o[1] + j * G.h[1]);
+    }
+    if (i == 0 || i == G.n[0] - 1) v *= 0.5;
+    if (j == 0 || j == G.n[1] - 1) v *= 0.5;
+    if (k == 0 || k == G.n[2] - 1) v *= 0.5;
+    return v;
+}
+
+// Forward-grid index range [lo, hi] of axis a that can lie under the tent of
+// inversion node i (one node of margin each side: the tent itself decides).
+__device__ __forceinline__ void mg_range(const Geo& G, int a, const double* c, int m, int i, int& lo, int& hi) {
+    const double x0 = c[i > 0 ? i - 1 : i], x1 = c[i < m - 1 ? i + 1 : i];
+    lo = (int)floor((x0 - G.o[a]) / G.h[a]) - 1;
+    hi = (int)ceil((x1 - G.o[a]) / G.h[a]) + 1;
+    lo = lo < 0 ? 0 : lo;
+    hi = hi > G.n[a] - 1 ? G.n[a] - 1 : hi;
+}
+
+// Eq. (17): one wave per inversion node (blockIdx.x = (ci m1 + cj) m2 + ck) of
+// one grid; lanes share the node's support box in a fixed pattern and the
+// partial sums are combined by a fixed shuffle tree (deterministic).
+// out [3][m0][m1][m2] = sum_x K[p](x) B(x) V(x), B = u v w / H.
+__global__ void __launch_bounds__(64) k_mg_project(Geo G, int H, int m0, int m1, int m2,
+                                                   const double* __restrict__ c0, const double* __restrict__ c1,
+                                                   const double* __restrict__ c2, const double* __restrict__ K,
+                                                   double* __restrict__ out) {
+    const long long M = (long long)m0 * m1 * m2;
+    const long long l = blockIdx.x;
+    const int ck = (int)(l % m2), cj = (int)((l / m2) % m1), ci = (int)(l / ((long long)m1 * m2));
+    int ilo, ihi, jlo, jhi, klo, khi;
+    mg_range(G, 0, c0, m0, ci, ilo, ihi);
+    mg_range(G, 1, c1, m1, cj, jlo, jhi);
+    mg_range(G, 2, c2, m2, ck, klo, khi);
+    const int ni = ihi - ilo + 1, nj = jhi - jlo + 1, nk = khi - klo + 1;
+    const long long box = (ni > 0 && nj > 0 && nk > 0) ? (long long)ni * nj * nk : 0;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (long long e = threadIdx.x; e < box; e += 64) {
+        const int k = klo + (int)(e % nk);
+        const int j = jlo + (int)((e / nk) % nj);
+        const int i = ilo + (int)(e / ((long long)nk * nj));
+        const double u = mg_tent(c0, m0, ci, G.o[0] + i * G.h[0]);
+        const double v = mg_tent(c1, m1, cj, G.o[1] + j * G.h[1]);
+        const double w = mg_tent(c2, m2, ck, G.o[2] + k * G.h[2]);
+        const double b = u * v * w / H * node_volume(G, i, j, k);
+        if (b != 0.0) {
+            const long long x = ((long long)i * G.n[1] + j) * G.n[2] + k;
+            for (int p = 0; p < 3; ++p) acc[p] += K[p * G.N + x] * b;
+        }
+    }
+    for (int p = 0; p < 3; ++p) acc[p] = wave_sum(acc[p]);
+    if (threadIdx.x == 0)
+        for (int p = 0; p < 3; ++p) out[p * M + l] = acc[p];
+}
+
+// Nonzero tents of one axis at x: at most two inversion nodes (ascending
+// coordinates), in ascending node order.
+__device__ __forceinline__ int mg_axis(const double* c, int m, double x, int idx[2], double wt[2]) {
+    int cnt = 0;
+    for (int i = 0; i < m && cnt < 2; ++i) {
+        const double t = mg_tent(c, m, i, x);
+        if (t != 0.0) {
+            idx[cnt] = i;
+            wt[cnt] = t;
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+// Eq. (15): one thread per forward node; field[p](x) += sum C B over the
+// (at most 8) nonzero basis functions of one inversion grid.
+__global__ void k_mg_expand(Geo G, int H, int m0, int m1, int m2, const double* __restrict__ c0,
+                            const double* __restrict__ c1, const double* __restrict__ c2,
+                            const double* __restrict__ C, double* __restrict__ field, int first) {
+    const long long M = (long long)m0 * m1 * m2;
+    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < G.N;
+         x += (long long)gridDim.x * blockDim.x) {
+        const int k = (int)(x % G.n[2]);
+        const long long q = x / G.n[2];
+        const int j = (int)(q % G.n[1]), i = (int)(q / G.n[1]);
+        int ii[2], jj[2], kk[2];
+        double wi[2], wj[2], wk[2];
+        const int na = mg_axis(c0, m0, G.o[0] + i * G.h[0], ii, wi);
+        const int nb = mg_axis(c1, m1, G.o[1] + j * G.h[1], jj, wj);
+        const int nc = mg_axis(c2, m2, G.o[2] + k * G.h[2], kk, wk);
+        double acc[3];
+        for (int p = 0; p < 3; ++p) acc[p] = first ? 0.0 : field[p * G.N + x];
+        for (int a = 0; a < na; ++a)
+            for (int b = 0; b < nb; ++b)
+                for (int c = 0; c < nc; ++c) {
+                    const long long l = ((long long)ii[a] * m1 + jj[b]) * m2 + kk[c];
+                    const double bw = wi[a] * wj[b] * wk[c] / H;
+                    for (int p = 0; p < 3; ++p) acc[p] += C[p * M + l] * bw;
+                }
+        for (int p = 0; p < 3; ++p) field[p * G.N + x] = acc[p];
+    }
+}
+
 // Kernel-density normalisation (Eqs. (18)-(19)), one thread per node:
 // Kd = dens / (s V), K = (s grad_s, grad_xi, grad_eta) / V / (Kd + eps)^zeta with
 // V the trapezoidal node volume.
@@ -1159,14 +1273,7 @@ __global__ void k_kernel_density(Geo G, const double* __restrict__ s, const doub
         const int k = (int)(x % G.n[2]);
         const long long q = x / G.n[2];
         const int j = (int)(q % G.n[1]), i = (int)(q / G.n[1]);
-        double v = G.h[0] * G.h[1] * G.h[2];
-        if (G.coord == 1) {
-            const double r = G.o[0] + i * G.h[0];
-            v *= r * r * cos(G.o[1] + j * G.h[1]);
-        }
-        if (i == 0 || i == G.n[0] - 1) v *= 0.5;
-        if (j == 0 || j == G.n[1] - 1) v *= 0.5;
-        if (k == 0 || k == G.n[2] - 1) v *= 0.5;
+        const double v = node_volume(G, i, j, k);
         const double d = dens[x] / (s[x] * v);
         const double w = pow(d + eps, zeta);
         if (Kd) Kd[x] = d;
@@ -1180,6 +1287,34 @@ void launch_kernel_density(const Geo& G, const double* s, const double* dens, co
                            double zeta, double* K, double* Kd, hipStream_t st) {
     hipLaunchKernelGGL(k_kernel_density, dim3(fill_blocks(G.N)), dim3(256), 0, st, G, s, dens, grad, eps, zeta, K,
                        Kd);
+}
+
+void launch_mg_project(const Geo& G, int H, const int* m, const double* coords, const double* K, double* out,
+                       hipStream_t st) {
+    const double* cg = coords;
+    double* og = out;
+    for (int q = 0; q < H; ++q) {
+        const int* mq = m + 3 * q;
+        const long long M = (long long)mq[0] * mq[1] * mq[2];
+        hipLaunchKernelGGL(k_mg_project, dim3((unsigned)M), dim3(64), 0, st, G, H, mq[0], mq[1], mq[2], cg,
+                           cg + mq[0], cg + mq[0] + mq[1], K, og);
+        cg += mq[0] + mq[1] + mq[2];
+        og += 3 * M;
+    }
+}
+
+void launch_mg_expand(const Geo& G, int H, const int* m, const double* coords, const double* C, double* field,
+                      hipStream_t st) {
+    const double* cg = coords;
+    const double* Cg = C;
+    for (int q = 0; q < H; ++q) {
+        const int* mq = m + 3 * q;
+        const long long M = (long long)mq[0] * mq[1] * mq[2];
+        hipLaunchKernelGGL(k_mg_expand, dim3(fill_blocks(G.N)), dim3(256), 0, st, G, H, mq[0], mq[1], mq[2], cg,
+                           cg + mq[0], cg + mq[0] + mq[1], Cg, field, q == 0 ? 1 : 0);
+        cg += mq[0] + mq[1] + mq[2];
+        Cg += 3 * M;
+    }
 }
 
 void launch_kernel_accum(const Plan& P, const double* xi, const double* eta, const double* tau, const double* lam,
