@@ -30,6 +30,7 @@ def lib():
             _build.build()
         _lib = ctypes.CDLL(path)
         _lib.tto_misfit.restype = ctypes.c_double
+        _lib.tto_misfit_cr.restype = ctypes.c_double
         _lib.tto_lf_update.restype = ctypes.c_double
     return _lib
 
@@ -136,6 +137,21 @@ def misfit(T, T_obs, w=None, pairs=None, wpair=None, alpha=1.0, beta=1.0):
     chi = lib().tto_misfit(nsrc, nrec, _d(T), _d(_f64(T_obs)), _d(_f64(w)) if w is not None else None,
                            len(pairs_a), _i(pairs_a), _d(_f64(wpair)) if wpair is not None else None,
                            ctypes.c_double(alpha), ctypes.c_double(beta), _d(R))
+    return chi, R
+
+
+def misfit_cr(T, T_obs, tri, wtri=None, gamma=1.0, R=None):
+    """gamma * chi_cr (Eq. (4)) for source-pair triples tri [ntri, 3] = (n, j, m),
+    each unordered pair at a receiver listed once; adds d chi_cr / d T (Eq. (A4))
+    to R (zeros if None).  Returns (chi_cr, R)."""
+    T = _f64(T)
+    nsrc, nrec = T.shape
+    R = np.zeros_like(T) if R is None else np.ascontiguousarray(R, dtype=np.float64)
+    tri_a = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+    chi = lib().tto_misfit_cr(nsrc, nrec, _d(T), _d(_f64(T_obs)), len(tri_a), _i(tri_a),
+                              _d(_f64(wtri)) if wtri is not None else None, ctypes.c_double(gamma), _d(R))
+    if np.isnan(chi):
+        raise ValueError("common-receiver triple index out of range")
     return chi, R
 
 

@@ -17,8 +17,8 @@
  *       T = T0 * tau (Luo & Qian 2012), spherical coordinates.
  *   Sec. 2.1 step 2, Eq. (5): adjoint equation; here its exact discrete
  *       counterpart, the transpose of the Jacobian of the discrete forward system.
- *   Eqs. (2), (3), (A2), (A3): traveltime and common-source differential misfits
- *       and their adjoint sources R = d chi / d T(x_r).
+ *   Eqs. (2)-(4), (A2)-(A4): traveltime, common-source and common-receiver
+ *       differential misfits and their adjoint sources R = d chi / d T(x_r).
  *   Eqs. (6)-(9): kernels; here the discrete gradients d chi/d s, d chi/d xi,
  *       d chi/d eta, which Eq. (9) relates to K_s, K_xi, K_eta.
  *
@@ -63,6 +63,9 @@
  *   (R12) multiple-grid basis (Eqs. (11)-(17)): tents vanish outside each
  *        inversion grid's range; the integral of Eq. (17) is the node
  *        quadrature sum_x K B V; the s-coefficients perturb ds / s (Eq. (9)).
+ *   (R13) common-receiver pairs (Eqs. (4) and (A4)): an explicit list of
+ *        triples (n, j, m), the unordered source pair {n, j} recorded at
+ *        receiver m, each counted once, as in (R9).
  */
 #include <math.h>
 #include <stddef.h>
@@ -567,6 +570,29 @@ double tto_misfit(int nsrc, int nrec, const double* T, const double* T_obs, cons
             R[cm] += beta * ww * r;
             R[ci] -= beta * ww * r;
         }
+    }
+    return chi;
+}
+
+/* Common-receiver differential misfit gamma * chi_cr (Eq. (4), third misfit)
+ * and its adjoint sources (Eq. (A4)), added to R.  T, T_obs, R: [nsrc][nrec];
+ * tri [ntri][3] = (n, j, m), the source pair {n, j} at receiver m, each
+ * unordered pair listed once (R13); wtri [ntri] or NULL (= 1).  Triples are
+ * taken in list order.  Returns gamma * chi_cr, or NAN if an index is out of
+ * range. */
+double tto_misfit_cr(int nsrc, int nrec, const double* T, const double* T_obs, int ntri, const int* tri,
+                     const double* wtri, double gamma, double* R) {
+    double chi = 0.0;
+    for (int p = 0; p < ntri; ++p) {
+        int n = tri[3 * p], j = tri[3 * p + 1], m = tri[3 * p + 2];
+        if (n < 0 || n >= nsrc || j < 0 || j >= nsrc || m < 0 || m >= nrec) return NAN;
+        size_t cn = (size_t)n * nrec + m, cj = (size_t)j * nrec + m;
+        double ww = wtri ? wtri[p] : 1.0;
+        /* residual of the differential time T_n - T_j at receiver m */
+        double r = (T[cn] - T[cj]) - (T_obs[cn] - T_obs[cj]);
+        chi += gamma * 0.5 * ww * r * r;
+        R[cn] += gamma * ww * r;
+        R[cj] -= gamma * ww * r;
     }
     return chi;
 }

@@ -331,6 +331,98 @@ def test_misfit_R_is_gradient_of_chi():
             assert abs(fd - R[q, m]) < 1e-7
 
 
+def test_misfit_cr_hand_example():
+    """Eq. (4) common-receiver term and Eq. (A4) worked by hand (golden file)."""
+    with open(os.path.join(HERE, "golden", "misfit_cr_hand_example.json")) as f:
+        ex = json.load(f)
+    chi, R = O.misfit_cr(np.array(ex["T"]), np.array(ex["T_obs"]), np.array(ex["triples"]))
+    assert abs(chi - ex["chi"]) < 1e-15
+    assert np.array_equal(R, np.array(ex["R"]))
+
+
+def _cr_case(seed, nsrc=5, nrec=4):
+    rng = np.random.default_rng(seed)
+    T = rng.uniform(1, 10, (nsrc, nrec))
+    To = T + rng.normal(0, 0.3, T.shape)
+    tri = np.array([(n, j, m) for m in range(nrec) for n in range(nsrc) for j in range(n + 1, nsrc)
+                    if rng.uniform() < 0.7], dtype=np.int32)
+    wt = rng.uniform(0.5, 2, len(tri))
+    return T, To, tri, wt
+
+
+def test_misfit_cr_R_is_gradient_of_chi():
+    T, To, tri, wt = _cr_case(6)
+    chi, R = O.misfit_cr(T, To, tri, wt, gamma=0.8)
+    for q in range(T.shape[0]):
+        for m in range(T.shape[1]):
+            Tp, Tm = T.copy(), T.copy()
+            Tp[q, m] += 1e-6
+            Tm[q, m] -= 1e-6
+            fd = (O.misfit_cr(Tp, To, tri, wt, 0.8)[0] - O.misfit_cr(Tm, To, tri, wt, 0.8)[0]) / 2e-6
+            assert abs(fd - R[q, m]) < 1e-7
+
+
+def test_misfit_cr_receiver_invariance():
+    """A common-receiver differential time cancels anything shared by all
+    sources at one receiver: adding c_m to T[:, m] leaves chi_cr unchanged, and
+    the adjoint sources of each receiver sum to zero over the sources."""
+    T, To, tri, wt = _cr_case(7)
+    chi, R = O.misfit_cr(T, To, tri, wt, gamma=1.3)
+    shift = np.random.default_rng(8).uniform(-5, 5, T.shape[1])
+    chi2, R2 = O.misfit_cr(T + shift[None, :], To, tri, wt, gamma=1.3)
+    assert abs(chi2 - chi) <= 1e-12 * chi
+    assert np.abs(R2 - R).max() <= 1e-12
+    assert np.abs(R.sum(axis=0)).max() <= 1e-13 * np.abs(R).max()
+    assert np.abs(R).max() > 0.1
+
+
+def test_misfit_cr_is_common_source_misfit_of_transpose():
+    """Swapping the roles of sources and receivers turns Eq. (4)'s common-
+    receiver term into its common-source term, Eq. (3): with the same source
+    pairs at every receiver, chi_cr(T) = chi_cs(T^T) and R_cr = (R_cs)^T (the
+    common-source misfit is pinned by its own hand example and gradient)."""
+    rng = np.random.default_rng(9)
+    nsrc, nrec = 6, 5
+    T = rng.uniform(1, 10, (nsrc, nrec))
+    To = T + rng.normal(0, 0.3, T.shape)
+    pairs = np.array([[0, 1], [2, 5], [3, 4], [1, 5], [0, 4]], dtype=np.int32)
+    tri = np.array([(n, j, m) for m in range(nrec) for n, j in pairs], dtype=np.int32)
+    wp = rng.uniform(0.5, 2, (nrec, len(pairs)))
+    chi_cr, R_cr = O.misfit_cr(T, To, tri, wp.reshape(-1), gamma=1.0)
+    chi_cs, R_cs = O.misfit(T.T.copy(), To.T.copy(), None, pairs, wp, alpha=0.0, beta=1.0)
+    assert abs(chi_cr - chi_cs) <= 1e-14 * chi_cs
+    assert np.abs(R_cr - R_cs.T).max() <= 1e-14
+
+
+def test_misfit_cr_symmetric_double_listing():
+    """Listing every ordered source pair (both (n, j) and (j, n)) with
+    symmetric weights is the paper's full double sum of Eq. (4); it counts each
+    pair twice, and the adjoint source then takes the symmetric closed form of
+    Eq. (A4): R[n, m] = 2 sum_j w_nj,m ((T_n - T_j) - (T_n^obs - T_j^obs))."""
+    rng = np.random.default_rng(10)
+    nsrc, nrec = 4, 3
+    T = rng.uniform(1, 10, (nsrc, nrec))
+    To = T + rng.normal(0, 0.3, T.shape)
+    wsym = rng.uniform(0.5, 2, (nsrc, nsrc, nrec))
+    wsym = wsym + wsym.transpose(1, 0, 2)
+    once = [(n, j, m) for m in range(nrec) for n in range(nsrc) for j in range(n + 1, nsrc)]
+    both = [(n, j, m) for m in range(nrec) for n in range(nsrc) for j in range(nsrc) if j != n]
+    chi1, _ = O.misfit_cr(T, To, np.array(once, np.int32), np.array([wsym[t] for t in once]))
+    chi2, R2 = O.misfit_cr(T, To, np.array(both, np.int32), np.array([wsym[t] for t in both]))
+    assert abs(chi2 - 2 * chi1) <= 1e-13 * chi1
+    d = (T[:, None, :] - T[None, :, :]) - (To[:, None, :] - To[None, :, :])   # [n, j, m]
+    closed = 2 * (wsym * d).sum(axis=1)
+    assert np.abs(R2 - closed).max() <= 1e-12 * np.abs(closed).max()
+
+
+def test_misfit_cr_rejects_bad_index():
+    T = np.ones((2, 3))
+    with pytest.raises(ValueError):
+        O.misfit_cr(T, T, np.array([[0, 2, 1]], np.int32))
+    with pytest.raises(ValueError):
+        O.misfit_cr(T, T, np.array([[0, 1, 3]], np.int32))
+
+
 # ------------------------------------------------------ interpolation, cells
 def test_trilinear_sampling_exact_on_linear_fields():
     g = W.spherical_grid(9, 8.0, 0.05)
