@@ -126,10 +126,27 @@ int tt_sample(const tt_grid* grid, int32_t nsrc, const double* src_pos, const do
  *   pairs [npair][2] receiver index pairs shared by every source, each
  *   unordered pair listed once (npair may be 0, pairs NULL); wpair
  *   [nsrc][npair] or NULL (= 1).
- *   R out [nsrc][nrec]; chi out [1] (device scalar). */
+ *   R out [nsrc][nrec]; chi out [1] (device scalar).
+ * A pair index outside [0, nrec) is skipped and makes chi NaN.  Does not wait. */
 int tt_misfit(int32_t nsrc, int32_t nrec, const double* T_rec, const double* T_obs, const double* w,
               int32_t npair, const int32_t* pairs, const double* wpair, double alpha, double beta,
               double* R, double* chi, void* stream);
+
+/* Common-receiver differential misfit gamma*chi_cr (Eq. (4), third misfit)
+ * and its adjoint sources (Eq. (A4)), ADDED to R and chi: call it after
+ * tt_misfit on the same stream for chi = alpha*chi_t + beta*chi_cs +
+ * gamma*chi_cr (Eq. (1)).  The source pairs are grouped by receiver:
+ *   cr_off [nrec + 1] (device int32): the pairs recorded at receiver m are
+ *       numbers cr_off[m] .. cr_off[m+1]-1; cr_off[0] = 0 and non-decreasing;
+ *   cr_pair [cr_off[nrec]][2] (device int32) source indices (n, j), each
+ *       unordered pair at one receiver listed once (NULL if cr_off[nrec] = 0);
+ *   wcr [cr_off[nrec]] weights w_{n,j|m}, or NULL (= 1).
+ *   T_rec, T_obs [nsrc][nrec]; R in/out [nsrc][nrec]; chi in/out (device
+ *   scalar).  A negative or decreasing offset, pairs with cr_pair NULL, or a
+ *   source index outside [0, nsrc) is skipped and makes chi NaN.  Pairs of one receiver are applied in list
+ *   order (deterministic).  Does not wait. */
+int tt_misfit_cr(int32_t nsrc, int32_t nrec, const double* T_rec, const double* T_obs, const int32_t* cr_off,
+                 const int32_t* cr_pair, const double* wcr, double gamma, double* R, double* chi, void* stream);
 
 /* Adjoint solve (Sec. 2.1 step 2, Eq. (5)) as the exact transpose of the
  * discrete forward system at the converged tau: J^T lambda = d chi / d tau with

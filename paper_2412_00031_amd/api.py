@@ -145,8 +145,11 @@ def sample(grid, src_pos, src_par, tau, rec_pos, ws=None):
     return out
 
 
-def misfit(T_rec, T_obs, w=None, pairs=None, wpair=None, alpha=1.0, beta=1.0):
-    """chi (device scalar tensor) and adjoint sources R [nsrc, nrec]."""
+def misfit(T_rec, T_obs, w=None, pairs=None, wpair=None, alpha=1.0, beta=1.0, cr=None, wcr=None, gamma=1.0):
+    """chi = alpha chi_t + beta chi_cs [+ gamma chi_cr] (Eq. (1)) as a device
+    scalar tensor, and adjoint sources R [nsrc, nrec].  cr = (cr_off [nrec+1],
+    cr_pair [npair_cr, 2]) int32 device tensors: the source pairs of each
+    receiver (see misfit_cr); wcr [npair_cr] or None."""
     lib = _lib.load()
     nsrc, nrec = int(T_rec.shape[0]), int(T_rec.shape[1])
     dev = T_rec.device
@@ -158,6 +161,24 @@ def misfit(T_rec, T_obs, w=None, pairs=None, wpair=None, alpha=1.0, beta=1.0):
                              _dev(pairs, "pairs", torch.int32, numel=2 * npair) if npair else _null(),
                              _dev(wpair, "wpair", numel=nsrc * npair) if wpair is not None else _null(),
                              float(alpha), float(beta), _dev(R, "R"), _dev(chi, "chi"), _stream(dev)))
+    if cr is not None:
+        misfit_cr(T_rec, T_obs, cr[0], cr[1], wcr, gamma, R, chi)
+    return chi, R
+
+
+def misfit_cr(T_rec, T_obs, cr_off, cr_pair, wcr, gamma, R, chi):
+    """Adds gamma chi_cr (Eq. (4)) to chi and its adjoint sources (Eq. (A4)) to
+    R, in place.  cr_off [nrec+1] int32: the source pairs recorded at receiver m
+    are rows cr_off[m]..cr_off[m+1]-1 of cr_pair [npair_cr, 2] int32, each
+    unordered pair at a receiver listed once; wcr [npair_cr] or None (= 1)."""
+    lib = _lib.load()
+    nsrc, nrec = int(T_rec.shape[0]), int(T_rec.shape[1])
+    npc = int(cr_pair.shape[0])
+    _lib.check(lib.tt_misfit_cr(nsrc, nrec, _dev(T_rec, "T_rec"), _dev(T_obs, "T_obs", numel=nsrc * nrec),
+                                _dev(cr_off, "cr_off", torch.int32, numel=nrec + 1),
+                                _dev(cr_pair, "cr_pair", torch.int32, numel=2 * npc) if npc else _null(),
+                                _dev(wcr, "wcr", numel=npc) if wcr is not None else _null(), float(gamma),
+                                _dev(R, "R", numel=nsrc * nrec), _dev(chi, "chi", numel=1), _stream(T_rec.device)))
     return chi, R
 
 

@@ -1,8 +1,9 @@
 """Differentiable traveltime misfit: chi(s, xi, eta) as a torch.autograd.Function.
 
 Forward: batched fast-sweeping solve (Sec. 2.1 step 1), receiver traveltimes
-and the misfit chi = alpha chi_t + beta chi_cs (Eqs. (1)-(3)).  Backward: the
-adjoint solve at the adjoint sources R = d chi / d T (Eq. (5), (A2)-(A3)) and
+and the misfit chi = alpha chi_t + beta chi_cs + gamma chi_cr (Eqs. (1)-(4)).
+Backward: the adjoint solve at the adjoint sources R = d chi / d T (Eq. (5),
+(A2)-(A4)) and
 the kernels (Eqs. (6)-(8)) scaled by the incoming gradient.  Both passes run
 in libtt through the C ABI; this module only routes tensors.
 
@@ -28,7 +29,8 @@ class EikonalMisfit(torch.autograd.Function):
                               tile_k=problem.get("tile_k_fwd", 0))
         T = api.sample(g, src, par, tau, rec)
         chi, R = api.misfit(T, T_obs, problem.get("w"), problem.get("pairs"), problem.get("wpair"),
-                            problem.get("alpha", 1.0), problem.get("beta", 1.0))
+                            problem.get("alpha", 1.0), problem.get("beta", 1.0), problem.get("cr"),
+                            problem.get("wcr"), problem.get("gamma", 1.0))
         ctx.save_for_backward(s.detach(), xi.detach(), eta.detach(), tau, R, par)
         ctx.problem = problem
         ctx.status_fwd = st
@@ -49,5 +51,6 @@ class EikonalMisfit(torch.autograd.Function):
 def misfit(s, xi, eta, problem):
     """chi(s, xi, eta) for the sources, receivers and observations in
     ``problem`` (keys: grid, src, rec, T_obs, tol, kappa, optional max_iter,
-    adj_tol, src_par, w, pairs, wpair, alpha, beta, tile_k_fwd, tile_k_adj)."""
+    adj_tol, src_par, w, pairs, wpair, alpha, beta, cr = (cr_off, cr_pair), wcr,
+    gamma, tile_k_fwd, tile_k_adj; see api.misfit)."""
     return EikonalMisfit.apply(s, xi, eta, problem)

@@ -520,6 +520,19 @@ int tt_misfit(int32_t nsrc, int32_t nrec, const double* T_rec, const double* T_o
     return TT_OK;
 }
 
+int tt_misfit_cr(int32_t nsrc, int32_t nrec, const double* T_rec, const double* T_obs, const int32_t* cr_off,
+                 const int32_t* cr_pair, const double* wcr, double gamma, double* R, double* chi, void* stream) {
+    g_err.clear();
+    if (nsrc < 0 || nrec < 0) return fail(TT_EINVAL, "negative count");
+    int rc = check_ptrs({T_rec, T_obs, cr_off, R, chi});
+    if (rc) return rc;
+    if (!std::isfinite(gamma)) return fail(TT_EINVAL, "gamma not finite");
+    if (nrec == 0) return TT_OK;
+    tt::launch_misfit_cr(nsrc, nrec, T_rec, T_obs, cr_off, cr_pair, wcr, gamma, R, chi, (hipStream_t)stream);
+    TT_HIP(hipGetLastError());
+    return TT_OK;
+}
+
 int tt_adjoint(const tt_grid* grid, const double* s, const double* xi, const double* eta, int32_t nsrc,
                const double* src_pos, const double* src_par, const double* tau, int32_t nrec, const double* rec_pos,
                const double* R, const tt_opts* opts, double* lam, int32_t* status, void* ws, size_t ws_bytes,

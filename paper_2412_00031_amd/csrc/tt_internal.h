@@ -248,6 +248,8 @@ void launch_sample(const Plan& P, const double* tau, int nrec, const double* rec
 void launch_misfit(int nsrc, int nrec, const double* T, const double* Tobs, const double* w, int npair,
                    const int32_t* pairs, const double* wpair, double alpha, double beta, double* R,
                    double* chi, hipStream_t st);
+void launch_misfit_cr(int nsrc, int nrec, const double* T, const double* Tobs, const int32_t* off, const int32_t* pair,
+                      const double* wcr, double gamma, double* R, double* chi, hipStream_t st);
 void launch_mg_project(const Geo& G, int H, const int* m, const double* coords, const double* K, double* out,
                        hipStream_t st);
 void launch_mg_expand(const Geo& G, int H, const int* m, const double* coords, const double* C, double* field,

@@ -929,6 +929,9 @@ __global__ void __launch_bounds__(256) k_misfit(int nsrc, int nrec, const double
                                                 const double* __restrict__ wpair, double alpha, double beta,
                                                 double* __restrict__ R, double* __restrict__ chi) {
     __shared__ double sh[4];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
     double part = 0.0;
     for (int q = threadIdx.x; q < nsrc; q += blockDim.x) {
         const long long base = (long long)q * nrec;
@@ -940,6 +943,10 @@ __global__ void __launch_bounds__(256) k_misfit(int nsrc, int nrec, const double
         }
         for (int p = 0; p < npair; ++p) {
             const int m = pairs[2 * p], i = pairs[2 * p + 1];
+            if (m < 0 || m >= nrec || i < 0 || i >= nrec) {
+                bad = 1;
+                continue;
+            }
             const double ww = wpair ? wpair[(long long)q * npair + p] : 1.0;
             const double r = (T[base + m] - T[base + i]) - (Tobs[base + m] - Tobs[base + i]);
             part += beta * 0.5 * ww * r * r;
@@ -948,7 +955,44 @@ __global__ void __launch_bounds__(256) k_misfit(int nsrc, int nrec, const double
         }
     }
     const double tot = block_sum256(part, sh);
-    if (threadIdx.x == 0) *chi = tot;
+    if (threadIdx.x == 0) *chi = bad ? __builtin_nan("") : tot;
+}
+
+// Common-receiver differential misfit (Eq. (4), third misfit) and its adjoint
+// sources (Eq. (A4)), added to R and chi.  One thread owns receiver m (a column
+// of R) and walks that receiver's source pairs in list order, so no two
+// threads write one element and the sums are deterministic.
+__global__ void __launch_bounds__(256) k_misfit_cr(int nsrc, int nrec, const double* __restrict__ T,
+                                                   const double* __restrict__ Tobs, const int32_t* __restrict__ off,
+                                                   const int32_t* __restrict__ pair, const double* __restrict__ wcr,
+                                                   double gamma, double* __restrict__ R, double* __restrict__ chi) {
+    __shared__ double sh[4];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    double part = 0.0;
+    for (int m = threadIdx.x; m < nrec; m += blockDim.x) {
+        const int p0 = off[m], p1 = off[m + 1];
+        if (p0 < 0 || p1 < p0 || (p1 > p0 && !pair)) {
+            bad = 1;
+            continue;
+        }
+        for (int p = p0; p < p1; ++p) {
+            const int n = pair[2 * p], j = pair[2 * p + 1];
+            if (n < 0 || n >= nsrc || j < 0 || j >= nsrc) {
+                bad = 1;
+                continue;
+            }
+            const long long cn = (long long)n * nrec + m, cj = (long long)j * nrec + m;
+            const double ww = wcr ? wcr[p] : 1.0;
+            const double r = (T[cn] - T[cj]) - (Tobs[cn] - Tobs[cj]);
+            part += gamma * 0.5 * ww * r * r;
+            R[cn] += gamma * ww * r;
+            R[cj] -= gamma * ww * r;
+        }
+    }
+    const double tot = block_sum256(part, sh);
+    if (threadIdx.x == 0) *chi = bad ? __builtin_nan("") : *chi + tot;
 }
 
 template <int COORD>
@@ -1146,6 +1190,11 @@ void launch_misfit(int nsrc, int nrec, const double* T, const double* Tobs, cons
                    hipStream_t st) {
     hipLaunchKernelGGL(k_misfit, dim3(1), dim3(256), 0, st, nsrc, nrec, T, Tobs, w, npair, pairs, wpair, alpha, beta,
                        R, chi);
+}
+
+void launch_misfit_cr(int nsrc, int nrec, const double* T, const double* Tobs, const int32_t* off, const int32_t* pair,
+                      const double* wcr, double gamma, double* R, double* chi, hipStream_t st) {
+    hipLaunchKernelGGL(k_misfit_cr, dim3(1), dim3(256), 0, st, nsrc, nrec, T, Tobs, off, pair, wcr, gamma, R, chi);
 }
 
 // ------------------------------------------- multiple-grid parameterisation

@@ -126,6 +126,29 @@ def random_pairs(nrec, count, rng):
     return np.asarray(out, dtype=np.int32)
 
 
+def receiver_source_pairs(nsrc, nrec, per_rec, rng):
+    """Common-receiver pairs grouped by receiver: per_rec distinct unordered
+    source pairs (n, j), n < j, at each receiver (fewer if nsrc is small).
+    Returns (off [nrec+1], pair [off[-1], 2]) int32 and the same pairs as
+    triples (n, j, m) [off[-1], 3] in the same order."""
+    off = [0]
+    pair = []
+    for _ in range(nrec):
+        cnt = min(per_rec, nsrc * (nsrc - 1) // 2)
+        seen = set()
+        while len(seen) < cnt:
+            n, j = rng.integers(0, nsrc, 2)
+            if n == j or (min(n, j), max(n, j)) in seen:
+                continue
+            seen.add((min(n, j), max(n, j)))
+            pair.append((min(n, j), max(n, j)))
+        off.append(len(pair))
+    off = np.asarray(off, dtype=np.int32)
+    pair = np.asarray(pair, dtype=np.int32).reshape(-1, 2)
+    m = np.repeat(np.arange(nrec, dtype=np.int32), np.diff(off))
+    return off, pair, np.concatenate([pair, m[:, None]], axis=1)
+
+
 def straight_line_times(grid, src_pos, rec_pos, v_ref):
     """Observation stand-ins: straight-chord distance / v_ref (km/s).  A data
     generator only (no relation to the solver's discretisation)."""

@@ -15,7 +15,7 @@ def _dev(torch, a, dtype=None):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device="cuda")
 
 
-def _problem(torch, wl, nsrc, T_obs, tol, pairs=None):
+def _problem(torch, wl, nsrc, T_obs, tol, pairs=None, cr=None):
     from paper_2412_00031_amd import api
     s, xi, eta = (_dev(torch, wl[k]) for k in ("s", "xi", "eta"))
     src = _dev(torch, wl["src"][:nsrc])
@@ -24,13 +24,17 @@ def _problem(torch, wl, nsrc, T_obs, tol, pairs=None):
                 adj_tol=tol, kappa=wl["kappa"], max_iter=5000, src_par=par)
     if pairs is not None:
         prob["pairs"] = _dev(torch, pairs, torch.int32)
+    if cr is not None:
+        off, pair, _ = cr
+        prob.update(cr=(_dev(torch, off, torch.int32), _dev(torch, pair, torch.int32)), gamma=0.8,
+                    alpha=0.5)
     return s, xi, eta, prob
 
 
-def _fd_check(torch, wl, nsrc, ncell, seed, tol, steps=(2e-6, 2e-5, 2e-5), pairs=None, rtol=2e-5):
+def _fd_check(torch, wl, nsrc, ncell, seed, tol, steps=(2e-6, 2e-5, 2e-5), pairs=None, rtol=2e-5, cr=None):
     from paper_2412_00031_amd.autograd import misfit
     T_obs = W.straight_line_times(wl["grid"], wl["src"], wl["rec"], 6.4)
-    s, xi, eta, prob = _problem(torch, wl, nsrc, T_obs, tol, pairs)
+    s, xi, eta, prob = _problem(torch, wl, nsrc, T_obs, tol, pairs, cr)
     m = [s.clone().requires_grad_(True), xi.clone().requires_grad_(True), eta.clone().requires_grad_(True)]
     chi = misfit(m[0], m[1], m[2], prob)
     chi.backward()
@@ -67,6 +71,16 @@ def test_autograd_matches_fd_small_spherical(torch_cuda):
     wl = W.small_spherical(n=(14, 15, 16), nsrc=3, nrec=12, seed=41, aniso=0.05)
     pairs = W.random_pairs(12, 10, np.random.default_rng(3))
     _fd_check(torch_cuda, wl, 3, 16, 7, 1e-15, pairs=pairs)
+
+
+def test_autograd_matches_fd_with_common_receiver_pairs(torch_cuda):
+    """Eq. (1) with all three misfits: the common-receiver term couples the
+    sources' adjoint sources, and the gradient still matches differences."""
+    wl = W.small_spherical(n=(14, 15, 16), nsrc=3, nrec=12, seed=43, aniso=0.05)
+    rng = np.random.default_rng(5)
+    pairs = W.random_pairs(12, 10, rng)
+    cr = W.receiver_source_pairs(3, 12, 2, rng)
+    _fd_check(torch_cuda, wl, 3, 16, 9, 1e-15, pairs=pairs, cr=cr)
 
 
 @pytest.mark.slow

@@ -41,6 +41,10 @@ def oracle_path(wl, tol, max_iter, R=None, T_obs=None, adj_tol=None, max_iter_ad
     chi = None
     if R is None:
         chi, R = O.misfit(T, T_obs, pairs=wl.get("pairs"))
+        cr = wl.get("cr")
+        if cr is not None:
+            chi_cr, R = O.misfit_cr(T, T_obs, cr["tri"], cr.get("w"), cr["gamma"], R)
+            chi += chi_cr
     lams, ita = [], []
     grad = np.zeros((3,) + tuple(g["n"]))
     for q in range(len(src)):
@@ -68,7 +72,12 @@ def gpu_path(torch, wl, tol, max_iter, R=None, T_obs=None, adj_tol=None, max_ite
     chi = None
     if R is None:
         pairs = None if wl.get("pairs") is None else _dev(torch, wl["pairs"], torch.int32)
-        chi, Rd = api.misfit(T, _dev(torch, T_obs), pairs=pairs)
+        cr = wl.get("cr")
+        kw = {}
+        if cr is not None:
+            kw = dict(cr=(_dev(torch, cr["off"], torch.int32), _dev(torch, cr["pair"], torch.int32)),
+                      wcr=None if cr.get("w") is None else _dev(torch, cr["w"]), gamma=cr["gamma"])
+        chi, Rd = api.misfit(T, _dev(torch, T_obs), pairs=pairs, **kw)
         chi = float(chi.item())
     else:
         Rd = _dev(torch, R)
@@ -265,6 +274,93 @@ def test_misfit_path_with_pairs_spherical(torch_cuda):
     assert abs(gp["chi"] - op["chi"]) <= np.abs(op["R"]).sum() * dT + 1e-15 * abs(op["chi"])
     touch = np.bincount(wl["pairs"].reshape(-1), minlength=op["R"].shape[1])
     assert (np.abs(gp["R"] - op["R"]) <= (1 + 2 * touch)[None, :] * dT + 1e-15).all()
+    assert_parity(gp, op)
+
+
+def _cr_inputs(nsrc, nrec, per_rec, seed, empty_every=0):
+    rng = np.random.default_rng(seed)
+    off, pair, tri = W.receiver_source_pairs(nsrc, nrec, per_rec, rng)
+    if empty_every:
+        # receivers without any pair: drop every empty_every-th receiver's list
+        keep = tri[:, 2] % empty_every != 0
+        tri = tri[keep]
+        pair = tri[:, :2].copy()
+        off = np.concatenate([[0], np.cumsum(np.bincount(tri[:, 2], minlength=nrec))]).astype(np.int32)
+    return dict(off=off, pair=np.ascontiguousarray(pair), tri=np.ascontiguousarray(tri),
+                w=rng.uniform(0.5, 2.0, len(tri)), gamma=0.9)
+
+
+@pytest.mark.parametrize("nsrc,nrec,per_rec,empty_every", [(9, 300, 12, 0), (5, 40, 10, 3), (2, 7, 1, 0)])
+def test_misfit_cr_parity(torch_cuda, nsrc, nrec, per_rec, empty_every):
+    """Eq. (1) with all three misfits against the oracle: chi to 1e-13, R to
+    1e-14 (each R element sees the same additions in the same order; only
+    contraction of multiply-adds differs).  300 receivers exceed one pass of the
+    256-thread block; receivers with no pair and a single pair per receiver are
+    covered."""
+    from paper_2412_00031_amd import api
+    rng = np.random.default_rng(31 + nsrc)
+    T = rng.uniform(1, 20, (nsrc, nrec))
+    Tobs = T + rng.normal(0, 0.2, T.shape)
+    w = rng.uniform(0.5, 1.5, T.shape)
+    pairs = W.random_pairs(nrec, min(60, nrec * (nrec - 1) // 2), rng)
+    cr = _cr_inputs(nsrc, nrec, per_rec, 40 + nsrc, empty_every)
+    chi_o, R_o = O.misfit(T, Tobs, w, pairs, None, alpha=0.7, beta=1.3)
+    chi_cr, R_o = O.misfit_cr(T, Tobs, cr["tri"], cr["w"], cr["gamma"], R_o)
+    chi_o += chi_cr
+    d = lambda a, dt=None: _dev(torch_cuda, a, dt)
+    chi_g, R_g = api.misfit(d(T), d(Tobs), d(w), d(pairs, torch_cuda.int32), None, 0.7, 1.3,
+                            cr=(d(cr["off"], torch_cuda.int32), d(cr["pair"], torch_cuda.int32)), wcr=d(cr["w"]),
+                            gamma=cr["gamma"])
+    assert abs(chi_g.item() - chi_o) <= 1e-13 * abs(chi_o)
+    assert rel_inf(R_g.cpu().numpy(), R_o) <= 1e-14
+
+
+def test_misfit_cr_no_pairs_and_bad_indices(torch_cuda):
+    """No pairs (NULL pair list) leaves chi and R as tt_misfit left them; an
+    out-of-range source index or a decreasing offset is skipped by the
+    kernel's own checks and reported as chi = NaN."""
+    from paper_2412_00031_amd import api
+    rng = np.random.default_rng(50)
+    T = rng.uniform(1, 20, (3, 5))
+    Tobs = T + rng.normal(0, 0.2, T.shape)
+    d = lambda a, dt=None: _dev(torch_cuda, a, dt)
+    chi0, R0 = api.misfit(d(T), d(Tobs))
+    empty = (d(np.zeros(6, np.int32), torch_cuda.int32), d(np.zeros((0, 2), np.int32), torch_cuda.int32))
+    chi1, R1 = api.misfit(d(T), d(Tobs), cr=empty, gamma=2.0)
+    assert chi1.item() == chi0.item() and torch_cuda.equal(R1, R0)
+    bad_src = (d(np.array([0, 1, 1, 1, 1, 1], np.int32), torch_cuda.int32), d(np.array([[0, 3]], np.int32), torch_cuda.int32))
+    chi2, _ = api.misfit(d(T), d(Tobs), cr=bad_src)
+    assert np.isnan(chi2.item())
+    bad_off = (d(np.array([0, 1, 0, 1, 1, 1], np.int32), torch_cuda.int32), d(np.array([[0, 2]], np.int32), torch_cuda.int32))
+    chi3, _ = api.misfit(d(T), d(Tobs), cr=bad_off)
+    assert np.isnan(chi3.item())
+    bad_pair = d(np.array([[0, 7]], np.int32), torch_cuda.int32)
+    chi4, _ = api.misfit(d(T), d(Tobs), pairs=bad_pair)
+    assert np.isnan(chi4.item())
+
+
+def test_misfit_path_with_cr_pairs_spherical(torch_cuda):
+    """Forward, sampling, all three misfits, adjoint and kernels with the
+    common-receiver term coupling the sources."""
+    wl = W.small_spherical(n=(12, 13, 17), nsrc=4, nrec=12, seed=23)
+    rng = np.random.default_rng(24)
+    wl["pairs"] = W.random_pairs(len(wl["rec"]), 10, rng)
+    wl["cr"] = _cr_inputs(4, len(wl["rec"]), 3, 25)
+    T_obs = W.straight_line_times(wl["grid"], wl["src"], wl["rec"], 6.3)
+    op = oracle_path(wl, 1e-11, 300, T_obs=T_obs)
+    gp = gpu_path(torch_cuda, wl, 1e-11, 300, T_obs=T_obs)
+    # chi and R inherit the traveltime error |dT| <= 1e-12 max|T|: each R
+    # element moves by at most (1 + 2 * pairs touching it) |dT| times the
+    # largest weight
+    dT = 1e-12 * np.abs(op["T"]).max()
+    assert abs(gp["chi"] - op["chi"]) <= np.abs(op["R"]).sum() * dT + 1e-15 * abs(op["chi"])
+    touch = np.zeros(op["R"].shape)
+    touch += np.bincount(wl["pairs"].reshape(-1), minlength=op["R"].shape[1])[None, :]
+    for n, j, m in wl["cr"]["tri"]:
+        touch[n, m] += 1
+        touch[j, m] += 1
+    wmax = max(1.0, wl["cr"]["gamma"] * wl["cr"]["w"].max())
+    assert (np.abs(gp["R"] - op["R"]) <= (1 + 2 * touch) * wmax * dT + 1e-15).all()
     assert_parity(gp, op)
 
 
