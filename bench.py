@@ -16,8 +16,12 @@ figures in "plain".
 
 Prints one JSON line (rank 0).  Extra objects: "roofline" (the dominant sweep
 kernel, timed live with HIP event pairs around the back-to-back launches of
-each directional sweep, on the library's stream) and
-"cpu_baseline" (the CPU oracle on a bounded sample of the same workload).
+each directional sweep, on the library's stream),
+"cpu_baseline" (the CPU oracle on a bounded sample of the same workload) and
+"aux" (the kernels that run once per inversion step outside the solves --
+kernel density, multiple-grid projection and expansion, common-receiver
+misfit -- each timed on seeded inputs of the workload's shapes against its
+algorithmic bytes, with the oracle's time for the same call beside it).
 """
 import argparse
 import json
@@ -60,6 +64,10 @@ def parse():
     ap.add_argument("--weights", default=None, help="U-Net weights (.npz) of the warm start")
     ap.add_argument("--groups", type=int, default=0,
                     help="concurrently iterated source groups of each solve (0: library default)")
+    ap.add_argument("--aux-only", action="store_true",
+                    help="time only the per-step kernels outside the solves (kernel density, multiple-grid "
+                         "projection/expansion, common-receiver misfit) and print their object")
+    ap.add_argument("--no-aux", action="store_true", help="skip the auxiliary-kernel timings")
     ap.add_argument("--roofline-only", action="store_true",
                     help="run only the roofline step (sweep kernels timed per directional sweep)")
     return ap.parse_args()
@@ -138,6 +146,121 @@ def cpu_baseline(wl, it_f, it_a, threads):
     return threads / per_source, wall
 
 
+AUX_GRIDS = dict(m=(11, 13, 13), H=5)
+AUX_CR_PER_REC = 64
+
+
+def aux_inputs(wl, nsrc):
+    """Seeded synthetic inputs for the per-step kernels outside the solves, with
+    the workload's shapes: gradient fields [3, N] and an adjoint density field
+    [N], H = 5 staggered 11 x 13 x 13 inversion grids, traveltimes [nsrc, nrec]
+    and 64 common-receiver source pairs per receiver."""
+    import numpy as np
+    from paper_2412_00031_amd import workloads as W
+    g = wl["grid"]
+    n = tuple(g["n"])
+    rng = np.random.default_rng(9001)
+    grad = rng.standard_normal((3,) + n)
+    dens = np.abs(rng.standard_normal(n)) + 0.1
+    inv = W.staggered_inversion_grids(g, AUX_GRIDS["m"], AUX_GRIDS["H"])
+    C = [rng.standard_normal((3,) + tuple(len(c) for c in axes)) for axes in inv]
+    nrec = len(wl["rec"])
+    T = rng.uniform(5.0, 30.0, (nsrc, nrec))
+    T_obs = T + rng.normal(0.0, 0.2, T.shape)
+    off, pair, tri = W.receiver_source_pairs(nsrc, nrec, AUX_CR_PER_REC, rng)
+    wcr = rng.uniform(0.5, 2.0, len(tri))
+    return dict(grad=grad, dens=dens, inv=inv, C=C, T=T, T_obs=T_obs, off=off, pair=pair, tri=tri, wcr=wcr,
+                eps=1e-3, zeta=0.5, gamma=1.0)
+
+
+def aux_gpu(wl, a, dev, reps=20):
+    """Average launch time of each per-step kernel outside the solves, by
+    torch events on the stream the kernels run on (torch's current stream,
+    which the binding passes to the library), and its algorithmic HBM bytes."""
+    import ctypes
+    import numpy as np
+    import torch
+    from paper_2412_00031_amd import _lib, api
+    lib = _lib.load()
+    g = wl["grid"]
+    N = int(np.prod(g["n"]))
+    t = lambda x, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device=dev)
+    s, grad, dens = t(wl["s"]), t(a["grad"]), t(a["dens"])
+    m, coords, sizes = api._mg_args(a["inv"], dev)
+    M = sum(3 * x * y * z for x, y, z in sizes)
+    proj = torch.empty(M, dtype=torch.float64, device=dev)
+    Cf = t(np.concatenate([c.reshape(-1) for c in a["C"]]))
+    field = torch.empty((3, N), dtype=torch.float64, device=dev)
+    gr = api._grid(g)
+    T, Tobs = t(a["T"]), t(a["T_obs"])
+    off, pair, wcr = t(a["off"], torch.int32), t(a["pair"], torch.int32), t(a["wcr"])
+    R = torch.zeros_like(T)
+    chi = torch.zeros((), dtype=torch.float64, device=dev)
+    cp = lambda x: ctypes.c_void_p(x.data_ptr())
+    st = lambda: ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    calls = {
+        "k_kernel_density": (lambda: api.kernel_density(g, s, dens, grad, a["eps"], a["zeta"]), 72.0 * N, "hbm"),
+        "k_mg_project": (lambda: _lib.check(lib.tt_mg_project(ctypes.byref(gr), len(sizes), m, cp(coords), cp(grad),
+                                                                cp(proj), st())), 24.0 * N + 8.0 * M, "hbm"),
+        "k_mg_expand": (lambda: _lib.check(lib.tt_mg_expand(ctypes.byref(gr), len(sizes), m, cp(coords), cp(Cf),
+                                                              cp(field), st())), 24.0 * N + 8.0 * M, "hbm"),
+        "k_misfit_cr": (lambda: api.misfit_cr(T, Tobs, off, pair, wcr, a["gamma"], R, chi),
+                        80.0 * len(a["tri"]), "latency"),
+    }
+    out = {}
+    for name, (fn, nbytes, bound) in calls.items():
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out[name] = {"avg_launch_ms": round(ms, 4), "algorithmic_bytes": int(nbytes), "achieved": round(gbs, 1),
+                     "unit": "GB/s", "bound": bound}
+        if bound == "hbm":
+            out[name].update(peak=HBM_PEAK_GBS, frac=round(gbs / HBM_PEAK_GBS, 4))
+    return out
+
+
+def aux_cpu(wl, a):
+    """The oracle's version of each auxiliary kernel on the same inputs, one
+    thread, one call each (part of the CPU baseline leg)."""
+    import oracle as O
+    g = wl["grid"]
+    out = {}
+    t0 = time.perf_counter()
+    O.kernel_density(g, wl["s"], a["dens"], a["grad"], a["eps"], a["zeta"])
+    out["k_kernel_density"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.mg_project(g, a["inv"], a["grad"])
+    out["k_mg_project"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.mg_expand(g, a["inv"], a["C"])
+    out["k_mg_expand"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.misfit_cr(a["T"], a["T_obs"], a["tri"], a["wcr"], a["gamma"])
+    out["k_misfit_cr"] = time.perf_counter() - t0
+    return {k: round(v * 1e3, 3) for k, v in out.items()}
+
+
+def aux_section(wl, nsrc, dev, with_cpu):
+    a = aux_inputs(wl, nsrc)
+    res = aux_gpu(wl, a, dev)
+    if with_cpu:
+        for k, ms in aux_cpu(wl, a).items():
+            res[k]["oracle_ms"] = ms
+            res[k]["oracle_cores"] = 1
+    res["inputs"] = (f"101^3 grid; {AUX_GRIDS['H']} staggered {AUX_GRIDS['m']} inversion grids; {nsrc} sources x "
+                     f"{len(wl['rec'])} receivers with {AUX_CR_PER_REC} source pairs per receiver; seeded synthetic "
+                     f"fields; average of 20 launches after 3")
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -160,6 +283,9 @@ def main():
         log(f"copy probe: {args.copy_probe} MiB read + {args.copy_probe} MiB written")
     wl = W.sph101(nsrc=args.nsrc)
     g, kappa, tol = wl["grid"], wl["kappa"], wl["tol"]
+    if args.aux_only:
+        print(json.dumps({"aux": aux_section(wl, args.nsrc, dev, not args.no_cpu_baseline)}), flush=True)
+        return
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     s, xi, eta, src, rec = t(wl["s"]), t(wl["xi"]), t(wl["eta"]), t(wl["src"]), t(wl["rec"])
     nsrc = args.nsrc
@@ -302,6 +428,11 @@ def main():
                          f"capped at 1 and 3 iterations, one kernel pass; scaled per source to the converged "
                          f"iteration counts ({wall:.1f} s wall)"}
 
+    aux = None
+    if not args.no_aux:
+        log("auxiliary kernels")
+        aux = aux_section(wl, nsrc, dev, not args.no_cpu_baseline)
+
     def summary(r):
         return {"value": round(nsrc * r["steps"] / r["elapsed"], 4), "ms_per_step": round(1e3 * r["elapsed"] / r["steps"], 2),
                 "mean_iters_fwd": round(float(r["it_f"].mean()), 2), "mean_iters_adj": round(float(r["it_a"].mean()), 2),
@@ -323,7 +454,7 @@ def main():
                               "chosen_by": "autotune" if tuned else ("fixed" if (tk_f or tk_a) else "default")},
                    "graph": bool(args.graph),
                    "source_groups": args.groups or max(1, min(4, nsrc // 32))},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "aux": aux,
     }
     print(json.dumps(line), flush=True)
 

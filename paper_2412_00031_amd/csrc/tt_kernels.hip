@@ -1198,6 +1198,15 @@ void launch_misfit_cr(int nsrc, int nrec, const double* T, const double* Tobs, c
 }
 
 // ------------------------------------------- multiple-grid parameterisation
+// Coordinate of node i on axis a, rounded as o + i h is by definition (product,
+// then sum; no fused multiply-add).  A tent ends abruptly at the first and last
+// inversion node, so a node lying on such an end must land on the same side
+// of it whoever evaluates the basis.
+__device__ __forceinline__ double node_coord(const Geo& G, int a, int i) {
+#pragma clang fp contract(off)
+    return G.o[a] + (double)i * G.h[a];
+}
+
 // One-dimensional tent of inversion node i (ascending coordinates c[0..m-1])
 // at x (Eqs. (12)-(14)); zero outside [c[0], c[m-1]].
 __device__ __forceinline__ double mg_tent(const double* c, int m, int i, double x) {
@@ -1253,9 +1262,9 @@ __global__ void __launch_bounds__(64) k_mg_project(Geo G, int H, int m0, int m1,
         const int k = klo + (int)(e % nk);
         const int j = jlo + (int)((e / nk) % nj);
         const int i = ilo + (int)(e / ((long long)nk * nj));
-        const double u = mg_tent(c0, m0, ci, G.o[0] + i * G.h[0]);
-        const double v = mg_tent(c1, m1, cj, G.o[1] + j * G.h[1]);
-        const double w = mg_tent(c2, m2, ck, G.o[2] + k * G.h[2]);
+        const double u = mg_tent(c0, m0, ci, node_coord(G, 0, i));
+        const double v = mg_tent(c1, m1, cj, node_coord(G, 1, j));
+        const double w = mg_tent(c2, m2, ck, node_coord(G, 2, k));
         const double b = u * v * w / H * node_volume(G, i, j, k);
         if (b != 0.0) {
             const long long x = ((long long)i * G.n[1] + j) * G.n[2] + k;
@@ -1295,9 +1304,9 @@ __global__ void k_mg_expand(Geo G, int H, int m0, int m1, int m2, const double* 
         const int j = (int)(q % G.n[1]), i = (int)(q / G.n[1]);
         int ii[2], jj[2], kk[2];
         double wi[2], wj[2], wk[2];
-        const int na = mg_axis(c0, m0, G.o[0] + i * G.h[0], ii, wi);
-        const int nb = mg_axis(c1, m1, G.o[1] + j * G.h[1], jj, wj);
-        const int nc = mg_axis(c2, m2, G.o[2] + k * G.h[2], kk, wk);
+        const int na = mg_axis(c0, m0, node_coord(G, 0, i), ii, wi);
+        const int nb = mg_axis(c1, m1, node_coord(G, 1, j), jj, wj);
+        const int nc = mg_axis(c2, m2, node_coord(G, 2, k), kk, wk);
         double acc[3];
         for (int p = 0; p < 3; ++p) acc[p] = first ? 0.0 : field[p * G.N + x];
         for (int a = 0; a < na; ++a)

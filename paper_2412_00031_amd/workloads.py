@@ -126,6 +126,23 @@ def random_pairs(nrec, count, rng):
     return np.asarray(out, dtype=np.int32)
 
 
+def staggered_inversion_grids(grid, m, H):
+    """H regular inversion grids of m = (m0, m1, m2) nodes each, spacing
+    d_a = span_a / (m_a - 2), grid h shifted by h d_a / H along every axis, so
+    each covers the forward grid and the H grids interleave (the
+    multiple-grid parameterisation of Eqs. (11)-(17))."""
+    ax = axes(grid)
+    out = []
+    for h in range(H):
+        g = []
+        for a in range(3):
+            lo, hi = ax[a][0], ax[a][-1]
+            d = (hi - lo) / (m[a] - 2)
+            g.append(lo - d + d * h / H + d * np.arange(m[a]))
+        out.append(tuple(g))
+    return out
+
+
 def receiver_source_pairs(nsrc, nrec, per_rec, rng):
     """Common-receiver pairs grouped by receiver: per_rec distinct unordered
     source pairs (n, j), n < j, at each receiver (fewer if nsrc is small).

@@ -29,16 +29,20 @@ def _inv_grids(g, seed, sizes=((4, 3, 5), (5, 4, 4))):
     return grids
 
 
-@pytest.mark.parametrize("case", ["small", "sph101"])
+@pytest.mark.parametrize("case", ["small", "sph101", "sph101_staggered5"])
 def test_multigrid_project_expand_parity(torch_cuda, case):
     from paper_2412_00031_amd import api
     torch = torch_cuda
     if case == "small":
         g = W.small_spherical(n=(13, 14, 15), seed=3)["grid"]
         inv = _inv_grids(g, 7)
-    else:
+    elif case == "sph101":
         g = W.spherical_grid(101, 100.0, 2.0)
         inv = _inv_grids(g, 11, sizes=((11, 13, 12), (12, 11, 13)))
+    else:
+        # the inversion grids that the benchmark times: 5 staggered 11 x 13 x 13 grids
+        g = W.spherical_grid(101, 100.0, 2.0)
+        inv = W.staggered_inversion_grids(g, (11, 13, 13), 5)
     rng = np.random.default_rng(5)
     K = rng.standard_normal((3,) + tuple(g["n"]))
     P_o = O.mg_project(g, inv, K)
