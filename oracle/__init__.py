@@ -191,6 +191,24 @@ def adjoint(grid, s, xi, eta, src_pos, src_par, kappa, tau, rhs, tol, max_iter, 
     return lam, iters.value, bool(conv.value), hist[: iters.value].copy()
 
 
+def adjoint_cont(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter):
+    """P of Eq. (5) by the upwind finite-volume discretisation (reading R14):
+    point sources R_m at rec_pos through trilinear weights.  Returns
+    (P, iters, converged, eps_history)."""
+    n, coord, o, h = _grid_args(grid)
+    P = np.zeros(_shape(grid))
+    rec_pos = _f64(rec_pos).reshape(-1, 3)
+    iters, conv = ctypes.c_int(0), ctypes.c_int(0)
+    hist = np.zeros(max_iter)
+    rc = lib().tto_adjoint_cont(_i(n), coord, _d(o), _d(h), _d(_f64(s)), _d(_f64(xi)), _d(_f64(eta)),
+                                _d(_f64(src_pos)), _d(_f64(src_par)), _d(_f64(tau)), len(rec_pos), _d(rec_pos),
+                                _d(_f64(R)), ctypes.c_double(tol), int(max_iter), _d(P), ctypes.byref(iters),
+                                ctypes.byref(conv), _d(hist))
+    if rc:
+        raise ValueError("invalid arguments or receiver outside the grid")
+    return P, iters.value, bool(conv.value), hist[: iters.value].copy()
+
+
 def kernel(grid, s, xi, eta, src_pos, src_par, kappa, tau, lam, grad=None):
     """Discrete gradients [3, n] (d chi/d s, d chi/d xi, d chi/d eta); adds to grad if given."""
     n, coord, o, h = _grid_args(grid)

@@ -15,8 +15,10 @@
  *       M = [[1,0,0],[0,1-2xi,2eta],[0,2eta,1+2xi]],  T(x_s) = 0.
  *   Sec. 3.1: fast sweeping (Zhao 2005), multiplicative factorization
  *       T = T0 * tau (Luo & Qian 2012), spherical coordinates.
- *   Sec. 2.1 step 2, Eq. (5): adjoint equation; here its exact discrete
- *       counterpart, the transpose of the Jacobian of the discrete forward system.
+ *   Sec. 2.1 step 2, Eq. (5): adjoint equation; its exact discrete
+ *       counterpart, the transpose of the Jacobian of the discrete forward
+ *       system, and (R14) an upwind finite-volume discretisation of Eq. (5)
+ *       itself.
  *   Eqs. (2)-(4), (A2)-(A4): traveltime, common-source and common-receiver
  *       differential misfits and their adjoint sources R = d chi / d T(x_r).
  *   Eqs. (6)-(9): kernels; here the discrete gradients d chi/d s, d chi/d xi,
@@ -66,6 +68,16 @@
  *   (R13) common-receiver pairs (Eqs. (4) and (A4)): an explicit list of
  *        triples (n, j, m), the unordered source pair {n, j} recorded at
  *        receiver m, each counted once, as in (R9).
+ *   (R14) continuous adjoint (Eq. (5), the paper's own route): upwind finite
+ *        volumes.  The flux P w with w = -M grad T leaves each trapezoidal
+ *        control volume through six faces; the face velocity is the mean of the
+ *        two nodal normal components, the upwind side's P is carried, P = 0 on
+ *        the fixed set (the source absorbs) and outside the grid, and the point
+ *        sources of Eq. (5) enter through the trilinear weights of each
+ *        receiver.  grad T = T0 (central or, on a boundary axis, one-sided
+ *        differences of tau) + tau grad T0.  A node without outflow keeps
+ *        P = 0.  Solve: the 8 directional Gauss-Seidel sweeps over interior
+ *        nodes, each followed by one Jacobi pass over the boundary nodes.
  */
 #include <math.h>
 #include <stddef.h>
@@ -807,6 +819,195 @@ int tto_adjoint(const int* n, int coord, const double* o, const double* h,
     free(coef);
     free(list);
     free(bl);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Continuous adjoint of Eq. (5), (R14).
+ * ------------------------------------------------------------------------- */
+
+/* scaled gradient p of T = T0 tau at any node: central differences of tau on
+ * axes where the node is interior, one-sided where it is on the boundary */
+static void grad_T_any(const OGrid* g, const OSrc* S, const double* tau, int i, int j, int k, double p[3]) {
+    double T0, t[3], gm[3];
+    factor_at(g, S, i, j, k, &T0, t);
+    metric(g, i, j, gm);
+    int id[3] = {i, j, k};
+    size_t c = IDX(g, i, j, k);
+    size_t st[3] = {(size_t)g->n[1] * g->n[2], (size_t)g->n[2], 1};
+    for (int a = 0; a < 3; ++a) {
+        double q;
+        if (id[a] == 0) q = (tau[c + st[a]] - tau[c]) / g->h[a];
+        else if (id[a] == g->n[a] - 1) q = (tau[c] - tau[c - st[a]]) / g->h[a];
+        else q = (tau[c + st[a]] - tau[c - st[a]]) / (2.0 * g->h[a]);
+        p[a] = T0 * gm[a] * q + tau[c] * t[a];
+    }
+}
+
+/* control-volume extent of node index idx along axis a (coordinate units) */
+static double cv_extent(const OGrid* g, int a, int idx) {
+    return (idx == 0 || idx == g->n[a] - 1) ? 0.5 * g->h[a] : g->h[a];
+}
+
+/* area of the face of node (i,j,k) normal to axis a at coordinate xf of that
+ * axis (the face midpoint between two nodes, or the node itself on a grid face) */
+static double face_area(const OGrid* g, int a, int i, int j, int k, double xf) {
+    int id[3] = {i, j, k};
+    double A = 1.0;
+    for (int b = 0; b < 3; ++b)
+        if (b != a) A *= cv_extent(g, b, id[b]);
+    if (g->coord == 1) {
+        double r = cval(g, 0, i), th = cval(g, 1, j);
+        if (a == 0) A *= xf * xf * cos(th);   /* r = const:     r^2 cos(theta) dtheta dphi */
+        else if (a == 1) A *= r * cos(xf);    /* theta = const: r cos(theta) dr dphi */
+        else A *= r;                          /* phi = const:   r dr dtheta */
+    }
+    return A;
+}
+
+/* The finite-volume row of node x, solved by Gauss-Seidel:
+ *   diag = sum over faces of A max(u_out, 0)          (outflow),
+ *   off[2a + side] = A min(u_out, 0) for the neighbour x + (side ? -1 : +1) e_a
+ *                    (0 if it is fixed or outside),
+ * u_out the outward normal velocity of the face. */
+typedef struct {
+    double diag, off[6];
+} OCRow;
+
+static void cont_row(const OGrid* g, const OSrc* S, const double* w, int i, int j, int k, OCRow* R) {
+    int id[3] = {i, j, k};
+    size_t c = IDX(g, i, j, k);
+    size_t st[3] = {(size_t)g->n[1] * g->n[2], (size_t)g->n[2], 1};
+    R->diag = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        for (int side = 0; side < 2; ++side) {
+            int sg = side == 0 ? 1 : -1;
+            int nbi = id[a] + sg;
+            double xa = cval(g, a, id[a]);
+            double u, A;
+            int inside = nbi >= 0 && nbi < g->n[a];
+            if (inside) {
+                size_t nb = sg > 0 ? c + st[a] : c - st[a];
+                u = sg * 0.5 * (w[(size_t)a * g->N + c] + w[(size_t)a * g->N + nb]);
+                A = face_area(g, a, i, j, k, 0.5 * (xa + cval(g, a, nbi)));
+            } else {
+                u = sg * w[(size_t)a * g->N + c];
+                A = face_area(g, a, i, j, k, xa);
+            }
+            R->diag += A * (u > 0.0 ? u : 0.0);
+            double off = 0.0;
+            if (inside) {
+                int q[3] = {i, j, k};
+                q[a] = nbi;
+                if (!is_fixed(S, q[0], q[1], q[2])) off = A * (u < 0.0 ? u : 0.0);
+            }
+            R->off[2 * a + side] = off;
+        }
+    }
+}
+
+static double cont_update(const OGrid* g, const OCRow* R, const double* b, const double* P, size_t c) {
+    size_t st[3] = {(size_t)g->n[1] * g->n[2], (size_t)g->n[2], 1};
+    if (!(R->diag > 0.0)) return 0.0;
+    double acc = b[c];
+    for (int a = 0; a < 3; ++a) {
+        if (R->off[2 * a] != 0.0) acc -= R->off[2 * a] * P[c + st[a]];
+        if (R->off[2 * a + 1] != 0.0) acc -= R->off[2 * a + 1] * P[c - st[a]];
+    }
+    return acc / R->diag;
+}
+
+/* P of Eq. (5) for one source at the converged tau.  Receivers inject
+ * b_x = sum_m R_m w_x(m) (trilinear weights).  Iteration as tto_adjoint:
+ * eps = sum |dP| / max(sum |P|, 1e-300).  Returns -1 on bad input or a
+ * receiver outside the grid. */
+int tto_adjoint_cont(const int* n, int coord, const double* o, const double* h,
+                     const double* s, const double* xi, const double* eta,
+                     const double* src_pos, const double* src_par, const double* tau,
+                     int nrec, const double* rec_pos, const double* Rm, double tol, int max_iter,
+                     double* P, int* iters, int* converged, double* eps_hist) {
+    (void)s;
+    OGrid g;
+    grid_init(&g, n, coord, o, h);
+    if (check_grid(&g) || max_iter < 1) return -1;
+    OSrc S;
+    src_init(&S, &g, src_pos, src_par);
+    double* w = (double*)malloc(sizeof(double) * 3 * g.N);
+    double* b = (double*)calloc(g.N, sizeof(double));
+    OCRow* rows = (OCRow*)calloc(g.N, sizeof(OCRow));
+    size_t nbnd = boundary_count(&g);
+    size_t* bl = (size_t*)malloc(sizeof(size_t) * nbnd);
+    double* tmp = (double*)malloc(sizeof(double) * nbnd);
+    if (!w || !b || !rows || !bl || !tmp) { free(w); free(b); free(rows); free(bl); free(tmp); return -1; }
+    /* w = -M p at every node */
+    for (int i = 0; i < g.n[0]; ++i)
+        for (int j = 0; j < g.n[1]; ++j)
+            for (int k = 0; k < g.n[2]; ++k) {
+                size_t c = IDX(&g, i, j, k);
+                double p[3];
+                grad_T_any(&g, &S, tau, i, j, k, p);
+                w[c] = -p[0];
+                w[g.N + c] = -((1.0 - 2.0 * xi[c]) * p[1] + 2.0 * eta[c] * p[2]);
+                w[2 * g.N + c] = -(2.0 * eta[c] * p[1] + (1.0 + 2.0 * xi[c]) * p[2]);
+            }
+    for (int m = 0; m < nrec; ++m) {
+        size_t ci[8];
+        double wt[8];
+        if (trilinear(&g, rec_pos + 3 * m, ci, wt)) { free(w); free(b); free(rows); free(bl); free(tmp); return -1; }
+        for (int q = 0; q < 8; ++q) b[ci[q]] += Rm[m] * wt[q];
+    }
+    for (int i = 0; i < g.n[0]; ++i)
+        for (int j = 0; j < g.n[1]; ++j)
+            for (int k = 0; k < g.n[2]; ++k)
+                if (!is_fixed(&S, i, j, k)) cont_row(&g, &S, w, i, j, k, &rows[IDX(&g, i, j, k)]);
+    /* boundary nodes in index order */
+    size_t nb = 0;
+    for (int i = 0; i < g.n[0]; ++i)
+        for (int j = 0; j < g.n[1]; ++j)
+            for (int k = 0; k < g.n[2]; ++k)
+                if (astar_of(&g, i, j, k) >= 0) bl[nb++] = IDX(&g, i, j, k);
+    memset(P, 0, sizeof(double) * g.N);
+    *converged = 0;
+    int it;
+    for (it = 1; it <= max_iter; ++it) {
+        double dsum = 0.0;
+        for (int d = 0; d < 8; ++d) {
+            int sg[3];
+            dir_signs(d, sg);
+            for (int a0 = 0; a0 < g.n[0] - 2; ++a0) {
+                int i = sg[0] > 0 ? 1 + a0 : g.n[0] - 2 - a0;
+                for (int a1 = 0; a1 < g.n[1] - 2; ++a1) {
+                    int j = sg[1] > 0 ? 1 + a1 : g.n[1] - 2 - a1;
+                    for (int a2 = 0; a2 < g.n[2] - 2; ++a2) {
+                        int k = sg[2] > 0 ? 1 + a2 : g.n[2] - 2 - a2;
+                        if (is_fixed(&S, i, j, k)) continue;
+                        size_t c = IDX(&g, i, j, k);
+                        double nv = cont_update(&g, &rows[c], b, P, c);
+                        dsum += fabs(nv - P[c]);
+                        P[c] = nv;
+                    }
+                }
+            }
+            /* Jacobi pass over the boundary nodes: every new value from the
+             * values present before the pass */
+            for (size_t q = 0; q < nb; ++q) {
+                int i, j, k;
+                unidx(&g, bl[q], &i, &j, &k);
+                tmp[q] = is_fixed(&S, i, j, k) ? 0.0 : cont_update(&g, &rows[bl[q]], b, P, bl[q]);
+            }
+            for (size_t q = 0; q < nb; ++q) {
+                dsum += fabs(tmp[q] - P[bl[q]]);
+                P[bl[q]] = tmp[q];
+            }
+        }
+        double asum = 0.0;
+        for (size_t c = 0; c < g.N; ++c) asum += fabs(P[c]);
+        double eps = dsum / (asum > 1e-300 ? asum : 1e-300);
+        if (eps_hist) eps_hist[it - 1] = eps;
+        if (eps < tol) { *converged = 1; break; }
+    }
+    *iters = (it > max_iter) ? max_iter : it;
+    free(w); free(b); free(rows); free(bl); free(tmp);
     return 0;
 }
 

@@ -5,6 +5,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -61,3 +62,20 @@ def test_last_error_without_gpu(libpath):
     rc = lib.tt_misfit(0, 1, None, None, None, 0, None, None, 1.0, 1.0, None, None, None)
     assert rc == _lib.TT_EINVAL
     assert lib.tt_last_error().decode()
+
+
+def test_mg_workspace_size_host_logic(libpath):
+    """The projection's plan is host logic: staged (with workspace) for the
+    benchmark's five 11 x 13 x 13 grids on 101^3, one wave per node (no
+    workspace) when the staging exceeds LDS, 0 for invalid sizes."""
+    from paper_2412_00031_amd import _lib, api, workloads as W
+    _lib.load(libpath)
+    g = W.spherical_grid(101, 100.0, 2.0)
+    inv = W.staggered_inversion_grids(g, (11, 13, 13), 5)
+    nb = api.mg_workspace_size(g, inv)
+    S12 = 5 * 13 * 13
+    assert nb > 0 and nb % (8 * 101 * 3 * S12) == 0 and nb // (8 * 101 * 3 * S12) <= 8
+    big = [(np.zeros(5), np.zeros(70), np.zeros(70))] * 2
+    assert api.mg_workspace_size(g, big) == 0
+    assert api.mg_workspace_size(g, [(np.zeros(0), np.zeros(2), np.zeros(2))]) == 0
+    assert api.mg_workspace_size(g, [(np.zeros(2), np.zeros(2), np.zeros(2))] * 17) == 0

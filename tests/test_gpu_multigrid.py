@@ -29,7 +29,7 @@ def _inv_grids(g, seed, sizes=((4, 3, 5), (5, 4, 4))):
     return grids
 
 
-@pytest.mark.parametrize("case", ["small", "sph101", "sph101_staggered5"])
+@pytest.mark.parametrize("case", ["small", "sph101", "sph101_staggered5", "wave_per_node"])
 def test_multigrid_project_expand_parity(torch_cuda, case):
     from paper_2412_00031_amd import api
     torch = torch_cuda
@@ -39,6 +39,11 @@ def test_multigrid_project_expand_parity(torch_cuda, case):
     elif case == "sph101":
         g = W.spherical_grid(101, 100.0, 2.0)
         inv = _inv_grids(g, 11, sizes=((11, 13, 12), (12, 11, 13)))
+    elif case == "wave_per_node":
+        # inversion grids whose staged form does not fit in LDS: one wave per node
+        g = W.small_spherical(n=(13, 14, 15), seed=3)["grid"]
+        inv = _inv_grids(g, 9, sizes=((5, 70, 70), (4, 66, 71)))
+        assert api.mg_workspace_size(g, inv) == 0
     else:
         # the inversion grids that the benchmark times: 5 staggered 11 x 13 x 13 grids
         g = W.spherical_grid(101, 100.0, 2.0)

@@ -475,6 +475,163 @@ def test_mirror_symmetry():
     assert np.abs(tau - tau[:, :, ::-1]).max() < 1e-11
 
 
+# ------------------------------------------- continuous adjoint, Eq. (5)
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_cont_adjoint_exact_on_grid_line_cartesian(axis):
+    """Homogeneous anisotropic Cartesian medium, receiver and on-node source on
+    one grid line along `axis`: the flow w = -M grad T points straight at the
+    source, so every node of the line between the receiver and the fixed cell
+    carries the receiver's flux R through a face of area h^2 at speed |w|, and
+    nothing leaves the line: P = R / (h^2 |w|) there and 0 elsewhere, with
+    |w| = s0 / sqrt((M^-1)_aa) from the closed-form T = s0 sqrt(d^T M^-1 d)."""
+    g = W.cartesian_grid(15, 1.0)
+    xi0, eta0, v = 0.08, -0.05, 5.5
+    s, xi, eta = _homog(g, v, xi0, eta0)
+    src = np.array([7.0, 7.0, 7.0])
+    src[axis] = 3.0
+    rec = src.copy()
+    rec[axis] = 11.0
+    par = O.source_params(g, s, xi, eta, src)[0]
+    tau, _, conv, _ = O.forward(g, s, xi, eta, src, par, 1.2, 1e-14, 50)
+    assert conv
+    P, it, conv, _ = O.adjoint_cont(g, s, xi, eta, src, par, tau, rec[None], np.array([2.5]), 1e-14, 100)
+    assert conv
+    M = np.array([[1, 0, 0], [0, 1 - 2 * xi0, 2 * eta0], [0, 2 * eta0, 1 + 2 * xi0]])
+    speed = (1.0 / v) / math.sqrt(np.linalg.inv(M)[axis, axis])
+    expect = np.zeros(tuple(g["n"]))
+    line = [7, 7, 7]
+    line[axis] = slice(5, 12)   # nodes 5..11; nodes 3, 4 are the fixed cell
+    expect[tuple(line)] = 2.5 / speed
+    assert np.abs(P - expect).max() <= 1e-12 * expect.max()
+
+
+def test_cont_adjoint_exact_on_radial_line_spherical():
+    """Homogeneous spherical medium, receiver on the surface node straight
+    above an on-node source: the flux R crosses each r-face of the line, of
+    area r_f^2 cos(theta) dtheta dphi (r_f halfway between nodes), at speed s,
+    so P = R / (s r_f^2 cos(theta) dtheta dphi) on the node above each face."""
+    g = W.spherical_grid(17, 16.0, 0.08)
+    g["o"] = (g["o"][0], g["o"][1] + 0.9, g["o"][2])   # around 52 degrees latitude: cos(theta) ~ 0.62
+    s, xi, eta = _homog(g)
+    ax = W.axes(g)
+    j0, k0, i_s = 9, 6, 4
+    src = np.array([ax[0][i_s], ax[1][j0], ax[2][k0]])
+    rec = np.array([[ax[0][-1], ax[1][j0], ax[2][k0]]])
+    par = O.source_params(g, s, xi, eta, src)[0]
+    tau, _, conv, _ = O.forward(g, s, xi, eta, src, par, 1.0, 1e-14, 50)
+    assert conv
+    P, it, conv, _ = O.adjoint_cont(g, s, xi, eta, src, par, tau, rec, np.array([1.7]), 1e-14, 100)
+    assert conv
+    h = g["h"]
+    expect = np.zeros(tuple(g["n"]))
+    for i in range(i_s + 2, g["n"][0]):          # i_s, i_s + 1 are fixed
+        rf = 0.5 * (ax[0][i] + ax[0][i - 1])
+        expect[i, j0, k0] = 1.7 / ((1.0 / 6.0) * rf * rf * math.cos(ax[1][j0]) * h[1] * h[2])
+    assert np.abs(P - expect).max() <= 1e-11 * expect.max()
+
+
+def test_cont_adjoint_linear_nonnegative_and_symmetric():
+    """P is linear in R and nonnegative for R >= 0 (the upwind matrix is an
+    M-matrix), and a model and receiver set mirror-symmetric about the mid-plane
+    of axis 2, with the source on that plane, give a mirror-symmetric P."""
+    g = W.cartesian_grid(1, 1.0)
+    g["n"] = (11, 12, 14)
+    ax = W.axes(g)
+    Z, Y, X = np.meshgrid(ax[0], ax[1], ax[2], indexing="ij")
+    s = 1.0 / (6.0 + 0.1 * Z + 0.3 * np.cos(0.4 * (X - 6.5)) * np.sin(0.3 * Y))
+    xi = 0.03 * np.cos(0.5 * (X - 6.5)) * np.ones_like(Z)
+    eta = np.zeros_like(Z)
+    src = np.array([4.3, 5.2, 6.5])
+    par = O.source_params(g, s, xi, eta, src)[0]
+    tau, _, conv, _ = O.forward(g, s, xi, eta, src, par, 1.1, 1e-14, 2000)
+    rec = np.array([[0.0, 1.3, 2.2], [0.0, 1.3, 10.8], [10.0, 9.7, 4.1], [10.0, 9.7, 8.9]])
+    R1, R2 = np.array([1.0, 1.0, 0.5, 0.5]), np.array([0.2, 0.2, 1.4, 1.4])
+    P1 = O.adjoint_cont(g, s, xi, eta, src, par, tau, rec, R1, 1e-15, 400)[0]
+    P2 = O.adjoint_cont(g, s, xi, eta, src, par, tau, rec, R2, 1e-15, 400)[0]
+    P3 = O.adjoint_cont(g, s, xi, eta, src, par, tau, rec, R1 - 2.0 * R2, 1e-15, 400)[0]
+    assert np.abs(P3 - (P1 - 2.0 * P2)).max() <= 1e-11 * np.abs(P1).max()
+    assert P1.min() >= 0.0 and P2.min() >= 0.0 and P1.max() > 0.0
+    assert np.abs(P1 - P1[:, :, ::-1]).max() <= 1e-10 * P1.max()
+
+
+def test_cont_adjoint_traveltime_identity():
+    """Multiplying Eq. (5) by T and integrating by parts (T = 0 at the source,
+    no flux through the grid faces for these receivers) gives
+    sum_m R_m T(x_m) = integral of P grad T^t M grad T = integral of P s^2.
+    The finite-volume P meets it to first order, for rays along each of the
+    three axes and oblique ones (oblique rays converge slowest), at 52 degrees
+    latitude where the cos(theta) of the face areas matters; dropping that
+    factor from the theta faces breaks the horizontal ray by 40 %."""
+    lat0 = 0.9
+    ratios = []
+    for n in (17, 33):
+        g = W.spherical_grid(n, 20.0, 0.1)
+        g["o"] = (g["o"][0], g["o"][1] + lat0, g["o"][2])
+        ax = W.axes(g)
+        hw = ax[2][-1]
+        A = np.meshgrid(*ax, indexing="ij")[0]
+        r_src = []
+        for case in ("homogeneous", "gradient"):
+            s = np.full(A.shape, 1.0 / 6.0) if case == "homogeneous" else 1.0 / (4.0 + 0.15 * (6371.0 - A))
+            xi = eta = np.zeros_like(A)
+            src = np.array([6371.0 - 14.3, lat0 + 0.3 * hw, -0.2 * hw])
+            par = O.source_params(g, s, xi, eta, src)[0]
+            tau, _, conv, _ = O.forward(g, s, xi, eta, src, par, 1.0, 1e-13, 300)
+            assert conv
+            V = O.node_volume(g)
+            for rec in ([6371.0, lat0 + 0.7 * hw, -0.2 * hw], [6371.0, lat0 + 0.3 * hw, 0.7 * hw],
+                        [6371.0 - 14.3, lat0 - 0.8 * hw, -0.2 * hw], [6371.0 - 14.3, lat0 + 0.3 * hw, 0.8 * hw],
+                        [6371.0, lat0 - 0.8 * hw, 0.6 * hw]):
+                rec = np.array([rec])
+                P, _, conv, _ = O.adjoint_cont(g, s, xi, eta, src, par, tau, rec, np.array([1.0]), 1e-12, 500)
+                assert conv
+                r_src.append((P * s * s * V).sum() / O.sample(g, src, par, tau, rec)[0])
+        ratios.append(np.array(r_src))
+    for err in (np.abs(ratios[0] - 1.0), np.abs(ratios[1] - 1.0)):
+        assert err.max() < 0.15, ratios
+        assert err[[2, 3, 7, 8]].max() < 0.05, ratios    # horizontal rays along theta and phi
+
+
+def test_cont_adjoint_approaches_discrete_gradient():
+    """The continuous adjoint and the exact discrete adjoint (pinned by
+    finite differences) estimate the same derivative: d chi / d s(x) is
+    P s V (Eqs. (6), (9)) on one side and the discrete s-gradient on the
+    other.  On smooth functionals of it their difference shrinks under
+    refinement (first order, slowed by the 1/distance curvature of the flow
+    near the source)."""
+    diffs = []
+    lat0 = 0.9   # around 52 degrees latitude, where cos(theta) ~ 0.62 weighs the theta and phi faces
+    for n in (17, 33):
+        g = W.spherical_grid(n, 20.0, 0.1)
+        g["o"] = (g["o"][0], g["o"][1] + lat0, g["o"][2])
+        ax = W.axes(g)
+        A, B, C = np.meshgrid(*ax, indexing="ij")
+        B = B - lat0
+        hw = ax[2][-1]
+        s = 1.0 / (5.0 + 0.08 * (6371.0 - A))
+        xi = 0.03 * np.cos(B / hw)
+        eta = 0.02 * np.sin(C / hw)
+        src = np.array([6371.0 - 14.3, lat0 + 0.3 * hw, -0.2 * hw])
+        rec = np.array([[6371.0, lat0 + 0.7 * hw, 0.5 * hw], [6371.0, lat0 - 0.6 * hw, 0.4 * hw]])
+        R = np.array([1.0, 0.7])
+        par = O.source_params(g, s, xi, eta, src)[0]
+        tau, _, conv, _ = O.forward(g, s, xi, eta, src, par, 1.2, 1e-12, 500)
+        P, _, conv_c, _ = O.adjoint_cont(g, s, xi, eta, src, par, tau, rec, R, 1e-12, 500)
+        lam, _, conv_d, _ = O.adjoint(g, s, xi, eta, src, par, 1.2, tau, O.adjoint_rhs(g, src, par, rec, R),
+                                      1e-12, 500)
+        assert conv and conv_c and conv_d
+        gd = O.kernel(g, s, xi, eta, src, par, 1.2, tau, lam)[0]
+        gc = P * s * O.node_volume(g)
+        d = []
+        for phi in (np.ones_like(A), 1.0 + 0.5 * np.sin(3 * B / hw) * np.cos(2 * C / hw)):
+            a, b = (gd * phi).sum(), (gc * phi).sum()
+            d.append(abs(b - a) / abs(a))
+        diffs.append(d)
+    for q in range(2):
+        assert diffs[1][q] < diffs[0][q] / 1.4, diffs
+        assert diffs[1][q] < 0.2, diffs
+
+
 # ------------------------------------------------- kernel-density normalisation
 def test_node_volume_integrates_domain():
     """Sum of the trapezoidal node volumes: exact for a Cartesian box; second
