@@ -191,6 +191,36 @@ def adjoint(grid, s, xi, eta, src_pos, src_par, kappa, tau, rhs, tol, max_iter, 
     return lam, iters.value, bool(conv.value), hist[: iters.value].copy()
 
 
+def reloc_times(grid, field_pos, field_par, tau, ev_pos, ev_t0=None):
+    """T [nev, nfield] = Gamma_m(x_n) + t_n (App. B): field m is the forward
+    solution with receiver m as the source."""
+    n, coord, o, h = _grid_args(grid)
+    field_pos = _f64(field_pos).reshape(-1, 3)
+    ev_pos = _f64(ev_pos).reshape(-1, 3)
+    T = np.zeros((len(ev_pos), len(field_pos)))
+    rc = lib().tto_reloc_times(_i(n), coord, _d(o), _d(h), len(field_pos), _d(field_pos),
+                               _d(_f64(field_par).reshape(-1, 3)), _d(_f64(tau)), len(ev_pos), _d(ev_pos),
+                               _d(_f64(ev_t0)) if ev_t0 is not None else None, _d(T))
+    if rc:
+        raise ValueError("earthquake outside the grid")
+    return T
+
+
+def reloc_kernel(grid, field_pos, field_par, tau, ev_pos, R):
+    """Eq. (10): K [nev, 4] = (d chi/d x_0, d chi/d x_1, d chi/d x_2 of each
+    earthquake in grid coordinates, d chi / d t_n) from R = d chi / d T [nev, nfield]."""
+    n, coord, o, h = _grid_args(grid)
+    field_pos = _f64(field_pos).reshape(-1, 3)
+    ev_pos = _f64(ev_pos).reshape(-1, 3)
+    K = np.zeros((len(ev_pos), 4))
+    rc = lib().tto_reloc_kernel(_i(n), coord, _d(o), _d(h), len(field_pos), _d(field_pos),
+                                _d(_f64(field_par).reshape(-1, 3)), _d(_f64(tau)), len(ev_pos), _d(ev_pos),
+                                _d(_f64(R)), _d(K))
+    if rc:
+        raise ValueError("earthquake outside the grid")
+    return K
+
+
 def adjoint_cont(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter):
     """P of Eq. (5) by the upwind finite-volume discretisation (reading R14):
     point sources R_m at rec_pos through trilinear weights.  Returns

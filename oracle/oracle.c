@@ -21,6 +21,7 @@
  *       itself.
  *   Eqs. (2)-(4), (A2)-(A4): traveltime, common-source and common-receiver
  *       differential misfits and their adjoint sources R = d chi / d T(x_r).
+ *   Eq. (10), App. B: relocation kernels from receiver-side fields.
  *   Eqs. (6)-(9): kernels; here the discrete gradients d chi/d s, d chi/d xi,
  *       d chi/d eta, which Eq. (9) relates to K_s, K_xi, K_eta.
  *
@@ -68,6 +69,12 @@
  *   (R13) common-receiver pairs (Eqs. (4) and (A4)): an explicit list of
  *        triples (n, j, m), the unordered source pair {n, j} recorded at
  *        receiver m, each counted once, as in (R9).
+ *   (R15) relocation (Eq. (10), App. B): by reciprocity T[n][m] = Gamma_m(x_n)
+ *        + t_n with Gamma_m the field of receiver m taken as the source, so
+ *        the misfits are those of Eqs. (2)-(4) and d chi / d Gamma_m(x_n) is
+ *        the adjoint source R[n][m]; grad Gamma_m(x_n) is the gradient of the
+ *        trilinear interpolant that samples Gamma_m (the cell of the sampling),
+ *        with respect to the grid coordinates.
  *   (R14) continuous adjoint (Eq. (5), the paper's own route): upwind finite
  *        volumes.  The flux P w with w = -M grad T leaves each trapezoidal
  *        control volume through six faces; the face velocity is the mean of the
@@ -819,6 +826,92 @@ int tto_adjoint(const int* n, int coord, const double* o, const double* h,
     free(coef);
     free(list);
     free(bl);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Earthquake relocation, Eq. (10) and App. B (R15).
+ * ------------------------------------------------------------------------- */
+
+/* corners of the cell holding x (as trilinear) and the gradient of each
+ * corner's weight with respect to the grid coordinates */
+static int trilinear_grad(const OGrid* g, const double* x, size_t cidx[8], double dw[8][3]) {
+    int b[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+        double lo = g->o[a], hi = g->o[a] + (double)(g->n[a] - 1) * g->h[a];
+        if (!(x[a] >= lo && x[a] <= hi)) return -1;
+        b[a] = cell_base(g, a, x[a]);
+        f[a] = (x[a] - g->o[a]) / g->h[a] - (double)b[a];
+    }
+    int q = 0;
+    for (int c0 = 0; c0 < 2; ++c0)
+        for (int c1 = 0; c1 < 2; ++c1)
+            for (int c2 = 0; c2 < 2; ++c2) {
+                int c[3] = {c0, c1, c2};
+                cidx[q] = IDX(g, b[0] + c0, b[1] + c1, b[2] + c2);
+                for (int a = 0; a < 3; ++a) {
+                    double v = (c[a] ? 1.0 : -1.0) / g->h[a];
+                    for (int e = 0; e < 3; ++e)
+                        if (e != a) v *= c[e] ? f[e] : 1.0 - f[e];
+                    dw[q][a] = v;
+                }
+                ++q;
+            }
+    return 0;
+}
+
+/* T[n][m] = Gamma_m(x_n) + t_n for nev earthquakes and nfield receiver fields
+ * (field m: source at field_pos[m], constants field_par[m], tau [N]);
+ * ev_t0 [nev] or NULL (= 0).  -1 if an earthquake lies outside the grid. */
+int tto_reloc_times(const int* n, int coord, const double* o, const double* h, int nfield,
+                    const double* field_pos, const double* field_par, const double* tau, int nev,
+                    const double* ev_pos, const double* ev_t0, double* T) {
+    OGrid g;
+    grid_init(&g, n, coord, o, h);
+    for (int m = 0; m < nfield; ++m) {
+        double col[1];
+        for (int q = 0; q < nev; ++q) {
+            if (tto_sample(n, coord, o, h, field_pos + 3 * m, field_par + 3 * m, tau + (size_t)m * g.N, 1,
+                           ev_pos + 3 * q, col))
+                return -1;
+            T[(size_t)q * nfield + m] = col[0] + (ev_t0 ? ev_t0[q] : 0.0);
+        }
+    }
+    return 0;
+}
+
+/* Eq. (10): K[n] = (sum_m R[n][m] dGamma_m/dx_a(x_n) for a = 0, 1, 2,
+ * sum_m R[n][m]), R [nev][nfield] the adjoint sources of the misfit in
+ * T[n][m] (tto_misfit, tto_misfit_cr); K [nev][4]. */
+int tto_reloc_kernel(const int* n, int coord, const double* o, const double* h, int nfield,
+                     const double* field_pos, const double* field_par, const double* tau, int nev,
+                     const double* ev_pos, const double* R, double* K) {
+    OGrid g;
+    grid_init(&g, n, coord, o, h);
+    for (int q = 0; q < nev; ++q) {
+        size_t ci[8];
+        double dw[8][3];
+        if (trilinear_grad(&g, ev_pos + 3 * q, ci, dw)) return -1;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int m = 0; m < nfield; ++m) {
+            OSrc S;
+            src_init(&S, &g, field_pos + 3 * m, field_par + 3 * m);
+            double gr[3] = {0.0, 0.0, 0.0};
+            for (int p = 0; p < 8; ++p) {
+                int i, j, k;
+                unidx(&g, ci[p], &i, &j, &k);
+                double T0, t[3];
+                factor_at(&g, &S, i, j, k, &T0, t);
+                double Gc = T0 * tau[(size_t)m * g.N + ci[p]];
+                for (int a = 0; a < 3; ++a) gr[a] += dw[p][a] * Gc;
+            }
+            double r = R[(size_t)q * nfield + m];
+            for (int a = 0; a < 3; ++a) acc[a] += r * gr[a];
+            acc[3] += r;
+        }
+        for (int a = 0; a < 4; ++a) K[(size_t)q * 4 + a] = acc[a];
+    }
     return 0;
 }
 

@@ -475,6 +475,96 @@ def test_mirror_symmetry():
     assert np.abs(tau - tau[:, :, ::-1]).max() < 1e-11
 
 
+# ------------------------------------------------ relocation, Eq. (10), App. B
+def _reloc_case(seed=5):
+    wl = W.small_spherical(n=(13, 14, 15), nsrc=3, nrec=6, seed=seed)
+    g = wl["grid"]
+    rec, ev = wl["rec"], wl["src"]
+    par = O.source_params(g, wl["s"], wl["xi"], wl["eta"], rec)
+    taus = np.stack([O.forward(g, wl["s"], wl["xi"], wl["eta"], rec[m], par[m], wl["kappa"], 1e-13, 500)[0]
+                     for m in range(len(rec))])
+    return wl, g, rec, ev, par, taus
+
+
+def test_reloc_kernel_is_gradient_of_misfit():
+    """Eq. (10) with all three misfits of Eqs. (B1)-(B3): the relocation
+    kernels equal central differences of chi in each earthquake coordinate and
+    origin time (the sampled fields are trilinear inside a cell, so the
+    derivative is exact up to differencing error)."""
+    wl, g, rec, ev, par, taus = _reloc_case()
+    t0 = np.array([0.1, -0.2, 0.05])
+    rng = np.random.default_rng(3)
+    Tobs = O.reloc_times(g, rec, par, taus, ev, t0) + rng.normal(0, 0.05, (3, 6))
+    pairs = np.array([[0, 1], [2, 4], [3, 5]], np.int32)
+    tri = np.array([[0, 1, 0], [1, 2, 3], [0, 2, 5], [0, 1, 4]], np.int32)
+
+    def chi_of(ev_, t0_):
+        T = O.reloc_times(g, rec, par, taus, ev_, t0_)
+        c, R = O.misfit(T, Tobs, None, pairs, None, 0.7, 1.1)
+        c2, R = O.misfit_cr(T, Tobs, tri, None, 0.9, R)
+        return c + c2, R
+
+    _, R = chi_of(ev, t0)
+    K = O.reloc_kernel(g, rec, par, taus, ev, R)
+    scale = np.abs(K[:, :3]).max()
+    for q in range(3):
+        for a in range(3):
+            d = 1e-6 * g["h"][a]
+            e1, e2 = ev.copy(), ev.copy()
+            e1[q, a] += d
+            e2[q, a] -= d
+            fd = (chi_of(e1, t0)[0] - chi_of(e2, t0)[0]) / (2 * d)
+            assert abs(fd - K[q, a]) <= 1e-7 * scale, (q, a, fd, K[q, a])
+        t1, t2 = t0.copy(), t0.copy()
+        t1[q] += 1e-6
+        t2[q] -= 1e-6
+        fd = (chi_of(ev, t1)[0] - chi_of(ev, t2)[0]) / 2e-6
+        assert abs(fd - K[q, 3]) <= 1e-8, (q, fd, K[q, 3])
+
+
+def test_reloc_origin_time_insensitive_to_common_source_pairs():
+    """Eq. (B10): a common-source differential time does not depend on the
+    origin time, so with chi = chi_cs alone d chi / d t_n = 0."""
+    wl, g, rec, ev, par, taus = _reloc_case(seed=6)
+    T = O.reloc_times(g, rec, par, taus, ev)
+    Tobs = T + np.random.default_rng(4).normal(0, 0.05, T.shape)
+    pairs = np.array([[0, 1], [2, 4], [3, 5], [1, 4]], np.int32)
+    _, R = O.misfit(T, Tobs, None, pairs, None, 0.0, 1.0)
+    K = O.reloc_kernel(g, rec, par, taus, ev, R)
+    assert np.abs(K[:, 3]).max() <= 1e-14 * np.abs(R).max()
+    assert np.abs(K[:, :3]).max() > 1e-3
+
+
+def test_reloc_reciprocity_and_gradient_closed_form():
+    """Homogeneous isotropic Cartesian medium: the receiver-side field sampled
+    at an on-node earthquake equals s |x_n - x_m| (reciprocity with the
+    earthquake-side solve), and with R one-hot the kernel is the gradient of
+    the sampled field, which approaches s (x - x_m) / |x - x_m| at first order
+    in h at an off-node earthquake."""
+    errs = []
+    for n, h in ((21, 1.0), (41, 0.5)):
+        g = W.cartesian_grid(n, h)
+        s, xi, eta = _homog(g)
+        rec = np.array([[0.0, 4.0, 3.0], [0.0, 15.0, 16.0]])
+        par = O.source_params(g, s, xi, eta, rec)
+        taus = np.stack([O.forward(g, s, xi, eta, rec[m], par[m], 1.0, 1e-13, 50)[0] for m in range(2)])
+        ev_node = np.array([[12.0, 9.0, 11.0]])
+        T = O.reloc_times(g, rec, par, taus, ev_node)
+        exact = np.linalg.norm(ev_node[0][None, :] - rec, axis=1) / 6.0
+        assert np.abs(T[0] - exact).max() <= 1e-12 * exact.max()
+        src_par = O.source_params(g, s, xi, eta, ev_node)[0]
+        tau_ev = O.forward(g, s, xi, eta, ev_node[0], src_par, 1.0, 1e-13, 50)[0]
+        back = O.sample(g, ev_node[0], src_par, tau_ev, rec)
+        assert np.abs(back - T[0]).max() <= 1e-12 * exact.max()
+        ev = np.array([[12.3, 9.6, 11.2]])
+        K = O.reloc_kernel(g, rec, par, taus, ev, np.array([[1.0, 0.0]]))
+        d = ev[0] - rec[0]
+        errs.append(np.abs(K[0, :3] - d / np.linalg.norm(d) / 6.0).max())
+        assert K[0, 3] == 1.0
+    assert errs[1] < 0.7 * errs[0], errs
+    assert errs[1] < 0.01 / 6.0, errs
+
+
 # ------------------------------------------- continuous adjoint, Eq. (5)
 @pytest.mark.parametrize("axis", [0, 1, 2])
 def test_cont_adjoint_exact_on_grid_line_cartesian(axis):
