@@ -174,7 +174,8 @@ def aux_inputs(wl, nsrc):
 
 
 def aux_gpu(wl, a, dev, reps=20):
-    """Average launch time of each per-step kernel outside the solves, by
+    """Average time of one call of each per-step entry point outside the solves
+    (one or two kernel launches), by
     torch events on the stream the kernels run on (torch's current stream,
     which the binding passes to the library), and its algorithmic HBM bytes."""
     import ctypes
@@ -189,6 +190,8 @@ def aux_gpu(wl, a, dev, reps=20):
     m, coords, sizes = api._mg_args(a["inv"], dev)
     M = sum(3 * x * y * z for x, y, z in sizes)
     proj = torch.empty(M, dtype=torch.float64, device=dev)
+    nws = int(lib.tt_mg_workspace_size(ctypes.byref(api._grid(g)), len(sizes), m))
+    mg_ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
     Cf = t(np.concatenate([c.reshape(-1) for c in a["C"]]))
     field = torch.empty((3, N), dtype=torch.float64, device=dev)
     gr = api._grid(g)
@@ -199,14 +202,17 @@ def aux_gpu(wl, a, dev, reps=20):
     cp = lambda x: ctypes.c_void_p(x.data_ptr())
     st = lambda: ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     calls = {
-        "k_kernel_density": (lambda: api.kernel_density(g, s, dens, grad, a["eps"], a["zeta"]), 72.0 * N, "hbm"),
-        "k_mg_project": (lambda: _lib.check(lib.tt_mg_project(ctypes.byref(gr), len(sizes), m, cp(coords), cp(grad),
-                                                                cp(proj), st())), 24.0 * N + 8.0 * M, "hbm"),
-        "k_mg_expand": (lambda: _lib.check(lib.tt_mg_expand(ctypes.byref(gr), len(sizes), m, cp(coords), cp(Cf),
+        "tt_kernel_density": (lambda: api.kernel_density(g, s, dens, grad, a["eps"], a["zeta"]), 72.0 * N, "hbm"),
+        "tt_mg_project": (lambda: _lib.check(lib.tt_mg_project(ctypes.byref(gr), len(sizes), m, cp(coords), cp(grad),
+                                                                cp(proj), cp(mg_ws), ctypes.c_size_t(nws), st())),
+                         24.0 * N + 8.0 * M, "hbm"),
+        "tt_mg_expand": (lambda: _lib.check(lib.tt_mg_expand(ctypes.byref(gr), len(sizes), m, cp(coords), cp(Cf),
                                                               cp(field), st())), 24.0 * N + 8.0 * M, "hbm"),
-        "k_misfit_cr": (lambda: api.misfit_cr(T, Tobs, off, pair, wcr, a["gamma"], R, chi),
+        "tt_misfit_cr": (lambda: api.misfit_cr(T, Tobs, off, pair, wcr, a["gamma"], R, chi),
                         80.0 * len(a["tri"]), "latency"),
     }
+    kernels = {"tt_kernel_density": "k_kernel_density", "tt_mg_project": "k_mg_proj_planes + k_mg_proj_final",
+               "tt_mg_expand": "k_mg_expand", "tt_misfit_cr": "k_misfit_cr"}
     out = {}
     for name, (fn, nbytes, bound) in calls.items():
         for _ in range(3):
@@ -220,8 +226,8 @@ def aux_gpu(wl, a, dev, reps=20):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         gbs = nbytes / (ms * 1e-3) / 1e9
-        out[name] = {"avg_launch_ms": round(ms, 4), "algorithmic_bytes": int(nbytes), "achieved": round(gbs, 1),
-                     "unit": "GB/s", "bound": bound}
+        out[name] = {"kernels": kernels[name], "avg_call_ms": round(ms, 4), "algorithmic_bytes": int(nbytes),
+                     "achieved": round(gbs, 1), "unit": "GB/s", "bound": bound}
         if bound == "hbm":
             out[name].update(peak=HBM_PEAK_GBS, frac=round(gbs / HBM_PEAK_GBS, 4))
     return out
@@ -235,16 +241,16 @@ def aux_cpu(wl, a):
     out = {}
     t0 = time.perf_counter()
     O.kernel_density(g, wl["s"], a["dens"], a["grad"], a["eps"], a["zeta"])
-    out["k_kernel_density"] = time.perf_counter() - t0
+    out["tt_kernel_density"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     O.mg_project(g, a["inv"], a["grad"])
-    out["k_mg_project"] = time.perf_counter() - t0
+    out["tt_mg_project"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     O.mg_expand(g, a["inv"], a["C"])
-    out["k_mg_expand"] = time.perf_counter() - t0
+    out["tt_mg_expand"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     O.misfit_cr(a["T"], a["T_obs"], a["tri"], a["wcr"], a["gamma"])
-    out["k_misfit_cr"] = time.perf_counter() - t0
+    out["tt_misfit_cr"] = time.perf_counter() - t0
     return {k: round(v * 1e3, 3) for k, v in out.items()}
 
 

@@ -83,6 +83,18 @@ typedef struct tt_opts {
  * as a hipGraph once per call and replay it each iteration.  Ignored when
  * TT_FLAG_TIME_SWEEPS is set (per-launch events are recorded eagerly). */
 #define TT_FLAG_GRAPH 2
+/* bit 2 (tt_adjoint only): solve the continuous adjoint equation (5) by upwind
+ * finite volumes instead of the exact transpose of the discrete forward
+ * system.  Each node owns its trapezoidal control volume; the flux P w,
+ * w = -M grad T, leaves through six faces at the mean of the two nodal normal
+ * velocities and carries the upwind node's P; P = 0 on the fixed cell and
+ * outside the grid; the receivers inject sum_m R_m (trilinear weights).  The
+ * same 8 directional Gauss-Seidel sweeps update the interior, each followed by
+ * one Jacobi pass over the boundary nodes.  lam is returned as P s V (V the
+ * trapezoidal node volume), the estimate of d chi / d s that Eqs. (6) and (9)
+ * give, so tt_kernel and tt_kernel_density apply unchanged.  It agrees with
+ * the exact discrete gradient to first order in the grid spacing. */
+#define TT_FLAG_CONTINUOUS_ADJOINT 4
 
 /* Bytes of device workspace needed by tt_forward (which = 0), tt_adjoint
  * (which = 1), tt_sample (which = 2) or tt_kernel (which = 3) for this grid,
@@ -119,6 +131,30 @@ int tt_forward(const tt_grid* grid, const double* s, const double* xi, const dou
 int tt_sample(const tt_grid* grid, int32_t nsrc, const double* src_pos, const double* src_par,
               const double* tau, int32_t nrec, const double* rec_pos, double* T_rec, void* ws,
               size_t ws_bytes, void* stream);
+
+/* Relocation (Eq. (10), App. B).  By reciprocity the time from earthquake n
+ * to receiver m is Gamma_m(x_n) + t_n, Gamma_m the traveltime field with
+ * receiver m taken as the source (tt_forward with the receivers as sources,
+ * nfield of them), t_n the earthquake's origin-time shift.  The misfits of
+ * Eqs. (B1)-(B3) are then tt_misfit / tt_misfit_cr of T[n][m], whose adjoint
+ * sources R = d chi / d T are d chi / d Gamma_m(x_n).
+ *   field_pos [nfield][3], field_par [nfield][3] (tt_source_params of the
+ *   receivers), tau [nfield][N] their converged fields; ev_pos [nev][3].
+ *   Workspace: tt_workspace_size(grid, nfield, NULL, 2) bytes.
+ * tt_reloc_times: T [nev][nfield] = Gamma_m(x_n) + t_n, Gamma_m sampled by its
+ *   trilinear interpolant; ev_t0 [nev] or NULL (= 0).
+ * tt_reloc_kernel: K [nev][4] = (sum_m R[n][m] dGamma_m/dx_a(x_n), a = 0, 1, 2,
+ *   sum_m R[n][m]) = (the location kernel of Eq. (10) in grid coordinates --
+ *   r km, latitude rad, longitude rad, or z, y, x km -- and K_tau), with
+ *   R [nev][nfield].  The gradient is that of the trilinear interpolant inside
+ *   the cell that samples x_n, so K is the exact derivative of the sampled
+ *   misfit.  Deterministic.  Both asynchronous on stream. */
+int tt_reloc_times(const tt_grid* grid, int32_t nfield, const double* field_pos, const double* field_par,
+                   const double* tau, int32_t nev, const double* ev_pos, const double* ev_t0, double* T, void* ws,
+                   size_t ws_bytes, void* stream);
+int tt_reloc_kernel(const tt_grid* grid, int32_t nfield, const double* field_pos, const double* field_par,
+                    const double* tau, int32_t nev, const double* ev_pos, const double* R, double* K, void* ws,
+                    size_t ws_bytes, void* stream);
 
 /* Misfit chi = alpha*chi_t + beta*chi_cs (Eqs. (1)-(3)) and adjoint sources
  * R = d chi / d T(x_r) (Eqs. (A1)-(A3)).
@@ -189,7 +225,8 @@ int tt_kernel(const tt_grid* grid, const double* s, const double* xi, const doub
 int tt_kernel_density(const tt_grid* grid, const double* s, const double* dens, const double* grad, double eps,
                       double zeta, double* K, double* Kd, void* stream);
 
-/* Multiple-grid parameterisation (Eqs. (11)-(17)).  H inversion grids; grid q
+/* Multiple-grid parameterisation (Eqs. (11)-(17)).  H (1..TT_MG_MAX_GRIDS)
+ * inversion grids; grid q
  * has m[3q + a] (>= 1) strictly ascending node coordinates on axis a (r km,
  * latitude, longitude rad; or z, y, x km), concatenated in coords (device,
  * grid after grid, axes in turn).  Basis B = u v w / H with the tents of
@@ -202,11 +239,17 @@ int tt_kernel_density(const tt_grid* grid, const double* s, const double* dens, 
  * tt_mg_project: out = d chi / d C (Eq. (17)) from the kernels K [3][N] (e.g.
  *   tt_kernel_density), by node quadrature: out = sum_x K(x) B(x) V(x).  With
  *   ds / s = sum C B (s row) and dxi = sum C B, d eta likewise (Eq. (15)), this
- *   is the gradient of Eq. (16).  One wave per inversion node, deterministic.
+ *   is the gradient of Eq. (16).  B and V factor over the axes, so the sum is
+ *   taken one axis at a time (K read once, partial sums in ws); grids whose
+ *   staging does not fit in LDS take one wave per inversion node instead (no
+ *   workspace).  Deterministic.  ws: device memory of at least
+ *   tt_mg_workspace_size(grid, H, m) bytes (may be NULL when that is 0).
  * tt_mg_expand: field [3][N] = sum over grids and nodes of C B (Eq. (15)),
  *   overwritten.  Asynchronous on stream. */
+#define TT_MG_MAX_GRIDS 16
+size_t tt_mg_workspace_size(const tt_grid* grid, int32_t H, const int32_t* m);
 int tt_mg_project(const tt_grid* grid, int32_t H, const int32_t* m, const double* coords, const double* K,
-                  double* out, void* stream);
+                  double* out, void* ws, size_t ws_bytes, void* stream);
 int tt_mg_expand(const tt_grid* grid, int32_t H, const int32_t* m, const double* coords, const double* C,
                  double* field, void* stream);
 

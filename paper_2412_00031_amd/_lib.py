@@ -21,9 +21,9 @@ class TTOpts(ctypes.Structure):
                 ("groups", ctypes.c_int32)]
 
 
-EXPORTS = ["tt_workspace_size", "tt_source_params", "tt_forward", "tt_sample", "tt_misfit", "tt_misfit_cr",
-           "tt_adjoint", "tt_kernel", "tt_kernel_density", "tt_mg_project", "tt_mg_expand", "tt_sweep_timing",
-           "tt_last_error"]
+EXPORTS = ["tt_workspace_size", "tt_source_params", "tt_forward", "tt_sample", "tt_misfit", "tt_misfit_cr", "tt_reloc_times", "tt_reloc_kernel",
+           "tt_adjoint", "tt_kernel", "tt_kernel_density", "tt_mg_workspace_size", "tt_mg_project", "tt_mg_expand",
+           "tt_sweep_timing", "tt_last_error"]
 
 NN_EXPORTS = ["nn_to_bf16", "nn_from_bf16", "nn_conv3_pack", "nn_conv3_fwd", "nn_conv3_wgrad_work", "nn_conv3_wgrad",
               "nn_relu_mask", "nn_pool_fwd", "nn_pool_bwd", "nn_up_fwd", "nn_up_wgrad_work", "nn_up_bwd",
@@ -44,6 +44,7 @@ class NNUnetCfg(ctypes.Structure):
 
 TT_FLAG_TIME_SWEEPS = 1
 TT_FLAG_GRAPH = 2
+TT_FLAG_CONTINUOUS_ADJOINT = 4
 TT_MAX_GROUPS = 8
 
 _lib = None
@@ -74,18 +75,22 @@ def load(path=LIB_PATH):
     lib.tt_forward.argtypes = [G, P, P, P, i32, P, P, P, O, P, P, P, sz, P]
     lib.tt_sample.argtypes = [G, i32, P, P, P, i32, P, P, P, sz, P]
     lib.tt_misfit.argtypes = [i32, i32, P, P, P, i32, P, P, ctypes.c_double, ctypes.c_double, P, P, P]
+    lib.tt_reloc_times.argtypes = [G, i32, P, P, P, i32, P, P, P, P, sz, P]
+    lib.tt_reloc_kernel.argtypes = [G, i32, P, P, P, i32, P, P, P, P, sz, P]
     lib.tt_misfit_cr.argtypes = [i32, i32, P, P, P, P, P, ctypes.c_double, P, P, P]
     lib.tt_adjoint.argtypes = [G, P, P, P, i32, P, P, P, i32, P, P, O, P, P, P, sz, P]
     lib.tt_kernel.argtypes = [G, P, P, P, i32, P, P, P, P, P, i32, P, sz, P]
     lib.tt_kernel_density.argtypes = [G, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P]
-    lib.tt_mg_project.argtypes = [G, i32, ctypes.POINTER(i32), P, P, P, P]
+    lib.tt_mg_workspace_size.argtypes = [G, i32, ctypes.POINTER(i32)]
+    lib.tt_mg_workspace_size.restype = sz
+    lib.tt_mg_project.argtypes = [G, i32, ctypes.POINTER(i32), P, P, P, P, sz, P]
     lib.tt_mg_expand.argtypes = [G, i32, ctypes.POINTER(i32), P, P, P, P]
     lib.tt_sweep_timing.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
     lib.tt_sweep_timing.restype = ctypes.c_int
     lib.tt_last_error.argtypes = []
     lib.tt_last_error.restype = ctypes.c_char_p
-    for name in ("tt_source_params", "tt_forward", "tt_sample", "tt_misfit", "tt_misfit_cr", "tt_adjoint",
-                 "tt_kernel", "tt_kernel_density", "tt_mg_project", "tt_mg_expand"):
+    for name in ("tt_source_params", "tt_forward", "tt_sample", "tt_misfit", "tt_misfit_cr", "tt_reloc_times",
+                 "tt_reloc_kernel", "tt_adjoint", "tt_kernel", "tt_kernel_density", "tt_mg_project", "tt_mg_expand"):
         getattr(lib, name).restype = ctypes.c_int
     _declare_nn(lib)
     _lib = lib

@@ -26,7 +26,7 @@ def _grid(grid):
     return g
 
 
-def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None, graph=False, groups=0):
+def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None, graph=False, groups=0, continuous=False):
     o = _lib.TTOpts()
     o.groups = int(groups)
     o.eps_hist = _dev(eps_hist, "eps_hist").value if eps_hist is not None else None
@@ -34,7 +34,8 @@ def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None, grap
     o.max_iter = int(max_iter)
     o.kappa = float(kappa)
     o.tile_k = int(tile_k)
-    o.flags = (_lib.TT_FLAG_TIME_SWEEPS if time_sweeps else 0) | (_lib.TT_FLAG_GRAPH if graph else 0)
+    o.flags = ((_lib.TT_FLAG_TIME_SWEEPS if time_sweeps else 0) | (_lib.TT_FLAG_GRAPH if graph else 0)
+               | (_lib.TT_FLAG_CONTINUOUS_ADJOINT if continuous else 0))
     return o
 
 
@@ -145,6 +146,43 @@ def sample(grid, src_pos, src_par, tau, rec_pos, ws=None):
     return out
 
 
+def reloc_times(grid, field_pos, field_par, tau, ev_pos, ev_t0=None, ws=None):
+    """T [nev, nfield] = Gamma_m(x_n) + t_n (Eq. (10), App. B): field m is the
+    forward solution with receiver m as the source (tau [nfield, *n])."""
+    lib = _lib.load()
+    nfield, nev = int(field_pos.shape[0]), int(ev_pos.shape[0])
+    dev = tau.device
+    T = torch.empty((nev, nfield), dtype=_F64, device=dev)
+    if ws is None:
+        ws = workspace(grid, max(nfield, 1), 2, 0, dev)
+    g = _grid(grid)
+    _lib.check(lib.tt_reloc_times(ctypes.byref(g), nfield, _dev(field_pos, "field_pos", numel=3 * nfield),
+                                  _dev(field_par, "field_par", numel=3 * nfield),
+                                  _dev(tau, "tau", numel=nfield * _N(grid)), nev,
+                                  _dev(ev_pos, "ev_pos", numel=3 * nev),
+                                  _dev(ev_t0, "ev_t0", numel=nev) if ev_t0 is not None else _null(), _dev(T, "T"),
+                                  _dev(ws, "ws", torch.uint8), ws.numel(), _stream(dev)))
+    return T
+
+
+def reloc_kernel(grid, field_pos, field_par, tau, ev_pos, R, ws=None):
+    """Eq. (10): K [nev, 4] = location kernel in grid coordinates (3) and the
+    origin-time kernel, from R = d chi / d T [nev, nfield]."""
+    lib = _lib.load()
+    nfield, nev = int(field_pos.shape[0]), int(ev_pos.shape[0])
+    dev = tau.device
+    K = torch.empty((nev, 4), dtype=_F64, device=dev)
+    if ws is None:
+        ws = workspace(grid, max(nfield, 1), 2, 0, dev)
+    g = _grid(grid)
+    _lib.check(lib.tt_reloc_kernel(ctypes.byref(g), nfield, _dev(field_pos, "field_pos", numel=3 * nfield),
+                                   _dev(field_par, "field_par", numel=3 * nfield),
+                                   _dev(tau, "tau", numel=nfield * _N(grid)), nev,
+                                   _dev(ev_pos, "ev_pos", numel=3 * nev), _dev(R, "R", numel=nev * nfield),
+                                   _dev(K, "K"), _dev(ws, "ws", torch.uint8), ws.numel(), _stream(dev)))
+    return K
+
+
 def misfit(T_rec, T_obs, w=None, pairs=None, wpair=None, alpha=1.0, beta=1.0, cr=None, wcr=None, gamma=1.0):
     """chi = alpha chi_t + beta chi_cs [+ gamma chi_cr] (Eq. (1)) as a device
     scalar tensor, and adjoint sources R [nsrc, nrec].  cr = (cr_off [nrec+1],
@@ -183,9 +221,10 @@ def misfit_cr(T_rec, T_obs, cr_off, cr_pair, wcr, gamma, R, chi):
 
 
 def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, kappa, tile_k=0, ws=None,
-            out=None, time_sweeps=False, eps_hist=None, graph=False, groups=0):
+            out=None, time_sweeps=False, eps_hist=None, graph=False, groups=0, continuous=False):
     """Batched adjoint solve.  Returns (lambda [nsrc, *n], status int32 [nsrc]);
-    eps_hist and groups as for forward."""
+    eps_hist and groups as for forward.  continuous=True solves Eq. (5) by
+    upwind finite volumes and returns P s V in place of lambda."""
     lib = _lib.load()
     N = _N(grid)
     nsrc, nrec = int(src_pos.shape[0]), int(rec_pos.shape[0])
@@ -197,7 +236,7 @@ def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, 
     g = _grid(grid)
     if eps_hist is not None and eps_hist.numel() != nsrc * int(max_iter):
         raise ValueError("eps_hist must have nsrc * max_iter elements")
-    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph, groups)
+    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph, groups, continuous)
     _lib.check(lib.tt_adjoint(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
                               _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
                               _dev(src_par, "src_par", numel=3 * nsrc), _dev(tau, "tau", numel=nsrc * N), nrec,
@@ -253,6 +292,16 @@ def _mg_args(inv_grids, device):
     return m, coords, sizes
 
 
+def mg_workspace_size(grid, inv_grids):
+    """Bytes of workspace tt_mg_project needs for these inversion grids (0: the
+    one-wave-per-node form, no workspace)."""
+    lib = _lib.load()
+    sizes = [tuple(len(c) for c in axes) for axes in inv_grids]
+    m = (ctypes.c_int32 * (3 * len(sizes)))(*[v for sz in sizes for v in sz])
+    g = _grid(grid)
+    return int(lib.tt_mg_workspace_size(ctypes.byref(g), len(sizes), m))
+
+
 def mg_project(grid, inv_grids, K):
     """d chi / d C (Eq. (17)) on each inversion grid: list of [3, m0, m1, m2] tensors."""
     lib = _lib.load()
@@ -261,8 +310,11 @@ def mg_project(grid, inv_grids, K):
     total = sum(3 * a * b * c for a, b, c in sizes)
     out = torch.empty(total, dtype=_F64, device=dev)
     g = _grid(grid)
+    nws = int(lib.tt_mg_workspace_size(ctypes.byref(g), len(inv_grids), m))
+    ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
     _lib.check(lib.tt_mg_project(ctypes.byref(g), len(inv_grids), m, _dev(coords, "coords"),
-                                 _dev(K, "K", numel=3 * _N(grid)), _dev(out, "out"), _stream(dev)))
+                                 _dev(K, "K", numel=3 * _N(grid)), _dev(out, "out"),
+                                 _dev(ws, "ws", torch.uint8), ctypes.c_size_t(nws), _stream(dev)))
     res, off = [], 0
     for sz in sizes:
         n = 3 * sz[0] * sz[1] * sz[2]

@@ -42,7 +42,8 @@ class EikonalMisfit(torch.autograd.Function):
         p = ctx.problem
         g = p["grid"]
         lam, st = api.adjoint(g, s, xi, eta, p["src"], par, tau, p["rec"], R, p.get("adj_tol", p["tol"]),
-                              p.get("max_iter", 2000), p["kappa"], tile_k=p.get("tile_k_adj", 0))
+                              p.get("max_iter", 2000), p["kappa"], tile_k=p.get("tile_k_adj", 0),
+                              continuous=p.get("continuous_adjoint", False))
         grad = api.kernel(g, s, xi, eta, p["src"], par, tau, lam)
         grad = grad * grad_chi.to(grad.dtype)
         return grad[0], grad[1], grad[2], None
@@ -52,5 +53,7 @@ def misfit(s, xi, eta, problem):
     """chi(s, xi, eta) for the sources, receivers and observations in
     ``problem`` (keys: grid, src, rec, T_obs, tol, kappa, optional max_iter,
     adj_tol, src_par, w, pairs, wpair, alpha, beta, cr = (cr_off, cr_pair), wcr,
-    gamma, tile_k_fwd, tile_k_adj; see api.misfit)."""
+    gamma, tile_k_fwd, tile_k_adj, continuous_adjoint; see api.misfit).  With
+    continuous_adjoint the backward takes the upwind solution of Eq. (5): the
+    paper's gradient, first-order close to the exact derivative."""
     return EikonalMisfit.apply(s, xi, eta, problem)

@@ -6,7 +6,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libtt.so")
-SOURCES = ["tt_kernels.hip", "tt_api.hip", "nn.hip"]
+SOURCES = ["tt_kernels.hip", "tt_aux.hip", "tt_api.hip", "nn.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.

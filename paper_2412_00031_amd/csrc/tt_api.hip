@@ -506,6 +506,64 @@ int tt_sample(const tt_grid* grid, int32_t nsrc, const double* src_pos, const do
     return TT_OK;
 }
 
+// shared set-up of the relocation entry points: the receiver-side fields as
+// sources of a sampling plan
+static int reloc_plan(const tt_grid* grid, int32_t nfield, const double* field_pos, const double* field_par,
+                      const double* tau, int32_t nev, const double* ev_pos, void* ws, size_t ws_bytes,
+                      hipStream_t st, tt::Plan& P) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (nfield < 0 || nev < 0) return fail(TT_EINVAL, "negative count");
+    if (nfield > 65535) return fail(TT_EINVAL, "nfield > 65535");
+    if (nev > 0x7fffffff / 4) return fail(TT_EINVAL, "nev too large");
+    if ((rc = check_ptrs({field_pos, field_par, tau, ev_pos, ws}))) return rc;
+    tt::Geo G = make_geo(grid, kDefaultTileK);
+    fill_plan(P, G, nfield);
+    Layout L = layout(G, nfield, P.nslots, 2);
+    if (ws_bytes < L.total) return fail(TT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    bind_workspace(P, ws, L);
+    tt::launch_tables(P, st);
+    tt::launch_src_setup(P, field_pos, field_par, st);
+    return TT_OK;
+}
+
+int tt_reloc_times(const tt_grid* grid, int32_t nfield, const double* field_pos, const double* field_par,
+                   const double* tau, int32_t nev, const double* ev_pos, const double* ev_t0, double* T, void* ws,
+                   size_t ws_bytes, void* stream) {
+    g_err.clear();
+    if (nfield == 0 || nev == 0) return (nfield < 0 || nev < 0) ? fail(TT_EINVAL, "negative count") : TT_OK;
+    if (!T) return fail(TT_EINVAL, "T is NULL");
+    tt::Plan P;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = reloc_plan(grid, nfield, field_pos, field_par, tau, nev, ev_pos, ws, ws_bytes, st, P);
+    if (rc) return rc;
+    tt::launch_reloc_times(P, tau, nev, ev_pos, ev_t0, T, st);
+    TT_HIP(hipGetLastError());
+    return TT_OK;
+}
+
+int tt_reloc_kernel(const tt_grid* grid, int32_t nfield, const double* field_pos, const double* field_par,
+                    const double* tau, int32_t nev, const double* ev_pos, const double* R, double* K, void* ws,
+                    size_t ws_bytes, void* stream) {
+    g_err.clear();
+    if (nfield < 0 || nev < 0) return fail(TT_EINVAL, "negative count");
+    if (nev == 0) return TT_OK;
+    if (!K) return fail(TT_EINVAL, "K is NULL");
+    if (nfield == 0) {
+        tt::launch_fill(K, 4LL * nev, 0.0, (hipStream_t)stream);
+        TT_HIP(hipGetLastError());
+        return TT_OK;
+    }
+    if (!R) return fail(TT_EINVAL, "R is NULL");
+    tt::Plan P;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = reloc_plan(grid, nfield, field_pos, field_par, tau, nev, ev_pos, ws, ws_bytes, st, P);
+    if (rc) return rc;
+    tt::launch_reloc_kernel(P, tau, nev, ev_pos, R, K, st);
+    TT_HIP(hipGetLastError());
+    return TT_OK;
+}
+
 int tt_misfit(int32_t nsrc, int32_t nrec, const double* T_rec, const double* T_obs, const double* w, int32_t npair,
               const int32_t* pairs, const double* wpair, double alpha, double beta, double* R, double* chi,
               void* stream) {
@@ -560,6 +618,7 @@ int tt_adjoint(const tt_grid* grid, const double* s, const double* xi, const dou
         Group& g = gs[q];
         const int q0 = group_begin(nsrc, groups, q);
         g.P.eps_hist = opts->eps_hist ? opts->eps_hist + (long long)q0 * opts->max_iter : nullptr;
+        g.P.continuous = (opts->flags & TT_FLAG_CONTINUOUS_ADJOINT) != 0;
         if (opts->flags & TT_FLAG_TIME_SWEEPS) g.P.timing = &ev;
         tt::launch_tables(g.P, g.st);
         tt::launch_src_setup(g.P, src_pos + 3LL * q0, src_par + 3LL * q0, g.st);
@@ -571,6 +630,12 @@ int tt_adjoint(const tt_grid* grid, const double* s, const double* xi, const dou
     const bool graph = (opts->flags & TT_FLAG_GRAPH) && !(opts->flags & TT_FLAG_TIME_SWEEPS);
     rc = run_iterations(gs, graph, [&](Group& g, hipStream_t s_) { tt::launch_adj_iteration(g.P, g.a, s_); });
     collect_timing(ev, 1);
+    if (rc == TT_OK && (opts->flags & TT_FLAG_CONTINUOUS_ADJOINT)) {
+        for (int q = 0; q < groups; ++q)
+            tt::launch_cadj_scale(gs[q].P, s, lam + (long long)group_begin(nsrc, groups, q) * G.N, gs[q].st);
+        TT_HIP(hipGetLastError());
+        for (int q = 0; q < groups; ++q) TT_HIP(hipStreamSynchronize(gs[q].st));
+    }
     return rc;
 }
 
@@ -615,24 +680,39 @@ int tt_kernel_density(const tt_grid* grid, const double* s, const double* dens, 
 }
 
 static int check_mg(int H, const int32_t* m, const double* coords) {
-    if (H < 1) return fail(TT_EINVAL, "H must be >= 1");
+    if (H < 1 || H > TT_MG_MAX_GRIDS) return fail(TT_EINVAL, "H = %d outside [1, %d]", H, TT_MG_MAX_GRIDS);
     if (!m || !coords) return fail(TT_EINVAL, "m and coords must not be NULL");
     for (int q = 0; q < 3 * H; ++q)
         if (m[q] < 1 || m[q] > 1 << 20) return fail(TT_EINVAL, "inversion grid size m[%d] = %d out of range", q, m[q]);
-    for (int q = 0; q < H; ++q)
+    long long s12 = 0;
+    for (int q = 0; q < H; ++q) {
         if ((long long)m[3 * q] * m[3 * q + 1] * m[3 * q + 2] > 0x7fffffffLL)
             return fail(TT_EINVAL, "inversion grid %d too large", q);
+        s12 += (long long)m[3 * q + 1] * m[3 * q + 2];
+    }
+    if (s12 > 0x7fffffffLL) return fail(TT_EINVAL, "inversion grids too large");
     return TT_OK;
 }
 
+size_t tt_mg_workspace_size(const tt_grid* grid, int32_t H, const int32_t* m) {
+    g_err.clear();
+    const double dummy = 0.0;
+    if (check_grid(grid) || check_mg(H, m, &dummy)) return 0;
+    const tt::Geo G = make_geo(grid, kDefaultTileK);
+    return tt::plan_mg_project(G, tt::make_mg(H, m)).ws_bytes;
+}
+
 int tt_mg_project(const tt_grid* grid, int32_t H, const int32_t* m, const double* coords, const double* K,
-                  double* out, void* stream) {
+                  double* out, void* ws, size_t ws_bytes, void* stream) {
     g_err.clear();
     int rc = check_grid(grid);
     if (rc || (rc = check_mg(H, m, coords))) return rc;
     if ((rc = check_ptrs({K, out}))) return rc;
     tt::Geo G = make_geo(grid, kDefaultTileK);
-    tt::launch_mg_project(G, H, m, coords, K, out, (hipStream_t)stream);
+    const size_t need = tt::plan_mg_project(G, tt::make_mg(H, m)).ws_bytes;
+    if (need > 0 && (!ws || ws_bytes < need))
+        return fail(TT_EINVAL, "workspace of %zu bytes too small (need %zu)", ws_bytes, need);
+    tt::launch_mg_project(G, H, m, coords, K, out, (double*)ws, (hipStream_t)stream);
     TT_HIP(hipGetLastError());
     return TT_OK;
 }

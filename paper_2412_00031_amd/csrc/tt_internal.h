@@ -203,7 +203,8 @@ struct Plan {
     double* part2 = nullptr;
     double* coef = nullptr;   // adjoint: [nsrc][2][S][8] (row-coalesced layouts)
     double* model = nullptr;  // forward: [2][S][4] = (s, xi, eta, 0) (row-coalesced layouts)
-    double* bnd_in = nullptr; // adjoint: [nsrc][NB]
+    double* bnd_in = nullptr; // adjoint: [nsrc][NB] (continuous adjoint: boundary pass scratch)
+    bool continuous = false;  // adjoint: upwind discretisation of Eq. (5) instead of the exact transpose
     std::vector<int> plane_count;
     // optional timing of the sweep kernels: an event pair around the
     // tile-plane launches of each directional sweep, with the launch count
@@ -243,15 +244,47 @@ void launch_fwd_iteration(const Plan& P, const SweepArgs& a, hipStream_t st);
 void launch_adj_init(const Plan& P, const SweepArgs& a, const double* tau, int nrec, const double* rec_pos,
                      const double* R, hipStream_t st);
 void launch_adj_iteration(const Plan& P, const SweepArgs& a, hipStream_t st);
+void launch_cadj_scale(const Plan& P, const double* s, double* lam, hipStream_t st);
 void launch_sample(const Plan& P, const double* tau, int nrec, const double* rec_pos, double* out,
                    hipStream_t st);
+void launch_fill(double* p, long long n, double v, hipStream_t st);
+void launch_reloc_times(const Plan& P, const double* tau, int nev, const double* ev, const double* t0, double* out,
+                        hipStream_t st);
+void launch_reloc_kernel(const Plan& P, const double* tau, int nev, const double* ev, const double* R, double* K,
+                         hipStream_t st);
 void launch_misfit(int nsrc, int nrec, const double* T, const double* Tobs, const double* w, int npair,
                    const int32_t* pairs, const double* wpair, double alpha, double beta, double* R,
                    double* chi, hipStream_t st);
 void launch_misfit_cr(int nsrc, int nrec, const double* T, const double* Tobs, const int32_t* off, const int32_t* pair,
                       const double* wcr, double gamma, double* R, double* chi, hipStream_t st);
+// Inversion grids of the multiple-grid parameterisation, flattened for kernel
+// arguments: sizes, offsets of each grid's axis coordinates in the
+// concatenated coords array, and running sums of m2, m1*m2 and 3*m0*m1*m2.
+struct MgGrids {
+    int H;
+    int ncoord;  // total coordinates of all grids
+    int m[TT_MG_MAX_GRIDS][3];
+    int coff[TT_MG_MAX_GRIDS][3];
+    int s2off[TT_MG_MAX_GRIDS + 1];
+    int s12off[TT_MG_MAX_GRIDS + 1];
+    long long outoff[TT_MG_MAX_GRIDS + 1];
+};
+
+// Projection plan: the separable staged form when its LDS fits, with nch
+// row chunks per plane and ws_bytes of partial sums; else one wave per node.
+constexpr long long kMgMaxLds = 64 * 1024;
+constexpr long long kMgCoordLds = 32 * 1024;  // coordinates staged in LDS up to this size
+struct MgPlan {
+    bool separable;
+    int nch;
+    size_t lds;
+    size_t ws_bytes;
+};
+
+MgGrids make_mg(int H, const int* m);
+MgPlan plan_mg_project(const Geo& G, const MgGrids& Q);
 void launch_mg_project(const Geo& G, int H, const int* m, const double* coords, const double* K, double* out,
-                       hipStream_t st);
+                       double* ws, hipStream_t st);
 void launch_mg_expand(const Geo& G, int H, const int* m, const double* coords, const double* C, double* field,
                       hipStream_t st);
 void launch_kernel_density(const Geo& G, const double* s, const double* dens, const double* grad, double eps,

@@ -27,25 +27,15 @@
 // per-tile partial sums in a fixed order (bitwise reproducible run to run).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <utility>
 
+#include "tt_device.h"
 #include "tt_internal.h"
 
 namespace tt {
 
 // ---------------------------------------------------------------- helpers
-__device__ __forceinline__ int cell_base(const Geo& G, int a, double x) {
-    double u = (x - G.o[a]) / G.h[a];
-    double fl = floor(u);
-    if (fl < 0.0) return 0;
-    if (fl > (double)(G.n[a] - 2)) return G.n[a] - 2;
-    return (int)fl;
-}
-
-__device__ __forceinline__ long long nidx(const Geo& G, int i, int j, int k) {
-    return (long long)i * G.si + (long long)j * G.sj + k;
-}
-
 // boundary node number b in [0, NB) -> (i, j, k); slabs i = 0 and n0-1 are full,
 // slabs in between contribute the ring j in {0, n1-1} or k in {0, n2-1}.
 __device__ __forceinline__ void bnd_decode(const Geo& G, long long b, int& i, int& j, int& k) {
@@ -99,23 +89,6 @@ __device__ __forceinline__ int astar_of(const Geo& G, const int p[3]) {
     for (int a = 0; a < 3; ++a)
         if (on_bnd(G, a, p[a])) as = a;
     return as;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// fixed-order sum over a 256-thread block (result valid in thread 0)
-__device__ __forceinline__ double block_sum256(double v, double* sh) {
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) sh[w] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-    __syncthreads();
-    return r;
 }
 
 // tile (TI', TJ', TK') number b of tile-plane p (TI'+TJ'+TK' = p), ordered by
@@ -180,26 +153,6 @@ __global__ void k_src_setup(Geo G, const double* __restrict__ pos, const double*
 }
 
 // trilinear cell and weights at a continuous position (clamped to the grid)
-struct Tri {
-    int b[3];
-    double f[3];
-};
-
-__device__ __forceinline__ Tri tri_of(const Geo& G, double p0, double p1, double p2) {
-    Tri t;
-    const double p[3] = {p0, p1, p2};
-    for (int a = 0; a < 3; ++a) {
-        t.b[a] = cell_base(G, a, p[a]);
-        const double f = (p[a] - G.o[a]) / G.h[a] - (double)t.b[a];
-        t.f[a] = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
-    }
-    return t;
-}
-
-__device__ __forceinline__ double tri_w(const Tri& t, int c0, int c1, int c2) {
-    return (c0 ? t.f[0] : 1.0 - t.f[0]) * (c1 ? t.f[1] : 1.0 - t.f[1]) * (c2 ? t.f[2] : 1.0 - t.f[2]);
-}
-
 __global__ void k_source_params(Geo G, const double* __restrict__ s, const double* __restrict__ xi,
                                 const double* __restrict__ eta, const double* __restrict__ pos,
                                 double* __restrict__ par, int nsrc) {
@@ -712,11 +665,12 @@ __global__ void __launch_bounds__(256) k_adj_coef(SweepArgs a, const double* __r
     }
 }
 
-// d chi / d tau = sum_m R_m w_c T0(c), added in receiver order (one thread per
-// source: deterministic)
+// d chi / d tau = sum_m R_m w_c T0(c) (discrete adjoint), or the point sources
+// sum_m R_m w_c of Eq. (5) (continuous adjoint, with_t0 = 0), added in receiver
+// order (one thread per source: deterministic)
 template <int COORD>
 __global__ void k_adj_rhs(SweepArgs a, double* __restrict__ coef_all, int nrec, const double* __restrict__ rec,
-                          const double* __restrict__ R) {
+                          const double* __restrict__ R, int with_t0) {
     const int src = blockIdx.x * blockDim.x + threadIdx.x;
     if (src >= a.nsrc) return;
     const Geo& G = a.G;
@@ -733,7 +687,7 @@ __global__ void k_adj_rhs(SweepArgs a, double* __restrict__ coef_all, int nrec, 
                     const double2 t2 = a.T.t2[k];
                     double T0, tt[3];
                     factor<COORD>(S, c, t2.x, t2.y, T0, tt);
-                    const double v = r * tri_w(t, c0, c1, c2) * T0;
+                    const double v = with_t0 ? r * tri_w(t, c0, c1, c2) * T0 : r * tri_w(t, c0, c1, c2);
                     cf[skew_idx(G, 0, i, j, k) * 8 + 7] += v;
                     cf[(G.S + skew_idx(G, 1, i, j, k)) * 8 + 7] += v;
                 }
@@ -899,6 +853,192 @@ __global__ void __launch_bounds__(256) k_adj_finalize(SweepArgs a) {
     if (threadIdx.x == 0) finish_iteration(a, src, dtot / (atot > 1e-300 ? atot : 1e-300));
 }
 
+// ------------------------------------------ continuous adjoint (Eq. (5))
+// Upwind finite volumes for div(P w) = sum_m R_m delta(x - x_m), w = -M grad T.
+// Each node owns the trapezoidal control volume around it; the flux leaves
+// through six faces with the face velocity the mean of the two nodal normal
+// components (the node's own on a grid face) and carries the upwind node's P.
+// P = 0 on the fixed cell (the source absorbs) and outside the grid.
+
+// w = -M p at any node, p the scaled gradient of T = T0 tau: central
+// differences of tau along axes where the node is interior, one-sided where
+// it lies on the grid face.
+template <int COORD>
+__device__ __forceinline__ void cadj_vel(const Geo& G, const Tabs& T, const Src& S, const double* __restrict__ tau,
+                                         const double* __restrict__ xi, const double* __restrict__ eta, int i, int j,
+                                         int k, double w[3]) {
+    const Col c = make_col(G, T, i, j);
+    const double2 t2 = T.t2[k];
+    double T0, t[3];
+    factor<COORD>(S, c, t2.x, t2.y, T0, t);
+    const long long x = nidx(G, i, j, k);
+    const int id[3] = {i, j, k};
+    const long long st[3] = {G.si, G.sj, 1};
+    const double tx = tau[x];
+    double p[3];
+#pragma unroll
+    for (int a2 = 0; a2 < 3; ++a2) {
+        double q;
+        if (id[a2] == 0) q = (tau[x + st[a2]] - tx) * G.invh[a2];
+        else if (id[a2] == G.n[a2] - 1) q = (tx - tau[x - st[a2]]) * G.invh[a2];
+        else q = (tau[x + st[a2]] - tau[x - st[a2]]) * G.inv2h[a2];
+        p[a2] = T0 * g_of(c, a2) * q + tx * t[a2];
+    }
+    const double xv = xi[x], ev = eta[x];
+    w[0] = -p[0];
+    w[1] = -((1.0 - 2.0 * xv) * p[1] + 2.0 * ev * p[2]);
+    w[2] = -(2.0 * ev * p[1] + (1.0 + 2.0 * xv) * p[2]);
+}
+
+// control-volume extent of node index idx along axis a
+__device__ __forceinline__ double cv_ext(const Geo& G, int a, int idx) {
+    return (idx == 0 || idx == G.n[a] - 1) ? 0.5 * G.h[a] : G.h[a];
+}
+
+// Area of the face of node (i, j, k) normal to axis a at coordinate xf of that
+// axis: r^2 cos(theta) dtheta dphi (r faces), r cos(theta) dr dphi (theta
+// faces), r dr dtheta (phi faces); products of the other extents in Cartesian
+// coordinates.
+__device__ __forceinline__ double cadj_area(const Geo& G, int a, int i, int j, int k, double xf) {
+    const int id[3] = {i, j, k};
+    double A = 1.0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+        if (b != a) A *= cv_ext(G, b, id[b]);
+    if (G.coord == 1) {
+        const double r = G.o[0] + i * G.h[0];
+        if (a == 0) A *= xf * xf * cos(G.o[1] + j * G.h[1]);
+        else if (a == 1) A *= r * cos(xf);
+        else A *= r;
+    }
+    return A;
+}
+
+// Records of the continuous system in the adjoint layout {c+_0, c-_0, c+_1,
+// c-_1, c+_2, c-_2, outflow, rhs}: c+-_a = A min(u_out, 0) couples P(x +- e_a)
+// (0 when that node is fixed or outside), outflow = sum A max(u_out, 0).  A
+// node without outflow gets outflow = inf, so that its update is P = 0.
+template <int COORD>
+__global__ void __launch_bounds__(256) k_cadj_coef(SweepArgs a, const double* __restrict__ tau_all,
+                                                   double* __restrict__ coef_all) {
+    const Geo& G = a.G;
+    const int src = blockIdx.y;
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= G.N) return;
+    const Src S = a.src[src];
+    const double* tau = tau_all + (long long)src * G.N;
+    const int k = (int)(x % G.n[2]);
+    const long long q = x / G.n[2];
+    const int j = (int)(q % G.n[1]), i = (int)(q / G.n[1]);
+    double out[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (!in_fixed(S, i, j, k)) {
+        double w[3];
+        cadj_vel<COORD>(G, a.T, S, tau, a.xi, a.eta, i, j, k, w);
+        const int id[3] = {i, j, k};
+        double diag = 0.0;
+        for (int ax = 0; ax < 3; ++ax) {
+            const double xa = G.o[ax] + id[ax] * G.h[ax];
+            for (int side = 0; side < 2; ++side) {
+                const int sg = side == 0 ? 1 : -1;
+                const int nb = id[ax] + sg;
+                int y[3] = {i, j, k};
+                y[ax] = nb;
+                double u, A;
+                const bool inside = nb >= 0 && nb < G.n[ax];
+                if (inside) {
+                    double wy[3];
+                    cadj_vel<COORD>(G, a.T, S, tau, a.xi, a.eta, y[0], y[1], y[2], wy);
+                    u = sg * 0.5 * (w[ax] + wy[ax]);
+                    A = cadj_area(G, ax, i, j, k, 0.5 * (xa + (G.o[ax] + nb * G.h[ax])));
+                } else {
+                    u = sg * w[ax];
+                    A = cadj_area(G, ax, i, j, k, xa);
+                }
+                diag += A * (u > 0.0 ? u : 0.0);
+                out[2 * ax + side] = (inside && !in_fixed(S, y[0], y[1], y[2])) ? A * (u < 0.0 ? u : 0.0) : 0.0;
+            }
+        }
+        out[6] = diag > 0.0 ? diag : HUGE_VAL;
+    }
+    for (int f = 0; f < 2; ++f) {
+        double2* cf = reinterpret_cast<double2*>(coef_all + (((long long)src * 2 + f) * G.S + skew_idx(G, f, i, j, k)) * 8);
+#pragma unroll
+        for (int q2 = 0; q2 < 4; ++q2) cf[q2] = make_double2(out[2 * q2], out[2 * q2 + 1]);
+    }
+}
+
+// Boundary pass of the continuous system, Jacobi: every boundary node's new P
+// from the values present before the pass, into tmp [nsrc][NB] ...
+__global__ void __launch_bounds__(kBndThreads) k_cadj_bnd_calc(SweepArgs a, double* __restrict__ tmp_all) {
+    const int src = blockIdx.y;
+    if (!a.active[src]) return;
+    const Geo& G = a.G;
+    const long long b = (long long)blockIdx.x * kBndThreads + threadIdx.x;
+    if (b >= G.NB) return;
+    const Src S = a.src[src];
+    const double* P = a.field + (long long)src * G.N;
+    const double* cf = a.coef + (long long)src * 2 * G.S * 8;
+    int i, j, k;
+    bnd_decode(G, b, i, j, k);
+    double nv = 0.0;
+    if (!in_fixed(S, i, j, k)) {
+        const double* r = cf + skew_idx(G, 0, i, j, k) * 8;
+        const long long x = nidx(G, i, j, k);
+        const int id[3] = {i, j, k};
+        const long long st[3] = {G.si, G.sj, 1};
+        double acc = r[7];
+        for (int ax = 0; ax < 3; ++ax) {
+            if (r[2 * ax] != 0.0 && id[ax] + 1 < G.n[ax]) acc -= r[2 * ax] * P[x + st[ax]];
+            if (r[2 * ax + 1] != 0.0 && id[ax] > 0) acc -= r[2 * ax + 1] * P[x - st[ax]];
+        }
+        nv = acc / r[6];
+    }
+    tmp_all[(long long)src * G.NB + b] = nv;
+}
+
+// ... then written back, with the convergence sums in the boundary slots.
+__global__ void __launch_bounds__(kBndThreads) k_cadj_bnd_store(SweepArgs a, const double* __restrict__ tmp_all,
+                                                                int dir) {
+    __shared__ double sh[4];
+    const int src = blockIdx.y;
+    if (!a.active[src]) return;
+    const Geo& G = a.G;
+    double* P = a.field + (long long)src * G.N;
+    const long long b = (long long)blockIdx.x * kBndThreads + threadIdx.x;
+    double d = 0.0, av = 0.0;
+    if (b < G.NB) {
+        int i, j, k;
+        bnd_decode(G, b, i, j, k);
+        const long long x = nidx(G, i, j, k);
+        const double nv = tmp_all[(long long)src * G.NB + b];
+        d = fabs(nv - P[x]);
+        av = fabs(nv);
+        P[x] = nv;
+    }
+    d = block_sum256(d, sh);
+    const double as = (dir == 7) ? block_sum256(av, sh) : 0.0;
+    if (threadIdx.x == 0) {
+        a.part[(long long)src * a.nslots + 8 * G.ntiles + dir * a.nbblocks + blockIdx.x] = d;
+        if (dir == 7) a.part2[(long long)src * a.nslots + G.ntiles + blockIdx.x] = as;
+    }
+}
+
+// The continuous adjoint's P as the derivative it estimates: d chi / d s(x) =
+// P s V (Eqs. (6), (9)), V the trapezoidal node volume.
+__global__ void __launch_bounds__(256) k_cadj_scale(Geo G, const double* __restrict__ s, double* __restrict__ lam_all,
+                                                    int nsrc) {
+    const int src = blockIdx.y;
+    double* lam = lam_all + (long long)src * G.N;
+    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < G.N;
+         x += (long long)gridDim.x * blockDim.x) {
+        const int k = (int)(x % G.n[2]);
+        const long long q = x / G.n[2];
+        const int j = (int)(q % G.n[1]), i = (int)(q / G.n[1]);
+        lam[x] *= s[x] * node_volume(G, i, j, k);
+    }
+    (void)nsrc;
+}
+
 // --------------------------------------------------------- sampling etc.
 template <int COORD>
 __global__ void k_sample(Geo G, Tabs T, const Src* __restrict__ srcs, int nsrc, const double* __restrict__ tau_all,
@@ -921,78 +1061,6 @@ __global__ void k_sample(Geo G, Tabs T, const Src* __restrict__ srcs, int nsrc, 
                 acc += tri_w(t, c0, c1, c2) * T0 * tau[nidx(G, i, j, k)];
             }
     out[q] = acc;
-}
-
-__global__ void __launch_bounds__(256) k_misfit(int nsrc, int nrec, const double* __restrict__ T,
-                                                const double* __restrict__ Tobs, const double* __restrict__ w,
-                                                int npair, const int32_t* __restrict__ pairs,
-                                                const double* __restrict__ wpair, double alpha, double beta,
-                                                double* __restrict__ R, double* __restrict__ chi) {
-    __shared__ double sh[4];
-    __shared__ int bad;
-    if (threadIdx.x == 0) bad = 0;
-    __syncthreads();
-    double part = 0.0;
-    for (int q = threadIdx.x; q < nsrc; q += blockDim.x) {
-        const long long base = (long long)q * nrec;
-        for (int m = 0; m < nrec; ++m) {
-            const double ww = w ? w[base + m] : 1.0;
-            const double r = T[base + m] - Tobs[base + m];
-            part += alpha * 0.5 * ww * r * r;
-            R[base + m] = alpha * ww * r;
-        }
-        for (int p = 0; p < npair; ++p) {
-            const int m = pairs[2 * p], i = pairs[2 * p + 1];
-            if (m < 0 || m >= nrec || i < 0 || i >= nrec) {
-                bad = 1;
-                continue;
-            }
-            const double ww = wpair ? wpair[(long long)q * npair + p] : 1.0;
-            const double r = (T[base + m] - T[base + i]) - (Tobs[base + m] - Tobs[base + i]);
-            part += beta * 0.5 * ww * r * r;
-            R[base + m] += beta * ww * r;
-            R[base + i] -= beta * ww * r;
-        }
-    }
-    const double tot = block_sum256(part, sh);
-    if (threadIdx.x == 0) *chi = bad ? __builtin_nan("") : tot;
-}
-
-// Common-receiver differential misfit (Eq. (4), third misfit) and its adjoint
-// sources (Eq. (A4)), added to R and chi.  One thread owns receiver m (a column
-// of R) and walks that receiver's source pairs in list order, so no two
-// threads write one element and the sums are deterministic.
-__global__ void __launch_bounds__(256) k_misfit_cr(int nsrc, int nrec, const double* __restrict__ T,
-                                                   const double* __restrict__ Tobs, const int32_t* __restrict__ off,
-                                                   const int32_t* __restrict__ pair, const double* __restrict__ wcr,
-                                                   double gamma, double* __restrict__ R, double* __restrict__ chi) {
-    __shared__ double sh[4];
-    __shared__ int bad;
-    if (threadIdx.x == 0) bad = 0;
-    __syncthreads();
-    double part = 0.0;
-    for (int m = threadIdx.x; m < nrec; m += blockDim.x) {
-        const int p0 = off[m], p1 = off[m + 1];
-        if (p0 < 0 || p1 < p0 || (p1 > p0 && !pair)) {
-            bad = 1;
-            continue;
-        }
-        for (int p = p0; p < p1; ++p) {
-            const int n = pair[2 * p], j = pair[2 * p + 1];
-            if (n < 0 || n >= nsrc || j < 0 || j >= nsrc) {
-                bad = 1;
-                continue;
-            }
-            const long long cn = (long long)n * nrec + m, cj = (long long)j * nrec + m;
-            const double ww = wcr ? wcr[p] : 1.0;
-            const double r = (T[cn] - T[cj]) - (Tobs[cn] - Tobs[cj]);
-            part += gamma * 0.5 * ww * r * r;
-            R[cn] += gamma * ww * r;
-            R[cj] -= gamma * ww * r;
-        }
-    }
-    const double tot = block_sum256(part, sh);
-    if (threadIdx.x == 0) *chi = bad ? __builtin_nan("") : *chi + tot;
 }
 
 template <int COORD>
@@ -1029,7 +1097,6 @@ __global__ void __launch_bounds__(256) k_kernel_accum(Geo G, Tabs T, const Src* 
 }
 
 // ---------------------------------------------------------------- launchers
-static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 SweepArgs make_args(const Plan& P, const double* s, const double* xi, const double* eta, double* field,
                     int32_t* status) {
@@ -1074,10 +1141,6 @@ void launch_source_params(const Geo& G, const double* s, const double* xi, const
     hipLaunchKernelGGL(k_source_params, dim3(blocks_for(nsrc, 64)), dim3(64), 0, st, G, s, xi, eta, pos, par, nsrc);
 }
 
-static unsigned fill_blocks(long long n) {
-    unsigned nb = blocks_for(n, 256);
-    return nb > 2048 ? 2048 : (nb == 0 ? 1 : nb);
-}
 
 void launch_fwd_init(const Plan& P, const SweepArgs& a, const double* tau_init, const double* s, const double* xi,
                      const double* eta, hipStream_t st) {
@@ -1151,12 +1214,16 @@ void launch_adj_init(const Plan& P, const SweepArgs& a, const double* tau, int n
                      const double* R, hipStream_t st) {
     hipLaunchKernelGGL(k_fill, dim3(fill_blocks(P.G.NB * P.nsrc)), dim3(256), 0, st, P.bnd_in, P.G.NB * P.nsrc, 0.0);
     const dim3 grid(blocks_for(P.G.N, 256), P.nsrc);
+    const dim3 rgrid(blocks_for(P.nsrc, 64));
+    const int t0 = P.continuous ? 0 : 1;
     if (P.G.coord == 1) {
-        hipLaunchKernelGGL(k_adj_coef<1>, grid, dim3(256), 0, st, a, tau, P.coef, P.bnd_in);
-        hipLaunchKernelGGL(k_adj_rhs<1>, dim3(blocks_for(P.nsrc, 64)), dim3(64), 0, st, a, P.coef, nrec, rec, R);
+        if (P.continuous) hipLaunchKernelGGL(k_cadj_coef<1>, grid, dim3(256), 0, st, a, tau, P.coef);
+        else hipLaunchKernelGGL(k_adj_coef<1>, grid, dim3(256), 0, st, a, tau, P.coef, P.bnd_in);
+        hipLaunchKernelGGL(k_adj_rhs<1>, rgrid, dim3(64), 0, st, a, P.coef, nrec, rec, R, t0);
     } else {
-        hipLaunchKernelGGL(k_adj_coef<0>, grid, dim3(256), 0, st, a, tau, P.coef, P.bnd_in);
-        hipLaunchKernelGGL(k_adj_rhs<0>, dim3(blocks_for(P.nsrc, 64)), dim3(64), 0, st, a, P.coef, nrec, rec, R);
+        if (P.continuous) hipLaunchKernelGGL(k_cadj_coef<0>, grid, dim3(256), 0, st, a, tau, P.coef);
+        else hipLaunchKernelGGL(k_adj_coef<0>, grid, dim3(256), 0, st, a, tau, P.coef, P.bnd_in);
+        hipLaunchKernelGGL(k_adj_rhs<0>, rgrid, dim3(64), 0, st, a, P.coef, nrec, rec, R, t0);
     }
     hipLaunchKernelGGL(k_solve_init, dim3(fill_blocks(P.G.N), P.nsrc), dim3(256), 0, st, a, nullptr, 0.0, 0.0);
 }
@@ -1169,9 +1236,22 @@ void launch_adj_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
         for (int p = 0; p < P.nplanes; ++p)
             hipLaunchKernelGGL(fn, dim3(P.nsrc, P.plane_count[p]), dim3(64), tile_lds_bytes(P.G), st, a, p);
         }
-        hipLaunchKernelGGL(k_adj_bnd, dim3(P.nbblocks, P.nsrc), dim3(kBndThreads), 0, st, a, d);
+        if (P.continuous) {
+            hipLaunchKernelGGL(k_cadj_bnd_calc, dim3(P.nbblocks, P.nsrc), dim3(kBndThreads), 0, st, a, P.bnd_in);
+            hipLaunchKernelGGL(k_cadj_bnd_store, dim3(P.nbblocks, P.nsrc), dim3(kBndThreads), 0, st, a, P.bnd_in, d);
+        } else {
+            hipLaunchKernelGGL(k_adj_bnd, dim3(P.nbblocks, P.nsrc), dim3(kBndThreads), 0, st, a, d);
+        }
     }
     hipLaunchKernelGGL(k_adj_finalize, dim3(P.nsrc), dim3(256), 0, st, a);
+}
+
+void launch_cadj_scale(const Plan& P, const double* s, double* lam, hipStream_t st) {
+    hipLaunchKernelGGL(k_cadj_scale, dim3(fill_blocks(P.G.N), P.nsrc), dim3(256), 0, st, P.G, s, lam, P.nsrc);
+}
+
+void launch_fill(double* p, long long n, double v, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_fill, dim3(fill_blocks(n)), dim3(256), 0, st, p, n, v);
 }
 
 void launch_sample(const Plan& P, const double* tau, int nrec, const double* rec, double* out, hipStream_t st) {
@@ -1183,196 +1263,6 @@ void launch_sample(const Plan& P, const double* tau, int nrec, const double* rec
     else
         hipLaunchKernelGGL(k_sample<0>, dim3(blocks_for(tot, 256)), dim3(256), 0, st, P.G, P.T, P.src, P.nsrc, tau,
                            nrec, rec, out);
-}
-
-void launch_misfit(int nsrc, int nrec, const double* T, const double* Tobs, const double* w, int npair,
-                   const int32_t* pairs, const double* wpair, double alpha, double beta, double* R, double* chi,
-                   hipStream_t st) {
-    hipLaunchKernelGGL(k_misfit, dim3(1), dim3(256), 0, st, nsrc, nrec, T, Tobs, w, npair, pairs, wpair, alpha, beta,
-                       R, chi);
-}
-
-void launch_misfit_cr(int nsrc, int nrec, const double* T, const double* Tobs, const int32_t* off, const int32_t* pair,
-                      const double* wcr, double gamma, double* R, double* chi, hipStream_t st) {
-    hipLaunchKernelGGL(k_misfit_cr, dim3(1), dim3(256), 0, st, nsrc, nrec, T, Tobs, off, pair, wcr, gamma, R, chi);
-}
-
-// ------------------------------------------- multiple-grid parameterisation
-// Coordinate of node i on axis a, rounded as o + i h is by definition (product,
-// then sum; no fused multiply-add).  A tent ends abruptly at the first and last
-// inversion node, so a node lying on such an end must land on the same side
-// of it whoever evaluates the basis.
-__device__ __forceinline__ double node_coord(const Geo& G, int a, int i) {
-#pragma clang fp contract(off)
-    return G.o[a] + (double)i * G.h[a];
-}
-
-// One-dimensional tent of inversion node i (ascending coordinates c[0..m-1])
-// at x (Eqs. (12)-(14)); zero outside [c[0], c[m-1]].
-__device__ __forceinline__ double mg_tent(const double* c, int m, int i, double x) {
-    if (i > 0 && x >= c[i - 1] && x <= c[i]) return (x - c[i - 1]) / (c[i] - c[i - 1]);
-    if (i < m - 1 && x >= c[i] && x <= c[i + 1]) return (c[i + 1] - x) / (c[i + 1] - c[i]);
-    if (m == 1 && x == c[0]) return 1.0;
-    return 0.0;
-}
-
-// Trapezoidal node volume (r^2 cos(theta) dr dtheta dphi in spherical
-// coordinates, halved once per boundary axis).
-__device__ __forceinline__ double node_volume(const Geo& G, int i, int j, int k) {
-    double v = G.h[0] * G.h[1] * G.h[2];
-    if (G.coord == 1) {
-        const double r = G.o[0] + i * G.h[0];
-        v *= r * r * cos(G.o[1] + j * G.h[1]);
-    }
-    if (i == 0 || i == G.n[0] - 1) v *= 0.5;
-    if (j == 0 || j == G.n[1] - 1) v *= 0.5;
-    if (k == 0 || k == G.n[2] - 1) v *= 0.5;
-    return v;
-}
-
-// Forward-grid index range [lo, hi] of axis a that can lie under the tent of
-// inversion node i (one node of margin each side: the tent itself decides).
-__device__ __forceinline__ void mg_range(const Geo& G, int a, const double* c, int m, int i, int& lo, int& hi) {
-    const double x0 = c[i > 0 ? i - 1 : i], x1 = c[i < m - 1 ? i + 1 : i];
-    lo = (int)floor((x0 - G.o[a]) / G.h[a]) - 1;
-    hi = (int)ceil((x1 - G.o[a]) / G.h[a]) + 1;
-    lo = lo < 0 ? 0 : lo;
-    hi = hi > G.n[a] - 1 ? G.n[a] - 1 : hi;
-}
-
-// Eq. (17): one wave per inversion node (blockIdx.x = (ci m1 + cj) m2 + ck) of
-// one grid; lanes share the node's support box in a fixed pattern and the
-// partial sums are combined by a fixed shuffle tree (deterministic).
-// out [3][m0][m1][m2] = sum_x K[p](x) B(x) V(x), B = u v w / H.
-__global__ void __launch_bounds__(64) k_mg_project(Geo G, int H, int m0, int m1, int m2,
-                                                   const double* __restrict__ c0, const double* __restrict__ c1,
-                                                   const double* __restrict__ c2, const double* __restrict__ K,
-                                                   double* __restrict__ out) {
-    const long long M = (long long)m0 * m1 * m2;
-    const long long l = blockIdx.x;
-    const int ck = (int)(l % m2), cj = (int)((l / m2) % m1), ci = (int)(l / ((long long)m1 * m2));
-    int ilo, ihi, jlo, jhi, klo, khi;
-    mg_range(G, 0, c0, m0, ci, ilo, ihi);
-    mg_range(G, 1, c1, m1, cj, jlo, jhi);
-    mg_range(G, 2, c2, m2, ck, klo, khi);
-    const int ni = ihi - ilo + 1, nj = jhi - jlo + 1, nk = khi - klo + 1;
-    const long long box = (ni > 0 && nj > 0 && nk > 0) ? (long long)ni * nj * nk : 0;
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (long long e = threadIdx.x; e < box; e += 64) {
-        const int k = klo + (int)(e % nk);
-        const int j = jlo + (int)((e / nk) % nj);
-        const int i = ilo + (int)(e / ((long long)nk * nj));
-        const double u = mg_tent(c0, m0, ci, node_coord(G, 0, i));
-        const double v = mg_tent(c1, m1, cj, node_coord(G, 1, j));
-        const double w = mg_tent(c2, m2, ck, node_coord(G, 2, k));
-        const double b = u * v * w / H * node_volume(G, i, j, k);
-        if (b != 0.0) {
-            const long long x = ((long long)i * G.n[1] + j) * G.n[2] + k;
-            for (int p = 0; p < 3; ++p) acc[p] += K[p * G.N + x] * b;
-        }
-    }
-    for (int p = 0; p < 3; ++p) acc[p] = wave_sum(acc[p]);
-    if (threadIdx.x == 0)
-        for (int p = 0; p < 3; ++p) out[p * M + l] = acc[p];
-}
-
-// Nonzero tents of one axis at x: at most two inversion nodes (ascending
-// coordinates), in ascending node order.
-__device__ __forceinline__ int mg_axis(const double* c, int m, double x, int idx[2], double wt[2]) {
-    int cnt = 0;
-    for (int i = 0; i < m && cnt < 2; ++i) {
-        const double t = mg_tent(c, m, i, x);
-        if (t != 0.0) {
-            idx[cnt] = i;
-            wt[cnt] = t;
-            ++cnt;
-        }
-    }
-    return cnt;
-}
-
-// Eq. (15): one thread per forward node; field[p](x) += sum C B over the
-// (at most 8) nonzero basis functions of one inversion grid.
-__global__ void k_mg_expand(Geo G, int H, int m0, int m1, int m2, const double* __restrict__ c0,
-                            const double* __restrict__ c1, const double* __restrict__ c2,
-                            const double* __restrict__ C, double* __restrict__ field, int first) {
-    const long long M = (long long)m0 * m1 * m2;
-    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < G.N;
-         x += (long long)gridDim.x * blockDim.x) {
-        const int k = (int)(x % G.n[2]);
-        const long long q = x / G.n[2];
-        const int j = (int)(q % G.n[1]), i = (int)(q / G.n[1]);
-        int ii[2], jj[2], kk[2];
-        double wi[2], wj[2], wk[2];
-        const int na = mg_axis(c0, m0, node_coord(G, 0, i), ii, wi);
-        const int nb = mg_axis(c1, m1, node_coord(G, 1, j), jj, wj);
-        const int nc = mg_axis(c2, m2, node_coord(G, 2, k), kk, wk);
-        double acc[3];
-        for (int p = 0; p < 3; ++p) acc[p] = first ? 0.0 : field[p * G.N + x];
-        for (int a = 0; a < na; ++a)
-            for (int b = 0; b < nb; ++b)
-                for (int c = 0; c < nc; ++c) {
-                    const long long l = ((long long)ii[a] * m1 + jj[b]) * m2 + kk[c];
-                    const double bw = wi[a] * wj[b] * wk[c] / H;
-                    for (int p = 0; p < 3; ++p) acc[p] += C[p * M + l] * bw;
-                }
-        for (int p = 0; p < 3; ++p) field[p * G.N + x] = acc[p];
-    }
-}
-
-// Kernel-density normalisation (Eqs. (18)-(19)), one thread per node:
-// Kd = dens / (s V), K = (s grad_s, grad_xi, grad_eta) / V / (Kd + eps)^zeta with
-// V the trapezoidal node volume.
-__global__ void k_kernel_density(Geo G, const double* __restrict__ s, const double* __restrict__ dens,
-                                 const double* __restrict__ grad, double eps, double zeta, double* __restrict__ K,
-                                 double* __restrict__ Kd) {
-    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < G.N;
-         x += (long long)gridDim.x * blockDim.x) {
-        const int k = (int)(x % G.n[2]);
-        const long long q = x / G.n[2];
-        const int j = (int)(q % G.n[1]), i = (int)(q / G.n[1]);
-        const double v = node_volume(G, i, j, k);
-        const double d = dens[x] / (s[x] * v);
-        const double w = pow(d + eps, zeta);
-        if (Kd) Kd[x] = d;
-        K[x] = s[x] * grad[x] / v / w;
-        K[G.N + x] = grad[G.N + x] / v / w;
-        K[2 * G.N + x] = grad[2 * G.N + x] / v / w;
-    }
-}
-
-void launch_kernel_density(const Geo& G, const double* s, const double* dens, const double* grad, double eps,
-                           double zeta, double* K, double* Kd, hipStream_t st) {
-    hipLaunchKernelGGL(k_kernel_density, dim3(fill_blocks(G.N)), dim3(256), 0, st, G, s, dens, grad, eps, zeta, K,
-                       Kd);
-}
-
-void launch_mg_project(const Geo& G, int H, const int* m, const double* coords, const double* K, double* out,
-                       hipStream_t st) {
-    const double* cg = coords;
-    double* og = out;
-    for (int q = 0; q < H; ++q) {
-        const int* mq = m + 3 * q;
-        const long long M = (long long)mq[0] * mq[1] * mq[2];
-        hipLaunchKernelGGL(k_mg_project, dim3((unsigned)M), dim3(64), 0, st, G, H, mq[0], mq[1], mq[2], cg,
-                           cg + mq[0], cg + mq[0] + mq[1], K, og);
-        cg += mq[0] + mq[1] + mq[2];
-        og += 3 * M;
-    }
-}
-
-void launch_mg_expand(const Geo& G, int H, const int* m, const double* coords, const double* C, double* field,
-                      hipStream_t st) {
-    const double* cg = coords;
-    const double* Cg = C;
-    for (int q = 0; q < H; ++q) {
-        const int* mq = m + 3 * q;
-        const long long M = (long long)mq[0] * mq[1] * mq[2];
-        hipLaunchKernelGGL(k_mg_expand, dim3(fill_blocks(G.N)), dim3(256), 0, st, G, H, mq[0], mq[1], mq[2], cg,
-                           cg + mq[0], cg + mq[0] + mq[1], Cg, field, q == 0 ? 1 : 0);
-        cg += mq[0] + mq[1] + mq[2];
-        Cg += 3 * M;
-    }
 }
 
 void launch_kernel_accum(const Plan& P, const double* xi, const double* eta, const double* tau, const double* lam,

@@ -1,0 +1,73 @@
+"""Relocation (Eq. (10), App. B) on the GPU against the oracle: receiver-side
+fields solved with the receivers as sources, sampled at the earthquakes
+(T = Gamma_m(x_n) + t_n), the misfits of Eqs. (B1)-(B3) and the location and
+origin-time kernels.  Each side runs its own forward solves from the same
+seeded inputs.  Tolerances: T to 1e-12 (the fields' own tolerance), K to 1e-9
+normwise (it differentiates the fields, and its sums run in another order)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from conftest import rel_inf
+from paper_2412_00031_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(torch, a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("nfield,nev", [(6, 3), (70, 9)])
+def test_reloc_parity(torch_cuda, nfield, nev):
+    from paper_2412_00031_amd import api
+    torch = torch_cuda
+    wl = W.small_spherical(n=(13, 14, 15), nsrc=nev, nrec=nfield, seed=31 + nfield)
+    g, kappa, tol = wl["grid"], wl["kappa"], 1e-12
+    rec, ev = wl["rec"], wl["src"]
+    rng = np.random.default_rng(7)
+    t0 = rng.normal(0.0, 0.1, nev)
+    pairs = W.random_pairs(nfield, min(20, nfield * (nfield - 1) // 2), rng)
+    off, cpair, tri = W.receiver_source_pairs(nev, nfield, 2, rng)
+    # oracle
+    par_o = O.source_params(g, wl["s"], wl["xi"], wl["eta"], rec)
+    tau_o = np.stack([O.forward(g, wl["s"], wl["xi"], wl["eta"], rec[m], par_o[m], kappa, tol, 2000)[0]
+                      for m in range(nfield)])
+    T_o = O.reloc_times(g, rec, par_o, tau_o, ev, t0)
+    T_obs = T_o + rng.normal(0.0, 0.05, T_o.shape)
+    chi_o, R_o = O.misfit(T_o, T_obs, None, pairs, None, 0.8, 1.2)
+    chi_cr, R_o = O.misfit_cr(T_o, T_obs, tri, None, 0.6, R_o)
+    K_o = O.reloc_kernel(g, rec, par_o, tau_o, ev, R_o)
+    # GPU
+    s, xi, eta = (_dev(torch, wl[k]) for k in ("s", "xi", "eta"))
+    recd, evd = _dev(torch, rec), _dev(torch, ev)
+    par = api.source_params(g, s, xi, eta, recd)
+    tau, st = api.forward(g, s, xi, eta, recd, par, tol, 2000, kappa)
+    T = api.reloc_times(g, recd, par, tau, evd, _dev(torch, t0))
+    chi, R = api.misfit(T, _dev(torch, T_obs), None, _dev(torch, pairs, torch.int32), None, 0.8, 1.2,
+                        cr=(_dev(torch, off, torch.int32), _dev(torch, cpair, torch.int32)), gamma=0.6)
+    K = api.reloc_kernel(g, recd, par, tau, evd, R)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() > 0).all()
+    assert rel_inf(T.cpu().numpy(), T_o) <= 1e-12
+    assert rel_inf(R.cpu().numpy(), R_o) <= 1e-8
+    Kg = K.cpu().numpy()
+    assert rel_inf(Kg[:, :3], K_o[:, :3]) <= 1e-9, rel_inf(Kg[:, :3], K_o[:, :3])
+    assert np.abs(Kg[:, 3] - K_o[:, 3]).max() <= 1e-9 * np.abs(R_o).sum()
+
+
+def test_reloc_empty_and_no_fields(torch_cuda):
+    """No earthquakes: nothing to do; no fields: K = 0."""
+    from paper_2412_00031_amd import api
+    torch = torch_cuda
+    wl = W.small_spherical(n=(13, 14, 15), nsrc=2, nrec=3, seed=3)
+    g = wl["grid"]
+    z3 = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    tau = torch.zeros((0,) + tuple(g["n"]), dtype=torch.float64, device="cuda")
+    ws = api.workspace(g, 1, 2, 0, "cuda")
+    K = api.reloc_kernel(g, z3, z3, tau, _dev(torch, wl["src"]), torch.zeros((2, 0), dtype=torch.float64,
+                                                                                   device="cuda"), ws=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(K, torch.zeros_like(K))
+    T = api.reloc_times(g, z3, z3, tau, z3, ws=ws)
+    assert T.shape == (0, 0)
