@@ -73,14 +73,24 @@ def parse():
     return ap.parse_args()
 
 
+SOLVER_SOURCES = ("tt_kernels.hip", "tt_device.h", "tt_internal.h")
+
+
+def solver_sha256():
+    """sha256 over the device sources the sweep kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in SOLVER_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2412_00031_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel, updates_per_launch, tiles):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (bytes per node update, calibrated against a plain copy), or None
-    when the kernel source changed since the counters were taken or the tile
+    when the solver sources (SOLVER_SOURCES) changed since the counters were taken or the tile
     depths (forward, adjoint) differ from the ones measured."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "sweeps_sph101_pmc.md")
-    src = os.path.join(ROOT, "paper_2412_00031_amd", "csrc", "tt_kernels.hip")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -88,7 +98,7 @@ def measured_traffic(kernel, updates_per_launch, tiles):
         if "=" in line and not line.startswith(("|", "`", "#")):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    if vals.get("kernel_sha256") != solver_sha256():
         return None
     if (vals.get("tile_k_fwd"), vals.get("tile_k_adj")) != (str(tiles[0]), str(tiles[1])):
         return None
@@ -169,8 +179,9 @@ def aux_inputs(wl, nsrc):
     T_obs = T + rng.normal(0.0, 0.2, T.shape)
     off, pair, tri = W.receiver_source_pairs(nsrc, nrec, AUX_CR_PER_REC, rng)
     wcr = rng.uniform(0.5, 2.0, len(tri))
+    Rr = rng.normal(0.0, 0.1, (len(wl["src"]), nrec))
     return dict(grad=grad, dens=dens, inv=inv, C=C, T=T, T_obs=T_obs, off=off, pair=pair, tri=tri, wcr=wcr,
-                eps=1e-3, zeta=0.5, gamma=1.0)
+                eps=1e-3, zeta=0.5, gamma=1.0, Rr=Rr)
 
 
 def aux_gpu(wl, a, dev, reps=20):
@@ -199,6 +210,14 @@ def aux_gpu(wl, a, dev, reps=20):
     off, pair, wcr = t(a["off"], torch.int32), t(a["pair"], torch.int32), t(a["wcr"])
     R = torch.zeros_like(T)
     chi = torch.zeros((), dtype=torch.float64, device=dev)
+    # relocation: receiver-side fields (tau = 1, i.e. Gamma_m = T0 of the receiver; the
+    # kernels' cost does not depend on the values) sampled at the workload's sources
+    recd, evd = t(wl["rec"]), t(wl["src"])
+    nfield, nev = recd.shape[0], evd.shape[0]
+    fpar = api.source_params(g, s, t(wl["xi"]), t(wl["eta"]), recd)
+    ftau = torch.ones((nfield, N), dtype=torch.float64, device=dev)
+    rws = api.workspace(g, nfield, 2, 0, dev)
+    Rr = t(a["Rr"])
     cp = lambda x: ctypes.c_void_p(x.data_ptr())
     st = lambda: ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     calls = {
@@ -210,9 +229,15 @@ def aux_gpu(wl, a, dev, reps=20):
                                                               cp(field), st())), 24.0 * N + 8.0 * M, "hbm"),
         "tt_misfit_cr": (lambda: api.misfit_cr(T, Tobs, off, pair, wcr, a["gamma"], R, chi),
                         80.0 * len(a["tri"]), "latency"),
+        # algorithmic: the 8 corners of every (earthquake, field) pair, read once
+        "tt_reloc_times": (lambda: api.reloc_times(g, recd, fpar, ftau, evd, ws=rws), 64.0 * nev * nfield + 8.0 * nev * nfield,
+                           "latency"),
+        "tt_reloc_kernel": (lambda: api.reloc_kernel(g, recd, fpar, ftau, evd, Rr, ws=rws),
+                            64.0 * nev * nfield + 8.0 * nev * nfield, "latency"),
     }
     kernels = {"tt_kernel_density": "k_kernel_density", "tt_mg_project": "k_mg_proj_planes + k_mg_proj_final",
-               "tt_mg_expand": "k_mg_expand", "tt_misfit_cr": "k_misfit_cr"}
+               "tt_mg_expand": "k_mg_expand", "tt_misfit_cr": "k_misfit_cr_R + k_misfit_cr_chi",
+               "tt_reloc_times": "k_reloc_times", "tt_reloc_kernel": "k_reloc_kernel"}
     out = {}
     for name, (fn, nbytes, bound) in calls.items():
         for _ in range(3):
@@ -251,7 +276,43 @@ def aux_cpu(wl, a):
     t0 = time.perf_counter()
     O.misfit_cr(a["T"], a["T_obs"], a["tri"], a["wcr"], a["gamma"])
     out["tt_misfit_cr"] = time.perf_counter() - t0
+    # relocation on 8 earthquakes x 50 fields, scaled to all of them
+    import numpy as np
+    nf = 50
+    fpar = O.source_params(g, wl["s"], wl["xi"], wl["eta"], wl["rec"][:nf])
+    ftau = np.ones((nf,) + tuple(g["n"]))
+    ev = wl["src"][:8]
+    scale = len(wl["src"]) / len(ev) * len(wl["rec"]) / nf
+    t0 = time.perf_counter()
+    O.reloc_times(g, wl["rec"][:nf], fpar, ftau, ev)
+    out["tt_reloc_times"] = (time.perf_counter() - t0) * scale
+    t0 = time.perf_counter()
+    O.reloc_kernel(g, wl["rec"][:nf], fpar, ftau, ev, a["Rr"][:8, :nf])
+    out["tt_reloc_kernel"] = (time.perf_counter() - t0) * scale
+    del ftau
     return {k: round(v * 1e3, 3) for k, v in out.items()}
+
+
+def cpu_cont_adjoint(wl, iters, nsrc):
+    """The oracle's continuous adjoint on one source (its own 3-iteration
+    forward): set-up plus 1 and 2 iterations give the per-iteration cost,
+    scaled to the GPU's mean iteration count and to the batch."""
+    import numpy as np
+    import oracle as O
+    g, s, xi, eta = wl["grid"], wl["s"], wl["xi"], wl["eta"]
+    src = wl["src"][:1]
+    par = O.source_params(g, s, xi, eta, src)[0]
+    tau, _, _, _ = O.forward(g, s, xi, eta, src[0], par, wl["kappa"], 1e-30, 3)
+    R = np.asarray(wl["R"])[0]
+    t0 = time.perf_counter()
+    O.adjoint_cont(g, s, xi, eta, src[0], par, tau, wl["rec"], R, 1e-30, 1)
+    t1 = time.perf_counter()
+    O.adjoint_cont(g, s, xi, eta, src[0], par, tau, wl["rec"], R, 1e-30, 2)
+    t2 = time.perf_counter()
+    per_it = (t2 - t1) - (t1 - t0)
+    per_src = (t1 - t0) - per_it + per_it * iters
+    return {"oracle_s_per_source": round(per_src, 3), "oracle_cores": 1,
+            "oracle_solves_per_s": round(1.0 / per_src, 4)}
 
 
 def aux_section(wl, nsrc, dev, with_cpu):
@@ -262,8 +323,10 @@ def aux_section(wl, nsrc, dev, with_cpu):
             res[k]["oracle_ms"] = ms
             res[k]["oracle_cores"] = 1
     res["inputs"] = (f"101^3 grid; {AUX_GRIDS['H']} staggered {AUX_GRIDS['m']} inversion grids; {nsrc} sources x "
-                     f"{len(wl['rec'])} receivers with {AUX_CR_PER_REC} source pairs per receiver; seeded synthetic "
-                     f"fields; average of 20 launches after 3")
+                     f"{len(wl['rec'])} receivers with {AUX_CR_PER_REC} source pairs per receiver; relocation of the "
+                     f"{len(wl['src'])} sources as earthquakes against {len(wl['rec'])} receiver-side fields; seeded "
+                     f"synthetic fields; average of 20 calls after 3 (oracle: one call, relocation on 8 earthquakes "
+                     f"scaled)")
     return res
 
 
@@ -438,6 +501,22 @@ def main():
     if not args.no_aux:
         log("auxiliary kernels")
         aux = aux_section(wl, nsrc, dev, not args.no_cpu_baseline)
+        # the continuous adjoint of Eq. (5) on the last step's fields, beside the discrete one
+        par = api.source_params(g, s, xi, eta, src)
+        chi, R = api.misfit(api.sample(g, src, par, tau, rec), T_obs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st_c = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, tol, args.max_iter, kappa, tile_k=tk_a, ws=ws_a,
+                              out=lam, groups=args.groups, continuous=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        it_c = np.abs(st_c.cpu().numpy())
+        aux["tt_adjoint_continuous"] = {
+            "solves_per_s": round(nsrc / el, 3), "ms": round(1e3 * el, 2), "mean_iters": round(float(it_c.mean()), 2),
+            "mean_iters_discrete": round(float(it_a.mean()), 2), "kernels": "k_cadj_coef, k_adj_sweep, k_cadj_bnd_*"}
+        if not args.no_cpu_baseline:
+            aux["tt_adjoint_continuous"].update(cpu_cont_adjoint(wl, float(it_c.mean()), nsrc))
+        log(f"continuous adjoint: {el:.2f} s for {nsrc} sources, mean {it_c.mean():.1f} iterations")
 
     def summary(r):
         return {"value": round(nsrc * r["steps"] / r["elapsed"], 4), "ms_per_step": round(1e3 * r["elapsed"] / r["steps"], 2),

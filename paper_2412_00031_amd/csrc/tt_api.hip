@@ -154,7 +154,7 @@ Layout layout(const tt::Geo& G, int nsrc, int nslots, int which) {
     if (which == 1) {
         L.off_part2 = o; o = align_up(o + sizeof(double) * (size_t)nsrc * nslots);
         L.off_coef = o; o = align_up(o + sizeof(double) * 8 * 2 * (size_t)nsrc * (size_t)G.S);
-        L.off_bnd = o; o = align_up(o + sizeof(double) * (size_t)nsrc * (size_t)G.NB);
+        L.off_bnd = o; o = align_up(o + sizeof(double) * 2 * (size_t)nsrc * (size_t)G.NB);  // bnd_in, bnd_rhs
     }
     L.total = o;
     return L;
@@ -187,6 +187,7 @@ void bind_workspace(tt::Plan& P, void* ws, const Layout& L) {
     P.part2 = reinterpret_cast<double*>(b + L.off_part2);
     P.coef = reinterpret_cast<double*>(b + L.off_coef);
     P.bnd_in = reinterpret_cast<double*>(b + L.off_bnd);
+    P.bnd_rhs = P.bnd_in + (size_t)P.nsrc * (size_t)P.G.NB;
     P.model = reinterpret_cast<double*>(b + L.off_model);
     P.T.t0 = P.tab0;
     P.T.t1 = P.tab1;

@@ -48,40 +48,113 @@ __global__ void __launch_bounds__(256) k_misfit(int nsrc, int nrec, const double
 }
 
 // Common-receiver differential misfit (Eq. (4), third misfit) and its adjoint
-// sources (Eq. (A4)), added to R and chi.  One thread owns receiver m (a column
-// of R) and walks that receiver's source pairs in list order, so no two
-// threads write one element and the sums are deterministic.
-__global__ void __launch_bounds__(256) k_misfit_cr(int nsrc, int nrec, const double* __restrict__ T,
-                                                   const double* __restrict__ Tobs, const int32_t* __restrict__ off,
-                                                   const int32_t* __restrict__ pair, const double* __restrict__ wcr,
-                                                   double gamma, double* __restrict__ R, double* __restrict__ chi) {
-    __shared__ double sh[4];
-    __shared__ int bad;
-    if (threadIdx.x == 0) bad = 0;
-    __syncthreads();
-    double part = 0.0;
-    for (int m = threadIdx.x; m < nrec; m += blockDim.x) {
-        const int p0 = off[m], p1 = off[m + 1];
-        if (p0 < 0 || p1 < p0 || (p1 > p0 && !pair)) {
-            bad = 1;
-            continue;
+// sources (Eq. (A4)), added to R and chi.
+//
+// Adjoint sources: one wave per receiver m.  The wave stages 64 of the
+// receiver's pairs at a time (indices and gamma w r in LDS); lane l owns source
+// n = base + l and adds the staged contributions that name it, in list order,
+// to its R[n][m] -- the additions each element receives come in the order of
+// the pair list, as in the plain definition, and no two lanes write one
+// element.
+constexpr int kCrStage = 64;
+
+__global__ void __launch_bounds__(64) k_misfit_cr_R(int nsrc, int nrec, const double* __restrict__ T,
+                                                    const double* __restrict__ Tobs, const int32_t* __restrict__ off,
+                                                    const int32_t* __restrict__ pair, const double* __restrict__ wcr,
+                                                    double gamma, double* __restrict__ R) {
+    __shared__ int sn[kCrStage], sj[kCrStage];
+    __shared__ double sg[kCrStage];
+    const int m = blockIdx.x;
+    const int p0 = off[m], p1 = off[m + 1];
+    if (p0 < 0 || p1 <= p0 || !pair) return;  // nothing to add (malformed offsets: chi reports it)
+    for (int base = 0; base < nsrc; base += kCrStage) {
+        const int n = base + (int)threadIdx.x;
+        const long long cn = (long long)n * nrec + m;
+        double acc = n < nsrc ? R[cn] : 0.0;
+        bool touched = false;
+        for (int pc = p0; pc < p1; pc += kCrStage) {
+            const int p = pc + (int)threadIdx.x;
+            int a = -1, b = -1;
+            double g = 0.0;
+            if (p < p1) {
+                a = pair[2 * p];
+                b = pair[2 * p + 1];
+                if (a >= 0 && a < nsrc && b >= 0 && b < nsrc) {
+                    const long long ca = (long long)a * nrec + m, cb = (long long)b * nrec + m;
+                    const double ww = wcr ? wcr[p] : 1.0;
+                    g = gamma * ww * ((T[ca] - T[cb]) - (Tobs[ca] - Tobs[cb]));
+                } else {
+                    a = b = -1;
+                }
+            }
+            sn[threadIdx.x] = a;
+            sj[threadIdx.x] = b;
+            sg[threadIdx.x] = g;
+            __syncthreads();
+            const int cnt = min(kCrStage, p1 - pc);
+            for (int q = 0; q < cnt; ++q) {
+                if (sn[q] == n) {
+                    acc += sg[q];
+                    touched = true;
+                }
+                if (sj[q] == n) {
+                    acc -= sg[q];
+                    touched = true;
+                }
+            }
+            __syncthreads();
         }
-        for (int p = p0; p < p1; ++p) {
+        if (n < nsrc && touched) R[cn] = acc;
+    }
+}
+
+// gamma chi_cr over all pairs: one block, pair p of the flat list taken by
+// thread p mod 1024 (its receiver found by binary search in the offsets),
+// fixed-order block reduction; malformed offsets or indices make chi NaN.
+__global__ void __launch_bounds__(1024) k_misfit_cr_chi(int nsrc, int nrec, const double* __restrict__ T,
+                                                        const double* __restrict__ Tobs,
+                                                        const int32_t* __restrict__ off,
+                                                        const int32_t* __restrict__ pair,
+                                                        const double* __restrict__ wcr, double gamma,
+                                                        double* __restrict__ chi) {
+    __shared__ double sh[16];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = (off[0] != 0);
+    __syncthreads();
+    for (int m = threadIdx.x; m < nrec; m += blockDim.x)
+        if (off[m + 1] < off[m]) bad = 1;
+    __syncthreads();
+    const int total = bad ? 0 : off[nrec];
+    if (total > 0 && !pair) bad = 1;
+    double part = 0.0;
+    if (!bad) {
+        for (int p = threadIdx.x; p < total; p += blockDim.x) {
+            int lo = 0, hi = nrec;  // off[lo] <= p < off[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (off[mid] <= p) lo = mid;
+                else hi = mid;
+            }
             const int n = pair[2 * p], j = pair[2 * p + 1];
             if (n < 0 || n >= nsrc || j < 0 || j >= nsrc) {
                 bad = 1;
                 continue;
             }
-            const long long cn = (long long)n * nrec + m, cj = (long long)j * nrec + m;
+            const long long cn = (long long)n * nrec + lo, cj = (long long)j * nrec + lo;
             const double ww = wcr ? wcr[p] : 1.0;
             const double r = (T[cn] - T[cj]) - (Tobs[cn] - Tobs[cj]);
             part += gamma * 0.5 * ww * r * r;
-            R[cn] += gamma * ww * r;
-            R[cj] -= gamma * ww * r;
         }
     }
-    const double tot = block_sum256(part, sh);
-    if (threadIdx.x == 0) *chi = bad ? __builtin_nan("") : *chi + tot;
+    part = wave_sum(part);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int q = 0; q < 16; ++q) tot += sh[q];
+        *chi = bad ? __builtin_nan("") : *chi + tot;
+    }
 }
 
 // ------------------------------------------------ relocation (Eq. (10), App. B)
@@ -195,7 +268,8 @@ void launch_misfit(int nsrc, int nrec, const double* T, const double* Tobs, cons
 
 void launch_misfit_cr(int nsrc, int nrec, const double* T, const double* Tobs, const int32_t* off, const int32_t* pair,
                       const double* wcr, double gamma, double* R, double* chi, hipStream_t st) {
-    hipLaunchKernelGGL(k_misfit_cr, dim3(1), dim3(256), 0, st, nsrc, nrec, T, Tobs, off, pair, wcr, gamma, R, chi);
+    hipLaunchKernelGGL(k_misfit_cr_R, dim3(nrec), dim3(64), 0, st, nsrc, nrec, T, Tobs, off, pair, wcr, gamma, R);
+    hipLaunchKernelGGL(k_misfit_cr_chi, dim3(1), dim3(1024), 0, st, nsrc, nrec, T, Tobs, off, pair, wcr, gamma, chi);
 }
 
 // ------------------------------------------- multiple-grid parameterisation
@@ -349,6 +423,8 @@ __global__ void __launch_bounds__(256) k_mg_proj_planes(Geo G, MgGrids Q, const 
                                                         const double* __restrict__ K, double* __restrict__ part,
                                                         int nch) {
     extern __shared__ double lds[];
+    __shared__ MgGrids QL;  // per-grid sizes and offsets, indexed per lane below
+    if (threadIdx.x == 0) QL = Q;
     const int H = Q.H, n1 = G.n[1], n2 = G.n[2];
     const int S2 = Q.s2off[H], S12 = Q.s12off[H];
     double* cl = lds;
@@ -362,21 +438,21 @@ __global__ void __launch_bounds__(256) k_mg_proj_planes(Geo G, MgGrids Q, const 
     const int ch = blockIdx.x % nch, p = (blockIdx.x / nch) % 3, i = blockIdx.x / (3 * nch);
     for (int e = threadIdx.x; e < Q.ncoord; e += blockDim.x) cl[e] = coords[e];
     for (int e = threadIdx.x; e <= H; e += blockDim.x) off12[e] = Q.s12off[e];
-    __syncthreads();
+    __syncthreads();  // QL, cl, off12
     for (int e = threadIdx.x; e < H * n1; e += blockDim.x) {
         const int h = e / n1, j = e % n1;
-        tab1[e] = mg_tab(cl + Q.coff[h][1], Q.m[h][1], node_coord(G, 1, j), vol_axis(G, 1, j));
+        tab1[e] = mg_tab(cl + QL.coff[h][1], QL.m[h][1], node_coord(G, 1, j), vol_axis(G, 1, j));
     }
     for (int e = threadIdx.x; e < H * n2; e += blockDim.x) {
         const int h = e / n2, k = e % n2;
-        tab2[e] = mg_tab(cl + Q.coff[h][2], Q.m[h][2], node_coord(G, 2, k), vol_axis(G, 2, k));
+        tab2[e] = mg_tab(cl + QL.coff[h][2], QL.m[h][2], node_coord(G, 2, k), vol_axis(G, 2, k));
     }
     for (int q = threadIdx.x; q < S2; q += blockDim.x) {
         MgCol c;
         c.h = 0;
-        while (c.h + 1 < H && q >= Q.s2off[c.h + 1]) ++c.h;
-        c.ck = q - Q.s2off[c.h];
-        mg_range(G, 2, cl + Q.coff[c.h][2], Q.m[c.h][2], c.ck, c.klo, c.khi);
+        while (c.h + 1 < H && q >= QL.s2off[c.h + 1]) ++c.h;
+        c.ck = q - QL.s2off[c.h];
+        mg_range(G, 2, cl + QL.coff[c.h][2], QL.m[c.h][2], c.ck, c.klo, c.khi);
         cols[q] = c;
     }
     for (int e = threadIdx.x; e < S12; e += blockDim.x) acc[e] = 0.0;
@@ -399,10 +475,10 @@ __global__ void __launch_bounds__(256) k_mg_proj_planes(Geo G, MgGrids Q, const 
         __syncthreads();
         for (int e = threadIdx.x; e < S12; e += blockDim.x) {
             const int h = mg_grid_of(off12, H, e);
-            const int m2 = Q.m[h][2], q = e - off12[h];
+            const int m2 = QL.m[h][2], q = e - off12[h];
             const int cj = q / m2, ck = q % m2;
             const MgTab* t1 = tab1 + h * n1 + jb;
-            const double* Ac = A + Q.s2off[h] + ck;
+            const double* Ac = A + QL.s2off[h] + ck;
             double v = acc[e];
             for (int r = 0; r < nr; ++r) {
                 const double w = mg_w(t1[r], cj);
@@ -416,37 +492,35 @@ __global__ void __launch_bounds__(256) k_mg_proj_planes(Geo G, MgGrids Q, const 
     for (int e = threadIdx.x; e < S12; e += blockDim.x) out[e] = acc[e];
 }
 
-// Inversion coordinates of a launch: staged in LDS when they fit (clds), else
-// read from global memory.
-__device__ __forceinline__ const double* mg_coords(const MgGrids& Q, const double* coords, double* lds, bool clds) {
-    if (!clds) return coords;
-    for (int e = threadIdx.x; e < Q.ncoord; e += blockDim.x) lds[e] = coords[e];
-    __syncthreads();
-    return lds;
-}
-
 // Stage 3: one thread per coefficient, contraction over the planes i under its
-// tent (ascending i, j-chunks summed in order), then the 1/H of Eq. (11).
+// tent (ascending i, j-chunks summed in order), then the 1/H of Eq. (11).  The
+// grid sizes and (CLDS) the inversion coordinates are staged in LDS.
+template <bool CLDS>
 __global__ void __launch_bounds__(256) k_mg_proj_final(Geo G, MgGrids Q, const double* __restrict__ coords,
                                                        const double* __restrict__ part, int nch,
-                                                       double* __restrict__ out, int clds) {
+                                                       double* __restrict__ out) {
     extern __shared__ double lds[];
-    const double* cb = mg_coords(Q, coords, lds, clds != 0);
+    __shared__ MgGrids QL;
+    if (threadIdx.x == 0) QL = Q;
+    if (CLDS)
+        for (int e = threadIdx.x; e < Q.ncoord; e += blockDim.x) lds[e] = coords[e];
+    __syncthreads();
+    const double* cb = CLDS ? lds : coords;
     const long long total = Q.outoff[Q.H];
     const int S12 = Q.s12off[Q.H];
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
         int h = 0;
-        while (h + 1 < Q.H && e >= Q.outoff[h + 1]) ++h;
-        const int m0 = Q.m[h][0], m1 = Q.m[h][1], m2 = Q.m[h][2];
-        const long long M = (long long)m0 * m1 * m2, q = e - Q.outoff[h];
+        while (h + 1 < Q.H && e >= QL.outoff[h + 1]) ++h;
+        const int m0 = QL.m[h][0], m1 = QL.m[h][1], m2 = QL.m[h][2];
+        const long long M = (long long)m0 * m1 * m2, q = e - QL.outoff[h];
         const int p = (int)(q / M);
         const long long l = q % M;
         const int ck = (int)(l % m2), cj = (int)((l / m2) % m1), ci = (int)(l / ((long long)m1 * m2));
-        const double* c0 = cb + Q.coff[h][0];
+        const double* c0 = cb + QL.coff[h][0];
         int ilo, ihi;
         mg_range(G, 0, c0, m0, ci, ilo, ihi);
-        const long long col = Q.s12off[h] + (long long)cj * m2 + ck;
+        const long long col = QL.s12off[h] + (long long)cj * m2 + ck;
         double a = 0.0;
         for (int i = ilo; i <= ihi; ++i) {
             const double u = mg_tent(c0, m0, ci, node_coord(G, 0, i));
@@ -460,14 +534,85 @@ __global__ void __launch_bounds__(256) k_mg_proj_final(Geo G, MgGrids Q, const d
     }
 }
 
-// Eq. (15): one thread per forward node; field[p](x) = sum over the grids of
-// C B over the (at most 8 per grid) nonzero basis functions, accumulated in
-// grid order and written once.
-__global__ void __launch_bounds__(256) k_mg_expand(Geo G, MgGrids Q, const double* __restrict__ coords,
-                                                   const double* __restrict__ C, double* __restrict__ field,
-                                                   int clds) {
+// Eq. (15), staged form: one block per (plane i, chunk of j).  With at most two
+// nonzero tents per axis and grid, the block first contracts the coefficients
+// over axis 0 at its plane, E[p][grid][cj][ck] = sum_ci u_ci(i) C[grid][p][ci][cj][ck],
+// in LDS, then each thread forms field(i, j, k) from at most 4 terms of E per
+// grid (tables of the axis-1 and axis-2 tents in LDS), summed over the grids in
+// order and written once.
+__global__ void __launch_bounds__(256) k_mg_expand_planes(Geo G, MgGrids Q, const double* __restrict__ coords,
+                                                          const double* __restrict__ C, double* __restrict__ field,
+                                                          int nch) {
     extern __shared__ double lds[];
-    const double* cb = mg_coords(Q, coords, lds, clds != 0);
+    __shared__ MgGrids QL;
+    __shared__ MgTab tab0[TT_MG_MAX_GRIDS];
+    if (threadIdx.x == 0) QL = Q;
+    const int H = Q.H, n1 = G.n[1], n2 = G.n[2];
+    const int S12 = Q.s12off[H];
+    double* cl = lds;
+    MgTab* tab1 = reinterpret_cast<MgTab*>(cl + Q.ncoord);
+    MgTab* tab2 = tab1 + H * n1;
+    double* E = reinterpret_cast<double*>(tab2 + H * n2);
+    const int ch = blockIdx.x % nch, i = blockIdx.x / nch;
+    for (int e = threadIdx.x; e < Q.ncoord; e += blockDim.x) cl[e] = coords[e];
+    __syncthreads();  // QL, cl
+    for (int h = threadIdx.x; h < H; h += blockDim.x)
+        tab0[h] = mg_tab(cl + QL.coff[h][0], QL.m[h][0], node_coord(G, 0, i), 1.0);
+    for (int e = threadIdx.x; e < H * n1; e += blockDim.x) {
+        const int h = e / n1, j = e % n1;
+        tab1[e] = mg_tab(cl + QL.coff[h][1], QL.m[h][1], node_coord(G, 1, j), 1.0);
+    }
+    for (int e = threadIdx.x; e < H * n2; e += blockDim.x) {
+        const int h = e / n2, k = e % n2;
+        tab2[e] = mg_tab(cl + QL.coff[h][2], QL.m[h][2], node_coord(G, 2, k), 1.0);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 3 * S12; e += blockDim.x) {
+        const int p = e / S12, q = e % S12;
+        int h = 0;
+        while (h + 1 < H && q >= QL.s12off[h + 1]) ++h;
+        const long long M12 = (long long)QL.m[h][1] * QL.m[h][2];
+        const double* Cp = C + QL.outoff[h] + (long long)p * QL.m[h][0] * M12 + (q - QL.s12off[h]);
+        const MgTab t = tab0[h];
+        double v = 0.0;
+        if (t.i0 >= 0) v += t.w0 * Cp[(long long)t.i0 * M12];
+        if (t.i1 >= 0) v += t.w1 * Cp[(long long)t.i1 * M12];
+        E[e] = v;
+    }
+    __syncthreads();
+    const int j0 = (int)((long long)ch * n1 / nch), j1 = (int)((long long)(ch + 1) * n1 / nch);
+    const long long base = (long long)i * n1 * n2;
+    for (int e = threadIdx.x; e < (j1 - j0) * n2; e += blockDim.x) {
+        const int j = j0 + e / n2, k = e % n2;
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int h = 0; h < H; ++h) {
+            const MgTab t1 = tab1[h * n1 + j], t2 = tab2[h * n2 + k];
+            const int m2 = QL.m[h][2], o12 = QL.s12off[h];
+            const int cj[2] = {t1.i0, t1.i1}, ck[2] = {t2.i0, t2.i1};
+            const double wj[2] = {t1.w0, t1.w1}, wk[2] = {t2.w0, t2.w1};
+            for (int a = 0; a < 2; ++a) {
+                if (cj[a] < 0) continue;
+                for (int b = 0; b < 2; ++b) {
+                    if (ck[b] < 0) continue;
+                    const double bw = wj[a] * wk[b] / H;
+                    const int q = o12 + cj[a] * m2 + ck[b];
+                    for (int p = 0; p < 3; ++p) acc[p] += E[p * S12 + q] * bw;
+                }
+            }
+        }
+        const long long x = base + (long long)j * n2 + k;
+        for (int p = 0; p < 3; ++p) field[p * G.N + x] = acc[p];
+    }
+}
+
+// Eq. (15) for grids whose staging does not fit in LDS: one thread per forward
+// node; field[p](x) = sum over the grids of C B over the (at most 8 per grid)
+// nonzero basis functions, accumulated in grid order and written once.
+__global__ void __launch_bounds__(256) k_mg_expand(Geo G, MgGrids Q, const double* __restrict__ coords,
+                                                   const double* __restrict__ C, double* __restrict__ field) {
+    __shared__ MgGrids QL;
+    if (threadIdx.x == 0) QL = Q;
+    __syncthreads();
     for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < G.N;
          x += (long long)gridDim.x * blockDim.x) {
         const int k = (int)(x % G.n[2]);
@@ -475,20 +620,20 @@ __global__ void __launch_bounds__(256) k_mg_expand(Geo G, MgGrids Q, const doubl
         const int j = (int)(q % G.n[1]), i = (int)(q / G.n[1]);
         const double xi = node_coord(G, 0, i), xj = node_coord(G, 1, j), xk = node_coord(G, 2, k);
         double acc[3] = {0.0, 0.0, 0.0};
-        for (int h = 0; h < Q.H; ++h) {
-            const int m1 = Q.m[h][1], m2 = Q.m[h][2];
-            const long long M = (long long)Q.m[h][0] * m1 * m2;
+        for (int h = 0; h < QL.H; ++h) {
+            const int m1 = QL.m[h][1], m2 = QL.m[h][2];
+            const long long M = (long long)QL.m[h][0] * m1 * m2;
             int ii[2], jj[2], kk[2];
             double wi[2], wj[2], wk[2];
-            const int na = mg_axis(cb + Q.coff[h][0], Q.m[h][0], xi, ii, wi);
-            const int nb = mg_axis(cb + Q.coff[h][1], m1, xj, jj, wj);
-            const int nc = mg_axis(cb + Q.coff[h][2], m2, xk, kk, wk);
-            const double* Ch = C + Q.outoff[h];
+            const int na = mg_axis(coords + QL.coff[h][0], QL.m[h][0], xi, ii, wi);
+            const int nb = mg_axis(coords + QL.coff[h][1], m1, xj, jj, wj);
+            const int nc = mg_axis(coords + QL.coff[h][2], m2, xk, kk, wk);
+            const double* Ch = C + QL.outoff[h];
             for (int a = 0; a < na; ++a)
                 for (int b = 0; b < nb; ++b)
                     for (int c = 0; c < nc; ++c) {
                         const long long l = ((long long)ii[a] * m1 + jj[b]) * m2 + kk[c];
-                        const double bw = wi[a] * wj[b] * wk[c] / Q.H;
+                        const double bw = wi[a] * wj[b] * wk[c] / QL.H;
                         for (int p = 0; p < 3; ++p) acc[p] += Ch[p * M + l] * bw;
                     }
         }
@@ -565,9 +710,12 @@ void launch_mg_project(const Geo& G, int H, const int* m, const double* coords, 
     if (P.separable) {
         hipLaunchKernelGGL(k_mg_proj_planes, dim3((unsigned)(G.n[0] * 3 * P.nch)), dim3(256), P.lds, st, G, Q,
                            coords, K, ws, P.nch);
-        const int clds = 8LL * Q.ncoord <= kMgCoordLds;
-        hipLaunchKernelGGL(k_mg_proj_final, dim3(fill_blocks(Q.outoff[H])), dim3(256),
-                           clds ? 8 * Q.ncoord : 0, st, G, Q, coords, ws, P.nch, out, clds);
+        if (8LL * Q.ncoord <= kMgCoordLds)
+            hipLaunchKernelGGL(k_mg_proj_final<true>, dim3(fill_blocks(Q.outoff[H])), dim3(256), 8 * Q.ncoord, st,
+                               G, Q, coords, ws, P.nch, out);
+        else
+            hipLaunchKernelGGL(k_mg_proj_final<false>, dim3(fill_blocks(Q.outoff[H])), dim3(256), 0, st, G, Q,
+                               coords, ws, P.nch, out);
         return;
     }
     // grids too large for the staged form: one wave per inversion node
@@ -586,9 +734,14 @@ void launch_mg_project(const Geo& G, int H, const int* m, const double* coords, 
 void launch_mg_expand(const Geo& G, int H, const int* m, const double* coords, const double* C, double* field,
                       hipStream_t st) {
     const MgGrids Q = make_mg(H, m);
-    const int clds = 8LL * Q.ncoord <= kMgCoordLds;
-    hipLaunchKernelGGL(k_mg_expand, dim3(fill_blocks(G.N)), dim3(256), clds ? 8 * Q.ncoord : 0, st, G, Q, coords, C,
-                       field, clds);
+    const long long lds = 8LL * Q.ncoord + (long long)sizeof(MgTab) * H * (G.n[1] + G.n[2]) + 8LL * 3 * Q.s12off[H];
+    if (lds <= kMgMaxLds) {
+        const int nch = (int)std::min<long long>(std::max<long long>((1024 + G.n[0] - 1) / G.n[0], 1), G.n[1]);
+        hipLaunchKernelGGL(k_mg_expand_planes, dim3((unsigned)(G.n[0] * nch)), dim3(256), (size_t)lds, st, G, Q,
+                           coords, C, field, nch);
+        return;
+    }
+    hipLaunchKernelGGL(k_mg_expand, dim3(fill_blocks(G.N)), dim3(256), 0, st, G, Q, coords, C, field);
 }
 
 }  // namespace tt

@@ -204,6 +204,7 @@ struct Plan {
     double* coef = nullptr;   // adjoint: [nsrc][2][S][8] (row-coalesced layouts)
     double* model = nullptr;  // forward: [2][S][4] = (s, xi, eta, 0) (row-coalesced layouts)
     double* bnd_in = nullptr; // adjoint: [nsrc][NB] (continuous adjoint: boundary pass scratch)
+    double* bnd_rhs = nullptr; // adjoint: right-hand side of the boundary nodes, [nsrc][NB]
     bool continuous = false;  // adjoint: upwind discretisation of Eq. (5) instead of the exact transpose
     std::vector<int> plane_count;
     // optional timing of the sweep kernels: an event pair around the
@@ -221,6 +222,7 @@ struct SweepArgs {
     const double* coef;     // adjoint coefficients [nsrc][2][S][8]
     const double* model;    // forward model records [2][S][4]
     const double* bnd_in;   // adjoint face couplings [nsrc][NB]
+    const double* bnd_rhs;  // adjoint right-hand side of the boundary nodes [nsrc][NB]
     int* active;
     int* iter;
     int32_t* status;
@@ -272,7 +274,7 @@ struct MgGrids {
 
 // Projection plan: the separable staged form when its LDS fits, with nch
 // row chunks per plane and ws_bytes of partial sums; else one wave per node.
-constexpr long long kMgMaxLds = 64 * 1024;
+constexpr long long kMgMaxLds = 60 * 1024;  // dynamic LDS of the staged forms (static LDS comes on top)
 constexpr long long kMgCoordLds = 32 * 1024;  // coordinates staged in LDS up to this size
 struct MgPlan {
     bool separable;

@@ -676,6 +676,7 @@ __global__ void k_adj_rhs(SweepArgs a, double* __restrict__ coef_all, int nrec, 
     const Geo& G = a.G;
     const Src S = a.src[src];
     double* cf = coef_all + (long long)src * 2 * G.S * 8;
+    double* brhs = const_cast<double*>(a.bnd_rhs) + (long long)src * G.NB;
     for (int m = 0; m < nrec; ++m) {
         const Tri t = tri_of(G, rec[3 * m], rec[3 * m + 1], rec[3 * m + 2]);
         const double r = R[(long long)src * nrec + m];
@@ -690,6 +691,8 @@ __global__ void k_adj_rhs(SweepArgs a, double* __restrict__ coef_all, int nrec, 
                     const double v = with_t0 ? r * tri_w(t, c0, c1, c2) * T0 : r * tri_w(t, c0, c1, c2);
                     cf[skew_idx(G, 0, i, j, k) * 8 + 7] += v;
                     cf[(G.S + skew_idx(G, 1, i, j, k)) * 8 + 7] += v;
+                    if (on_bnd(G, 0, i) || on_bnd(G, 1, j) || on_bnd(G, 2, k))
+                        brhs[bnd_encode(G, i, j, k)] += v;
                 }
     }
 }
@@ -780,17 +783,19 @@ __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane) {
     }
 }
 
-// Transposed boundary pass: lambda_b = rhs_b - sum_{rows r != b} J_{r, b} lambda_r.
+// Transposed boundary pass: lambda_b = rhs_b - sum_{rows r != b} J_{r, b} lambda_r,
+// rhs_b read from the compact per-boundary-node copy (bnd_rhs) rather than from
+// the 64-byte record.
 // The rows that reference a boundary node b are its interior neighbour (face
 // nodes only, coefficient bnd_in[b]) and boundary rows b' that copy b along an
 // axis a' above a*(b) (b' one step outward along a', coefficient -1);
 // lambda(b') is evaluated in place (a* grows strictly: depth <= 3).
 template <int BUDGET>
-__device__ double adj_bval(const Geo& G, const Src& S, const double* lam, const double* cf, const double* bin, int i,
-                           int j, int k) {
+__device__ double adj_bval(const Geo& G, const Src& S, const double* lam, const double* brhs, const double* bin,
+                           int i, int j, int k) {
     const int p[3] = {i, j, k};
     const int as = astar_of(G, p);
-    double acc = cf[skew_idx(G, 0, i, j, k) * 8 + 7];
+    double acc = brhs[bnd_encode(G, i, j, k)];
     const int nb = (int)on_bnd(G, 0, i) + (int)on_bnd(G, 1, j) + (int)on_bnd(G, 2, k);
     if (nb == 1) {
         int x[3] = {i, j, k};
@@ -807,7 +812,7 @@ __device__ double adj_bval(const Geo& G, const Src& S, const double* lam, const 
                 int q[3] = {i, j, k};
                 q[ap] = side == 0 ? 0 : G.n[ap] - 1;
                 if (in_fixed(S, q[0], q[1], q[2])) continue;
-                acc += adj_bval<BUDGET - 1>(G, S, lam, cf, bin, q[0], q[1], q[2]);
+                acc += adj_bval<BUDGET - 1>(G, S, lam, brhs, bin, q[0], q[1], q[2]);
             }
         }
     }
@@ -821,7 +826,7 @@ __global__ void __launch_bounds__(kBndThreads) k_adj_bnd(SweepArgs a, int dir) {
     const Geo& G = a.G;
     const Src S = a.src[src];
     double* lam = a.field + (long long)src * G.N;
-    const double* cf = a.coef + (long long)src * 2 * G.S * 8;
+    const double* brhs = a.bnd_rhs + (long long)src * G.NB;
     const double* bin = a.bnd_in + (long long)src * G.NB;
     const long long b = (long long)blockIdx.x * kBndThreads + threadIdx.x;
     double d = 0.0, av = 0.0;
@@ -829,7 +834,7 @@ __global__ void __launch_bounds__(kBndThreads) k_adj_bnd(SweepArgs a, int dir) {
         int i, j, k;
         bnd_decode(G, b, i, j, k);
         if (!in_fixed(S, i, j, k)) {
-            const double nv = adj_bval<2>(G, S, lam, cf, bin, i, j, k);
+            const double nv = adj_bval<2>(G, S, lam, brhs, bin, i, j, k);
             const long long x = nidx(G, i, j, k);
             d = fabs(nv - lam[x]);
             av = fabs(nv);
@@ -1109,6 +1114,7 @@ SweepArgs make_args(const Plan& P, const double* s, const double* xi, const doub
     a.coef = P.coef;
     a.model = P.model;
     a.bnd_in = P.bnd_in;
+    a.bnd_rhs = P.bnd_rhs;
     a.active = P.active;
     a.iter = P.iter;
     a.status = status;
@@ -1212,7 +1218,8 @@ void launch_fwd_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
 
 void launch_adj_init(const Plan& P, const SweepArgs& a, const double* tau, int nrec, const double* rec,
                      const double* R, hipStream_t st) {
-    hipLaunchKernelGGL(k_fill, dim3(fill_blocks(P.G.NB * P.nsrc)), dim3(256), 0, st, P.bnd_in, P.G.NB * P.nsrc, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(fill_blocks(2 * P.G.NB * P.nsrc)), dim3(256), 0, st, P.bnd_in,
+                       2 * P.G.NB * P.nsrc, 0.0);  // bnd_in and bnd_rhs
     const dim3 grid(blocks_for(P.G.N, 256), P.nsrc);
     const dim3 rgrid(blocks_for(P.nsrc, 64));
     const int t0 = P.continuous ? 0 : 1;
