@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--weights", default=None, help="U-Net weights (.npz) of the warm start")
     ap.add_argument("--groups", type=int, default=0,
                     help="concurrently iterated source groups of each solve (0: library default)")
+    ap.add_argument("--adjoint", choices=("discrete", "continuous"), default="discrete",
+                    help="adjoint of the timed steps: the exact discrete transpose (default) or the upwind "
+                         "discretisation of Eq. (5)")
     ap.add_argument("--aux-only", action="store_true",
                     help="time only the per-step kernels outside the solves (kernel density, multiple-grid "
                          "projection/expansion, common-receiver misfit) and print their object")
@@ -406,7 +409,8 @@ def main():
         T = api.sample(g, src, par, tau, rec)
         chi, R = api.misfit(T, T_obs)
         _, st_a = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, tol, args.max_iter, kappa, tile_k=tk_a,
-                              ws=ws_a, out=lam, time_sweeps=timed, graph=args.graph, groups=args.groups)
+                              ws=ws_a, out=lam, time_sweeps=timed, graph=args.graph, groups=args.groups,
+                              continuous=args.adjoint == "continuous")
         api.kernel(g, s, xi, eta, src, par, tau, lam, grad=grad.zero_())
         return st_f, st_a, chi
 
@@ -537,7 +541,7 @@ def main():
                    "mean_iters_fwd": round(float(it_f.mean()), 2), "mean_iters_adj": round(float(it_a.mean()), 2),
                    "tile_k": {"fwd": tk_f or 16, "adj": tk_a or 48,
                               "chosen_by": "autotune" if tuned else ("fixed" if (tk_f or tk_a) else "default")},
-                   "graph": bool(args.graph),
+                   "graph": bool(args.graph), "adjoint": args.adjoint,
                    "source_groups": args.groups or max(1, min(4, nsrc // 32))},
         "roofline": roofline, "cpu_baseline": cpu, "aux": aux,
     }

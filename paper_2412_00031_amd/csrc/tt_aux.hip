@@ -109,18 +109,26 @@ __global__ void __launch_bounds__(64) k_misfit_cr_R(int nsrc, int nrec, const do
 }
 
 // gamma chi_cr over all pairs: one block, pair p of the flat list taken by
-// thread p mod 1024 (its receiver found by binary search in the offsets),
-// fixed-order block reduction; malformed offsets or indices make chi NaN.
+// thread p mod 1024 (its receiver found by binary search in the offsets, staged
+// in LDS when they fit), fixed-order block reduction; malformed offsets or
+// indices make chi NaN.
+constexpr int kCrOffLds = 8192;
+
 __global__ void __launch_bounds__(1024) k_misfit_cr_chi(int nsrc, int nrec, const double* __restrict__ T,
                                                         const double* __restrict__ Tobs,
-                                                        const int32_t* __restrict__ off,
+                                                        const int32_t* __restrict__ off_g,
                                                         const int32_t* __restrict__ pair,
                                                         const double* __restrict__ wcr, double gamma,
                                                         double* __restrict__ chi) {
     __shared__ double sh[16];
     __shared__ int bad;
-    if (threadIdx.x == 0) bad = (off[0] != 0);
+    __shared__ int offl[kCrOffLds];
+    const bool staged = nrec + 1 <= kCrOffLds;
+    if (staged)
+        for (int m = threadIdx.x; m <= nrec; m += blockDim.x) offl[m] = off_g[m];
+    if (threadIdx.x == 0) bad = (off_g[0] != 0);
     __syncthreads();
+    const int32_t* off = staged ? offl : off_g;
     for (int m = threadIdx.x; m < nrec; m += blockDim.x)
         if (off[m + 1] < off[m]) bad = 1;
     __syncthreads();
