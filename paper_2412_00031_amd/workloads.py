@@ -266,6 +266,17 @@ def sph101(seed=4001, n=101, nsrc=128, nrec=500, with_true=True):
     return out
 
 
+def sph121(seed=5001, n=121, nsrc=512):
+    """Evaluation workload of the learned warm start: the 0-100 km, 4 x 4 degree
+    spherical box of sph101 on a finer 121^3 grid (h = 0.83 km), a GRF model of
+    the same statistics (never trained on) and 512 sources at 5-90 km."""
+    rng = np.random.default_rng(seed)
+    grid = spherical_grid(n, 100.0, 2.0)
+    s, xi, eta = _grf_model(grid, rng)
+    src = random_sources(grid, nsrc, (5.0, 90.0), rng)
+    return dict(name="sph121", grid=grid, s=s, xi=xi, eta=eta, src=src, kappa=1.05, tol=1e-6)
+
+
 def small_spherical(n=(13, 14, 15), depth_km=12.0, half_width_deg=0.12, seed=7, aniso=0.03, nsrc=2,
                     nrec=9):
     """Tiny spherical case with a smooth anisotropic model (several tiles and
