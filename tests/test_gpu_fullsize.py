@@ -135,3 +135,56 @@ def test_sph61_batch_with_pairs(torch_cuda):
                                         tol, 1000)
         assert conva and ita == sa[q]
         assert rel_inf(lam[q].cpu().numpy(), olam) <= 1e-10
+
+
+def test_fullsize_continuous_adjoint_truncated_parity(torch_cuda, sph101):
+    """The continuous adjoint (Eq. (5), upwind) on the full 128-source batch:
+    two forward iterations, then two continuous-adjoint iterations, compared
+    with the oracle's own truncated solves on sampled sources."""
+    from paper_2412_00031_amd import api
+    wl = sph101
+    g, kap = wl["grid"], wl["kappa"]
+    s, xi, eta = (_dev(torch_cuda, wl[k]) for k in ("s", "xi", "eta"))
+    src, rec = _dev(torch_cuda, wl["src"]), _dev(torch_cuda, wl["rec"])
+    Rn = np.abs(wl["R"]) + 0.01
+    par = api.source_params(g, s, xi, eta, src)
+    tau, st = api.forward(g, s, xi, eta, src, par, 1e-30, 2, kap)
+    lam, sa = api.adjoint(g, s, xi, eta, src, par, tau, rec, _dev(torch_cuda, Rn), 1e-30, 2, kap, continuous=True)
+    torch_cuda.cuda.synchronize()
+    assert (sa.cpu().numpy() == -2).all()
+    opar = O.source_params(g, wl["s"], wl["xi"], wl["eta"], wl["src"])
+    V = O.node_volume(g)
+    for q in (3, 101):
+        otau, _, _, _ = O.forward(g, wl["s"], wl["xi"], wl["eta"], wl["src"][q], opar[q], kap, 1e-30, 2)
+        P, it, conv, _ = O.adjoint_cont(g, wl["s"], wl["xi"], wl["eta"], wl["src"][q], opar[q], otau, wl["rec"], Rn[q],
+                                        1e-30, 2)
+        assert rel_inf(lam[q].cpu().numpy(), P * wl["s"] * V) <= 1e-10
+
+
+def test_fullsize_per_step_kernels_parity(torch_cuda, sph101):
+    """The per-step kernels outside the solves at the benchmark's sizes, on the
+    inputs bench.py times (seeded synthetic fields of the workload's shapes):
+    kernel density at 101^3, the common-receiver misfit with 128 sources x 500
+    receivers x 64 pairs per receiver."""
+    from paper_2412_00031_amd import api
+    torch = torch_cuda
+    wl = sph101
+    g = wl["grid"]
+    n = tuple(g["n"])
+    rng = np.random.default_rng(9001)
+    grad = rng.standard_normal((3,) + n)
+    dens = np.abs(rng.standard_normal(n)) + 0.1
+    K, Kd = api.kernel_density(g, _dev(torch, wl["s"]), _dev(torch, dens), _dev(torch, grad), 1e-3, 0.5)
+    Ko, Kdo = O.kernel_density(g, wl["s"], dens, grad, 1e-3, 0.5)
+    assert rel_inf(K.cpu().numpy(), Ko) <= 1e-13 and rel_inf(Kd.cpu().numpy(), Kdo) <= 1e-14
+    nsrc, nrec = len(wl["src"]), len(wl["rec"])
+    T = rng.uniform(5.0, 30.0, (nsrc, nrec))
+    Tobs = T + rng.normal(0.0, 0.2, T.shape)
+    off, pair, tri = W.receiver_source_pairs(nsrc, nrec, 64, rng)
+    wcr = rng.uniform(0.5, 2.0, len(tri))
+    chi_o, R_o = O.misfit(T, Tobs)
+    c2, R_o = O.misfit_cr(T, Tobs, tri, wcr, 1.0, R_o)
+    chi, R = api.misfit(_dev(torch, T), _dev(torch, Tobs), cr=(_dev(torch, off, torch.int32), _dev(torch, pair, torch.int32)),
+                        wcr=_dev(torch, wcr), gamma=1.0)
+    assert abs(chi.item() - (chi_o + c2)) <= 1e-12 * (chi_o + c2)
+    assert rel_inf(R.cpu().numpy(), R_o) <= 1e-14
