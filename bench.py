@@ -88,11 +88,12 @@ def solver_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, updates_per_launch, tiles):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (bytes per node update, calibrated against a plain copy), or None
-    when the solver sources (SOLVER_SOURCES) changed since the counters were taken or the tile
-    depths (forward, adjoint) differ from the ones measured."""
+def measured_traffic(kernel, updates_per_launch, tile_k):
+    """HBM bytes per launch of `kernel` at tile depth `tile_k` from the
+    committed rocprofv3 counter summary (bytes per node update, calibrated
+    against a plain copy, for each profiled tile depth), or None when the
+    solver sources (SOLVER_SOURCES) changed since the counters were taken or
+    that tile depth was not profiled."""
     path = os.path.join(ROOT, "profiles", "sweeps_sph101_pmc.md")
     if not os.path.exists(path):
         return None
@@ -103,10 +104,9 @@ def measured_traffic(kernel, updates_per_launch, tiles):
             vals[k.strip()] = v.strip()
     if vals.get("kernel_sha256") != solver_sha256():
         return None
-    if (vals.get("tile_k_fwd"), vals.get("tile_k_adj")) != (str(tiles[0]), str(tiles[1])):
-        return None
     try:
-        per_update = float(vals[f"{kernel} read_bytes_per_update"]) + float(vals[f"{kernel} write_bytes_per_update"])
+        per_update = (float(vals[f"{kernel} tile_k {tile_k} read_bytes_per_update"]) +
+                      float(vals[f"{kernel} tile_k {tile_k} write_bytes_per_update"]))
     except KeyError:
         return None
     return per_update * updates_per_launch
@@ -479,7 +479,8 @@ def main():
         K = kern[dom]
         avg_ms = K["ms"] / max(K["launches"], 1)
         achieved = K["bytes"] / (K["ms"] * 1e-3) / 1e9 if K["ms"] > 0 else 0.0
-        traffic = measured_traffic(dom, K["updates"] / max(K["launches"], 1), (tk_f or 16, tk_a or 48))
+        traffic = measured_traffic(dom, K["updates"] / max(K["launches"], 1),
+                                   (tk_f or 16) if dom == "k_fwd_sweep" else (tk_a or 48))
         roofline = {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None if traffic is None else round(traffic),
