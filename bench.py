@@ -336,8 +336,8 @@ def aux_section(wl, nsrc, dev, with_cpu):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sources of a batch shard "
-              "across GPUs with no communication but this build measures the one-GPU share", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the sources of a batch shard "
+              "across GPUs with no communication, and this benchmark measures one GPU's share", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

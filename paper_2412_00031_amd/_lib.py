@@ -61,8 +61,8 @@ def load(path=LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise LibraryMissing(f"{path} not found: build it with paper_2412_00031_amd/build.py "
-                             "(or __graft_entry__.build()); there is no CPU fallback")
+        raise LibraryMissing(f"{path} not found: build it with `python -m paper_2412_00031_amd.build`; "
+                             "there is no CPU fallback")
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     G = ctypes.POINTER(TTGrid)
