@@ -12,7 +12,8 @@ observed times come from a forward solve in an independent random model
 (computed before timing).  The plain path (tau = 1 start) and the warm-started
 path run the same steps back to back; value = sources per second (fwd +
 adjoint + kernel per source) of the warm-started path, with the plain path's
-figures in "plain".
+figures in "plain", and the plain-start step with the upwind adjoint of
+Eq. (5) in "plain_continuous_adjoint".
 
 Prints one JSON line (rank 0).  Extra objects: "roofline" (the dominant sweep
 kernel, timed live with HIP event pairs around the back-to-back launches of
@@ -401,7 +402,7 @@ def main():
         else:
             log(f"no warm-start weights at {wpath}: timing the plain path only")
 
-    def step(timed, use_warm):
+    def step(timed, use_warm, continuous=args.adjoint == "continuous"):
         par = api.source_params(g, s, xi, eta, src)
         init = warm.predict(s, xi, eta, src, par, out=init_buf) if use_warm else None
         _, st_f = api.forward(g, s, xi, eta, src, par, tol, args.max_iter, kappa, tau_init=init, tile_k=tk_f,
@@ -410,14 +411,14 @@ def main():
         chi, R = api.misfit(T, T_obs)
         _, st_a = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, tol, args.max_iter, kappa, tile_k=tk_a,
                               ws=ws_a, out=lam, time_sweeps=timed, graph=args.graph, groups=args.groups,
-                              continuous=args.adjoint == "continuous")
+                              continuous=continuous)
         api.kernel(g, s, xi, eta, src, par, tau, lam, grad=grad.zero_())
         return st_f, st_a, chi
 
-    def run(use_warm, steps, warmup, timed):
-        name = "warm" if use_warm else "plain"
+    def run(use_warm, steps, warmup, timed, continuous=args.adjoint == "continuous"):
+        name = ("warm" if use_warm else "plain") + (" (continuous adjoint)" if continuous else "")
         for w in range(warmup):
-            step(False, use_warm)
+            step(False, use_warm, continuous)
             torch.cuda.synchronize()
             log(f"{name}: warmup step {w + 1} done")
         torch.cuda.synchronize()
@@ -426,7 +427,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            st_f, st_a, chi = step(timed, use_warm)
+            st_f, st_a, chi = step(timed, use_warm, continuous)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         log(f"{name}: timed {steps} steps{' (sweep timing)' if timed else ''}: {elapsed:.2f} s")
@@ -449,6 +450,10 @@ def main():
                 warm.predict(s, xi, eta, src, api.source_params(g, s, xi, eta, src), out=init_buf)
             torch.cuda.synchronize()
             runs["warm"]["predict_ms"] = (time.perf_counter() - t0) / 3 * 1e3
+        if args.adjoint == "discrete" and not args.no_aux:
+            # the same plain-start step with the upwind adjoint of Eq. (5) (the
+            # paper's route), reported beside the headline discrete-adjoint figures
+            runs["continuous"] = run(False, args.steps, 1, False, continuous=True)
     # roofline step: the same step once more with every directional sweep of the
     # sweep kernels timed by HIP events on the library's stream (one source
     # group, so each launch carries a tile-plane of every active source)
@@ -535,6 +540,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "plain": summary(runs["plain"]) if "plain" in runs else None,
         "warm": dict(summary(runs["warm"]), predict_ms=round(runs["warm"]["predict_ms"], 2)) if "warm" in runs else None,
+        "plain_continuous_adjoint": summary(runs["continuous"]) if "continuous" in runs else None,
         "roofline_only": bool(args.roofline_only),
         "config": {"workload": f"sph101: 101^3 spherical (0-100 km, 4x4 deg), GRF model, {nsrc} sources, "
                                f"{len(wl['rec'])} receivers, tol {tol:g}, {start}",
