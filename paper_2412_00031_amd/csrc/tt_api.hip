@@ -110,7 +110,11 @@ tt::Geo make_geo(const tt_grid* g, int tk) {
     G.tk = tk;
     G.nt[0] = (G.m[0] + tt::kBI - 1) / tt::kBI;
     G.nt[1] = (G.m[1] + tt::kBJ - 1) / tt::kBJ;
-    G.nt[2] = (G.m[2] + tk - 1) / tk;
+    G.nt[2] = 0;
+    for (int sd = 0; sd <= G.nt[0] + G.nt[1] - 2; ++sd) {
+        const int c = tt::col_tile_hi(G, sd) - tt::col_tile_lo(G, sd) + 1;
+        G.nt[2] = c > G.nt[2] ? c : G.nt[2];
+    }
     G.ntiles = G.nt[0] * G.nt[1] * G.nt[2];
     G.N = (long long)G.n[0] * G.n[1] * G.n[2];
     G.si = (long long)G.n[1] * G.n[2];
@@ -163,15 +167,61 @@ Layout layout(const tt::Geo& G, int nsrc, int nslots, int which) {
 void fill_plan(tt::Plan& P, const tt::Geo& G, int nsrc) {
     P.G = G;
     P.nsrc = nsrc;
-    P.nplanes = G.nt[0] + G.nt[1] + G.nt[2] - 2;
-    P.plane_count.assign(P.nplanes, 0);
-    for (int ti = 0; ti < G.nt[0]; ++ti)
-        for (int tj = 0; tj < G.nt[1]; ++tj)
-            for (int tk = 0; tk < G.nt[2]; ++tk) P.plane_count[ti + tj + tk]++;
+    // tile-plane p holds the tiles (TI, TJ, p - s) of the tile columns with
+    // s = TI + TJ and lo(s) <= p - s <= hi(s); s + lo(s) and s + hi(s) grow with
+    // s, so those s form one run
+    const int smax = G.nt[0] + G.nt[1] - 2;
+    const int pmax = smax + tt::col_tile_hi(G, smax);
+    P.plane_count.clear();
+    P.plane_id.clear();
+    P.plane_s0.clear();
+    for (int p = 0; p <= pmax; ++p) {
+        int cnt = 0, s0 = -1;
+        for (int sd = 0; sd <= smax; ++sd) {
+            if (sd + tt::col_tile_lo(G, sd) > p || sd + tt::col_tile_hi(G, sd) < p) continue;
+            if (s0 < 0) s0 = sd;
+            cnt += tt::diag_count(G, sd);
+        }
+        if (cnt == 0) continue;
+        P.plane_count.push_back(cnt);
+        P.plane_id.push_back(p);
+        P.plane_s0.push_back(s0);
+    }
+    P.nplanes = (int)P.plane_count.size();
     P.max_plane_tiles = 0;
     for (int c : P.plane_count) P.max_plane_tiles = c > P.max_plane_tiles ? c : P.max_plane_tiles;
     P.nbblocks = (int)((G.NB + tt::kBndThreads - 1) / tt::kBndThreads);
     P.nslots = 8 * G.ntiles + 8 * P.nbblocks;
+}
+
+// Host check of the tile-plane enumeration before any sweep is launched:
+// every tile the kernels decode lies in the grid's tile columns and in its
+// column's slab range, its plane number is TI + TJ + TK, and the planes cover
+// each tile exactly once.
+int check_tiling(const tt::Plan& P) {
+    const tt::Geo& G = P.G;
+    std::vector<unsigned char> seen((size_t)G.ntiles, 0);
+    long long total = 0;
+    for (int q = 0; q < P.nplanes; ++q) {
+        for (int b = 0; b < P.plane_count[q]; ++b) {
+            int TI, TJ, TK;
+            tt::tile_decode(G, P.plane_id[q], P.plane_s0[q], b, TI, TJ, TK);
+            const int sd = TI + TJ;
+            const int rel = TK - tt::col_tile_lo(G, sd);
+            if (TI < 0 || TI >= G.nt[0] || TJ < 0 || TJ >= G.nt[1] || rel < 0 || TK > tt::col_tile_hi(G, sd) ||
+                rel >= G.nt[2] || TI + TJ + TK != P.plane_id[q])
+                return fail(TT_EINVAL, "internal: tile %d of tile-plane %d decodes outside the grid", b, P.plane_id[q]);
+            unsigned char& f = seen[((size_t)TI * G.nt[1] + TJ) * G.nt[2] + rel];
+            if (f) return fail(TT_EINVAL, "internal: tile-plane %d repeats a tile", P.plane_id[q]);
+            f = 1;
+            ++total;
+        }
+    }
+    long long want = 0;
+    for (int sd = 0; sd <= G.nt[0] + G.nt[1] - 2; ++sd)
+        want += (long long)tt::diag_count(G, sd) * (tt::col_tile_hi(G, sd) - tt::col_tile_lo(G, sd) + 1);
+    if (total != want) return fail(TT_EINVAL, "internal: tile-planes cover %lld of %lld tiles", total, want);
+    return TT_OK;
 }
 
 void bind_workspace(tt::Plan& P, void* ws, const Layout& L) {
@@ -462,6 +512,7 @@ int tt_forward(const tt_grid* grid, const double* s, const double* xi, const dou
         tt::Plan P;
         fill_plan(P, G, 1);
         if (P.max_plane_tiles > 65535) return fail(TT_EINVAL, "too many tiles per tile-plane; raise opts.tile_k");
+        if ((rc = check_tiling(P))) return rc;
     }
     const int groups = groups_of(opts, nsrc);
     hipStream_t caller = (hipStream_t)stream;
@@ -609,6 +660,7 @@ int tt_adjoint(const tt_grid* grid, const double* s, const double* xi, const dou
         tt::Plan P;
         fill_plan(P, G, 1);
         if (P.max_plane_tiles > 65535) return fail(TT_EINVAL, "too many tiles per tile-plane; raise opts.tile_k");
+        if ((rc = check_tiling(P))) return rc;
     }
     const int groups = groups_of(opts, nsrc);
     hipStream_t caller = (hipStream_t)stream;

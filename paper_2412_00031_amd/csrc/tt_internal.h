@@ -31,9 +31,9 @@ struct Geo {
     int n[3];          // nodes per axis
     int m[3];          // interior nodes per axis (n - 2)
     int coord;         // 0 Cartesian, 1 spherical
-    int nt[3];         // tiles per axis in sweep-relative coordinates
-    int tk;            // k-extent of a tile
-    int ntiles;        // nt0 * nt1 * nt2
+    int nt[3];         // tile columns along i' and j'; nt[2] = most tiles of one tile column
+    int tk;            // hyperplane steps of a tile (its extent along u = i' + j' + k')
+    int ntiles;        // nt0 * nt1 * nt2 (partial-sum slots per directional sweep)
     long long N;       // n0 * n1 * n2
     long long si, sj;  // strides of axes 0 and 1 (axis 2 has stride 1)
     long long NB;      // boundary nodes
@@ -41,6 +41,42 @@ struct Geo {
     long long S;       // records per row-coalesced layout: n0 * W * n1
     double o[3], h[3], inv2h[3], invh[3];
 };
+
+// Sheared sweep tiles.  In sweep-relative interior coordinates (i', j', k')
+// a tile is the 8 x 8 (i', j') tile column (TI, TJ) intersected with the slab
+// TK tk <= u < (TK + 1) tk of the hyperplane index u = i' + j' + k'.  Tile column
+// TI + TJ = s spans u in [8 s, 8 s + 14 + m2) (full columns; ragged ones end
+// earlier), i.e. slabs lo(s)..hi(s).  A tile reads its upstream neighbours'
+// nodes at u - 1 (slabs TK - 1 and TK of the neighbouring columns) and its
+// downstream ones' at u + 1 (slabs TK and TK + 1), so all tiles with the same
+// tile-plane number TI + TJ + TK are independent and each depends only on
+// lower tile-planes.
+__host__ __device__ inline int col_tile_lo(const Geo& G, int s) { return (kBI * s) / G.tk; }
+__host__ __device__ inline int col_tile_hi(const Geo& G, int s) {
+    return (kBI * s + (kBI - 1) + (kBJ - 1) + G.m[2] - 1) / G.tk;
+}
+// tile columns with TI + TJ = s
+__host__ __device__ inline int diag_first(const Geo& G, int s) { return s - (G.nt[1] - 1) > 0 ? s - (G.nt[1] - 1) : 0; }
+__host__ __device__ inline int diag_count(const Geo& G, int s) {
+    const int hi = s < G.nt[0] - 1 ? s : G.nt[0] - 1;
+    return hi - diag_first(G, s) + 1;
+}
+// tile b of tile-plane p whose first tile column sum is s0 (tiles ordered by s,
+// then TI); the host enumerates the planes so that b is always in range
+__host__ __device__ inline void tile_decode(const Geo& G, int p, int s0, int b, int& TI, int& TJ, int& TK) {
+    const int smax = G.nt[0] + G.nt[1] - 2;
+    int s = s0;
+    for (; s < smax; ++s) {
+        const int c = diag_count(G, s);
+        if (b < c) break;
+        b -= c;
+    }
+    TI = diag_first(G, s) + b;
+    TJ = s - TI;
+    TK = p - s;
+}
+// LDS words per staged column: tk + 2 entries, padded to an odd count
+__host__ __device__ inline int tile_pitch(int tk) { return (tk + 2) | 1; }
 
 // Per-source constants, produced on the device by k_src_setup.
 struct Src {
@@ -184,7 +220,7 @@ struct Plan {
     Geo G;
     Tabs T;
     int nsrc = 0;
-    int nplanes = 0;          // tile-planes per sweep
+    int nplanes = 0;          // non-empty tile-planes per sweep
     int max_plane_tiles = 0;  // largest tile-plane
     int nbblocks = 0;         // boundary-pass blocks per source
     int nslots = 0;           // partial-sum slots per source per iteration
@@ -206,7 +242,9 @@ struct Plan {
     double* bnd_in = nullptr; // adjoint: [nsrc][NB] (continuous adjoint: boundary pass scratch)
     double* bnd_rhs = nullptr; // adjoint: right-hand side of the boundary nodes, [nsrc][NB]
     bool continuous = false;  // adjoint: upwind discretisation of Eq. (5) instead of the exact transpose
-    std::vector<int> plane_count;
+    std::vector<int> plane_count;  // tiles of each non-empty tile-plane
+    std::vector<int> plane_id;     // its tile-plane number TI + TJ + TK
+    std::vector<int> plane_s0;     // its first tile column sum TI + TJ
     // optional timing of the sweep kernels: an event pair around the
     // tile-plane launches of each directional sweep, with the launch count
     std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>>* timing = nullptr;

@@ -6,8 +6,10 @@
 // and boundary nodes are not written during a sweep, so every such order yields
 // the same numbers as the lexicographic one; the hyperplane-stepping idea of
 // Sec. 3.4 (nodes with i'+j'+k' = L are independent) is used in this form:
-//   - the interior is cut into tiles of 8 x 8 (i, j) columns x tk nodes along k
-//     (sweep-relative coordinates, ragged last tiles);
+//   - the interior is cut into 8 x 8 (i', j') tile columns (sweep-relative
+//     coordinates, ragged last ones), and each tile column into slabs of tk
+//     consecutive hyperplanes u = i' + j' + k' (sheared tiles: the 14-step ramp
+//     of a skewed 8 x 8 walk is paid once per column, not once per tile);
 //   - tiles with the same TI'+TJ'+TK' form a tile-plane; one launch processes
 //     one tile-plane of every active source.  grid.x is the source, so
 //     consecutive workgroups are one tile of consecutive sources: workgroups
@@ -16,9 +18,9 @@
 //     share an XCD read the same model lines;
 //   - inside a tile one 64-lane wave owns the 8 x 8 columns; the tile and its
 //     one-node halo are staged in LDS with contiguous column loads, then at
-//     step t lane (li, lj) updates k' = k0' + t - li - lj (the tile is walked
-//     along its own hyperplanes) reading and writing LDS only, and the tile is
-//     written back with contiguous column stores;
+//     step t lane (li, lj) updates the node of its column on hyperplane
+//     u = TK' tk + t, reading and writing LDS only, and the tile is written
+//     back with contiguous column stores;
 //   - per-node records (model, adjoint coefficients) are read from
 //     row-coalesced layouts in which the 8 lanes of a tile row find their
 //     records side by side on every step.
@@ -89,25 +91,6 @@ __device__ __forceinline__ int astar_of(const Geo& G, const int p[3]) {
     for (int a = 0; a < 3; ++a)
         if (on_bnd(G, a, p[a])) as = a;
     return as;
-}
-
-// tile (TI', TJ', TK') number b of tile-plane p (TI'+TJ'+TK' = p), ordered by
-// TI' then TJ'
-__device__ __forceinline__ void tile_decode(const Geo& G, int p, int b, int& TI, int& TJ, int& TK) {
-    const int lo = max(0, p - (G.nt[1] - 1) - (G.nt[2] - 1));
-    const int hi = min(G.nt[0] - 1, p);
-    TI = lo; TJ = 0; TK = 0;
-    for (int ti = lo; ti <= hi; ++ti) {
-        const int r = p - ti;
-        const int jlo = max(0, r - (G.nt[2] - 1)), jhi = min(G.nt[1] - 1, r);
-        const int cnt = jhi - jlo + 1;
-        if (cnt <= 0) continue;
-        if (b < cnt) {
-            TI = ti; TJ = jlo + b; TK = r - TJ;
-            return;
-        }
-        b -= cnt;
-    }
 }
 
 // ---------------------------------------------------------------- set-up
@@ -189,6 +172,13 @@ __global__ void k_solve_init(SweepArgs a, const double* __restrict__ init, doubl
         const int j = (int)(q % a.G.n[1]), i = (int)(q / a.G.n[1]);
         f[x] = in_fixed(S, i, j, k) ? vfix : (ti ? ti[x] : v0);
     }
+    // partial-sum slots start at zero: slots of slab indices a short tile
+    // column does not have are never written
+    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < a.nslots;
+         x += (long long)gridDim.x * blockDim.x) {
+        a.part[(long long)src * a.nslots + x] = 0.0;
+        if (a.part2) a.part2[(long long)src * a.nslots + x] = 0.0;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.active[src] = 1;
         a.iter[src] = 0;
@@ -210,46 +200,58 @@ struct Dir {
 };
 
 struct TileCtx {
-    int TI, TJ, TK, lane, li, lj, ext_i, ext_j, k0p, k1p, kp0, kbase, nsteps;
+    int TI, TJ, TK, lane, li, lj, ext_i, ext_j;
+    int t0, t1;    // wave-uniform walk: steps t0 <= t < t1 (u = TK tk + t)
+    int kp0;       // this lane's k' at step 0 (k' = kp0 + t)
+    int kq0;       // staged entry (ci, cj, kk) holds k' = kq0 - ci - cj + kk
+    int kbase;     // absolute k = kbase + s2 k'
     bool colv, fcol;
     int i, j;
     int rbase, rstep;  // record index of this lane's column at k' = 0, and its change per k'
+    int slot;          // partial-sum slot of the tile within one directional sweep
 };
 
 template <int DIR>
-__device__ __forceinline__ TileCtx tile_ctx(const Geo& G, const Src& S, int plane) {
+__device__ __forceinline__ TileCtx tile_ctx(const Geo& G, const Src& S, int plane, int s0) {
     using D = Dir<DIR>;
     TileCtx c;
-    tile_decode(G, plane, blockIdx.y, c.TI, c.TJ, c.TK);
+    tile_decode(G, plane, s0, blockIdx.y, c.TI, c.TJ, c.TK);
     c.lane = threadIdx.x;
     c.li = c.lane >> 3;
     c.lj = c.lane & 7;
     c.ext_i = min(kBI, G.m[0] - c.TI * kBI);
     c.ext_j = min(kBJ, G.m[1] - c.TJ * kBJ);
-    c.k0p = c.TK * G.tk;
-    c.k1p = min(c.k0p + G.tk, G.m[2]);
     c.colv = c.li < c.ext_i && c.lj < c.ext_j;
     const int ip = c.TI * kBI + (c.colv ? c.li : 0), jp = c.TJ * kBJ + (c.colv ? c.lj : 0);
     c.i = D::s0 > 0 ? 1 + ip : G.n[0] - 2 - ip;
     c.j = D::s1 > 0 ? 1 + jp : G.n[1] - 2 - jp;
     c.fcol = (unsigned)(c.i - S.fb[0]) <= 1u && (unsigned)(c.j - S.fb[1]) <= 1u;
-    c.nsteps = (c.k1p - c.k0p) + c.ext_i - 1 + c.ext_j - 1;
-    c.kp0 = c.k0p - c.li - c.lj;               // this lane's k' at step 0
-    c.kbase = D::s2 > 0 ? 1 : G.n[2] - 2;      // absolute k = kbase + s2 * k'
+    const int U0 = c.TK * G.tk;
+    const int ucol = kBI * (c.TI + c.TJ);  // u of the column's first node (i', j' at the tile corner, k' = 0)
+    c.t0 = max(0, ucol - U0);
+    c.t1 = min(G.tk, ucol + (c.ext_i - 1) + (c.ext_j - 1) + G.m[2] - U0);
+    c.kp0 = U0 - ip - jp;
+    c.kq0 = U0 - ucol + 1;
+    c.kbase = D::s2 > 0 ? 1 : G.n[2] - 2;
     // record index ((i W + w) n1 + j) with w = j + k (family 0) or j - k + n2 - 1
     // (family 1), k = kbase + s2 k': linear in k' with slope s1 n1 in both families
     const int w0 = D::fam == 0 ? c.j + c.kbase : c.j - c.kbase + G.n[2] - 1;
     c.rbase = (c.i * G.W + w0) * G.n[1] + c.j;
     c.rstep = D::s1 * G.n[1];
+    c.slot = (c.TI * G.nt[1] + c.TJ) * G.nt[2] + (c.TK - col_tile_lo(G, c.TI + c.TJ));
     return c;
 }
 
-// Staged tile: the (8+2) x (8+2) columns of the tile and its i/j halo, each
-// with the k'-range [k0'-1, k1'] (tk + 2 values), in LDS as [ci][cj][kk]
-// (ci = li + 1, cj = lj + 1, kk = k' - k0' + 1).  Everything a step reads from
-// the field is staged (upstream tiles are finished, downstream ones untouched),
-// so the march touches LDS only; the tile is loaded and written back with
-// contiguous column segments.
+// Staged tile: the (8+2) x (8+2) columns of the tile and its i'/j' halo, each
+// with the entries kk = 0..tk+1, in LDS as [ci][cj][kk] with an odd column
+// pitch (ci = li + 1, cj = lj + 1).  Entry kk of column (ci, cj) is the node
+// k' = kq0 - ci - cj + kk: the column windows are sheared along the tile's
+// slab, so at step t lane (li, lj) owns entry t + 1 of its column and finds
+// its upstream i'/j'/k' neighbours at entry t and its downstream ones at
+// entry t + 2.  Everything a step reads from the field is staged (upstream
+// tiles are finished, downstream ones untouched), so the walk touches LDS
+// only; staged k' are clamped to the column's nodes [-1, m2] (entries outside
+// are never read).  Loads and stores move contiguous column segments.
 constexpr int kTC = kBI + 2;
 
 // Staging covers the tile's columns as one flat list of (column, k) elements
@@ -270,50 +272,56 @@ __device__ __forceinline__ int stage_origin(const Geo& G, int a, int T) {
 
 template <int DIR>
 __device__ __forceinline__ void stage_tile_incr(const Geo& G, const TileCtx& c, const double* __restrict__ fld,
-                                           double* lds, int L) {
+                                                double* lds, int Lp) {
     using D = Dir<DIR>;
-    const int Lk = c.k1p - c.k0p + 2;                 // staged k entries per column
+    const int Lk = G.tk + 2;                          // staged entries per column
     const int nj = c.ext_j + 2, ncol = (c.ext_i + 2) * nj;
     const int total = ncol * Lk;
     const long long si = D::s0 * G.si, sj = D::s1 * G.sj;
-    const long long base = nidx(G, stage_origin<D::s0>(G, 0, c.TI), stage_origin<D::s1>(G, 1, c.TJ),
-                                c.kbase + D::s2 * (c.k0p - 1));
+    const long long base = nidx(G, stage_origin<D::s0>(G, 0, c.TI), stage_origin<D::s1>(G, 1, c.TJ), c.kbase);
+    const int kmax = G.m[2];
     // element e = lane + 64 r  <->  column col = e / Lk = ci nj + cj, kk = e % Lk
     int col = c.lane / Lk, kk = c.lane - col * Lk;
     int ci = col / nj, cj = col - ci * nj;
-    long long goff = ci * si + cj * sj + D::s2 * kk;  // field offset from base
-    int loff = (ci * kTC + cj) * L + kk;              // LDS offset
+    long long gcol = ci * si + cj * sj;  // field offset of the column from base
+    int dq = kk - ci - cj;               // k' = kq0 + dq
+    int loff = (ci * kTC + cj) * Lp + kk;
     const int dcol = 64 / Lk, dkk = 64 - dcol * Lk;
-    const long long g_step = dcol * sj + D::s2 * dkk, g_kwrap = sj - D::s2 * Lk, g_jwrap = si - nj * sj;
-    const int l_step = dcol * L + dkk, l_kwrap = L - Lk, l_jwrap = (kTC - nj) * L;
+    const long long g_step = dcol * sj, g_jwrap = si - nj * sj;
+    const int l_step = dcol * Lp + dkk, l_kwrap = Lp - Lk, l_jwrap = (kTC - nj) * Lp;
     for (int e0 = 0; e0 < total; e0 += 64 * kStageBatch) {
         double v[kStageBatch];
         int lo[kStageBatch];
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u) {
             const bool ok = col < ncol;
-            v[u] = fld[base + (ok ? goff : 0)];
+            const int kp = min(max(c.kq0 + dq, -1), kmax);
+            v[u] = fld[base + (ok ? gcol + D::s2 * kp : 0)];
             lo[u] = ok ? loff : -1;
             col += dcol;
             cj += dcol;
             kk += dkk;
-            goff += g_step;
+            gcol += g_step;
+            dq += dkk - dcol;
             loff += l_step;
             const bool kw = kk >= Lk;  // selects, not branches
             kk -= kw ? Lk : 0;
             col += kw;
             cj += kw;
-            goff += kw ? g_kwrap : 0;
+            gcol += kw ? sj : 0;
+            dq -= kw ? Lk + 1 : 0;
             loff += kw ? l_kwrap : 0;
             if (dcol < nj) {  // wave-uniform: at most one row wrap
                 const bool jw = cj >= nj;
                 cj -= jw ? nj : 0;
-                goff += jw ? g_jwrap : 0;
+                gcol += jw ? g_jwrap : 0;
+                dq += jw ? nj - 1 : 0;
                 loff += jw ? l_jwrap : 0;
             } else {
                 while (cj >= nj) {
                     cj -= nj;
-                    goff += g_jwrap;
+                    gcol += g_jwrap;
+                    dq += nj - 1;
                     loff += l_jwrap;
                 }
             }
@@ -329,14 +337,13 @@ __device__ __forceinline__ void stage_tile_incr(const Geo& G, const TileCtx& c, 
 // scalar registers, spills with that form), more vector registers.
 template <int DIR>
 __device__ __forceinline__ void stage_tile_div(const Geo& G, const TileCtx& c, const double* __restrict__ fld,
-                                               double* lds, int L) {
+                                               double* lds, int Lp) {
     using D = Dir<DIR>;
-    const int Lk = c.k1p - c.k0p + 2;
+    const int Lk = G.tk + 2;
     const int nj = c.ext_j + 2, ncol = (c.ext_i + 2) * nj;
     const int total = ncol * Lk;
     const long long si = D::s0 * G.si, sj = D::s1 * G.sj;
-    const long long base = nidx(G, stage_origin<D::s0>(G, 0, c.TI), stage_origin<D::s1>(G, 1, c.TJ),
-                                c.kbase + D::s2 * (c.k0p - 1));
+    const long long base = nidx(G, stage_origin<D::s0>(G, 0, c.TI), stage_origin<D::s1>(G, 1, c.TJ), c.kbase);
     int col = c.lane / Lk, kk = c.lane - col * Lk;
     const int dcol = 64 / Lk, dkk = 64 - dcol * Lk;
     for (int e0 = 0; e0 < total; e0 += 64 * kStageBatch) {
@@ -346,8 +353,9 @@ __device__ __forceinline__ void stage_tile_div(const Geo& G, const TileCtx& c, c
         for (int u = 0; u < kStageBatch; ++u) {
             const int cc = min(col, ncol - 1);
             const int ci = cc / nj, cj = cc - ci * nj;
-            v[u] = fld[base + ci * si + cj * sj + D::s2 * kk];
-            lo[u] = col < ncol ? (ci * kTC + cj) * L + kk : -1;
+            const int kp = min(max(c.kq0 - ci - cj + kk, -1), G.m[2]);
+            v[u] = fld[base + ci * si + cj * sj + D::s2 * kp];
+            lo[u] = col < ncol ? (ci * kTC + cj) * Lp + kk : -1;
             col += dcol;
             kk += dkk;
             if (kk >= Lk) {
@@ -361,47 +369,58 @@ __device__ __forceinline__ void stage_tile_div(const Geo& G, const TileCtx& c, c
     }
 }
 
+// Write back the tile's own nodes: entries 1..tk of its columns whose k' is
+// an interior node (the others are halo or outside the column).
 template <int DIR>
 __device__ __forceinline__ void unstage_tile(const Geo& G, const TileCtx& c, double* __restrict__ fld,
-                                             const double* lds, int L) {
+                                             const double* lds, int Lp) {
     using D = Dir<DIR>;
-    const int ek = c.k1p - c.k0p;
+    const int ek = G.tk;
     const int nj = c.ext_j, n = c.ext_i * nj, total = n * ek;
     const long long si = D::s0 * G.si, sj = D::s1 * G.sj;
     const long long base = nidx(G, stage_origin<D::s0>(G, 0, c.TI) + D::s0, stage_origin<D::s1>(G, 1, c.TJ) + D::s1,
-                                c.kbase + D::s2 * c.k0p);
-    // element e <-> column col = e / ek = li nj + lj, kk = e % ek (kk = k' - k0')
-    int col = c.lane / ek, kk = c.lane - col * ek;
+                                c.kbase);
+    const unsigned kmax = (unsigned)G.m[2];
+    // element e <-> column col = e / ek = li nj + lj, q = e % ek (entry q + 1,
+    // k' = kq0 - 1 - li - lj + q)
+    int col = c.lane / ek, q = c.lane - col * ek;
     int li = col / nj, lj = col - li * nj;
-    long long goff = li * si + lj * sj + D::s2 * kk;
-    int loff = ((li + 1) * kTC + lj + 1) * L + kk + 1;
-    const int dcol = 64 / ek, dkk = 64 - dcol * ek;
-    const long long g_step = dcol * sj + D::s2 * dkk, g_kwrap = sj - D::s2 * ek, g_jwrap = si - nj * sj;
-    const int l_step = dcol * L + dkk, l_kwrap = L - ek, l_jwrap = (kTC - nj) * L;
+    long long gcol = li * si + lj * sj;
+    int dq = q - li - lj;
+    int loff = ((li + 1) * kTC + lj + 1) * Lp + q + 1;
+    const int dcol = 64 / ek, dq_step = 64 - dcol * ek;
+    const long long g_step = dcol * sj, g_jwrap = si - nj * sj;
+    const int l_step = dcol * Lp + dq_step, l_kwrap = Lp - ek, l_jwrap = (kTC - nj) * Lp;
+    const int kq = c.kq0 - 1;
     for (int e0 = 0; e0 < total; e0 += 64 * kStageBatch) {
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u) {
-            if (col < n) fld[base + goff] = lds[loff];
+            const int kp = kq + dq;
+            if (col < n && (unsigned)kp < kmax) fld[base + gcol + D::s2 * kp] = lds[loff];
             col += dcol;
             lj += dcol;
-            kk += dkk;
-            goff += g_step;
+            q += dq_step;
+            gcol += g_step;
+            dq += dq_step - dcol;
             loff += l_step;
-            const bool kw = kk >= ek;
-            kk -= kw ? ek : 0;
+            const bool kw = q >= ek;
+            q -= kw ? ek : 0;
             col += kw;
             lj += kw;
-            goff += kw ? g_kwrap : 0;
+            gcol += kw ? sj : 0;
+            dq -= kw ? ek + 1 : 0;
             loff += kw ? l_kwrap : 0;
             if (dcol < nj) {
                 const bool jw = lj >= nj;
                 lj -= jw ? nj : 0;
-                goff += jw ? g_jwrap : 0;
+                gcol += jw ? g_jwrap : 0;
+                dq += jw ? nj - 1 : 0;
                 loff += jw ? l_jwrap : 0;
             } else {
                 while (lj >= nj) {
                     lj -= nj;
-                    goff += g_jwrap;
+                    gcol += g_jwrap;
+                    dq += nj - 1;
                     loff += l_jwrap;
                 }
             }
@@ -418,11 +437,11 @@ struct FwdSlot {
     double sx, xi, eta, c2, s2;
 };
 
-// unconditional: k' is clamped into the tile, so the address is always valid
+// unconditional: k' is clamped into the column, so the address is always valid
 template <int DIR>
 __device__ __forceinline__ void fwd_fetch(const TileCtx& c, const double* __restrict__ mdl,
-                                          const double2* __restrict__ t2, int t, FwdSlot& r) {
-    const int kp = min(max(c.kp0 + t, c.k0p), c.k1p - 1);
+                                          const double2* __restrict__ t2, int kmax, int t, FwdSlot& r) {
+    const int kp = min(max(c.kp0 + t, 0), kmax - 1);
     const double2* m = reinterpret_cast<const double2*>(mdl + (c.rbase + c.rstep * kp) * 4LL);
     const double2 m0 = m[0], m1 = m[1];
     r.sx = m0.x;
@@ -434,66 +453,67 @@ __device__ __forceinline__ void fwd_fetch(const TileCtx& c, const double* __rest
 }
 
 template <int COORD, int DIR>
-__global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane) {
+__global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane, int s0) {
     using D = Dir<DIR>;
     extern __shared__ double lds[];
     const int src = blockIdx.x;
     if (!a.active[src]) return;
     const Geo& G = a.G;
     const Src S = a.src[src];
-    const TileCtx c = tile_ctx<DIR>(G, S, plane);
+    const TileCtx c = tile_ctx<DIR>(G, S, plane, s0);
+    if (c.t1 <= c.t0) {  // a ragged column's slab with no nodes
+        if (c.lane == 0) a.part[(long long)src * a.nslots + DIR * G.ntiles + c.slot] = 0.0;
+        return;
+    }
     const Col cl = make_col(G, a.T, c.i, c.j);
     double* __restrict__ fld = a.field + (long long)src * G.N;
     const double* __restrict__ mdl = a.model + (long long)D::fam * G.S * 4;
     const double2* __restrict__ t2 = a.T.t2;
-    const int L = G.tk + 2;
+    const int Lp = tile_pitch(G.tk);
+    const int kmax = G.m[2];
 
     FwdSlot ring[kPre];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) fwd_fetch<DIR>(c, mdl, t2, u, ring[u]);
-    stage_tile_div<DIR>(G, c, fld, lds, L);
+    for (int u = 0; u < kPre; ++u) fwd_fetch<DIR>(c, mdl, t2, kmax, c.t0 + u, ring[u]);
+    stage_tile_div<DIR>(G, c, fld, lds, Lp);
     __syncthreads();
 
-    const int own = ((c.li + 1) * kTC + c.lj + 1) * L;
-    const int oim = own - kTC * L, oip = own + kTC * L;  // column upstream / downstream in sweep i
+    const int own = ((c.li + 1) * kTC + c.lj + 1) * Lp;
     double eps = 0.0;
     // the step count is padded to a multiple of kPre: no branch encloses a load
-    for (int t0 = 0; t0 < c.nsteps; t0 += kPre) {
+    for (int tb = c.t0; tb < c.t1; tb += kPre) {
 #pragma unroll
         for (int u = 0; u < kPre; ++u) {
-            const int t = t0 + u;
+            const int t = tb + u;
             {
                 FwdSlot& r = ring[u];
                 const int kp = c.kp0 + t;
-                if (c.colv && kp >= c.k0p && kp < c.k1p) {
-                    const int kk = kp - c.k0p + 1;
+                if (c.colv && t < c.t1 && (unsigned)kp < (unsigned)kmax) {
                     const int ka = c.kbase + D::s2 * kp;
                     if (!(c.fcol && (unsigned)(ka - S.fb[2]) <= 1u)) {
                         // sweep-relative neighbours: "up" = already updated this sweep
-                        const double cur = lds[own + kk];
-                        const double up_i = lds[oim + kk], dn_i = lds[oip + kk];
-                        const double up_j = lds[own - L + kk], dn_j = lds[own + L + kk];
-                        const double up_k = lds[own + kk - 1], dn_k = lds[own + kk + 1];
+                        const int o = own + t;
+                        const double cur = lds[o + 1];
+                        const double up_i = lds[o - kTC * Lp], dn_i = lds[o + kTC * Lp + 2];
+                        const double up_j = lds[o - Lp], dn_j = lds[o + Lp + 2];
+                        const double up_k = lds[o], dn_k = lds[o + 2];
                         const double m0 = D::s0 > 0 ? up_i : dn_i, p0 = D::s0 > 0 ? dn_i : up_i;
                         const double m1 = D::s1 > 0 ? up_j : dn_j, p1 = D::s1 > 0 ? dn_j : up_j;
                         const double m2 = D::s2 > 0 ? up_k : dn_k, p2 = D::s2 > 0 ? dn_k : up_k;
                         const double nv = lf_update<COORD>(G, S, cl, r.c2, r.s2, a.kappa, r.sx, r.xi, r.eta, cur, m0,
                                                            p0, m1, p1, m2, p2);
-                        lds[own + kk] = nv;
+                        lds[o + 1] = nv;
                         eps += fabs(nv - cur);
                     }
                 }
-                fwd_fetch<DIR>(c, mdl, t2, t + kPre, r);
+                fwd_fetch<DIR>(c, mdl, t2, kmax, t + kPre, r);
             }
         }
     }
     __syncthreads();
-    unstage_tile<DIR>(G, c, fld, lds, L);
+    unstage_tile<DIR>(G, c, fld, lds, Lp);
     eps = wave_sum(eps);
-    if (c.lane == 0) {
-        const int tile_id = (c.TI * G.nt[1] + c.TJ) * G.nt[2] + c.TK;
-        a.part[(long long)src * a.nslots + DIR * G.ntiles + tile_id] = eps;
-    }
+    if (c.lane == 0) a.part[(long long)src * a.nslots + DIR * G.ntiles + c.slot] = eps;
 }
 
 // model records (s, xi, eta, 0) in both row-coalesced layouts
@@ -702,8 +722,9 @@ struct AdjSlot {
 };
 
 template <int DIR>
-__device__ __forceinline__ void adj_fetch(const TileCtx& c, const double* __restrict__ cf, int t, AdjSlot& r) {
-    const int kp = min(max(c.kp0 + t, c.k0p), c.k1p - 1);
+__device__ __forceinline__ void adj_fetch(const TileCtx& c, const double* __restrict__ cf, int kmax, int t,
+                                          AdjSlot& r) {
+    const int kp = min(max(c.kp0 + t, 0), kmax - 1);
     const double2* rc = reinterpret_cast<const double2*>(cf + (c.rbase + c.rstep * kp) * 8LL);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -714,44 +735,51 @@ __device__ __forceinline__ void adj_fetch(const TileCtx& c, const double* __rest
 }
 
 template <int COORD, int DIR>
-__global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane) {
+__global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane, int s0) {
     using D = Dir<DIR>;
     extern __shared__ double lds[];
     const int src = blockIdx.x;
     if (!a.active[src]) return;
     const Geo& G = a.G;
     const Src S = a.src[src];
-    const TileCtx c = tile_ctx<DIR>(G, S, plane);
+    const TileCtx c = tile_ctx<DIR>(G, S, plane, s0);
+    constexpr bool last = (DIR == 7);
+    if (c.t1 <= c.t0) {  // a ragged column's slab with no nodes
+        if (c.lane == 0) {
+            a.part[(long long)src * a.nslots + DIR * G.ntiles + c.slot] = 0.0;
+            if (last) a.part2[(long long)src * a.nslots + c.slot] = 0.0;
+        }
+        return;
+    }
     double* __restrict__ fld = a.field + (long long)src * G.N;
     const double* __restrict__ cf = a.coef + ((long long)src * 2 + D::fam) * G.S * 8;
-    constexpr bool last = (DIR == 7);
-    const int L = G.tk + 2;
+    const int Lp = tile_pitch(G.tk);
+    const int kmax = G.m[2];
 
     AdjSlot ring[kPreAdj];
 #pragma unroll
-    for (int u = 0; u < kPreAdj; ++u) adj_fetch<DIR>(c, cf, u, ring[u]);
-    stage_tile_incr<DIR>(G, c, fld, lds, L);
+    for (int u = 0; u < kPreAdj; ++u) adj_fetch<DIR>(c, cf, kmax, c.t0 + u, ring[u]);
+    stage_tile_incr<DIR>(G, c, fld, lds, Lp);
     __syncthreads();
 
-    const int own = ((c.li + 1) * kTC + c.lj + 1) * L;
-    const int oim = own - kTC * L, oip = own + kTC * L;
+    const int own = ((c.li + 1) * kTC + c.lj + 1) * Lp;
     double dsum = 0.0, asum = 0.0;
     // the step count is padded to a multiple of kPreAdj: no branch encloses a load
-    for (int t0 = 0; t0 < c.nsteps; t0 += kPreAdj) {
+    for (int tb = c.t0; tb < c.t1; tb += kPreAdj) {
 #pragma unroll
         for (int u = 0; u < kPreAdj; ++u) {
-            const int t = t0 + u;
+            const int t = tb + u;
             {
                 AdjSlot& r = ring[u];
                 const int kp = c.kp0 + t;
-                if (c.colv && kp >= c.k0p && kp < c.k1p) {
-                    const int kk = kp - c.k0p + 1;
+                if (c.colv && t < c.t1 && (unsigned)kp < (unsigned)kmax) {
                     const int ka = c.kbase + D::s2 * kp;
                     if (!(c.fcol && (unsigned)(ka - S.fb[2]) <= 1u)) {
-                        const double cur = lds[own + kk];
-                        const double up_i = lds[oim + kk], dn_i = lds[oip + kk];
-                        const double up_j = lds[own - L + kk], dn_j = lds[own + L + kk];
-                        const double up_k = lds[own + kk - 1], dn_k = lds[own + kk + 1];
+                        const int o = own + t;
+                        const double cur = lds[o + 1];
+                        const double up_i = lds[o - kTC * Lp], dn_i = lds[o + kTC * Lp + 2];
+                        const double up_j = lds[o - Lp], dn_j = lds[o + Lp + 2];
+                        const double up_k = lds[o], dn_k = lds[o + 2];
                         const double m0 = D::s0 > 0 ? up_i : dn_i, p0 = D::s0 > 0 ? dn_i : up_i;
                         const double m1 = D::s1 > 0 ? up_j : dn_j, p1 = D::s1 > 0 ? dn_j : up_j;
                         const double m2 = D::s2 > 0 ? up_k : dn_k, p2 = D::s2 > 0 ? dn_k : up_k;
@@ -763,23 +791,22 @@ __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane) {
                         acc -= r.r[4] * p2;
                         acc -= r.r[5] * m2;
                         const double nv = acc / r.r[6];
-                        lds[own + kk] = nv;
+                        lds[o + 1] = nv;
                         dsum += fabs(nv - cur);
                         if (last) asum += fabs(nv);
                     }
                 }
-                adj_fetch<DIR>(c, cf, t + kPreAdj, r);
+                adj_fetch<DIR>(c, cf, kmax, t + kPreAdj, r);
             }
         }
     }
     __syncthreads();
-    unstage_tile<DIR>(G, c, fld, lds, L);
+    unstage_tile<DIR>(G, c, fld, lds, Lp);
     dsum = wave_sum(dsum);
     asum = wave_sum(asum);
     if (c.lane == 0) {
-        const int tile_id = (c.TI * G.nt[1] + c.TJ) * G.nt[2] + c.TK;
-        a.part[(long long)src * a.nslots + DIR * G.ntiles + tile_id] = dsum;
-        if (last) a.part2[(long long)src * a.nslots + tile_id] = asum;
+        a.part[(long long)src * a.nslots + DIR * G.ntiles + c.slot] = dsum;
+        if (last) a.part2[(long long)src * a.nslots + c.slot] = asum;
     }
 }
 
@@ -1154,7 +1181,7 @@ void launch_fwd_init(const Plan& P, const SweepArgs& a, const double* tau_init, 
     hipLaunchKernelGGL(k_solve_init, dim3(fill_blocks(P.G.N), P.nsrc), dim3(256), 0, st, a, tau_init, 1.0, 1.0);
 }
 
-static size_t tile_lds_bytes(const Geo& G) { return sizeof(double) * kTC * kTC * (size_t)(G.tk + 2); }
+static size_t tile_lds_bytes(const Geo& G) { return sizeof(double) * kTC * kTC * (size_t)tile_pitch(G.tk); }
 
 // Event pair around the tile-plane launches of one directional sweep when
 // timing is on; the launch count of the group is recorded with it.
@@ -1179,7 +1206,7 @@ struct TimedLaunch {
 };
 
 // Sweep kernels are instantiated per coordinate system and direction.
-typedef void (*SweepFn)(SweepArgs, int);
+typedef void (*SweepFn)(SweepArgs, int, int);
 
 template <int COORD, int... DS>
 constexpr SweepFn pick_fwd(int d, std::integer_sequence<int, DS...>) {
@@ -1209,7 +1236,8 @@ void launch_fwd_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
         TimedLaunch tl(P, st, P.nplanes);
         const SweepFn fn = fwd_sweep_fn(P.G.coord, d);
         for (int p = 0; p < P.nplanes; ++p)
-            hipLaunchKernelGGL(fn, dim3(P.nsrc, P.plane_count[p]), dim3(64), tile_lds_bytes(P.G), st, a, p);
+            hipLaunchKernelGGL(fn, dim3(P.nsrc, P.plane_count[p]), dim3(64), tile_lds_bytes(P.G), st, a,
+                               P.plane_id[p], P.plane_s0[p]);
         }
         hipLaunchKernelGGL(k_fwd_bnd, dim3(P.nbblocks, P.nsrc), dim3(kBndThreads), 0, st, a, d);
     }
@@ -1241,7 +1269,8 @@ void launch_adj_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
         TimedLaunch tl(P, st, P.nplanes);
         const SweepFn fn = adj_sweep_fn(P.G.coord, d);
         for (int p = 0; p < P.nplanes; ++p)
-            hipLaunchKernelGGL(fn, dim3(P.nsrc, P.plane_count[p]), dim3(64), tile_lds_bytes(P.G), st, a, p);
+            hipLaunchKernelGGL(fn, dim3(P.nsrc, P.plane_count[p]), dim3(64), tile_lds_bytes(P.G), st, a,
+                               P.plane_id[p], P.plane_s0[p]);
         }
         if (P.continuous) {
             hipLaunchKernelGGL(k_cadj_bnd_calc, dim3(P.nbblocks, P.nsrc), dim3(kBndThreads), 0, st, a, P.bnd_in);
