@@ -1,8 +1,8 @@
 """Autotuner for the sweep tile depth (tile_k) of the forward and adjoint solves.
 
 For a grid and source count it times a few iterations of each solve for every
-candidate tile depth (summed device time of the sweep-kernel launches, from the
-library's per-launch HIP events) and keeps the fastest.  Any tile depth gives
+candidate tile depth (the whole call, with the library's default source groups
+running concurrently, as in production) and keeps the fastest.  Any tile depth gives
 bit-identical results, so the choice affects speed only.  Choices are cached in
 a JSON file keyed by (kind, coordinates, grid shape, source count); the file is
 ``$TT_TUNE_CACHE`` or ``~/.cache/paper_2412_00031_amd/tiles.json``.
@@ -49,23 +49,28 @@ def _store(d):
         pass
 
 
-def _time_fwd(grid, s, xi, eta, src, par, kappa, tk, iters):
-    api.sweep_timing(0, reset=True)
-    api.forward(grid, s, xi, eta, src, par, 1e-300, iters, kappa, tile_k=tk, time_sweeps=True)
+# Each candidate is timed as the solves run in production: the whole call
+# (sweeps, boundary passes, convergence checks) with the library's default
+# source groups running concurrently, over a fixed iteration count.
+def _elapsed_ms(fn):
     torch.cuda.synchronize()
-    ms, n = api.sweep_timing(0, reset=True)
-    return ms
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def _time_fwd(grid, s, xi, eta, src, par, kappa, tk, iters):
+    return _elapsed_ms(lambda: api.forward(grid, s, xi, eta, src, par, 1e-300, iters, kappa, tile_k=tk))
 
 
 def _time_adj(grid, s, xi, eta, src, par, tau, rec, R, kappa, tk, iters):
-    api.sweep_timing(1, reset=True)
-    api.adjoint(grid, s, xi, eta, src, par, tau, rec, R, 1e-300, iters, kappa, tile_k=tk, time_sweeps=True)
-    torch.cuda.synchronize()
-    ms, n = api.sweep_timing(1, reset=True)
-    return ms
+    return _elapsed_ms(lambda: api.adjoint(grid, s, xi, eta, src, par, tau, rec, R, 1e-300, iters, kappa, tile_k=tk))
 
 
-def tune(grid, s, xi, eta, src, par, kappa, rec, R, iters=2, candidates=CANDIDATES, use_cache=True, log=None):
+def tune(grid, s, xi, eta, src, par, kappa, rec, R, iters=3, candidates=CANDIDATES, use_cache=True, log=None):
     """Return {"fwd": tile_k, "adj": tile_k} for this grid and batch size."""
     nsrc = int(src.shape[0])
     cache = _load() if use_cache else {}
