@@ -121,13 +121,16 @@ def test_small_spherical_several_tiles(torch_cuda):
 
 
 def test_tile_shapes_bitwise(torch_cuda):
-    """Any tile shape visits the same dependencies: results are bit-identical."""
-    wl = W.small_spherical(n=(21, 19, 23), nsrc=2, seed=11)
-    ref = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=62)
-    for tk in (1, 3, 5, 8, 21, 32):
-        gp = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=tk)
-        for key in ("tau", "lam", "grad", "it_f", "it_a", "T"):
-            assert np.array_equal(gp[key], ref[key]), (tk, key)
+    """Any tile depth visits the same dependencies: results are bit-identical.
+    The grids have ragged 8 x 8 tile columns (interior 19, 17, 21 and 27, 3, 2)
+    and slab depths below, near and above the hyperplane extent of a column."""
+    for n, seed in (((21, 19, 23), 11), ((29, 5, 4), 12)):
+        wl = W.small_spherical(n=n, nsrc=2, seed=seed)
+        ref = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=62)
+        for tk in (1, 2, 3, 5, 7, 8, 13, 21, 32, 48):
+            gp = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=tk)
+            for key in ("tau", "lam", "grad", "it_f", "it_a", "T"):
+                assert np.array_equal(gp[key], ref[key]), (n, tk, key)
 
 
 def test_graph_replay_matches_eager(torch_cuda):
