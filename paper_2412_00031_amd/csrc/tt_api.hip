@@ -128,10 +128,10 @@ tt::Geo make_geo(const tt_grid* g, int tk) {
 // Workspace layout (each region 256-byte aligned):
 //   Src[nsrc] | tab0[n0] | tab1[n1] | tab2[n2] | active[nsrc] | iter[nsrc] | counter |
 //   part[nsrc*nslots] | model[2*S*4] (forward) | part2[nsrc*nslots] (adjoint) |
-//   coef[nsrc*2*S*8] (adjoint) | bnd_in[nsrc*NB] (adjoint)
+//   coef[nsrc*2*S*7] (adjoint) | diag[nsrc*N] (adjoint) | bnd_in, bnd_rhs[nsrc*NB] (adjoint)
 struct Layout {
     size_t off_src, off_t0, off_t1, off_t2, off_active, off_iter, off_counter, off_part, off_part2, off_coef,
-        off_bnd, off_model, total;
+        off_diag, off_bnd, off_model, total;
 };
 
 Layout layout(const tt::Geo& G, int nsrc, int nslots, int which) {
@@ -147,6 +147,7 @@ Layout layout(const tt::Geo& G, int nsrc, int nslots, int which) {
     L.off_part = o;
     L.off_part2 = o;
     L.off_coef = o;
+    L.off_diag = o;
     L.off_bnd = o;
     L.off_model = o;
     if (which == 0 || which == 1) {
@@ -157,7 +158,8 @@ Layout layout(const tt::Geo& G, int nsrc, int nslots, int which) {
     }
     if (which == 1) {
         L.off_part2 = o; o = align_up(o + sizeof(double) * (size_t)nsrc * nslots);
-        L.off_coef = o; o = align_up(o + sizeof(double) * 8 * 2 * (size_t)nsrc * (size_t)G.S);
+        L.off_coef = o; o = align_up(o + sizeof(double) * 7 * 2 * (size_t)nsrc * (size_t)G.S);
+        L.off_diag = o; o = align_up(o + sizeof(double) * (size_t)nsrc * (size_t)G.N);
         L.off_bnd = o; o = align_up(o + sizeof(double) * 2 * (size_t)nsrc * (size_t)G.NB);  // bnd_in, bnd_rhs
     }
     L.total = o;
@@ -236,6 +238,7 @@ void bind_workspace(tt::Plan& P, void* ws, const Layout& L) {
     P.part = reinterpret_cast<double*>(b + L.off_part);
     P.part2 = reinterpret_cast<double*>(b + L.off_part2);
     P.coef = reinterpret_cast<double*>(b + L.off_coef);
+    P.diag = reinterpret_cast<double*>(b + L.off_diag);
     P.bnd_in = reinterpret_cast<double*>(b + L.off_bnd);
     P.bnd_rhs = P.bnd_in + (size_t)P.nsrc * (size_t)P.G.NB;
     P.model = reinterpret_cast<double*>(b + L.off_model);

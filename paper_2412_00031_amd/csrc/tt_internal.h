@@ -237,7 +237,8 @@ struct Plan {
     int* counter = nullptr;
     double* part = nullptr;
     double* part2 = nullptr;
-    double* coef = nullptr;   // adjoint: [nsrc][2][S][8] (row-coalesced layouts)
+    double* coef = nullptr;   // adjoint: [nsrc][2][S][7] (row-coalesced layouts)
+    double* diag = nullptr;   // adjoint: diagonal of each node's row [nsrc][N]
     double* model = nullptr;  // forward: [2][S][4] = (s, xi, eta, 0) (row-coalesced layouts)
     double* bnd_in = nullptr; // adjoint: [nsrc][NB] (continuous adjoint: boundary pass scratch)
     double* bnd_rhs = nullptr; // adjoint: right-hand side of the boundary nodes, [nsrc][NB]
@@ -257,7 +258,7 @@ struct SweepArgs {
     const double *s, *xi, *eta;
     const Src* src;
     double* field;          // tau or lambda [nsrc][N]
-    const double* coef;     // adjoint coefficients [nsrc][2][S][8]
+    const double* coef;     // adjoint coefficients [nsrc][2][S][7]
     const double* model;    // forward model records [2][S][4]
     const double* bnd_in;   // adjoint face couplings [nsrc][NB]
     const double* bnd_rhs;  // adjoint right-hand side of the boundary nodes [nsrc][NB]

@@ -628,15 +628,38 @@ __device__ __forceinline__ double row_off(const Geo& G, const Col& c, const Loc&
     return dirn > 0 ? alpha - beta : -alpha - beta;
 }
 
+constexpr int kRec = 7;  // doubles per adjoint record
+
+// store a node's row {c+_0, c-_0, c+_1, c-_1, c+_2, c-_2, diag, 0} divided by
+// its diagonal into both layouts, and the diagonal into diag_all (a zero
+// diagonal, no row, leaves the zero record)
+__device__ __forceinline__ void store_record(const Geo& G, double* __restrict__ coef_all, double* __restrict__ diag_all,
+                                             int src, long long x, int i, int j, int k, const double (&out)[8]) {
+    const double d = out[6];
+    double rec[kRec];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) rec[q] = d != 0.0 ? out[q] / d : 0.0;
+    rec[6] = 0.0;
+    diag_all[(long long)src * G.N + x] = d;
+    for (int f = 0; f < 2; ++f) {
+        double* cf = coef_all + (((long long)src * 2 + f) * G.S + skew_idx(G, f, i, j, k)) * kRec;
+#pragma unroll
+        for (int q = 0; q < kRec; ++q) cf[q] = rec[q];
+    }
+}
+
 // Coefficients of the transposed system at every node of every source, stored
-// in both row-coalesced layouts: record {in+_0, in-_0, in+_1, in-_1, in+_2,
-// in-_2, J_xx, rhs} with
-// in+-_a = J_{x +- e_a, x}, the coefficient of lambda(x +- e_a) in the column
-// equation of x (zero unless x is interior and not fixed); bnd_in[b] = J_{x, b}
-// for each face node b and its interior neighbour x (zero when x is fixed).
+// in both row-coalesced layouts as the column equation of x divided by its
+// diagonal J_xx: record {in+_0, in-_0, in+_1, in-_1, in+_2, in-_2, rhs} / J_xx
+// (kRec doubles; rhs added by k_adj_rhs), with in+-_a = J_{x +- e_a, x}, the
+// coefficient of lambda(x +- e_a) (zero unless x is interior and not fixed).
+// J_xx itself goes to diag [nsrc][N] (0 where there is no row).  bnd_in[b] =
+// J_{x, b} for each face node b and its interior neighbour x (zero when x is
+// fixed).
 template <int COORD>
 __global__ void __launch_bounds__(256) k_adj_coef(SweepArgs a, const double* __restrict__ tau_all,
-                                                  double* __restrict__ coef_all, double* __restrict__ bnd_all) {
+                                                  double* __restrict__ coef_all, double* __restrict__ bnd_all,
+                                                  double* __restrict__ diag_all) {
     const Geo& G = a.G;
     const int src = blockIdx.y;
     const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -678,24 +701,21 @@ __global__ void __launch_bounds__(256) k_adj_coef(SweepArgs a, const double* __r
             }
         }
     }
-    for (int f = 0; f < 2; ++f) {
-        double2* cf = reinterpret_cast<double2*>(coef_all + (((long long)src * 2 + f) * G.S + skew_idx(G, f, i, j, k)) * 8);
-#pragma unroll
-        for (int q2 = 0; q2 < 4; ++q2) cf[q2] = make_double2(out[2 * q2], out[2 * q2 + 1]);
-    }
+    store_record(G, coef_all, diag_all, src, x, i, j, k, out);
 }
 
 // d chi / d tau = sum_m R_m w_c T0(c) (discrete adjoint), or the point sources
 // sum_m R_m w_c of Eq. (5) (continuous adjoint, with_t0 = 0), added in receiver
 // order (one thread per source: deterministic)
 template <int COORD>
-__global__ void k_adj_rhs(SweepArgs a, double* __restrict__ coef_all, int nrec, const double* __restrict__ rec,
-                          const double* __restrict__ R, int with_t0) {
+__global__ void k_adj_rhs(SweepArgs a, double* __restrict__ coef_all, const double* __restrict__ diag_all, int nrec,
+                          const double* __restrict__ rec, const double* __restrict__ R, int with_t0) {
     const int src = blockIdx.x * blockDim.x + threadIdx.x;
     if (src >= a.nsrc) return;
     const Geo& G = a.G;
     const Src S = a.src[src];
-    double* cf = coef_all + (long long)src * 2 * G.S * 8;
+    double* cf = coef_all + (long long)src * 2 * G.S * kRec;
+    const double* dg = diag_all + (long long)src * G.N;
     double* brhs = const_cast<double*>(a.bnd_rhs) + (long long)src * G.NB;
     for (int m = 0; m < nrec; ++m) {
         const Tri t = tri_of(G, rec[3 * m], rec[3 * m + 1], rec[3 * m + 2]);
@@ -709,8 +729,12 @@ __global__ void k_adj_rhs(SweepArgs a, double* __restrict__ coef_all, int nrec, 
                     double T0, tt[3];
                     factor<COORD>(S, c, t2.x, t2.y, T0, tt);
                     const double v = with_t0 ? r * tri_w(t, c0, c1, c2) * T0 : r * tri_w(t, c0, c1, c2);
-                    cf[skew_idx(G, 0, i, j, k) * 8 + 7] += v;
-                    cf[(G.S + skew_idx(G, 1, i, j, k)) * 8 + 7] += v;
+                    // records hold their row divided by its diagonal (a row-less node's
+                    // record is never read by the sweeps)
+                    const double d = dg[nidx(G, i, j, k)];
+                    const double vd = d != 0.0 ? v / d : v;
+                    cf[skew_idx(G, 0, i, j, k) * kRec + 6] += vd;
+                    cf[(G.S + skew_idx(G, 1, i, j, k)) * kRec + 6] += vd;
                     if (on_bnd(G, 0, i) || on_bnd(G, 1, j) || on_bnd(G, 2, k))
                         brhs[bnd_encode(G, i, j, k)] += v;
                 }
@@ -718,20 +742,16 @@ __global__ void k_adj_rhs(SweepArgs a, double* __restrict__ coef_all, int nrec, 
 }
 
 struct AdjSlot {
-    double r[8];  // coefficient record of the node at k'
+    double r[kRec];  // coefficient record of the node at k'
 };
 
 template <int DIR>
 __device__ __forceinline__ void adj_fetch(const TileCtx& c, const double* __restrict__ cf, int kmax, int t,
                                           AdjSlot& r) {
     const int kp = min(max(c.kp0 + t, 0), kmax - 1);
-    const double2* rc = reinterpret_cast<const double2*>(cf + (c.rbase + c.rstep * kp) * 8LL);
+    const double* rc = cf + (c.rbase + c.rstep * kp) * (long long)kRec;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const double2 v = rc[q];
-        r.r[2 * q] = v.x;
-        r.r[2 * q + 1] = v.y;
-    }
+    for (int q = 0; q < kRec; ++q) r.r[q] = rc[q];
 }
 
 template <int COORD, int DIR>
@@ -752,7 +772,7 @@ __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane, int s0
         return;
     }
     double* __restrict__ fld = a.field + (long long)src * G.N;
-    const double* __restrict__ cf = a.coef + ((long long)src * 2 + D::fam) * G.S * 8;
+    const double* __restrict__ cf = a.coef + ((long long)src * 2 + D::fam) * G.S * kRec;
     const int Lp = tile_pitch(G.tk);
     const int kmax = G.m[2];
 
@@ -780,17 +800,19 @@ __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane, int s0
                         const double up_i = lds[o - kTC * Lp], dn_i = lds[o + kTC * Lp + 2];
                         const double up_j = lds[o - Lp], dn_j = lds[o + Lp + 2];
                         const double up_k = lds[o], dn_k = lds[o + 2];
-                        const double m0 = D::s0 > 0 ? up_i : dn_i, p0 = D::s0 > 0 ? dn_i : up_i;
-                        const double m1 = D::s1 > 0 ? up_j : dn_j, p1 = D::s1 > 0 ? dn_j : up_j;
-                        const double m2 = D::s2 > 0 ? up_k : dn_k, p2 = D::s2 > 0 ? dn_k : up_k;
-                        double acc = r.r[7];
-                        acc -= r.r[0] * p0;
-                        acc -= r.r[1] * m0;
-                        acc -= r.r[2] * p1;
-                        acc -= r.r[3] * m1;
-                        acc -= r.r[4] * p2;
-                        acc -= r.r[5] * m2;
-                        const double nv = acc / r.r[6];
+                        // record: coefficients of lambda(x + e_a), lambda(x - e_a) at 2a, 2a + 1
+                        // and the right-hand side at 6, all divided by the diagonal.  The
+                        // sweep-downstream terms (values of the previous sweep) go first, the
+                        // upstream ones (updated on the previous step) last.
+                        constexpr int di = D::s0 > 0 ? 0 : 1, dj = D::s1 > 0 ? 2 : 3, dk = D::s2 > 0 ? 4 : 5;
+                        double acc = r.r[6];
+                        acc -= r.r[di] * dn_i;
+                        acc -= r.r[dj] * dn_j;
+                        acc -= r.r[dk] * dn_k;
+                        acc -= r.r[di ^ 1] * up_i;
+                        acc -= r.r[dj ^ 1] * up_j;
+                        acc -= r.r[dk ^ 1] * up_k;
+                        const double nv = acc;
                         lds[o + 1] = nv;
                         dsum += fabs(nv - cur);
                         if (last) asum += fabs(nv);
@@ -946,13 +968,14 @@ __device__ __forceinline__ double cadj_area(const Geo& G, int a, int i, int j, i
     return A;
 }
 
-// Records of the continuous system in the adjoint layout {c+_0, c-_0, c+_1,
-// c-_1, c+_2, c-_2, outflow, rhs}: c+-_a = A min(u_out, 0) couples P(x +- e_a)
-// (0 when that node is fixed or outside), outflow = sum A max(u_out, 0).  A
-// node without outflow gets outflow = inf, so that its update is P = 0.
+// Records of the continuous system in the adjoint layout (the row divided by
+// its diagonal, store_record): c+-_a = A min(u_out, 0) couples P(x +- e_a)
+// (0 when that node is fixed or outside), and the diagonal is the outflow
+// sum A max(u_out, 0).  A node without outflow gets outflow = inf, so that its
+// update is P = 0.
 template <int COORD>
 __global__ void __launch_bounds__(256) k_cadj_coef(SweepArgs a, const double* __restrict__ tau_all,
-                                                   double* __restrict__ coef_all) {
+                                                   double* __restrict__ coef_all, double* __restrict__ diag_all) {
     const Geo& G = a.G;
     const int src = blockIdx.y;
     const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -992,11 +1015,7 @@ __global__ void __launch_bounds__(256) k_cadj_coef(SweepArgs a, const double* __
         }
         out[6] = diag > 0.0 ? diag : HUGE_VAL;
     }
-    for (int f = 0; f < 2; ++f) {
-        double2* cf = reinterpret_cast<double2*>(coef_all + (((long long)src * 2 + f) * G.S + skew_idx(G, f, i, j, k)) * 8);
-#pragma unroll
-        for (int q2 = 0; q2 < 4; ++q2) cf[q2] = make_double2(out[2 * q2], out[2 * q2 + 1]);
-    }
+    store_record(G, coef_all, diag_all, src, x, i, j, k, out);
 }
 
 // Boundary pass of the continuous system, Jacobi: every boundary node's new P
@@ -1009,21 +1028,21 @@ __global__ void __launch_bounds__(kBndThreads) k_cadj_bnd_calc(SweepArgs a, doub
     if (b >= G.NB) return;
     const Src S = a.src[src];
     const double* P = a.field + (long long)src * G.N;
-    const double* cf = a.coef + (long long)src * 2 * G.S * 8;
+    const double* cf = a.coef + (long long)src * 2 * G.S * kRec;
     int i, j, k;
     bnd_decode(G, b, i, j, k);
     double nv = 0.0;
     if (!in_fixed(S, i, j, k)) {
-        const double* r = cf + skew_idx(G, 0, i, j, k) * 8;
+        const double* r = cf + skew_idx(G, 0, i, j, k) * kRec;  // the row divided by its diagonal
         const long long x = nidx(G, i, j, k);
         const int id[3] = {i, j, k};
         const long long st[3] = {G.si, G.sj, 1};
-        double acc = r[7];
+        double acc = r[6];
         for (int ax = 0; ax < 3; ++ax) {
             if (r[2 * ax] != 0.0 && id[ax] + 1 < G.n[ax]) acc -= r[2 * ax] * P[x + st[ax]];
             if (r[2 * ax + 1] != 0.0 && id[ax] > 0) acc -= r[2 * ax + 1] * P[x - st[ax]];
         }
-        nv = acc / r[6];
+        nv = acc;
     }
     tmp_all[(long long)src * G.NB + b] = nv;
 }
@@ -1252,13 +1271,13 @@ void launch_adj_init(const Plan& P, const SweepArgs& a, const double* tau, int n
     const dim3 rgrid(blocks_for(P.nsrc, 64));
     const int t0 = P.continuous ? 0 : 1;
     if (P.G.coord == 1) {
-        if (P.continuous) hipLaunchKernelGGL(k_cadj_coef<1>, grid, dim3(256), 0, st, a, tau, P.coef);
-        else hipLaunchKernelGGL(k_adj_coef<1>, grid, dim3(256), 0, st, a, tau, P.coef, P.bnd_in);
-        hipLaunchKernelGGL(k_adj_rhs<1>, rgrid, dim3(64), 0, st, a, P.coef, nrec, rec, R, t0);
+        if (P.continuous) hipLaunchKernelGGL(k_cadj_coef<1>, grid, dim3(256), 0, st, a, tau, P.coef, P.diag);
+        else hipLaunchKernelGGL(k_adj_coef<1>, grid, dim3(256), 0, st, a, tau, P.coef, P.bnd_in, P.diag);
+        hipLaunchKernelGGL(k_adj_rhs<1>, rgrid, dim3(64), 0, st, a, P.coef, P.diag, nrec, rec, R, t0);
     } else {
-        if (P.continuous) hipLaunchKernelGGL(k_cadj_coef<0>, grid, dim3(256), 0, st, a, tau, P.coef);
-        else hipLaunchKernelGGL(k_adj_coef<0>, grid, dim3(256), 0, st, a, tau, P.coef, P.bnd_in);
-        hipLaunchKernelGGL(k_adj_rhs<0>, rgrid, dim3(64), 0, st, a, P.coef, nrec, rec, R, t0);
+        if (P.continuous) hipLaunchKernelGGL(k_cadj_coef<0>, grid, dim3(256), 0, st, a, tau, P.coef, P.diag);
+        else hipLaunchKernelGGL(k_adj_coef<0>, grid, dim3(256), 0, st, a, tau, P.coef, P.bnd_in, P.diag);
+        hipLaunchKernelGGL(k_adj_rhs<0>, rgrid, dim3(64), 0, st, a, P.coef, P.diag, nrec, rec, R, t0);
     }
     hipLaunchKernelGGL(k_solve_init, dim3(fill_blocks(P.G.N), P.nsrc), dim3(256), 0, st, a, nullptr, 0.0, 0.0);
 }
