@@ -475,7 +475,7 @@ def main():
         upd_f = float(rf["it_f"].sum()) * 8 * nodes
         upd_a = float(rf["it_a"].sum()) * 8 * nodes
         bytes_f = upd_f * (16.0 + 24.0 / nsrc)
-        bytes_a = upd_a * (16.0 + 56.0 + 24.0 / nsrc)
+        bytes_a = upd_a * (16.0 + 48.0 + 24.0 / nsrc)
         kern = {
             "k_fwd_sweep": dict(ms=ms_f, launches=n_f, bytes=bytes_f, updates=upd_f),
             "k_adj_sweep": dict(ms=ms_a, launches=n_a, bytes=bytes_a, updates=upd_a),

@@ -122,16 +122,22 @@ tt::Geo make_geo(const tt_grid* g, int tk) {
     G.NB = G.N - (long long)G.m[0] * G.m[1] * G.m[2];
     G.W = G.n[1] + G.n[2] - 1;
     G.S = (long long)G.n[0] * G.W * G.n[1];
+    // adjoint layouts: a tile row's 8 records start on a multiple of 8 records
+    // (three 128-byte lines of 48-byte records) for either sign of the j sweep
+    G.n1p = (G.n[1] + 7 + 7) / 8 * 8;
+    G.joff[0] = 7;
+    G.joff[1] = ((9 - G.n[1]) % 8 + 8) % 8;
+    G.Sa = (long long)G.n[0] * G.W * G.n1p;
     return G;
 }
 
 // Workspace layout (each region 256-byte aligned):
 //   Src[nsrc] | tab0[n0] | tab1[n1] | tab2[n2] | active[nsrc] | iter[nsrc] | counter |
 //   part[nsrc*nslots] | model[2*S*4] (forward) | part2[nsrc*nslots] (adjoint) |
-//   coef[nsrc*2*S*7] (adjoint) | diag[nsrc*N] (adjoint) | bnd_in, bnd_rhs[nsrc*NB] (adjoint)
+//   coef[nsrc*4*Sa*6] | diag[nsrc*N] | rhs[nsrc*N] | box[nsrc*6] | bnd_in, bnd_rhs[nsrc*NB] (adjoint)
 struct Layout {
     size_t off_src, off_t0, off_t1, off_t2, off_active, off_iter, off_counter, off_part, off_part2, off_coef,
-        off_diag, off_bnd, off_model, total;
+        off_diag, off_rhs, off_box, off_bnd, off_model, total;
 };
 
 Layout layout(const tt::Geo& G, int nsrc, int nslots, int which) {
@@ -148,6 +154,8 @@ Layout layout(const tt::Geo& G, int nsrc, int nslots, int which) {
     L.off_part2 = o;
     L.off_coef = o;
     L.off_diag = o;
+    L.off_rhs = o;
+    L.off_box = o;
     L.off_bnd = o;
     L.off_model = o;
     if (which == 0 || which == 1) {
@@ -158,8 +166,10 @@ Layout layout(const tt::Geo& G, int nsrc, int nslots, int which) {
     }
     if (which == 1) {
         L.off_part2 = o; o = align_up(o + sizeof(double) * (size_t)nsrc * nslots);
-        L.off_coef = o; o = align_up(o + sizeof(double) * 7 * 2 * (size_t)nsrc * (size_t)G.S);
+        L.off_coef = o; o = align_up(o + sizeof(double) * 6 * 4 * (size_t)nsrc * (size_t)G.Sa);
         L.off_diag = o; o = align_up(o + sizeof(double) * (size_t)nsrc * (size_t)G.N);
+        L.off_rhs = o; o = align_up(o + sizeof(double) * (size_t)nsrc * (size_t)G.N);
+        L.off_box = o; o = align_up(o + sizeof(int) * 6 * (size_t)nsrc);
         L.off_bnd = o; o = align_up(o + sizeof(double) * 2 * (size_t)nsrc * (size_t)G.NB);  // bnd_in, bnd_rhs
     }
     L.total = o;
@@ -239,6 +249,8 @@ void bind_workspace(tt::Plan& P, void* ws, const Layout& L) {
     P.part2 = reinterpret_cast<double*>(b + L.off_part2);
     P.coef = reinterpret_cast<double*>(b + L.off_coef);
     P.diag = reinterpret_cast<double*>(b + L.off_diag);
+    P.rhs = reinterpret_cast<double*>(b + L.off_rhs);
+    P.box = reinterpret_cast<int*>(b + L.off_box);
     P.bnd_in = reinterpret_cast<double*>(b + L.off_bnd);
     P.bnd_rhs = P.bnd_in + (size_t)P.nsrc * (size_t)P.G.NB;
     P.model = reinterpret_cast<double*>(b + L.off_model);

@@ -39,6 +39,9 @@ struct Geo {
     long long NB;      // boundary nodes
     int W;             // n1 + n2 - 1: width of the row-coalesced layouts
     long long S;       // records per row-coalesced layout: n0 * W * n1
+    int n1p;           // adjoint layouts: row pitch (a multiple of 8 records, >= n1 + 7)
+    int joff[2];       // adjoint layouts: record offset of j in a row for sweeps with s1 > 0, s1 < 0
+    long long Sa;      // records per adjoint layout: n0 * W * n1p
     double o[3], h[3], inv2h[3], invh[3];
 };
 
@@ -237,8 +240,10 @@ struct Plan {
     int* counter = nullptr;
     double* part = nullptr;
     double* part2 = nullptr;
-    double* coef = nullptr;   // adjoint: [nsrc][2][S][7] (row-coalesced layouts)
+    double* coef = nullptr;   // adjoint: [nsrc][4][Sa][6] (line-aligned row-coalesced layouts)
     double* diag = nullptr;   // adjoint: diagonal of each node's row [nsrc][N]
+    double* rhs = nullptr;    // adjoint: right-hand side divided by the diagonal [nsrc][N]
+    int* box = nullptr;       // adjoint: index box of each source's nonzero rhs [nsrc][6]
     double* model = nullptr;  // forward: [2][S][4] = (s, xi, eta, 0) (row-coalesced layouts)
     double* bnd_in = nullptr; // adjoint: [nsrc][NB] (continuous adjoint: boundary pass scratch)
     double* bnd_rhs = nullptr; // adjoint: right-hand side of the boundary nodes, [nsrc][NB]
@@ -258,7 +263,9 @@ struct SweepArgs {
     const double *s, *xi, *eta;
     const Src* src;
     double* field;          // tau or lambda [nsrc][N]
-    const double* coef;     // adjoint coefficients [nsrc][2][S][7]
+    const double* coef;     // adjoint coefficients [nsrc][4][Sa][6]
+    const double* rhs;      // adjoint right-hand side / diagonal [nsrc][N]
+    const int* box;         // [nsrc][6]: i, j, k ranges of the nonzero rhs (empty: lo > hi)
     const double* model;    // forward model records [2][S][4]
     const double* bnd_in;   // adjoint face couplings [nsrc][NB]
     const double* bnd_rhs;  // adjoint right-hand side of the boundary nodes [nsrc][NB]

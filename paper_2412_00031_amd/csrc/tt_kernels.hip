@@ -628,38 +628,52 @@ __device__ __forceinline__ double row_off(const Geo& G, const Col& c, const Loc&
     return dirn > 0 ? alpha - beta : -alpha - beta;
 }
 
-constexpr int kRec = 7;  // doubles per adjoint record
+// Adjoint coefficient layouts.  A record is the six couplings of a node's
+// column equation divided by its diagonal (48 bytes).  Four row-coalesced
+// layouts, lay = 2 fam + (s1 < 0): rows of the record family fam with a pitch
+// of n1p records, and j placed at j + joff[s1 < 0], so that the 8 records a
+// tile row reads on one step are one aligned run of three 128-byte lines for
+// either sign of the j sweep.
+constexpr int kRec = 6;
 
-// store a node's row {c+_0, c-_0, c+_1, c-_1, c+_2, c-_2, diag, 0} divided by
-// its diagonal into both layouts, and the diagonal into diag_all (a zero
-// diagonal, no row, leaves the zero record)
+__device__ __forceinline__ long long arec_idx(const Geo& G, int lay, int i, int j, int k) {
+    const int w = (lay >> 1) == 0 ? j + k : j - k + (G.n[2] - 1);
+    return ((long long)i * G.W + w) * G.n1p + j + G.joff[lay & 1];
+}
+
+// store a node's row {c+_0, c-_0, c+_1, c-_1, c+_2, c-_2, diag, -} divided by
+// its diagonal into the four layouts, the diagonal into diag_all, and a zero
+// right-hand side (k_adj_rhs adds to it); a zero diagonal (no row) stores a
+// zero record
 __device__ __forceinline__ void store_record(const Geo& G, double* __restrict__ coef_all, double* __restrict__ diag_all,
-                                             int src, long long x, int i, int j, int k, const double (&out)[8]) {
+                                             double* __restrict__ rhs_all, int src, long long x, int i, int j, int k,
+                                             const double (&out)[8]) {
     const double d = out[6];
-    double rec[kRec];
+    double2 rec[3];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) rec[q] = d != 0.0 ? out[q] / d : 0.0;
-    rec[6] = 0.0;
+    for (int q = 0; q < 3; ++q)
+        rec[q] = d != 0.0 ? make_double2(out[2 * q] / d, out[2 * q + 1] / d) : make_double2(0.0, 0.0);
     diag_all[(long long)src * G.N + x] = d;
-    for (int f = 0; f < 2; ++f) {
-        double* cf = coef_all + (((long long)src * 2 + f) * G.S + skew_idx(G, f, i, j, k)) * kRec;
+    rhs_all[(long long)src * G.N + x] = 0.0;
+    for (int lay = 0; lay < 4; ++lay) {
+        double2* cf = reinterpret_cast<double2*>(coef_all + (((long long)src * 4 + lay) * G.Sa + arec_idx(G, lay, i, j, k)) * kRec);
 #pragma unroll
-        for (int q = 0; q < kRec; ++q) cf[q] = rec[q];
+        for (int q = 0; q < 3; ++q) cf[q] = rec[q];
     }
 }
 
 // Coefficients of the transposed system at every node of every source, stored
-// in both row-coalesced layouts as the column equation of x divided by its
-// diagonal J_xx: record {in+_0, in-_0, in+_1, in-_1, in+_2, in-_2, rhs} / J_xx
-// (kRec doubles; rhs added by k_adj_rhs), with in+-_a = J_{x +- e_a, x}, the
-// coefficient of lambda(x +- e_a) (zero unless x is interior and not fixed).
-// J_xx itself goes to diag [nsrc][N] (0 where there is no row).  bnd_in[b] =
-// J_{x, b} for each face node b and its interior neighbour x (zero when x is
-// fixed).
+// in the adjoint layouts as the column equation of x divided by its diagonal
+// J_xx: record {in+_0, in-_0, in+_1, in-_1, in+_2, in-_2} / J_xx, with
+// in+-_a = J_{x +- e_a, x}, the coefficient of lambda(x +- e_a) (zero unless x
+// is interior and not fixed).  J_xx goes to diag [nsrc][N] (0 where there is
+// no row); the right-hand side, divided likewise, is added to rhs [nsrc][N] by
+// k_adj_rhs.  bnd_in[b] = J_{x, b} for each face node b and its interior
+// neighbour x (zero when x is fixed).
 template <int COORD>
 __global__ void __launch_bounds__(256) k_adj_coef(SweepArgs a, const double* __restrict__ tau_all,
                                                   double* __restrict__ coef_all, double* __restrict__ bnd_all,
-                                                  double* __restrict__ diag_all) {
+                                                  double* __restrict__ diag_all, double* __restrict__ rhs_all) {
     const Geo& G = a.G;
     const int src = blockIdx.y;
     const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -701,21 +715,23 @@ __global__ void __launch_bounds__(256) k_adj_coef(SweepArgs a, const double* __r
             }
         }
     }
-    store_record(G, coef_all, diag_all, src, x, i, j, k, out);
+    store_record(G, coef_all, diag_all, rhs_all, src, x, i, j, k, out);
 }
 
 // d chi / d tau = sum_m R_m w_c T0(c) (discrete adjoint), or the point sources
 // sum_m R_m w_c of Eq. (5) (continuous adjoint, with_t0 = 0), added in receiver
 // order (one thread per source: deterministic)
 template <int COORD>
-__global__ void k_adj_rhs(SweepArgs a, double* __restrict__ coef_all, const double* __restrict__ diag_all, int nrec,
-                          const double* __restrict__ rec, const double* __restrict__ R, int with_t0) {
+__global__ void k_adj_rhs(SweepArgs a, const double* __restrict__ diag_all, double* __restrict__ rhs_all,
+                          int* __restrict__ box_all, int nrec, const double* __restrict__ rec,
+                          const double* __restrict__ R, int with_t0) {
     const int src = blockIdx.x * blockDim.x + threadIdx.x;
     if (src >= a.nsrc) return;
     const Geo& G = a.G;
     const Src S = a.src[src];
-    double* cf = coef_all + (long long)src * 2 * G.S * kRec;
     const double* dg = diag_all + (long long)src * G.N;
+    double* rh = rhs_all + (long long)src * G.N;
+    int lo[3] = {G.n[0], G.n[1], G.n[2]}, hi[3] = {-1, -1, -1};
     double* brhs = const_cast<double*>(a.bnd_rhs) + (long long)src * G.NB;
     for (int m = 0; m < nrec; ++m) {
         const Tri t = tri_of(G, rec[3 * m], rec[3 * m + 1], rec[3 * m + 2]);
@@ -729,56 +745,81 @@ __global__ void k_adj_rhs(SweepArgs a, double* __restrict__ coef_all, const doub
                     double T0, tt[3];
                     factor<COORD>(S, c, t2.x, t2.y, T0, tt);
                     const double v = with_t0 ? r * tri_w(t, c0, c1, c2) * T0 : r * tri_w(t, c0, c1, c2);
-                    // records hold their row divided by its diagonal (a row-less node's
-                    // record is never read by the sweeps)
-                    const double d = dg[nidx(G, i, j, k)];
-                    const double vd = d != 0.0 ? v / d : v;
-                    cf[skew_idx(G, 0, i, j, k) * kRec + 6] += vd;
-                    cf[(G.S + skew_idx(G, 1, i, j, k)) * kRec + 6] += vd;
+                    // divided by the row's diagonal like the records (a row-less node's
+                    // value is never read by the sweeps)
+                    const long long xn = nidx(G, i, j, k);
+                    const double d = dg[xn];
+                    rh[xn] += d != 0.0 ? v / d : v;
+                    const int id[3] = {i, j, k};
+                    for (int ax = 0; ax < 3; ++ax) {
+                        lo[ax] = min(lo[ax], id[ax]);
+                        hi[ax] = max(hi[ax], id[ax]);
+                    }
                     if (on_bnd(G, 0, i) || on_bnd(G, 1, j) || on_bnd(G, 2, k))
                         brhs[bnd_encode(G, i, j, k)] += v;
                 }
     }
+    for (int ax = 0; ax < 3; ++ax) {
+        box_all[src * 6 + 2 * ax] = lo[ax];
+        box_all[src * 6 + 2 * ax + 1] = hi[ax];
+    }
 }
 
+// a step's record (and, in tiles that meet the source's right-hand side, its
+// right-hand side value), fetched kPreAdj steps ahead
 struct AdjSlot {
-    double r[kRec];  // coefficient record of the node at k'
+    double r[kRec];
+    double b;
 };
 
-template <int DIR>
-__device__ __forceinline__ void adj_fetch(const TileCtx& c, const double* __restrict__ cf, int kmax, int t,
-                                          AdjSlot& r) {
+template <int DIR, bool RHS>
+__device__ __forceinline__ void adj_fetch(const TileCtx& c, const double* __restrict__ cf, int abase, int astep,
+                                          const double* __restrict__ rh, long long xb, int kmax, int t, AdjSlot& r) {
+    using D = Dir<DIR>;
     const int kp = min(max(c.kp0 + t, 0), kmax - 1);
-    const double* rc = cf + (c.rbase + c.rstep * kp) * (long long)kRec;
+    const double2* rc = reinterpret_cast<const double2*>(cf + (abase + astep * kp) * (long long)kRec);
 #pragma unroll
-    for (int q = 0; q < kRec; ++q) r.r[q] = rc[q];
+    for (int q = 0; q < 3; ++q) {
+        const double2 v = rc[q];
+        r.r[2 * q] = v.x;
+        r.r[2 * q + 1] = v.y;
+    }
+    r.b = RHS ? rh[xb + D::s2 * kp] : 0.0;
 }
 
-template <int COORD, int DIR>
-__global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane, int s0) {
+// does the tile (its columns, and the k' range of its slab) meet the index box
+// of the source's nonzero right-hand side?
+template <int DIR>
+__device__ __forceinline__ bool tile_meets_box(const Geo& G, const TileCtx& c, const int* bx) {
     using D = Dir<DIR>;
-    extern __shared__ double lds[];
-    const int src = blockIdx.x;
-    if (!a.active[src]) return;
+    const int i0 = 8 * c.TI, i1 = 8 * c.TI + c.ext_i - 1, j0 = 8 * c.TJ, j1 = 8 * c.TJ + c.ext_j - 1;
+    const int kq0 = max(0, c.TK * G.tk - i1 - j1), kq1 = min(G.m[2] - 1, c.TK * G.tk + G.tk - 1 - i0 - j0);
+    const int ia = D::s0 > 0 ? 1 + i0 : G.n[0] - 2 - i1, ib = D::s0 > 0 ? 1 + i1 : G.n[0] - 2 - i0;
+    const int ja = D::s1 > 0 ? 1 + j0 : G.n[1] - 2 - j1, jb = D::s1 > 0 ? 1 + j1 : G.n[1] - 2 - j0;
+    const int ka = D::s2 > 0 ? 1 + kq0 : G.n[2] - 2 - kq1, kb = D::s2 > 0 ? 1 + kq1 : G.n[2] - 2 - kq0;
+    return ia <= bx[1] && ib >= bx[0] && ja <= bx[3] && jb >= bx[2] && ka <= bx[5] && kb >= bx[4] && kq0 <= kq1;
+}
+
+template <int DIR, bool RHS>
+__device__ __forceinline__ void adj_tile(const SweepArgs& a, const Src& S, const TileCtx& c, int src, double* lds) {
+    using D = Dir<DIR>;
     const Geo& G = a.G;
-    const Src S = a.src[src];
-    const TileCtx c = tile_ctx<DIR>(G, S, plane, s0);
     constexpr bool last = (DIR == 7);
-    if (c.t1 <= c.t0) {  // a ragged column's slab with no nodes
-        if (c.lane == 0) {
-            a.part[(long long)src * a.nslots + DIR * G.ntiles + c.slot] = 0.0;
-            if (last) a.part2[(long long)src * a.nslots + c.slot] = 0.0;
-        }
-        return;
-    }
     double* __restrict__ fld = a.field + (long long)src * G.N;
-    const double* __restrict__ cf = a.coef + ((long long)src * 2 + D::fam) * G.S * kRec;
+    constexpr int lay = 2 * D::fam + (D::s1 > 0 ? 0 : 1);
+    const double* __restrict__ cf = a.coef + ((long long)src * 4 + lay) * G.Sa * kRec;
+    // this lane's record at k' = 0; the row moves by s1 (n1p records) per k'
+    const int w0 = D::fam == 0 ? c.j + c.kbase : c.j - c.kbase + G.n[2] - 1;
+    const int abase = (c.i * G.W + w0) * G.n1p + c.j + G.joff[D::s1 > 0 ? 0 : 1];
+    const int astep = D::s1 * G.n1p;
+    const double* __restrict__ rh = a.rhs + (long long)src * G.N;
+    const long long xb = nidx(G, c.i, c.j, c.kbase);
     const int Lp = tile_pitch(G.tk);
     const int kmax = G.m[2];
 
     AdjSlot ring[kPreAdj];
 #pragma unroll
-    for (int u = 0; u < kPreAdj; ++u) adj_fetch<DIR>(c, cf, kmax, c.t0 + u, ring[u]);
+    for (int u = 0; u < kPreAdj; ++u) adj_fetch<DIR, RHS>(c, cf, abase, astep, rh, xb, kmax, c.t0 + u, ring[u]);
     stage_tile_incr<DIR>(G, c, fld, lds, Lp);
     __syncthreads();
 
@@ -800,12 +841,12 @@ __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane, int s0
                         const double up_i = lds[o - kTC * Lp], dn_i = lds[o + kTC * Lp + 2];
                         const double up_j = lds[o - Lp], dn_j = lds[o + Lp + 2];
                         const double up_k = lds[o], dn_k = lds[o + 2];
-                        // record: coefficients of lambda(x + e_a), lambda(x - e_a) at 2a, 2a + 1
-                        // and the right-hand side at 6, all divided by the diagonal.  The
+                        // record: coefficients of lambda(x + e_a), lambda(x - e_a) at 2a, 2a + 1,
+                        // divided by the diagonal like the right-hand side.  The
                         // sweep-downstream terms (values of the previous sweep) go first, the
                         // upstream ones (updated on the previous step) last.
                         constexpr int di = D::s0 > 0 ? 0 : 1, dj = D::s1 > 0 ? 2 : 3, dk = D::s2 > 0 ? 4 : 5;
-                        double acc = r.r[6];
+                        double acc = r.b;
                         acc -= r.r[di] * dn_i;
                         acc -= r.r[dj] * dn_j;
                         acc -= r.r[dk] * dn_k;
@@ -818,7 +859,7 @@ __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane, int s0
                         if (last) asum += fabs(nv);
                     }
                 }
-                adj_fetch<DIR>(c, cf, kmax, t + kPreAdj, r);
+                adj_fetch<DIR, RHS>(c, cf, abase, astep, rh, xb, kmax, t + kPreAdj, r);
             }
         }
     }
@@ -832,9 +873,28 @@ __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane, int s0
     }
 }
 
+template <int COORD, int DIR>
+__global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane, int s0) {
+    extern __shared__ double lds[];
+    const int src = blockIdx.x;
+    if (!a.active[src]) return;
+    const Geo& G = a.G;
+    const Src S = a.src[src];
+    const TileCtx c = tile_ctx<DIR>(G, S, plane, s0);
+    if (c.t1 <= c.t0) {  // a ragged column's slab with no nodes
+        if (c.lane == 0) {
+            a.part[(long long)src * a.nslots + DIR * G.ntiles + c.slot] = 0.0;
+            if (DIR == 7) a.part2[(long long)src * a.nslots + c.slot] = 0.0;
+        }
+        return;
+    }
+    // wave-uniform: only tiles that meet the right-hand side read it
+    if (tile_meets_box<DIR>(G, c, a.box + src * 6)) adj_tile<DIR, true>(a, S, c, src, lds);
+    else adj_tile<DIR, false>(a, S, c, src, lds);
+}
+
 // Transposed boundary pass: lambda_b = rhs_b - sum_{rows r != b} J_{r, b} lambda_r,
-// rhs_b read from the compact per-boundary-node copy (bnd_rhs) rather than from
-// the 64-byte record.
+// rhs_b read from the compact per-boundary-node copy (bnd_rhs).
 // The rows that reference a boundary node b are its interior neighbour (face
 // nodes only, coefficient bnd_in[b]) and boundary rows b' that copy b along an
 // axis a' above a*(b) (b' one step outward along a', coefficient -1);
@@ -975,7 +1035,8 @@ __device__ __forceinline__ double cadj_area(const Geo& G, int a, int i, int j, i
 // update is P = 0.
 template <int COORD>
 __global__ void __launch_bounds__(256) k_cadj_coef(SweepArgs a, const double* __restrict__ tau_all,
-                                                   double* __restrict__ coef_all, double* __restrict__ diag_all) {
+                                                   double* __restrict__ coef_all, double* __restrict__ diag_all,
+                                                   double* __restrict__ rhs_all) {
     const Geo& G = a.G;
     const int src = blockIdx.y;
     const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1015,7 +1076,7 @@ __global__ void __launch_bounds__(256) k_cadj_coef(SweepArgs a, const double* __
         }
         out[6] = diag > 0.0 ? diag : HUGE_VAL;
     }
-    store_record(G, coef_all, diag_all, src, x, i, j, k, out);
+    store_record(G, coef_all, diag_all, rhs_all, src, x, i, j, k, out);
 }
 
 // Boundary pass of the continuous system, Jacobi: every boundary node's new P
@@ -1028,16 +1089,16 @@ __global__ void __launch_bounds__(kBndThreads) k_cadj_bnd_calc(SweepArgs a, doub
     if (b >= G.NB) return;
     const Src S = a.src[src];
     const double* P = a.field + (long long)src * G.N;
-    const double* cf = a.coef + (long long)src * 2 * G.S * kRec;
+    const double* cf = a.coef + (long long)src * 4 * G.Sa * kRec;  // layout 0
     int i, j, k;
     bnd_decode(G, b, i, j, k);
     double nv = 0.0;
     if (!in_fixed(S, i, j, k)) {
-        const double* r = cf + skew_idx(G, 0, i, j, k) * kRec;  // the row divided by its diagonal
+        const double* r = cf + arec_idx(G, 0, i, j, k) * kRec;  // the row divided by its diagonal
         const long long x = nidx(G, i, j, k);
         const int id[3] = {i, j, k};
         const long long st[3] = {G.si, G.sj, 1};
-        double acc = r[6];
+        double acc = a.rhs[(long long)src * G.N + nidx(G, i, j, k)];
         for (int ax = 0; ax < 3; ++ax) {
             if (r[2 * ax] != 0.0 && id[ax] + 1 < G.n[ax]) acc -= r[2 * ax] * P[x + st[ax]];
             if (r[2 * ax + 1] != 0.0 && id[ax] > 0) acc -= r[2 * ax + 1] * P[x - st[ax]];
@@ -1158,6 +1219,8 @@ SweepArgs make_args(const Plan& P, const double* s, const double* xi, const doub
     a.src = P.src;
     a.field = field;
     a.coef = P.coef;
+    a.rhs = P.rhs;
+    a.box = P.box;
     a.model = P.model;
     a.bnd_in = P.bnd_in;
     a.bnd_rhs = P.bnd_rhs;
@@ -1271,13 +1334,13 @@ void launch_adj_init(const Plan& P, const SweepArgs& a, const double* tau, int n
     const dim3 rgrid(blocks_for(P.nsrc, 64));
     const int t0 = P.continuous ? 0 : 1;
     if (P.G.coord == 1) {
-        if (P.continuous) hipLaunchKernelGGL(k_cadj_coef<1>, grid, dim3(256), 0, st, a, tau, P.coef, P.diag);
-        else hipLaunchKernelGGL(k_adj_coef<1>, grid, dim3(256), 0, st, a, tau, P.coef, P.bnd_in, P.diag);
-        hipLaunchKernelGGL(k_adj_rhs<1>, rgrid, dim3(64), 0, st, a, P.coef, P.diag, nrec, rec, R, t0);
+        if (P.continuous) hipLaunchKernelGGL(k_cadj_coef<1>, grid, dim3(256), 0, st, a, tau, P.coef, P.diag, P.rhs);
+        else hipLaunchKernelGGL(k_adj_coef<1>, grid, dim3(256), 0, st, a, tau, P.coef, P.bnd_in, P.diag, P.rhs);
+        hipLaunchKernelGGL(k_adj_rhs<1>, rgrid, dim3(64), 0, st, a, P.diag, P.rhs, P.box, nrec, rec, R, t0);
     } else {
-        if (P.continuous) hipLaunchKernelGGL(k_cadj_coef<0>, grid, dim3(256), 0, st, a, tau, P.coef, P.diag);
-        else hipLaunchKernelGGL(k_adj_coef<0>, grid, dim3(256), 0, st, a, tau, P.coef, P.bnd_in, P.diag);
-        hipLaunchKernelGGL(k_adj_rhs<0>, rgrid, dim3(64), 0, st, a, P.coef, P.diag, nrec, rec, R, t0);
+        if (P.continuous) hipLaunchKernelGGL(k_cadj_coef<0>, grid, dim3(256), 0, st, a, tau, P.coef, P.diag, P.rhs);
+        else hipLaunchKernelGGL(k_adj_coef<0>, grid, dim3(256), 0, st, a, tau, P.coef, P.bnd_in, P.diag, P.rhs);
+        hipLaunchKernelGGL(k_adj_rhs<0>, rgrid, dim3(64), 0, st, a, P.diag, P.rhs, P.box, nrec, rec, R, t0);
     }
     hipLaunchKernelGGL(k_solve_init, dim3(fill_blocks(P.G.N), P.nsrc), dim3(256), 0, st, a, nullptr, 0.0, 0.0);
 }
