@@ -2,7 +2,9 @@
 
 For a grid and source count it times a few iterations of each solve for every
 candidate tile depth (the whole call, with the library's default source groups
-running concurrently, as in production) and keeps the fastest.  Any tile depth gives
+running concurrently, as in production), on the whole batch and on a quarter of
+it (the convergence tail of a solve runs with few sources left), and keeps the
+fastest sum.  Any tile depth gives
 bit-identical results, so the choice affects speed only.  Choices are cached in
 a JSON file keyed by (kind, coordinates, grid shape, source count); the file is
 ``$TT_TUNE_CACHE`` or ``~/.cache/paper_2412_00031_amd/tiles.json``.
@@ -80,12 +82,19 @@ def tune(grid, s, xi, eta, src, par, kappa, rec, R, iters=3, candidates=CANDIDAT
     m2 = int(grid["n"][2]) - 2
     cands = sorted({min(c, m2, 62) for c in candidates})
     tau, _ = api.forward(grid, s, xi, eta, src, par, 1e-300, iters, kappa)
+    # a solve runs most iterations with the whole batch active and ends with a
+    # tail in which a few sources are left: each candidate is timed on the whole
+    # batch and on its first quarter, and the two times are added
+    nq = max(1, nsrc // 4)
+    parts = [(src, par, tau, R)] + ([(src[:nq], par[:nq], tau[:nq], R[:nq])] if nq < nsrc else [])
     res = {}
     for kind in ("fwd", "adj"):
         best, best_ms, times = None, None, {}
         for tk in cands:
-            ms = min((_time_fwd(grid, s, xi, eta, src, par, kappa, tk, iters) if kind == "fwd" else
-                      _time_adj(grid, s, xi, eta, src, par, tau, rec, R, kappa, tk, iters)) for _ in range(2))
+            ms = 0.0
+            for (sp, pp, tp, rp) in parts:
+                ms += min((_time_fwd(grid, s, xi, eta, sp, pp, kappa, tk, iters) if kind == "fwd" else
+                           _time_adj(grid, s, xi, eta, sp, pp, tp, rec, rp, kappa, tk, iters)) for _ in range(2))
             times[tk] = round(ms, 3)
             if best_ms is None or ms < best_ms:
                 best, best_ms = tk, ms
