@@ -121,7 +121,6 @@ tt::Geo make_geo(const tt_grid* g, int tk) {
     G.sj = G.n[2];
     G.NB = G.N - (long long)G.m[0] * G.m[1] * G.m[2];
     G.W = G.n[1] + G.n[2] - 1;
-    G.S = (long long)G.n[0] * G.W * G.n[1];
     // adjoint layouts: a tile row's 8 records start on a multiple of 8 records
     // (three 128-byte lines of 48-byte records) for either sign of the j sweep
     G.n1p = (G.n[1] + 7 + 7) / 8 * 8;
@@ -133,7 +132,7 @@ tt::Geo make_geo(const tt_grid* g, int tk) {
 
 // Workspace layout (each region 256-byte aligned):
 //   Src[nsrc] | tab0[n0] | tab1[n1] | tab2[n2] | active[nsrc] | iter[nsrc] | counter |
-//   part[nsrc*nslots] | model[2*S*4] (forward) | part2[nsrc*nslots] (adjoint) |
+//   part[nsrc*nslots] | model[4*Sa*4] (forward) | part2[nsrc*nslots] (adjoint) |
 //   coef[nsrc*4*Sa*6] | diag[nsrc*N] | rhs[nsrc*N] | box[nsrc*6] | bnd_in, bnd_rhs[nsrc*NB] (adjoint)
 struct Layout {
     size_t off_src, off_t0, off_t1, off_t2, off_active, off_iter, off_counter, off_part, off_part2, off_coef,
@@ -162,7 +161,7 @@ Layout layout(const tt::Geo& G, int nsrc, int nslots, int which) {
         L.off_part = o; o = align_up(o + sizeof(double) * (size_t)nsrc * nslots);
     }
     if (which == 0) {
-        L.off_model = o; o = align_up(o + sizeof(double) * 4 * 2 * (size_t)G.S);
+        L.off_model = o; o = align_up(o + sizeof(double) * 4 * 4 * (size_t)G.Sa);
     }
     if (which == 1) {
         L.off_part2 = o; o = align_up(o + sizeof(double) * (size_t)nsrc * nslots);

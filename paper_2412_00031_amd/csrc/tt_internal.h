@@ -38,10 +38,9 @@ struct Geo {
     long long si, sj;  // strides of axes 0 and 1 (axis 2 has stride 1)
     long long NB;      // boundary nodes
     int W;             // n1 + n2 - 1: width of the row-coalesced layouts
-    long long S;       // records per row-coalesced layout: n0 * W * n1
-    int n1p;           // adjoint layouts: row pitch (a multiple of 8 records, >= n1 + 7)
-    int joff[2];       // adjoint layouts: record offset of j in a row for sweeps with s1 > 0, s1 < 0
-    long long Sa;      // records per adjoint layout: n0 * W * n1p
+    int n1p;           // aligned layouts: row pitch (a multiple of 8 records, >= n1 + 7)
+    int joff[2];       // aligned layouts: record offset of j in a row for sweeps with s1 > 0, s1 < 0
+    long long Sa;      // records per aligned layout: n0 * W * n1p
     double o[3], h[3], inv2h[3], invh[3];
 };
 
@@ -244,7 +243,7 @@ struct Plan {
     double* diag = nullptr;   // adjoint: diagonal of each node's row [nsrc][N]
     double* rhs = nullptr;    // adjoint: right-hand side divided by the diagonal [nsrc][N]
     int* box = nullptr;       // adjoint: index box of each source's nonzero rhs [nsrc][6]
-    double* model = nullptr;  // forward: [2][S][4] = (s, xi, eta, 0) (row-coalesced layouts)
+    double* model = nullptr;  // forward: [4][Sa][4] = (s, xi, eta, 0) (aligned row-coalesced layouts)
     double* bnd_in = nullptr; // adjoint: [nsrc][NB] (continuous adjoint: boundary pass scratch)
     double* bnd_rhs = nullptr; // adjoint: right-hand side of the boundary nodes, [nsrc][NB]
     bool continuous = false;  // adjoint: upwind discretisation of Eq. (5) instead of the exact transpose
@@ -266,7 +265,7 @@ struct SweepArgs {
     const double* coef;     // adjoint coefficients [nsrc][4][Sa][6]
     const double* rhs;      // adjoint right-hand side / diagonal [nsrc][N]
     const int* box;         // [nsrc][6]: i, j, k ranges of the nonzero rhs (empty: lo > hi)
-    const double* model;    // forward model records [2][S][4]
+    const double* model;    // forward model records [4][Sa][4]
     const double* bnd_in;   // adjoint face couplings [nsrc][NB]
     const double* bnd_rhs;  // adjoint right-hand side of the boundary nodes [nsrc][NB]
     int* active;

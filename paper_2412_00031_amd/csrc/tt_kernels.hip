@@ -78,12 +78,16 @@ __device__ __forceinline__ bool on_bnd(const Geo& G, int a, int idx) { return id
 
 // Row-coalesced record layouts.  On a sweep hyperplane the 8 lanes of one
 // tile row (fixed i, consecutive j) satisfy j + rho k = const with
-// rho = sigma_1 sigma_2, so records stored as [i][w = j + rho k][j] put those 8
-// lanes' records next to each other.  fam 0: rho = +1, fam 1: rho = -1.
-
-__device__ __forceinline__ long long skew_idx(const Geo& G, int fam, int i, int j, int k) {
-    const int w = fam == 0 ? j + k : j - k + (G.n[2] - 1);
-    return ((long long)i * G.W + w) * G.n[1] + j;
+// rho = sigma_1 sigma_2, so records stored by rows [i][w = j + rho k][j] put
+// those 8 lanes' records next to each other (family fam 0: rho = +1, fam 1:
+// rho = -1).  Four layouts, lay = 2 fam + (s1 < 0), give each row a pitch of
+// n1p records and place j at j + joff[s1 < 0], so that the 8 records a tile
+// row reads on one step start on a multiple of 8 records (an aligned run of
+// whole 128-byte lines for 32- and 48-byte records) for either sign of the j
+// sweep.  Used for the model records and the adjoint coefficients.
+__device__ __forceinline__ long long arec_idx(const Geo& G, int lay, int i, int j, int k) {
+    const int w = (lay >> 1) == 0 ? j + k : j - k + (G.n[2] - 1);
+    return ((long long)i * G.W + w) * G.n1p + j + G.joff[lay & 1];
 }
 
 __device__ __forceinline__ int astar_of(const Geo& G, const int p[3]) {
@@ -196,7 +200,8 @@ struct Dir {
     static constexpr int s0 = (DIR & 4) ? -1 : 1;
     static constexpr int s1 = (DIR & 2) ? -1 : 1;
     static constexpr int s2 = (DIR & 1) ? -1 : 1;
-    static constexpr int fam = ((DIR >> 1) ^ DIR) & 1;  // row-coalesced layout of this sweep
+    static constexpr int fam = ((DIR >> 1) ^ DIR) & 1;  // row-coalesced layout family of this sweep
+    static constexpr int lay = 2 * fam + (s1 > 0 ? 0 : 1);  // its aligned layout
 };
 
 struct TileCtx {
@@ -233,11 +238,12 @@ __device__ __forceinline__ TileCtx tile_ctx(const Geo& G, const Src& S, int plan
     c.kp0 = U0 - ip - jp;
     c.kq0 = U0 - ucol + 1;
     c.kbase = D::s2 > 0 ? 1 : G.n[2] - 2;
-    // record index ((i W + w) n1 + j) with w = j + k (family 0) or j - k + n2 - 1
-    // (family 1), k = kbase + s2 k': linear in k' with slope s1 n1 in both families
+    // record index ((i W + w) n1p + j + joff) in the aligned layout of this sweep,
+    // w = j + k (family 0) or j - k + n2 - 1 (family 1), k = kbase + s2 k': linear
+    // in k' with slope s1 n1p in both families
     const int w0 = D::fam == 0 ? c.j + c.kbase : c.j - c.kbase + G.n[2] - 1;
-    c.rbase = (c.i * G.W + w0) * G.n[1] + c.j;
-    c.rstep = D::s1 * G.n[1];
+    c.rbase = (c.i * G.W + w0) * G.n1p + c.j + G.joff[D::s1 > 0 ? 0 : 1];
+    c.rstep = D::s1 * G.n1p;
     c.slot = (c.TI * G.nt[1] + c.TJ) * G.nt[2] + (c.TK - col_tile_lo(G, c.TI + c.TJ));
     return c;
 }
@@ -467,7 +473,7 @@ __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane, int s0
     }
     const Col cl = make_col(G, a.T, c.i, c.j);
     double* __restrict__ fld = a.field + (long long)src * G.N;
-    const double* __restrict__ mdl = a.model + (long long)D::fam * G.S * 4;
+    const double* __restrict__ mdl = a.model + (long long)D::lay * G.Sa * 4;
     const double2* __restrict__ t2 = a.T.t2;
     const int Lp = tile_pitch(G.tk);
     const int kmax = G.m[2];
@@ -516,7 +522,7 @@ __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane, int s0
     if (c.lane == 0) a.part[(long long)src * a.nslots + DIR * G.ntiles + c.slot] = eps;
 }
 
-// model records (s, xi, eta, 0) in both row-coalesced layouts
+// model records (s, xi, eta, 0) in the four aligned layouts
 __global__ void k_model_records(Geo G, const double* __restrict__ s, const double* __restrict__ xi,
                                 const double* __restrict__ eta, double* __restrict__ out) {
     const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -525,8 +531,8 @@ __global__ void k_model_records(Geo G, const double* __restrict__ s, const doubl
     const long long q = x / G.n[2];
     const int j = (int)(q % G.n[1]), i = (int)(q / G.n[1]);
     const double2 v0 = make_double2(s[x], xi[x]), v1 = make_double2(eta[x], 0.0);
-    for (int f = 0; f < 2; ++f) {
-        double2* o = reinterpret_cast<double2*>(out + ((long long)f * G.S + skew_idx(G, f, i, j, k)) * 4);
+    for (int lay = 0; lay < 4; ++lay) {
+        double2* o = reinterpret_cast<double2*>(out + ((long long)lay * G.Sa + arec_idx(G, lay, i, j, k)) * 4);
         o[0] = v0;
         o[1] = v1;
     }
@@ -628,18 +634,9 @@ __device__ __forceinline__ double row_off(const Geo& G, const Col& c, const Loc&
     return dirn > 0 ? alpha - beta : -alpha - beta;
 }
 
-// Adjoint coefficient layouts.  A record is the six couplings of a node's
-// column equation divided by its diagonal (48 bytes).  Four row-coalesced
-// layouts, lay = 2 fam + (s1 < 0): rows of the record family fam with a pitch
-// of n1p records, and j placed at j + joff[s1 < 0], so that the 8 records a
-// tile row reads on one step are one aligned run of three 128-byte lines for
-// either sign of the j sweep.
+// Adjoint coefficient records: the six couplings of a node's column equation
+// divided by its diagonal (48 bytes), in the four aligned layouts.
 constexpr int kRec = 6;
-
-__device__ __forceinline__ long long arec_idx(const Geo& G, int lay, int i, int j, int k) {
-    const int w = (lay >> 1) == 0 ? j + k : j - k + (G.n[2] - 1);
-    return ((long long)i * G.W + w) * G.n1p + j + G.joff[lay & 1];
-}
 
 // store a node's row {c+_0, c-_0, c+_1, c-_1, c+_2, c-_2, diag, -} divided by
 // its diagonal into the four layouts, the diagonal into diag_all, and a zero
@@ -773,11 +770,11 @@ struct AdjSlot {
 };
 
 template <int DIR, bool RHS>
-__device__ __forceinline__ void adj_fetch(const TileCtx& c, const double* __restrict__ cf, int abase, int astep,
+__device__ __forceinline__ void adj_fetch(const TileCtx& c, const double* __restrict__ cf,
                                           const double* __restrict__ rh, long long xb, int kmax, int t, AdjSlot& r) {
     using D = Dir<DIR>;
     const int kp = min(max(c.kp0 + t, 0), kmax - 1);
-    const double2* rc = reinterpret_cast<const double2*>(cf + (abase + astep * kp) * (long long)kRec);
+    const double2* rc = reinterpret_cast<const double2*>(cf + (c.rbase + c.rstep * kp) * (long long)kRec);
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         const double2 v = rc[q];
@@ -806,12 +803,7 @@ __device__ __forceinline__ void adj_tile(const SweepArgs& a, const Src& S, const
     const Geo& G = a.G;
     constexpr bool last = (DIR == 7);
     double* __restrict__ fld = a.field + (long long)src * G.N;
-    constexpr int lay = 2 * D::fam + (D::s1 > 0 ? 0 : 1);
-    const double* __restrict__ cf = a.coef + ((long long)src * 4 + lay) * G.Sa * kRec;
-    // this lane's record at k' = 0; the row moves by s1 (n1p records) per k'
-    const int w0 = D::fam == 0 ? c.j + c.kbase : c.j - c.kbase + G.n[2] - 1;
-    const int abase = (c.i * G.W + w0) * G.n1p + c.j + G.joff[D::s1 > 0 ? 0 : 1];
-    const int astep = D::s1 * G.n1p;
+    const double* __restrict__ cf = a.coef + ((long long)src * 4 + D::lay) * G.Sa * kRec;
     const double* __restrict__ rh = a.rhs + (long long)src * G.N;
     const long long xb = nidx(G, c.i, c.j, c.kbase);
     const int Lp = tile_pitch(G.tk);
@@ -819,7 +811,7 @@ __device__ __forceinline__ void adj_tile(const SweepArgs& a, const Src& S, const
 
     AdjSlot ring[kPreAdj];
 #pragma unroll
-    for (int u = 0; u < kPreAdj; ++u) adj_fetch<DIR, RHS>(c, cf, abase, astep, rh, xb, kmax, c.t0 + u, ring[u]);
+    for (int u = 0; u < kPreAdj; ++u) adj_fetch<DIR, RHS>(c, cf, rh, xb, kmax, c.t0 + u, ring[u]);
     stage_tile_incr<DIR>(G, c, fld, lds, Lp);
     __syncthreads();
 
@@ -859,7 +851,7 @@ __device__ __forceinline__ void adj_tile(const SweepArgs& a, const Src& S, const
                         if (last) asum += fabs(nv);
                     }
                 }
-                adj_fetch<DIR, RHS>(c, cf, abase, astep, rh, xb, kmax, t + kPreAdj, r);
+                adj_fetch<DIR, RHS>(c, cf, rh, xb, kmax, t + kPreAdj, r);
             }
         }
     }
