@@ -208,6 +208,7 @@ struct TileCtx {
     int TI, TJ, TK, lane, li, lj, ext_i, ext_j;
     int t0, t1;    // wave-uniform walk: steps t0 <= t < t1 (u = TK tk + t)
     int kp0;       // this lane's k' at step 0 (k' = kp0 + t)
+    int kplo, kphi;  // record fetch clamp: this lane's k' range in the tile (a valid k' if empty)
     int kq0;       // staged entry (ci, cj, kk) holds k' = kq0 - ci - cj + kk
     int kbase;     // absolute k = kbase + s2 k'
     bool colv, fcol;
@@ -236,6 +237,11 @@ __device__ __forceinline__ TileCtx tile_ctx(const Geo& G, const Src& S, int plan
     c.t0 = max(0, ucol - U0);
     c.t1 = min(G.tk, ucol + (c.ext_i - 1) + (c.ext_j - 1) + G.m[2] - U0);
     c.kp0 = U0 - ip - jp;
+    // prefetches past the walk re-read the lane's last record of this tile
+    // (a cache hit) instead of the next slab's
+    c.kplo = max(0, c.kp0 + c.t0);
+    c.kphi = min(G.m[2] - 1, c.kp0 + c.t1 - 1);
+    if (c.kplo > c.kphi) c.kplo = c.kphi = min(max(c.kp0 + c.t0, 0), G.m[2] - 1);
     c.kq0 = U0 - ucol + 1;
     c.kbase = D::s2 > 0 ? 1 : G.n[2] - 2;
     // record index ((i W + w) n1p + j + joff) in the aligned layout of this sweep,
@@ -443,11 +449,11 @@ struct FwdSlot {
     double sx, xi, eta, c2, s2;
 };
 
-// unconditional: k' is clamped into the column, so the address is always valid
+// unconditional: k' is clamped into the lane's range in the tile, so the address is always valid
 template <int DIR>
 __device__ __forceinline__ void fwd_fetch(const TileCtx& c, const double* __restrict__ mdl,
-                                          const double2* __restrict__ t2, int kmax, int t, FwdSlot& r) {
-    const int kp = min(max(c.kp0 + t, 0), kmax - 1);
+                                          const double2* __restrict__ t2, int t, FwdSlot& r) {
+    const int kp = min(max(c.kp0 + t, c.kplo), c.kphi);
     const double2* m = reinterpret_cast<const double2*>(mdl + (c.rbase + c.rstep * kp) * 4LL);
     const double2 m0 = m[0], m1 = m[1];
     r.sx = m0.x;
@@ -480,7 +486,7 @@ __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane, int s0
 
     FwdSlot ring[kPre];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) fwd_fetch<DIR>(c, mdl, t2, kmax, c.t0 + u, ring[u]);
+    for (int u = 0; u < kPre; ++u) fwd_fetch<DIR>(c, mdl, t2, c.t0 + u, ring[u]);
     stage_tile_div<DIR>(G, c, fld, lds, Lp);
     __syncthreads();
 
@@ -512,7 +518,7 @@ __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane, int s0
                         eps += fabs(nv - cur);
                     }
                 }
-                fwd_fetch<DIR>(c, mdl, t2, kmax, t + kPre, r);
+                fwd_fetch<DIR>(c, mdl, t2, t + kPre, r);
             }
         }
     }
@@ -771,9 +777,9 @@ struct AdjSlot {
 
 template <int DIR, bool RHS>
 __device__ __forceinline__ void adj_fetch(const TileCtx& c, const double* __restrict__ cf,
-                                          const double* __restrict__ rh, long long xb, int kmax, int t, AdjSlot& r) {
+                                          const double* __restrict__ rh, long long xb, int t, AdjSlot& r) {
     using D = Dir<DIR>;
-    const int kp = min(max(c.kp0 + t, 0), kmax - 1);
+    const int kp = min(max(c.kp0 + t, c.kplo), c.kphi);
     const double2* rc = reinterpret_cast<const double2*>(cf + (c.rbase + c.rstep * kp) * (long long)kRec);
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -811,7 +817,7 @@ __device__ __forceinline__ void adj_tile(const SweepArgs& a, const Src& S, const
 
     AdjSlot ring[kPreAdj];
 #pragma unroll
-    for (int u = 0; u < kPreAdj; ++u) adj_fetch<DIR, RHS>(c, cf, rh, xb, kmax, c.t0 + u, ring[u]);
+    for (int u = 0; u < kPreAdj; ++u) adj_fetch<DIR, RHS>(c, cf, rh, xb, c.t0 + u, ring[u]);
     stage_tile_incr<DIR>(G, c, fld, lds, Lp);
     __syncthreads();
 
@@ -851,7 +857,7 @@ __device__ __forceinline__ void adj_tile(const SweepArgs& a, const Src& S, const
                         if (last) asum += fabs(nv);
                     }
                 }
-                adj_fetch<DIR, RHS>(c, cf, rh, xb, kmax, t + kPreAdj, r);
+                adj_fetch<DIR, RHS>(c, cf, rh, xb, t + kPreAdj, r);
             }
         }
     }
