@@ -16,7 +16,7 @@ import torch
 
 from . import api
 
-CANDIDATES = (8, 12, 16, 20, 24, 32, 40, 48, 62)
+CANDIDATES = (8, 12, 16, 18, 20, 22, 24, 28, 32, 40, 48, 62)
 
 
 def cache_path():
