@@ -471,7 +471,8 @@ def main():
         nodes = interior_nonfixed(g) - 8
         # algorithmic bytes per node update: forward = tau read + write (16 B)
         # plus the model (24 B per node per sweep, shared by the batch);
-        # adjoint = lambda read + write plus the 8 stored coefficients of the node (80 B)
+        # adjoint = lambda read + write plus the node's 6 stored couplings (64 B; the
+        # right-hand side, read only in the tiles at the receivers, is not counted)
         upd_f = float(rf["it_f"].sum()) * 8 * nodes
         upd_a = float(rf["it_a"].sum()) * 8 * nodes
         bytes_f = upd_f * (16.0 + 24.0 / nsrc)
