@@ -77,8 +77,8 @@ __host__ __device__ inline void tile_decode(const Geo& G, int p, int s0, int b, 
     TJ = s - TI;
     TK = p - s;
 }
-// LDS words per staged column: tk + 2 entries, padded to an odd count
-__host__ __device__ inline int tile_pitch(int tk) { return (tk + 2) | 1; }
+// LDS words per staged column: tk + 2 entries
+__host__ __device__ inline int tile_pitch(int tk) { return tk + 2; }
 
 // Per-source constants, produced on the device by k_src_setup.
 struct Src {

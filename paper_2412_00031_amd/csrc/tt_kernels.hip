@@ -255,8 +255,9 @@ __device__ __forceinline__ TileCtx tile_ctx(const Geo& G, const Src& S, int plan
 }
 
 // Staged tile: the (8+2) x (8+2) columns of the tile and its i'/j' halo, each
-// with the entries kk = 0..tk+1, in LDS as [ci][cj][kk] with an odd column
-// pitch (ci = li + 1, cj = lj + 1).  Entry kk of column (ci, cj) is the node
+// with the entries kk = 0..tk+1, in LDS as [ci][cj][kk] (ci = li + 1,
+// cj = lj + 1; column pitch tk + 2: an odd pitch measured no better and costs
+// a tile per CU at some depths).  Entry kk of column (ci, cj) is the node
 // k' = kq0 - ci - cj + kk: the column windows are sheared along the tile's
 // slab, so at step t lane (li, lj) owns entry t + 1 of its column and finds
 // its upstream i'/j'/k' neighbours at entry t and its downstream ones at
