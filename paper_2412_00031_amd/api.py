@@ -79,8 +79,10 @@ def _N(grid):
 def workspace(grid, nsrc, which, tile_k=0, device=None, groups=0, time_sweeps=False):
     """Device workspace (uint8 tensor) for forward (0), adjoint (1), sample (2), kernel (3);
     groups / time_sweeps as for the solve that will use it (its size depends on
-    the number of source groups)."""
+    the number of source groups).  An empty batch needs no workspace: zero bytes."""
     lib = _lib.load()
+    if int(nsrc) == 0:
+        return torch.empty(0, dtype=torch.uint8, device=device)
     g = _grid(grid)
     o = _opts(1e-6, 1, 1.0, tile_k, time_sweeps=time_sweeps, groups=groups)
     nbytes = lib.tt_workspace_size(ctypes.byref(g), int(nsrc), ctypes.byref(o), int(which))

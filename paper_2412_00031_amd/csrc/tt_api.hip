@@ -493,6 +493,7 @@ int tt_sweep_timing(int32_t which, double* total_ms, int64_t* launches, int32_t 
 size_t tt_workspace_size(const tt_grid* grid, int32_t nsrc, const tt_opts* opts, int32_t which) {
     if (check_grid(grid) || nsrc < 1 || which < 0 || which > 3) return 0;
     if (opts && (opts->groups < 0 || opts->groups > TT_MAX_GROUPS)) return 0;
+    if (opts && (opts->tile_k < 0 || opts->tile_k > tt::kMaxTileK)) return 0;
     tt::Geo G = make_geo(grid, tile_k_of(opts, which));
     return grouped_total(G, nsrc, which <= 1 ? groups_of(opts, nsrc) : 1, which);
 }
@@ -635,8 +636,10 @@ int tt_misfit(int32_t nsrc, int32_t nrec, const double* T_rec, const double* T_o
               void* stream) {
     g_err.clear();
     if (nsrc < 0 || nrec < 0 || npair < 0) return fail(TT_EINVAL, "negative count");
-    int rc = check_ptrs({T_rec, T_obs, R, chi});
-    if (rc) return rc;
+    // chi is written even for an empty batch (as 0); the [nsrc][nrec] arrays
+    // are required only when they hold values
+    int rc = check_ptrs({chi});
+    if (rc || (nsrc > 0 && nrec > 0 && (rc = check_ptrs({T_rec, T_obs, R})))) return rc;
     if (npair > 0 && !pairs) return fail(TT_EINVAL, "pairs is NULL with npair > 0");
     if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(TT_EINVAL, "alpha/beta not finite");
     tt::launch_misfit(nsrc, nrec, T_rec, T_obs, w, npair, pairs, wpair, alpha, beta, R, chi, (hipStream_t)stream);
@@ -648,8 +651,8 @@ int tt_misfit_cr(int32_t nsrc, int32_t nrec, const double* T_rec, const double* 
                  const int32_t* cr_pair, const double* wcr, double gamma, double* R, double* chi, void* stream) {
     g_err.clear();
     if (nsrc < 0 || nrec < 0) return fail(TT_EINVAL, "negative count");
-    int rc = check_ptrs({T_rec, T_obs, cr_off, R, chi});
-    if (rc) return rc;
+    int rc = check_ptrs({cr_off, chi});
+    if (rc || (nsrc > 0 && nrec > 0 && (rc = check_ptrs({T_rec, T_obs, R})))) return rc;
     if (!std::isfinite(gamma)) return fail(TT_EINVAL, "gamma not finite");
     if (nrec == 0) return TT_OK;
     tt::launch_misfit_cr(nsrc, nrec, T_rec, T_obs, cr_off, cr_pair, wcr, gamma, R, chi, (hipStream_t)stream);

@@ -79,3 +79,20 @@ def test_mg_workspace_size_host_logic(libpath):
     assert api.mg_workspace_size(g, big) == 0
     assert api.mg_workspace_size(g, [(np.zeros(0), np.zeros(2), np.zeros(2))]) == 0
     assert api.mg_workspace_size(g, [(np.zeros(2), np.zeros(2), np.zeros(2))] * 17) == 0
+
+
+def test_workspace_sizes_host_logic(libpath):
+    """Workspace sizing is host logic: an empty batch needs zero bytes, every
+    non-empty one a positive size that grows with the batch, and a bad tile
+    depth or source count is refused (size 0 -> ValueError in the binding)."""
+    from paper_2412_00031_amd import _lib, api, workloads as W
+    _lib.load(libpath)
+    g = W.spherical_grid(21, 20.0, 2.0)
+    for which in range(4):
+        assert api.workspace(g, 0, which).numel() == 0
+        a, b = api.workspace(g, 1, which).numel(), api.workspace(g, 5, which).numel()
+        assert 0 < a <= b
+    with pytest.raises(ValueError):
+        api.workspace(g, 1, 0, tile_k=63)
+    with pytest.raises(ValueError):
+        api.workspace(g, -1, 1)

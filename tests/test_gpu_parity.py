@@ -415,6 +415,30 @@ def test_minimal_grid_and_cartesian_anisotropic(torch_cuda):
         assert_parity(gp, op)
 
 
+def test_empty_batch_is_a_no_op(torch_cuda):
+    """Zero sources through every step of the path: the solves and sampling
+    return empty results, chi is zero, and the kernels write zeros (or leave an
+    accumulated gradient unchanged)."""
+    from paper_2412_00031_amd import api
+    wl = W.small_spherical(n=(9, 10, 11), nsrc=1, nrec=4, seed=3)
+    g = wl["grid"]
+    s, xi, eta, rec = (_dev(torch_cuda, wl[k]) for k in ("s", "xi", "eta", "rec"))
+    src = torch_cuda.zeros((0, 3), dtype=torch_cuda.float64, device="cuda")
+    par = api.source_params(g, s, xi, eta, src)
+    tau, st = api.forward(g, s, xi, eta, src, par, 1e-8, 50, wl["kappa"])
+    assert tau.shape == (0,) + tuple(g["n"]) and st.numel() == 0
+    T = api.sample(g, src, par, tau, rec)
+    assert T.shape == (0, len(wl["rec"]))
+    chi, R = api.misfit(T, T.clone())
+    assert chi.item() == 0.0 and R.numel() == 0
+    lam, st = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, 1e-8, 50, wl["kappa"])
+    assert lam.shape == tau.shape and st.numel() == 0
+    grad = api.kernel(g, s, xi, eta, src, par, tau, lam)
+    assert torch_cuda.count_nonzero(grad).item() == 0
+    prior = torch_cuda.full_like(grad, 0.25)
+    assert torch_cuda.equal(api.kernel(g, s, xi, eta, src, par, tau, lam, grad=prior.clone()), prior)
+
+
 @pytest.mark.slow
 def test_sph61_two_sources(torch_cuda):
     wl = W.sph61(nsrc=32)
