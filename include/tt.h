@@ -23,6 +23,12 @@
  *     tt_workspace_size(...) bytes for the same arguments; its contents on
  *     entry do not matter and are scratch on exit.  Calls that overlap in
  *     time must not share a workspace.
+ *   - Empty batches: a count of 0 (sources, receivers, events) is valid, and
+ *     the pointers of arrays that then hold no element may be NULL.  The
+ *     call returns TT_OK after writing what its outputs define for no input:
+ *     chi = 0 in tt_misfit, zeros (or an unchanged sum with accumulate) in
+ *     tt_kernel, zeros in tt_reloc_kernel without fields, nothing elsewhere.  tt_workspace_size refuses nsrc = 0 (it
+ *     returns 0); such calls need no workspace.
  *   - Receivers and sources are expected inside the grid; positions outside
  *     are clamped to the nearest cell on the device (the host cannot read
  *     device data without a synchronisation).
