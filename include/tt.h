@@ -27,8 +27,9 @@
  *     the pointers of arrays that then hold no element may be NULL.  The
  *     call returns TT_OK after writing what its outputs define for no input:
  *     chi = 0 in tt_misfit, zeros (or an unchanged sum with accumulate) in
- *     tt_kernel, zeros in tt_reloc_kernel without fields, nothing elsewhere.  tt_workspace_size refuses nsrc = 0 (it
- *     returns 0); such calls need no workspace.
+ *     tt_kernel, zeros in tt_reloc_kernel without fields, nothing
+ *     elsewhere.  tt_workspace_size refuses nsrc = 0 (it returns 0); such
+ *     calls need no workspace.
  *   - Receivers and sources are expected inside the grid; positions outside
  *     are clamped to the nearest cell on the device (the host cannot read
  *     device data without a synchronisation).
@@ -65,7 +66,7 @@ typedef struct tt_opts {
     int32_t max_iter;  /* >= 1 */
     double kappa;      /* Lax-Friedrichs viscosity factor, >= max sqrt(1 + 2|xi|) */
     int32_t tile_k;    /* k-extent of one sweep tile, 1..62; 0 = library default
-                          (16 for tt_forward, 48 for tt_adjoint) */
+                          (16 for tt_forward, 28 for tt_adjoint) */
     int32_t flags;     /* bit 0 (TT_FLAG_TIME_SWEEPS): time the sweep kernels with a HIP
                           event pair around the tile-plane launches of every
                           directional sweep on the call's stream (tt_sweep_timing) */

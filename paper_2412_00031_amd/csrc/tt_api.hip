@@ -41,7 +41,7 @@ using tt::fail;
 // tiles amortise the staging better); measured on the 101^3 spherical batch
 constexpr int kDefaultTileK = 32;
 constexpr int kDefaultTileKFwd = 16;
-constexpr int kDefaultTileKAdj = 48;
+constexpr int kDefaultTileKAdj = 28;
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
