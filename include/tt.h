@@ -14,7 +14,9 @@
  *     fields are [nsrc][N].
  *   - Axes: coord = 0 Cartesian (z depth, y, x; km), coord = 1 spherical
  *     (r km ascending with the first index, latitude rad, longitude rad).
- *     Node (i,j,k) sits at o + (i,j,k) * h.  Every n_a >= 4.
+ *     Node (i,j,k) sits at o + (i,j,k) * h.  Every n_a >= 4 and <= 8192, and
+ *     n0 * (n1 + n2 - 1) * n1p < 2^31 with n1p = n1 + 7 rounded up to a
+ *     multiple of 8 (the solver's per-node records use 32-bit indices).
  *   - Positions (sources, receivers) are [count][3] in the same axis units.
  *   - stream is a hipStream_t (NULL = default stream).  Work is enqueued on it;
  *     tt_forward and tt_adjoint additionally wait on it (they poll convergence

@@ -54,9 +54,11 @@ int check_grid(const tt_grid* g) {
         if (!(g->h[a] > 0.0) || !std::isfinite(g->h[a])) return fail(TT_EINVAL, "grid.h[%d] must be > 0", a);
         if (!std::isfinite(g->o[a])) return fail(TT_EINVAL, "grid.o[%d] not finite", a);
     }
-    // per-node records are addressed with 32-bit indices: n0 (n1 + n2 - 1) n1 < 2^31
-    if ((double)g->n[0] * (g->n[1] + g->n[2] - 1) * g->n[1] >= 2147483647.0)
-        return fail(TT_EINVAL, "grid too large: n0 * (n1 + n2 - 1) * n1 must stay below 2^31");
+    // per-node records are addressed with 32-bit indices within one layout of
+    // n0 (n1 + n2 - 1) n1p records, n1p the row pitch (n1 + 7 rounded up to 8)
+    const double n1p = (double)((g->n[1] + 14) / 8 * 8);
+    if ((double)g->n[0] * (g->n[1] + g->n[2] - 1) * n1p >= 2147483647.0)
+        return fail(TT_EINVAL, "grid too large: n0 * (n1 + n2 - 1) * n1p must stay below 2^31");
     if (g->coord == 1) {
         double rmin = g->o[0];
         if (!(rmin > 0.0)) return fail(TT_EINVAL, "spherical grid needs r > 0");

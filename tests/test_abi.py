@@ -96,3 +96,23 @@ def test_workspace_sizes_host_logic(libpath):
         api.workspace(g, 1, 0, tile_k=63)
     with pytest.raises(ValueError):
         api.workspace(g, -1, 1)
+
+
+def test_grid_size_limit_uses_the_record_pitch(libpath):
+    """Records are addressed with 32-bit indices within one layout of
+    n0 (n1 + n2 - 1) n1p records (n1p = n1 + 7 rounded up to 8), so the grid
+    check bounds that product, not n0 (n1 + n2 - 1) n1: (8192, 31, 8192) has
+    2.09e9 < 2^31 unpadded but 2.69e9 padded records."""
+    import ctypes
+    from paper_2412_00031_amd import _lib, api
+    lib = _lib.load(libpath)
+
+    def size(n):
+        g = dict(n=n, coord=0, o=(0.0, 0.0, 0.0), h=(1.0, 1.0, 1.0))
+        return lib.tt_workspace_size(ctypes.byref(api._grid(g)), 1, None, 0)
+
+    assert size((8192, 31, 8192)) == 0
+    assert size((8192, 20, 8192)) == 0      # 1.35e9 unpadded, 2.15e9 padded (n1p = 32)
+    assert size((8192, 9, 8192)) > 0        # 1.07e9 padded (n1p = 16)
+    assert size((4096, 31, 4096)) > 0
+    assert size((101, 101, 101)) > 0
