@@ -54,16 +54,33 @@ class LibraryMissing(RuntimeError):
     pass
 
 
+_lib_path = None
+_build_id = None
+
+
+def build_id():
+    """Short sha256 of the loaded library file: identifies the build (tile-depth
+    choices measured on one build are not reused for another)."""
+    global _build_id
+    if _build_id is None:
+        import hashlib
+        load()
+        with open(_lib_path, "rb") as f:
+            _build_id = hashlib.sha256(f.read()).hexdigest()[:16]
+    return _build_id
+
+
 def load(path=LIB_PATH):
     """Load libtt.so.  Raises LibraryMissing if it has not been built: there is
     no fallback implementation."""
-    global _lib
+    global _lib, _lib_path
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
         raise LibraryMissing(f"{path} not found: build it with `python -m paper_2412_00031_amd.build`; "
                              "there is no CPU fallback")
     lib = ctypes.CDLL(path)
+    _lib_path = path
     P = ctypes.c_void_p
     G = ctypes.POINTER(TTGrid)
     O = ctypes.POINTER(TTOpts)

@@ -6,7 +6,8 @@ running concurrently, as in production), on the whole batch and on a quarter of
 it (the convergence tail of a solve runs with few sources left), and keeps the
 fastest sum.  Any tile depth gives
 bit-identical results, so the choice affects speed only.  Choices are cached in
-a JSON file keyed by (kind, coordinates, grid shape, source count); the file is
+a JSON file keyed by (kind, coordinates, grid shape, source count, library
+build, device name), so a rebuilt library is tuned afresh; the file is
 ``$TT_TUNE_CACHE`` or ``~/.cache/paper_2412_00031_amd/tiles.json``.
 """
 import json
@@ -14,7 +15,7 @@ import os
 
 import torch
 
-from . import api
+from . import _lib, api
 
 CANDIDATES = (8, 12, 16, 18, 20, 22, 24, 28, 32, 40, 48, 62)
 
@@ -28,7 +29,8 @@ def cache_path():
 
 def _key(kind, grid, nsrc):
     n = "x".join(str(int(v)) for v in grid["n"])
-    return f"{kind}:{int(grid['coord'])}:{n}:{int(nsrc)}"
+    dev = torch.cuda.get_device_name().replace(":", " ") if torch.cuda.is_available() else "none"
+    return f"{kind}:{int(grid['coord'])}:{n}:{int(nsrc)}:{_lib.build_id()}:{dev}"
 
 
 def _load():
