@@ -439,6 +439,48 @@ def test_empty_batch_is_a_no_op(torch_cuda):
     assert torch_cuda.equal(api.kernel(g, s, xi, eta, src, par, tau, lam, grad=prior.clone()), prior)
 
 
+def test_maximum_source_count(torch_cuda):
+    """The largest batch the entry points take (65535 sources: one launch
+    dimension per source) on a minimal spherical grid: forward, sampling and
+    adjoint over the whole batch, checked against the oracle on sampled sources
+    (both ends, and both sides of every boundary between the 4 source groups),
+    iteration counts included; 65536 sources are refused."""
+    from paper_2412_00031_amd import api, _lib
+    wl = W.small_spherical(n=(5, 6, 7), nsrc=1, nrec=6, seed=31)
+    g, kap = wl["grid"], wl["kappa"]
+    rng = np.random.default_rng(32)
+    nmax = 65535
+    lo, span = np.array(g["o"], float), (np.array(g["n"]) - 1) * np.array(g["h"], float)
+    src = lo + rng.uniform(0.05, 0.95, (nmax, 3)) * span
+    R = rng.normal(0.0, 0.1, (nmax, len(wl["rec"])))
+    s, xi, eta, rec = (_dev(torch_cuda, wl[k]) for k in ("s", "xi", "eta", "rec"))
+    srcd = _dev(torch_cuda, src)
+    par = api.source_params(g, s, xi, eta, srcd)
+    tau, st_f = api.forward(g, s, xi, eta, srcd, par, 1e-11, 300, kap)
+    T = api.sample(g, srcd, par, tau, rec)
+    lam, st_a = api.adjoint(g, s, xi, eta, srcd, par, tau, rec, _dev(torch_cuda, R), 1e-11, 300, kap)
+    torch_cuda.cuda.synchronize()
+    sel = [0, 1, 16383, 16384, 32767, 32768, 49151, 49152, nmax - 1]
+    par_o = O.source_params(g, wl["s"], wl["xi"], wl["eta"], src[sel])
+    assert rel_inf(par[sel].cpu().numpy(), par_o) <= 1e-15
+    for n, q in enumerate(sel):
+        tau_o, it, conv, _ = O.forward(g, wl["s"], wl["xi"], wl["eta"], src[q], par_o[n], kap, 1e-11, 300)
+        assert int(st_f[q]) == (it if conv else -it), q
+        assert rel_inf(tau[q].cpu().numpy(), tau_o) <= TOL_TAU, q
+        T_o = O.sample(g, src[q], par_o[n], tau_o, wl["rec"])
+        assert rel_inf(T[q].cpu().numpy(), T_o) <= TOL_TAU, q
+        rhs = O.adjoint_rhs(g, src[q], par_o[n], wl["rec"], R[q])
+        lam_o, it, conv, _ = O.adjoint(g, wl["s"], wl["xi"], wl["eta"], src[q], par_o[n], kap, tau_o, rhs, 1e-11,
+                                       300)
+        assert int(st_a[q]) == (it if conv else -it), q
+        assert rel_inf(lam[q].cpu().numpy(), lam_o) <= TOL_ADJ, q
+    assert (st_f > 0).all() and (st_a > 0).all()
+    del lam, tau
+    one = _dev(torch_cuda, np.concatenate([src, src[:1]]))
+    with pytest.raises(_lib.TTError):
+        api.forward(g, s, xi, eta, one, torch_cuda.cat([par, par[:1]]), 1e-11, 300, kap)
+
+
 @pytest.mark.slow
 def test_sph61_two_sources(torch_cuda):
     wl = W.sph61(nsrc=32)
