@@ -500,9 +500,13 @@ __global__ void __launch_bounds__(256) k_mg_proj_planes(Geo G, MgGrids Q, const 
     for (int e = threadIdx.x; e < S12; e += blockDim.x) out[e] = acc[e];
 }
 
-// Stage 3: one thread per coefficient, contraction over the planes i under its
-// tent (ascending i, j-chunks summed in order), then the 1/H of Eq. (11).  The
-// grid sizes and (CLDS) the inversion coordinates are staged in LDS.
+// Stage 3: kMgFinalLanes lanes per coefficient, contraction over the planes i
+// under its tent (lane l takes the planes ilo + l, ilo + l + kMgFinalLanes, ...
+// in ascending order, j-chunks summed in order), a fixed xor-shuffle tree over
+// the lanes, then the 1/H of Eq. (11).  The grid sizes and (CLDS) the
+// inversion coordinates are staged in LDS.
+constexpr int kMgFinalLanes = 8;
+
 template <bool CLDS>
 __global__ void __launch_bounds__(256) k_mg_proj_final(Geo G, MgGrids Q, const double* __restrict__ coords,
                                                        const double* __restrict__ part, int nch,
@@ -516,8 +520,10 @@ __global__ void __launch_bounds__(256) k_mg_proj_final(Geo G, MgGrids Q, const d
     const double* cb = CLDS ? lds : coords;
     const long long total = Q.outoff[Q.H];
     const int S12 = Q.s12off[Q.H];
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (long long)gridDim.x * blockDim.x) {
+    const int sub = (int)(threadIdx.x % kMgFinalLanes);
+    // the lanes of one coefficient share e, so they leave the loop together
+    for (long long e = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kMgFinalLanes; e < total;
+         e += (long long)gridDim.x * blockDim.x / kMgFinalLanes) {
         int h = 0;
         while (h + 1 < Q.H && e >= QL.outoff[h + 1]) ++h;
         const int m0 = QL.m[h][0], m1 = QL.m[h][1], m2 = QL.m[h][2];
@@ -530,7 +536,7 @@ __global__ void __launch_bounds__(256) k_mg_proj_final(Geo G, MgGrids Q, const d
         mg_range(G, 0, c0, m0, ci, ilo, ihi);
         const long long col = QL.s12off[h] + (long long)cj * m2 + ck;
         double a = 0.0;
-        for (int i = ilo; i <= ihi; ++i) {
+        for (int i = ilo + sub; i <= ihi; i += kMgFinalLanes) {
             const double u = mg_tent(c0, m0, ci, node_coord(G, 0, i));
             if (u == 0.0) continue;
             const double* pi = part + (long long)(i * 3 + p) * nch * S12 + col;
@@ -538,7 +544,9 @@ __global__ void __launch_bounds__(256) k_mg_proj_final(Geo G, MgGrids Q, const d
             for (int c = 0; c < nch; ++c) b += pi[(long long)c * S12];
             a += u * vol_axis(G, 0, i) * b;
         }
-        out[e] = a / Q.H;
+#pragma unroll
+        for (int off = kMgFinalLanes / 2; off >= 1; off >>= 1) a += __shfl_xor(a, off, kMgFinalLanes);
+        if (sub == 0) out[e] = a / Q.H;
     }
 }
 
@@ -721,12 +729,11 @@ void launch_mg_project(const Geo& G, int H, const int* m, const double* coords, 
     if (P.separable) {
         hipLaunchKernelGGL(k_mg_proj_planes, dim3((unsigned)(G.n[0] * 3 * P.nch)), dim3(256), P.lds, st, G, Q,
                            coords, K, ws, P.nch);
+        const dim3 fb(fill_blocks(Q.outoff[H] * kMgFinalLanes));
         if (8LL * Q.ncoord <= kMgCoordLds)
-            hipLaunchKernelGGL(k_mg_proj_final<true>, dim3(fill_blocks(Q.outoff[H])), dim3(256), 8 * Q.ncoord, st,
-                               G, Q, coords, ws, P.nch, out);
+            hipLaunchKernelGGL(k_mg_proj_final<true>, fb, dim3(256), 8 * Q.ncoord, st, G, Q, coords, ws, P.nch, out);
         else
-            hipLaunchKernelGGL(k_mg_proj_final<false>, dim3(fill_blocks(Q.outoff[H])), dim3(256), 0, st, G, Q,
-                               coords, ws, P.nch, out);
+            hipLaunchKernelGGL(k_mg_proj_final<false>, fb, dim3(256), 0, st, G, Q, coords, ws, P.nch, out);
         return;
     }
     // grids too large for the staged form: one wave per inversion node
