@@ -415,6 +415,8 @@ __device__ __forceinline__ double mg_w(const MgTab& t, int c) { return t.i0 == c
 // inversion coordinates, the tent tables of axes 1 and 2 and the k range of
 // every (grid, ck) are built in LDS first.
 constexpr int kMgRows = 8;
+// 8 waves per block share one copy of the tent tables in LDS
+constexpr int kMgPlaneThreads = 512;
 
 // k range and owner of one stage-1 output column
 struct MgCol {
@@ -427,7 +429,7 @@ __device__ __forceinline__ int mg_grid_of(const int* off, int H, int e) {
     return h;
 }
 
-__global__ void __launch_bounds__(256) k_mg_proj_planes(Geo G, MgGrids Q, const double* __restrict__ coords,
+__global__ void __launch_bounds__(kMgPlaneThreads) k_mg_proj_planes(Geo G, MgGrids Q, const double* __restrict__ coords,
                                                         const double* __restrict__ K, double* __restrict__ part,
                                                         int nch) {
     extern __shared__ double lds[];
@@ -727,7 +729,7 @@ void launch_mg_project(const Geo& G, int H, const int* m, const double* coords, 
     const MgGrids Q = make_mg(H, m);
     const MgPlan P = plan_mg_project(G, Q);
     if (P.separable) {
-        hipLaunchKernelGGL(k_mg_proj_planes, dim3((unsigned)(G.n[0] * 3 * P.nch)), dim3(256), P.lds, st, G, Q,
+        hipLaunchKernelGGL(k_mg_proj_planes, dim3((unsigned)(G.n[0] * 3 * P.nch)), dim3(kMgPlaneThreads), P.lds, st, G, Q,
                            coords, K, ws, P.nch);
         const dim3 fb(fill_blocks(Q.outoff[H] * kMgFinalLanes));
         if (8LL * Q.ncoord <= kMgCoordLds)
