@@ -558,7 +558,7 @@ __global__ void __launch_bounds__(256) k_mg_proj_final(Geo G, MgGrids Q, const d
 // in LDS, then each thread forms field(i, j, k) from at most 4 terms of E per
 // grid (tables of the axis-1 and axis-2 tents in LDS), summed over the grids in
 // order and written once.
-__global__ void __launch_bounds__(256) k_mg_expand_planes(Geo G, MgGrids Q, const double* __restrict__ coords,
+__global__ void __launch_bounds__(kMgPlaneThreads) k_mg_expand_planes(Geo G, MgGrids Q, const double* __restrict__ coords,
                                                           const double* __restrict__ C, double* __restrict__ field,
                                                           int nch) {
     extern __shared__ double lds[];
@@ -756,9 +756,10 @@ void launch_mg_expand(const Geo& G, int H, const int* m, const double* coords, c
     const MgGrids Q = make_mg(H, m);
     const long long lds = 8LL * Q.ncoord + (long long)sizeof(MgTab) * H * (G.n[1] + G.n[2]) + 8LL * 3 * Q.s12off[H];
     if (lds <= kMgMaxLds) {
-        const int nch = (int)std::min<long long>(std::max<long long>((1024 + G.n[0] - 1) / G.n[0], 1), G.n[1]);
-        hipLaunchKernelGGL(k_mg_expand_planes, dim3((unsigned)(G.n[0] * nch)), dim3(256), (size_t)lds, st, G, Q,
-                           coords, C, field, nch);
+        // about 512 blocks of 8 waves (three fit a CU's LDS)
+        const int nch = (int)std::min<long long>(std::max<long long>((512 + G.n[0] - 1) / G.n[0], 1), G.n[1]);
+        hipLaunchKernelGGL(k_mg_expand_planes, dim3((unsigned)(G.n[0] * nch)), dim3(kMgPlaneThreads), (size_t)lds, st,
+                           G, Q, coords, C, field, nch);
         return;
     }
     hipLaunchKernelGGL(k_mg_expand, dim3(fill_blocks(G.N)), dim3(256), 0, st, G, Q, coords, C, field);
