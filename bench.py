@@ -240,7 +240,7 @@ def aux_gpu(wl, a, dev, reps=20):
                             64.0 * nev * nfield + 8.0 * nev * nfield, "latency"),
     }
     kernels = {"tt_kernel_density": "k_kernel_density", "tt_mg_project": "k_mg_proj_planes + k_mg_proj_final",
-               "tt_mg_expand": "k_mg_expand", "tt_misfit_cr": "k_misfit_cr_R + k_misfit_cr_chi",
+               "tt_mg_expand": "k_mg_expand_planes", "tt_misfit_cr": "k_misfit_cr_R + k_misfit_cr_chi",
                "tt_reloc_times": "k_reloc_times", "tt_reloc_kernel": "k_reloc_kernel"}
     out = {}
     for name, (fn, nbytes, bound) in calls.items():
