@@ -116,3 +116,16 @@ def test_grid_size_limit_uses_the_record_pitch(libpath):
     assert size((8192, 9, 8192)) > 0        # 1.07e9 padded (n1p = 16)
     assert size((4096, 31, 4096)) > 0
     assert size((101, 101, 101)) > 0
+
+
+def test_tune_cache_key_names_build_and_device(libpath, monkeypatch):
+    """Tile-depth choices are cached per (kind, grid, source count, library
+    build, device): a rebuilt library must not reuse choices measured on
+    another build."""
+    from paper_2412_00031_amd import _lib, autotune, workloads as W
+    _lib.load(libpath)
+    g = W.spherical_grid(21, 20.0, 2.0)
+    k1 = autotune._key("fwd", g, 8)
+    assert _lib.build_id() in k1 and k1 != autotune._key("adj", g, 8) and k1 != autotune._key("fwd", g, 9)
+    monkeypatch.setattr(_lib, "_build_id", "0" * 16)
+    assert autotune._key("fwd", g, 8) != k1
