@@ -239,6 +239,19 @@ def adjoint_cont(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_i
     return P, iters.value, bool(conv.value), hist[: iters.value].copy()
 
 
+def cont_velocity(grid, xi, eta, src_pos, src_par, tau):
+    """The transport velocity w = -M grad T [3, n] of the continuous adjoint
+    (reading R14) for a given tau: central differences of tau on interior
+    axes, one-sided on boundary axes."""
+    n, coord, o, h = _grid_args(grid)
+    w = np.empty((3,) + _shape(grid))
+    rc = lib().tto_cont_velocity(_i(n), coord, _d(o), _d(h), _d(_f64(xi)), _d(_f64(eta)), _d(_f64(src_pos)),
+                                 _d(_f64(src_par)), _d(_f64(tau)), _d(w))
+    if rc:
+        raise ValueError("invalid grid")
+    return w
+
+
 def kernel(grid, s, xi, eta, src_pos, src_par, kappa, tau, lam, grad=None):
     """Discrete gradients [3, n] (d chi/d s, d chi/d xi, d chi/d eta); adds to grad if given."""
     n, coord, o, h = _grid_args(grid)

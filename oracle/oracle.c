@@ -937,6 +937,34 @@ static void grad_T_any(const OGrid* g, const OSrc* S, const double* tau, int i, 
     }
 }
 
+/* w = -M p at every node (the transport velocity of Eq. (5)), stored [3][N] */
+static void velocity_field(const OGrid* g, const OSrc* S, const double* xi, const double* eta, const double* tau,
+                           double* w) {
+    for (int i = 0; i < g->n[0]; ++i)
+        for (int j = 0; j < g->n[1]; ++j)
+            for (int k = 0; k < g->n[2]; ++k) {
+                size_t c = IDX(g, i, j, k);
+                double p[3];
+                grad_T_any(g, S, tau, i, j, k, p);
+                w[c] = -p[0];
+                w[g->N + c] = -((1.0 - 2.0 * xi[c]) * p[1] + 2.0 * eta[c] * p[2]);
+                w[2 * g->N + c] = -(2.0 * eta[c] * p[1] + (1.0 + 2.0 * xi[c]) * p[2]);
+            }
+}
+
+/* The velocity field w [3][N] that tto_adjoint_cont transports P with, for a
+ * given tau (any field, not only a converged one).  Returns -1 on bad input. */
+int tto_cont_velocity(const int* n, int coord, const double* o, const double* h, const double* xi,
+                      const double* eta, const double* src_pos, const double* src_par, const double* tau, double* w) {
+    OGrid g;
+    grid_init(&g, n, coord, o, h);
+    if (check_grid(&g)) return -1;
+    OSrc S;
+    src_init(&S, &g, src_pos, src_par);
+    velocity_field(&g, &S, xi, eta, tau, w);
+    return 0;
+}
+
 /* control-volume extent of node index idx along axis a (coordinate units) */
 static double cv_extent(const OGrid* g, int a, int idx) {
     return (idx == 0 || idx == g->n[a] - 1) ? 0.5 * g->h[a] : g->h[a];
@@ -1032,17 +1060,7 @@ int tto_adjoint_cont(const int* n, int coord, const double* o, const double* h,
     size_t* bl = (size_t*)malloc(sizeof(size_t) * nbnd);
     double* tmp = (double*)malloc(sizeof(double) * nbnd);
     if (!w || !b || !rows || !bl || !tmp) { free(w); free(b); free(rows); free(bl); free(tmp); return -1; }
-    /* w = -M p at every node */
-    for (int i = 0; i < g.n[0]; ++i)
-        for (int j = 0; j < g.n[1]; ++j)
-            for (int k = 0; k < g.n[2]; ++k) {
-                size_t c = IDX(&g, i, j, k);
-                double p[3];
-                grad_T_any(&g, &S, tau, i, j, k, p);
-                w[c] = -p[0];
-                w[g.N + c] = -((1.0 - 2.0 * xi[c]) * p[1] + 2.0 * eta[c] * p[2]);
-                w[2 * g.N + c] = -(2.0 * eta[c] * p[1] + (1.0 + 2.0 * xi[c]) * p[2]);
-            }
+    velocity_field(&g, &S, xi, eta, tau, w);
     for (int m = 0; m < nrec; ++m) {
         size_t ci[8];
         double wt[8];

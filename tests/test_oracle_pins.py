@@ -595,6 +595,194 @@ def test_cont_adjoint_exact_on_grid_line_cartesian(axis):
     assert np.abs(P - expect).max() <= 1e-12 * expect.max()
 
 
+def _test_areas(grid):
+    """Face areas of the trapezoidal control volumes, written from their
+    definition: A[a][side] [n] is the area of the face of each node normal to
+    axis a on the +side (side 0) or -side (side 1), at the midpoint between the
+    node and its neighbour (the node itself on a grid face).  The extents of
+    the other two axes are h, halved for a node on either end of that axis;
+    spherical faces: r_f^2 cos(theta) dtheta dphi (r), r cos(theta_f) dr dphi
+    (theta), r dr dtheta (phi)."""
+    n = tuple(grid["n"])
+    ax = W.axes(grid)
+    h = grid["h"]
+    ext = []
+    for a in range(3):
+        e = np.full(n[a], h[a])
+        e[0] = e[-1] = 0.5 * h[a]
+        ext.append(e)
+    E = np.meshgrid(*ext, indexing="ij")
+    X = np.meshgrid(*ax, indexing="ij")
+    out = []
+    for a in range(3):
+        sides = []
+        for side in (0, 1):
+            sg = 1 if side == 0 else -1
+            xf = X[a].copy()
+            nb = np.take(X[a], np.clip(np.arange(n[a]) + sg, 0, n[a] - 1), axis=a)
+            inside = np.zeros(n, dtype=bool)
+            idx = np.arange(n[a]) + sg
+            ok = (idx >= 0) & (idx < n[a])
+            sl = [None, None, None]
+            sl[a] = slice(None)
+            inside |= np.broadcast_to(ok[tuple(sl)], n)
+            xf = np.where(inside, 0.5 * (X[a] + nb), X[a])
+            A = np.ones(n)
+            for b in range(3):
+                if b != a:
+                    A = A * E[b]
+            if grid["coord"] == 1:
+                if a == 0:
+                    A = A * xf * xf * np.cos(X[1])
+                elif a == 1:
+                    A = A * X[0] * np.cos(xf)
+                else:
+                    A = A * X[0]
+            sides.append(A)
+        out.append(sides)
+    return out
+
+
+@pytest.mark.parametrize("coord", [0, 1])
+def test_cont_velocity_exact_on_linear_tau(coord):
+    """The transport velocity w = -M grad T of the continuous adjoint, for a
+    tau that is linear in the node indices: central and one-sided differences
+    of a linear function are exact, so at EVERY node -- faces, edges and
+    corners included, where the differences are one-sided -- w must equal
+    -M (T0 g_a c_a / h_a + tau t_a) with T0, t the (separately pinned) factor
+    field and g = (1, 1/r, 1/(r cos theta)).  A one-sided difference taken with
+    the wrong sign, or on the wrong side, leaves a boundary-node error of the
+    size of T0 |grad tau|."""
+    rng = np.random.default_rng(31 + coord)
+    if coord == 0:
+        g = dict(n=(7, 8, 9), coord=0, o=(0.0, 0.0, 0.0), h=(0.9, 1.1, 1.3))
+    else:
+        g = W.spherical_grid(8, 10.0, 0.08, n_lat=9, n_lon=7)
+        g["o"] = (g["o"][0], g["o"][1] + 0.9, g["o"][2])   # about 52 degrees latitude
+    n = tuple(g["n"])
+    ax = W.axes(g)
+    xi = rng.uniform(-0.04, 0.04, n)
+    eta = rng.uniform(-0.04, 0.04, n)
+    s = np.full(n, 1.0 / 6.0)
+    src = np.array([ax[0][2] + 0.37 * g["h"][0], ax[1][3] + 0.61 * g["h"][1], ax[2][4] + 0.2 * g["h"][2]])
+    par = O.source_params(g, s, xi, eta, src)[0]
+    c = np.array([0.013, -0.021, 0.017])            # per index step
+    I, J, K = np.meshgrid(*[np.arange(v) for v in n], indexing="ij")
+    tau = 1.0 + c[0] * I + c[1] * J + c[2] * K
+    w = O.cont_velocity(g, xi, eta, src, par, tau)
+    T0, t = O.factor_field(g, src, par)
+    Rr, Th = np.meshgrid(ax[0], ax[1], ax[2], indexing="ij")[:2]
+    gm = [np.ones(n), np.ones(n), np.ones(n)] if coord == 0 else [np.ones(n), 1.0 / Rr, 1.0 / (Rr * np.cos(Th))]
+    p = [T0 * gm[a] * c[a] / g["h"][a] + tau * t[a] for a in range(3)]
+    expect = np.stack([-p[0], -((1 - 2 * xi) * p[1] + 2 * eta * p[2]), -(2 * eta * p[1] + (1 + 2 * xi) * p[2])])
+    assert rel_inf(w, expect) <= 1e-12
+    # the boundary nodes (where the differences are one-sided) carry a gradient
+    # term that a sign error would visibly change
+    bnd = np.zeros(n, dtype=bool)
+    for a in range(3):
+        sl = [slice(None)] * 3
+        sl[a] = 0
+        bnd[tuple(sl)] = True
+        sl[a] = -1
+        bnd[tuple(sl)] = True
+    gterm = np.abs(np.stack([T0 * gm[a] * c[a] / g["h"][a] for a in range(3)]))[:, bnd]
+    assert gterm.max() > 1e4 * 1e-12 * np.abs(expect).max()
+
+
+@pytest.mark.parametrize("line", [(2, (0, 7)), (0, (7, 14)), (1, (0, 0)), (2, (14, 14)), (0, (0, 14))])
+def test_cont_adjoint_exact_on_face_and_edge_lines(line):
+    """Grid lines lying in a grid face (one boundary axis) or along a grid edge
+    (two boundary axes), homogeneous anisotropic Cartesian medium, receiver
+    and on-node source on the line: as on an interior line the flux R flows
+    straight to the source, but through faces whose control-volume extents are
+    halved on each boundary axis, A = h^2 / 2 on a face and h^2 / 4 on an
+    edge, so P = R / (A |w|) on the line between the receiver and the fixed
+    cell and 0 elsewhere."""
+    axis, fixed = line
+    g = W.cartesian_grid(15, 1.0)
+    xi0, eta0, v = -0.06, 0.07, 6.5
+    s, xi, eta = _homog(g, v, xi0, eta0)
+    others = [b for b in range(3) if b != axis]
+    src = np.zeros(3)
+    src[others[0]], src[others[1]] = fixed
+    src[axis] = 3.0
+    rec = src.copy()
+    rec[axis] = 11.0
+    par = O.source_params(g, s, xi, eta, src)[0]
+    tau, _, conv, _ = O.forward(g, s, xi, eta, src, par, 1.2, 1e-14, 50)
+    assert conv
+    P, it, conv, _ = O.adjoint_cont(g, s, xi, eta, src, par, tau, rec[None], np.array([1.9]), 1e-14, 100)
+    assert conv
+    M = np.array([[1, 0, 0], [0, 1 - 2 * xi0, 2 * eta0], [0, 2 * eta0, 1 + 2 * xi0]])
+    speed = (1.0 / v) / math.sqrt(np.linalg.inv(M)[axis, axis])
+    nbnd = sum(1 for b in others if src[b] in (0.0, 14.0))
+    A = 1.0 / 2 ** nbnd
+    expect = np.zeros(tuple(g["n"]))
+    idx = [int(src[0]), int(src[1]), int(src[2])]
+    idx[axis] = slice(5, 12)
+    expect[tuple(idx)] = 1.9 / (A * speed)
+    assert np.abs(P - expect).max() <= 1e-12 * expect.max()
+
+
+@pytest.mark.parametrize("coord", [0, 1])
+def test_cont_adjoint_conserves_flux(coord):
+    """Discrete conservation of Eq. (5)'s finite volumes: at convergence the
+    injected flux sum_m R_m (receivers on nodes outside the fixed cell) leaves
+    either into the fixed cell (absorbed by the source) or through the grid
+    faces (outflow out of the domain), face fluxes A max(u_out, 0) P with the
+    face velocity the mean of the two nodal normal components (the node's own
+    on a grid face) and the areas of the trapezoidal control volumes built
+    here from their definition.  tau is a smooth made-up field (any tau
+    defines a transport problem) whose flow leaves through the grid faces, so
+    the outflow term is a large part of the balance: dropping it, or taking
+    other areas, breaks the identity."""
+    if coord == 0:
+        g = dict(n=(10, 11, 12), coord=0, o=(0.0, 0.0, 0.0), h=(1.0, 0.9, 1.1))
+    else:
+        g = W.spherical_grid(10, 9.0, 0.05, n_lat=11, n_lon=12)
+        g["o"] = (g["o"][0], g["o"][1] + 0.9, g["o"][2])
+    n = tuple(g["n"])
+    ax = W.axes(g)
+    I, J, K = np.meshgrid(*[np.arange(v) / (v - 1) for v in n], indexing="ij")
+    xi = 0.03 * np.cos(2.0 * J) * np.ones(n)
+    eta = 0.04 * np.sin(1.5 * K + I)
+    s = np.full(n, 1.0 / 6.0)
+    src = np.array([ax[0][4] + 0.3 * g["h"][0], ax[1][5] + 0.55 * g["h"][1], ax[2][6] + 0.25 * g["h"][2]])
+    par = O.source_params(g, s, xi, eta, src)[0]
+    # T = T0 tau peaks about three nodes past the source along axis 2 and falls
+    # towards the last axis-2 face beyond: flow from the receivers past the
+    # ridge leaves the domain there, the rest reaches the source
+    kk = np.arange(n[2])[None, None, :] * np.ones(n)
+    tau = np.exp(-0.3 * kk) * (1.0 + 0.1 * np.sin(2.2 * I + 0.4) * np.cos(1.7 * J - 0.3))
+    recn = [(0, 0, 0), (n[0] - 1, 3, n[2] - 2), (2, n[1] - 1, 1), (8, 2, n[2] - 1), (7, 8, 3), (1, 9, 10)]
+    rec = np.array([[ax[0][i], ax[1][j], ax[2][k]] for i, j, k in recn])
+    R = np.array([1.0, 0.7, 1.3, 0.4, 0.9, 1.1])
+    P, _, conv, _ = O.adjoint_cont(g, s, xi, eta, src, par, tau, rec, R, 1e-15, 2000)
+    assert conv
+    w = O.cont_velocity(g, xi, eta, src, par, tau)
+    fb = O.fixed_base(g, src)
+    fixed = np.zeros(n, dtype=bool)
+    fixed[fb[0]:fb[0] + 2, fb[1]:fb[1] + 2, fb[2]:fb[2] + 2] = True
+    areas = _test_areas(g)
+    into_fixed = out_grid = 0.0
+    for a in range(3):
+        for side in (0, 1):
+            sg = 1 if side == 0 else -1
+            wn = np.roll(w[a], -sg, axis=a)       # neighbour's normal velocity (wraps at the ends)
+            nbf = np.roll(fixed, -sg, axis=a)
+            edge = np.zeros(n, dtype=bool)
+            sl = [slice(None)] * 3
+            sl[a] = -1 if sg > 0 else 0
+            edge[tuple(sl)] = True
+            u = np.where(edge, sg * w[a], sg * 0.5 * (w[a] + wn))
+            flux = areas[a][side] * np.maximum(u, 0.0) * P
+            into_fixed += flux[(~edge) & nbf & (~fixed)].sum()
+            out_grid += flux[edge & (~fixed)].sum()
+    total = R.sum()
+    assert abs(into_fixed + out_grid - total) <= 1e-10 * total, (into_fixed, out_grid, total)
+    assert out_grid > 0.05 * total and into_fixed > 0.05 * total, (into_fixed, out_grid)
+
+
 def test_cont_adjoint_exact_on_radial_line_spherical():
     """Homogeneous spherical medium, receiver on the surface node straight
     above an on-node source: the flux R crosses each r-face of the line, of
