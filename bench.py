@@ -9,20 +9,28 @@ kernels summed over sources (Eqs. (6)-(8)).  Workload: 101^3 spherical grid
 (0-100 km depth, 4 x 4 degrees), Gaussian-random-field slowness (+-10 %) and
 anisotropy (+-0.04), 128 sources, 500 surface receivers, tol 1e-6, FP64;
 observed times come from a forward solve in an independent random model
-(computed before timing).  The plain path (tau = 1 start) and the warm-started
-path run the same steps back to back; value = sources per second (fwd +
-adjoint + kernel per source) of the warm-started path, with the plain path's
-figures in "plain", and the plain-start step with the upwind adjoint of
-Eq. (5) in "plain_continuous_adjoint".
+(computed before timing).
 
-Prints one JSON line (rank 0).  Extra objects: "roofline" (the dominant sweep
-kernel, timed live with HIP event pairs around the back-to-back launches of
-each directional sweep, on the library's stream),
-"cpu_baseline" (the CPU oracle on a bounded sample of the same workload) and
-"aux" (the kernels that run once per inversion step outside the solves --
-kernel density, multiple-grid projection and expansion, common-receiver
-misfit -- each timed on seeded inputs of the workload's shapes against its
-algorithmic bytes, with the oracle's time for the same call beside it).
+The solves of a timed step are asynchronous: each enqueues its iteration
+budget (the largest iteration count of a host-polled calibration step of the
+same start, plus a margin) and nothing waits on the host; converged sources
+exit on the device.  After the timed steps every source's status is checked:
+a source that reached its budget unconverged voids the value (null, exit 3).
+The plain path (tau = 1 start) and the warm-started path run the same steps
+back to back; value = sources per second (fwd + adjoint + kernel per source)
+of the warm-started path, with the plain path's figures in "plain", and, on a
+few steps each, the plain path host-polled, with its iterations replayed from
+captured graphs, and with the upwind adjoint of Eq. (5).
+
+Prints one JSON line.  Extra objects: "roofline" (both sweep kernels, timed
+live with HIP event pairs around the back-to-back launches of each
+directional sweep on the library's stream; the dominant one is reported),
+"cpu_baseline" (converged oracle solves on all host cores, and on one
+thread) and "aux" (the kernels that run once per inversion step outside the
+solves -- kernel density, multiple-grid projection and expansion,
+common-receiver misfit, relocation -- each timed on seeded inputs of the
+workload's shapes against its algorithmic bytes, with the oracle's time for
+the same call beside it).
 """
 import argparse
 import json
@@ -52,12 +60,22 @@ def parse():
     ap.add_argument("--tile-k-fwd", type=int, default=0, help="forward tile depth (overrides --tile-k/autotune)")
     ap.add_argument("--tile-k-adj", type=int, default=0, help="adjoint tile depth (overrides --tile-k/autotune)")
     ap.add_argument("--no-autotune", action="store_true", help="use the library's default tile depths")
-    ap.add_argument("--graph", action="store_true", help="replay each iteration from a captured hipGraph")
     ap.add_argument("--no-sweep-timing", action="store_true",
                     help="skip the per-launch sweep events (roofline then unmeasured)")
-    ap.add_argument("--max-iter", type=int, default=1000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=1000,
+                    help="iteration cap of the host-polled calibration and comparison steps")
+    ap.add_argument("--budget-margin", type=int, default=8,
+                    help="iterations added to the calibration step's largest count to give the budget of the "
+                         "asynchronous solves")
+    ap.add_argument("--compare-steps", type=int, default=3,
+                    help="timed steps of the comparison paths (host-polled, graph replay, continuous adjoint); 0 "
+                         "skips them")
+    ap.add_argument("--cpu-baseline", choices=("full", "all-cores", "off"), default="full",
+                    help="converged oracle solves on all host cores (and one thread with 'full')")
+    ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_const", const="off")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--cpu-sources", type=int, default=0,
+                    help="oracle sources of the all-core run (default: one per thread)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB of a plain device-to-device copy run first (counter calibration)")
     ap.add_argument("--start", choices=("both", "plain", "warm"), default="both",
@@ -118,46 +136,35 @@ def interior_nonfixed(grid):
     return (n[0] - 2) * (n[1] - 2) * (n[2] - 2)
 
 
-def cpu_baseline(wl, it_f, it_a, threads):
-    """Time the oracle on `threads` sources at once (one per thread): 3 forward
-    iterations, then adjoint solves capped at 1 and 3 iterations and one kernel
-    accumulation; scale to whole solves with the per-source iteration counts
-    that the GPU reached (identical to the oracle's by construction of the
-    parity tests).  Returns solves/s over all threads."""
+def cpu_baseline(wl, nsrc, threads):
+    """Converged oracle solves timed on host threads: `nsrc` sources of the
+    workload, one per thread at a time (`threads` threads), each a forward
+    solve to tol, its adjoint solve to tol at the workload's seeded adjoint
+    sources and its kernel contribution.  Returns (solves/s, wall s, mean
+    forward and adjoint iterations)."""
+    from concurrent.futures import ThreadPoolExecutor
     import numpy as np
     import oracle as O
     g, s, xi, eta = wl["grid"], wl["s"], wl["xi"], wl["eta"]
-    src = wl["src"][:threads]
+    src = wl["src"][:nsrc]
     par = O.source_params(g, s, xi, eta, src)
-    kappa = wl["kappa"]
-    out = [None] * threads
+    kappa, tol = wl["kappa"], wl["tol"]
 
-    def work(q):
-        t0 = time.perf_counter()
-        tau, _, _, _ = O.forward(g, s, xi, eta, src[q], par[q], kappa, 1e-30, 3)
-        t1 = time.perf_counter()
+    def solve(q):
+        tau, itf, cf, _ = O.forward(g, s, xi, eta, src[q], par[q], kappa, tol, 1000)
         rhs = O.adjoint_rhs(g, src[q], par[q], wl["rec"], wl["R"][q])
-        t2 = time.perf_counter()
-        O.adjoint(g, s, xi, eta, src[q], par[q], kappa, tau, rhs, 1e-30, 1)
-        t3 = time.perf_counter()
-        lam, _, _, _ = O.adjoint(g, s, xi, eta, src[q], par[q], kappa, tau, rhs, 1e-30, 3)
-        t4 = time.perf_counter()
+        lam, ita, ca, _ = O.adjoint(g, s, xi, eta, src[q], par[q], kappa, tau, rhs, tol, 1000)
         O.kernel(g, s, xi, eta, src[q], par[q], kappa, tau, lam)
-        t5 = time.perf_counter()
-        per_f = (t1 - t0) / 3.0
-        per_a = ((t4 - t3) - (t3 - t2)) / 2.0
-        fixed_a = (t3 - t2) - per_a + (t2 - t1)
-        out[q] = per_f * it_f[q] + fixed_a + per_a * it_a[q] + (t5 - t4)
+        if not (cf and ca):
+            raise RuntimeError(f"oracle source {q} did not converge")
+        return itf, ita
 
     t0 = time.perf_counter()
-    ths = [threading.Thread(target=work, args=(q,)) for q in range(threads)]
-    for t in ths:
-        t.start()
-    for t in ths:
-        t.join()
+    with ThreadPoolExecutor(threads) as ex:
+        its = list(ex.map(solve, range(nsrc)))
     wall = time.perf_counter() - t0
-    per_source = float(np.mean(out))
-    return threads / per_source, wall
+    its = np.array(its, dtype=float)
+    return nsrc / wall, wall, float(its[:, 0].mean()), float(its[:, 1].mean())
 
 
 AUX_GRIDS = dict(m=(11, 13, 13), H=5)
@@ -297,28 +304,6 @@ def aux_cpu(wl, a):
     return {k: round(v * 1e3, 3) for k, v in out.items()}
 
 
-def cpu_cont_adjoint(wl, iters, nsrc):
-    """The oracle's continuous adjoint on one source (its own 3-iteration
-    forward): set-up plus 1 and 2 iterations give the per-iteration cost,
-    scaled to the GPU's mean iteration count and to the batch."""
-    import numpy as np
-    import oracle as O
-    g, s, xi, eta = wl["grid"], wl["s"], wl["xi"], wl["eta"]
-    src = wl["src"][:1]
-    par = O.source_params(g, s, xi, eta, src)[0]
-    tau, _, _, _ = O.forward(g, s, xi, eta, src[0], par, wl["kappa"], 1e-30, 3)
-    R = np.asarray(wl["R"])[0]
-    t0 = time.perf_counter()
-    O.adjoint_cont(g, s, xi, eta, src[0], par, tau, wl["rec"], R, 1e-30, 1)
-    t1 = time.perf_counter()
-    O.adjoint_cont(g, s, xi, eta, src[0], par, tau, wl["rec"], R, 1e-30, 2)
-    t2 = time.perf_counter()
-    per_it = (t2 - t1) - (t1 - t0)
-    per_src = (t1 - t0) - per_it + per_it * iters
-    return {"oracle_s_per_source": round(per_src, 3), "oracle_cores": 1,
-            "oracle_solves_per_s": round(1.0 / per_src, 4)}
-
-
 def aux_section(wl, nsrc, dev, with_cpu):
     a = aux_inputs(wl, nsrc)
     res = aux_gpu(wl, a, dev)
@@ -342,7 +327,7 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
-    from paper_2412_00031_amd import api, workloads as W
+    from paper_2412_00031_amd import _lib, api, workloads as W
 
     dev = torch.device("cuda:0")
     if args.copy_probe > 0:
@@ -357,37 +342,47 @@ def main():
     wl = W.sph101(nsrc=args.nsrc)
     g, kappa, tol = wl["grid"], wl["kappa"], wl["tol"]
     if args.aux_only:
-        print(json.dumps({"aux": aux_section(wl, args.nsrc, dev, not args.no_cpu_baseline)}), flush=True)
+        print(json.dumps({"aux": aux_section(wl, args.nsrc, dev, args.cpu_baseline != "off")}), flush=True)
         return
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     s, xi, eta, src, rec = t(wl["s"]), t(wl["xi"]), t(wl["eta"]), t(wl["src"]), t(wl["rec"])
     nsrc = args.nsrc
+    lib = _lib.load()
 
     # observations: forward solve in the independent "true" model (untimed)
     st_, xt_, et_ = t(wl["s_true"]), t(wl["xi_true"]), t(wl["eta_true"])
     par_t = api.source_params(g, st_, xt_, et_, src)
-    tau_t, _ = api.forward(g, st_, xt_, et_, src, par_t, tol, args.max_iter, kappa, tile_k=args.tile_k,
-                           groups=args.groups)
+    tau_t, st_t = api.forward(g, st_, xt_, et_, src, par_t, tol, args.max_iter, kappa, poll=True)
     T_obs = api.sample(g, src, par_t, tau_t, rec)
     del tau_t
     torch.cuda.synchronize()
+    if (st_t <= 0).any():
+        sys.exit("observations: the true-model forward solve did not converge")
     log("observations ready")
 
     tk_f = args.tile_k_fwd or args.tile_k
     tk_a = args.tile_k_adj or args.tile_k
+    gr_f = gr_a = args.groups
     tuned = None
     if (tk_f == 0 or tk_a == 0) and not args.no_autotune:
         from paper_2412_00031_amd import autotune
         par0 = api.source_params(g, s, xi, eta, src)
-        R0 = torch.zeros((nsrc, len(wl["rec"])), dtype=torch.float64, device=dev)
-        tuned = autotune.tune(g, s, xi, eta, src, par0, kappa, rec, R0, log=log)
+        tuned = autotune.tune(g, s, xi, eta, src, par0, kappa, rec, log=log)
         tk_f, tk_a = tk_f or tuned["fwd"], tk_a or tuned["adj"]
-        log(f"tile depths: forward {tk_f}, adjoint {tk_a}")
-    ws_f = api.workspace(g, nsrc, 0, tk_f, dev, groups=args.groups)
-    ws_a = api.workspace(g, nsrc, 1, tk_a, dev, groups=args.groups)
+        if args.groups == 0:
+            gr_f, gr_a = tuned["groups_fwd"], tuned["groups_adj"]
+    tk_f = tk_f or int(lib.tt_default_tile_k(0))
+    tk_a = tk_a or int(lib.tt_default_tile_k(1))
+    auto_groups = max(1, min(4, nsrc // 32))
+    gr_f, gr_a = gr_f or auto_groups, gr_a or auto_groups
+    log(f"tile depths: forward {tk_f}, adjoint {tk_a}; source groups: forward {gr_f}, adjoint {gr_a}")
+    ws_f = api.workspace(g, nsrc, 0, tk_f, dev, groups=gr_f)
+    ws_a = api.workspace(g, nsrc, 1, tk_a, dev, groups=gr_a)
     tau = torch.empty((nsrc,) + tuple(g["n"]), dtype=torch.float64, device=dev)
     lam = torch.empty_like(tau)
     grad = torch.empty((3,) + tuple(g["n"]), dtype=torch.float64, device=dev)
+    st_f = torch.empty(nsrc, dtype=torch.int32, device=dev)
+    st_a = torch.empty_like(st_f)
 
     warm = None
     if args.start != "plain":
@@ -402,67 +397,94 @@ def main():
         else:
             log(f"no warm-start weights at {wpath}: timing the plain path only")
 
-    def step(timed, use_warm, continuous=args.adjoint == "continuous"):
+    budget = {"fwd": args.max_iter, "adj": args.max_iter}
+
+    def step(use_warm, poll=False, timed=False, graph=False, continuous=args.adjoint == "continuous"):
         par = api.source_params(g, s, xi, eta, src)
         init = warm.predict(s, xi, eta, src, par, out=init_buf) if use_warm else None
-        _, st_f = api.forward(g, s, xi, eta, src, par, tol, args.max_iter, kappa, tau_init=init, tile_k=tk_f,
-                              ws=ws_f, out=tau, time_sweeps=timed, graph=args.graph, groups=args.groups)
+        api.forward(g, s, xi, eta, src, par, tol, budget["fwd"], kappa, tau_init=init, tile_k=tk_f, ws=ws_f,
+                    out=tau, time_sweeps=timed, graph=graph, groups=gr_f, poll=poll, status=st_f)
         T = api.sample(g, src, par, tau, rec)
         chi, R = api.misfit(T, T_obs)
-        _, st_a = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, tol, args.max_iter, kappa, tile_k=tk_a,
-                              ws=ws_a, out=lam, time_sweeps=timed, graph=args.graph, groups=args.groups,
-                              continuous=continuous)
+        api.adjoint(g, s, xi, eta, src, par, tau, rec, R, tol, budget["adj"], kappa, tile_k=tk_a, ws=ws_a, out=lam,
+                    time_sweeps=timed, graph=graph, groups=gr_a, continuous=continuous, poll=poll, status=st_a)
         api.kernel(g, s, xi, eta, src, par, tau, lam, grad=grad.zero_())
-        return st_f, st_a, chi
+        return chi
 
-    def run(use_warm, steps, warmup, timed, continuous=args.adjoint == "continuous"):
-        name = ("warm" if use_warm else "plain") + (" (continuous adjoint)" if continuous else "")
+    def run(name, steps, warmup, fn):
         for w in range(warmup):
-            step(False, use_warm, continuous)
+            fn()
             torch.cuda.synchronize()
-            log(f"{name}: warmup step {w + 1} done")
-        torch.cuda.synchronize()
+        log(f"{name}: {warmup} warmup step(s) done")
         api.sweep_timing(0, reset=True)
         api.sweep_timing(1, reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            st_f, st_a, chi = step(timed, use_warm, continuous)
+            chi = fn()
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        log(f"{name}: timed {steps} steps{' (sweep timing)' if timed else ''}: {elapsed:.2f} s")
-        st_f = st_f.cpu().numpy()
-        st_a = st_a.cpu().numpy()
-        if (st_f <= 0).any() or (st_a <= 0).any():
-            print(f"warning: not all sources converged (fwd {st_f.min()}, adj {st_a.min()})", file=sys.stderr)
-        return dict(elapsed=elapsed, steps=steps, it_f=np.abs(st_f), it_a=np.abs(st_a), chi=float(chi),
+        f, a = st_f.cpu().numpy(), st_a.cpu().numpy()
+        conv = bool((f > 0).all() and (a > 0).all())
+        log(f"{name}: timed {steps} steps: {elapsed:.2f} s ({1e3 * elapsed / steps:.1f} ms per step)"
+            + ("" if conv else f"; NOT CONVERGED (fwd {f.min()}, adj {a.min()})"))
+        return dict(elapsed=elapsed, steps=steps, it_f=np.abs(f), it_a=np.abs(a), chi=float(chi), converged=conv,
                     sweep=(api.sweep_timing(0, reset=True), api.sweep_timing(1, reset=True)))
 
-    runs = {}
+    # Iteration budgets of the asynchronous solves: a host-polled step of each
+    # start finds the iteration counts, and the budget is the largest count
+    # plus a margin; every timed step's statuses are checked afterwards.
+    def calibrate(use_warm, continuous=False):
+        step(use_warm, poll=True, continuous=continuous)
+        torch.cuda.synchronize()
+        f, a = st_f.cpu().numpy(), st_a.cpu().numpy()
+        if (f <= 0).any() or (a <= 0).any():
+            sys.exit(f"calibration step did not converge within {args.max_iter} iterations")
+        return int(f.max()), int(a.max())
+
+    def with_budget(fmax, amax, fn):
+        def wrapped():
+            budget["fwd"], budget["adj"] = fmax + args.budget_margin, amax + args.budget_margin
+            return fn()
+        return wrapped
+
+    runs, budgets = {}, {}
+    cal = {"plain": calibrate(False)}
+    if warm is not None:
+        cal["warm"] = calibrate(True)
+    budgets = {k: [v[0] + args.budget_margin, v[1] + args.budget_margin] for k, v in cal.items()}
+    log(f"iteration budgets (largest polled count + {args.budget_margin}): {budgets}")
     if not args.roofline_only:
-        if args.start in ("both", "plain") or warm is None:
-            runs["plain"] = run(False, args.steps, args.warmup, False)
+        runs["plain"] = run("plain", args.steps, args.warmup, with_budget(*cal["plain"], lambda: step(False)))
         if warm is not None:
-            runs["warm"] = run(True, args.steps, args.warmup, False)
+            runs["warm"] = run("warm", args.steps, args.warmup, with_budget(*cal["warm"], lambda: step(True)))
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(3):
                 warm.predict(s, xi, eta, src, api.source_params(g, s, xi, eta, src), out=init_buf)
             torch.cuda.synchronize()
             runs["warm"]["predict_ms"] = (time.perf_counter() - t0) / 3 * 1e3
-        if args.adjoint == "discrete" and not args.no_aux:
-            # the same plain-start step with the upwind adjoint of Eq. (5) (the
-            # paper's route), reported beside the headline discrete-adjoint figures
-            runs["continuous"] = run(False, args.steps, 1, False, continuous=True)
+        if args.compare_steps > 0:
+            cs = args.compare_steps
+            # the same plain step host-polled, and with iterations replayed from captured graphs
+            runs["plain_polled"] = run("plain, host-polled", cs, 1, lambda: step(False, poll=True))
+            runs["plain_graph"] = run("plain, graph replay", cs, 1,
+                                      with_budget(*cal["plain"], lambda: step(False, graph=True)))
+            if args.adjoint == "discrete":
+                # the plain-start step with the upwind adjoint of Eq. (5) (the paper's route)
+                runs["continuous"] = run("plain, continuous adjoint", cs, 1,
+                                         lambda: step(False, poll=True, continuous=True))
     # roofline step: the same step once more with every directional sweep of the
     # sweep kernels timed by HIP events on the library's stream (one source
     # group, so each launch carries a tile-plane of every active source)
     rf = None
     if not args.no_sweep_timing:
-        rf = run(warm is not None, 1, 0 if runs else args.warmup, True)
+        rf = run("roofline step", 1, 0 if runs else args.warmup,
+                 lambda: step(warm is not None, poll=True, timed=True))
     main_run = rf if args.roofline_only else (runs["warm"] if warm is not None else runs["plain"])
     elapsed, it_f, it_a = main_run["elapsed"], main_run["it_f"], main_run["it_a"]
     steps_main = main_run["steps"]
+    all_converged = all(r["converged"] for r in list(runs.values()) + ([rf] if rf else []))
 
     value = nsrc * steps_main / elapsed
     roofline = None
@@ -470,90 +492,92 @@ def main():
         (ms_f, n_f), (ms_a, n_a) = rf["sweep"]
         nodes = interior_nonfixed(g) - 8
         # algorithmic bytes per node update: forward = tau read + write (16 B)
-        # plus the model (24 B per node per sweep, shared by the batch);
-        # adjoint = lambda read + write plus the node's 6 stored couplings (64 B; the
-        # right-hand side, read only in the tiles at the receivers, is not counted)
+        # plus the model's s, xi, eta (24 B per node per sweep, shared by the
+        # batch); adjoint = lambda read + write (16 B) plus 32 B of stored
+        # coefficients plus the shared model (the right-hand side, read only
+        # in the tiles at the receivers, is not counted)
         upd_f = float(rf["it_f"].sum()) * 8 * nodes
         upd_a = float(rf["it_a"].sum()) * 8 * nodes
         bytes_f = upd_f * (16.0 + 24.0 / nsrc)
-        bytes_a = upd_a * (16.0 + 48.0 + 24.0 / nsrc)
+        bytes_a = upd_a * (16.0 + 32.0 + 24.0 / nsrc)
         kern = {
-            "k_fwd_sweep": dict(ms=ms_f, launches=n_f, bytes=bytes_f, updates=upd_f),
-            "k_adj_sweep": dict(ms=ms_a, launches=n_a, bytes=bytes_a, updates=upd_a),
+            "k_fwd_sweep": dict(ms=ms_f, launches=n_f, bytes=bytes_f, updates=upd_f, tk=tk_f),
+            "k_adj_sweep": dict(ms=ms_a, launches=n_a, bytes=bytes_a, updates=upd_a, tk=tk_a),
         }
+        for K in kern.values():
+            K["achieved"] = K["bytes"] / (K["ms"] * 1e-3) / 1e9 if K["ms"] > 0 else 0.0
         dom = max(kern, key=lambda k: kern[k]["ms"])
         K = kern[dom]
         avg_ms = K["ms"] / max(K["launches"], 1)
-        achieved = K["bytes"] / (K["ms"] * 1e-3) / 1e9 if K["ms"] > 0 else 0.0
-        traffic = measured_traffic(dom, K["updates"] / max(K["launches"], 1),
-                                   (tk_f or 16) if dom == "k_fwd_sweep" else (tk_a or 48))
+        traffic = measured_traffic(dom, K["updates"] / max(K["launches"], 1), K["tk"])
         roofline = {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None if traffic is None else round(traffic),
+            "bound": "hbm", "achieved": round(K["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(K["achieved"] / HBM_PEAK_GBS, 4), "traffic": None if traffic is None else round(traffic),
             "algorithmic_bytes_per_launch": round(K["bytes"] / max(K["launches"], 1)),
             "kernel": dom, "avg_launch_ms": round(avg_ms, 5), "launches": K["launches"],
             "bytes_per_update": round(K["bytes"] / K["updates"], 3),
             "sweep_ms": {k: round(v["ms"], 2) for k, v in kern.items()},
-            "region": "one extra step after the timed ones, one source group, every directional sweep timed",
+            "frac_by_kernel": {k: round(v["achieved"] / HBM_PEAK_GBS, 4) for k, v in kern.items()},
+            "region": "one extra step after the timed ones, host-polled, one source group, every directional sweep "
+                      "timed",
         }
 
     cpu = None
-    if not args.no_cpu_baseline:
-        threads = args.cpu_threads or min(len(os.sched_getaffinity(0)), 16)
-        threads = max(1, min(threads, nsrc))
-        log(f"cpu baseline on {threads} threads")
-        v_cpu, wall = cpu_baseline(wl, it_f[:threads], it_a[:threads], threads)
-        cpu = {"value": round(v_cpu, 5), "unit": "solves/s", "cores": threads, "kind": "oracle",
-               "sample": f"{threads} sources of the same workload, one per thread: 3 forward iterations, adjoint "
-                         f"capped at 1 and 3 iterations, one kernel pass; scaled per source to the converged "
-                         f"iteration counts ({wall:.1f} s wall)"}
+    if args.cpu_baseline != "off":
+        cores = len(os.sched_getaffinity(0))
+        threads = args.cpu_threads or cores
+        n_all = min(nsrc, max(threads, args.cpu_sources))
+        log(f"cpu baseline: {n_all} converged oracle solves on {threads} threads")
+        v_all, wall, mf, ma = cpu_baseline(wl, n_all, threads)
+        cpu = {"value": round(v_all, 5), "unit": "solves/s", "cores": threads, "kind": "oracle",
+               "sample": f"{n_all} sources of the workload, each solved by the oracle to convergence (forward and "
+                         f"adjoint to tol {tol:g}, mean {mf:.1f} / {ma:.1f} iterations, at the workload's seeded "
+                         f"adjoint sources) and its kernel accumulated, {threads} host threads "
+                         f"(sched_getaffinity: {cores} cores), {wall:.1f} s wall"}
+        if args.cpu_baseline == "full":
+            v1, wall1, mf1, ma1 = cpu_baseline(wl, 1, 1)
+            cpu["one_thread"] = {"value": round(v1, 5), "unit": "solves/s", "cores": 1,
+                                 "sample": f"source 0 converged on one thread ({wall1:.1f} s)"}
+        log(f"cpu baseline: {cpu['value']} solves/s")
 
     aux = None
     if not args.no_aux:
         log("auxiliary kernels")
-        aux = aux_section(wl, nsrc, dev, not args.no_cpu_baseline)
-        # the continuous adjoint of Eq. (5) on the last step's fields, beside the discrete one
-        par = api.source_params(g, s, xi, eta, src)
-        chi, R = api.misfit(api.sample(g, src, par, tau, rec), T_obs)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, st_c = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, tol, args.max_iter, kappa, tile_k=tk_a, ws=ws_a,
-                              out=lam, groups=args.groups, continuous=True)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        it_c = np.abs(st_c.cpu().numpy())
-        aux["tt_adjoint_continuous"] = {
-            "solves_per_s": round(nsrc / el, 3), "ms": round(1e3 * el, 2), "mean_iters": round(float(it_c.mean()), 2),
-            "mean_iters_discrete": round(float(it_a.mean()), 2), "kernels": "k_cadj_coef, k_adj_sweep, k_cadj_bnd_*"}
-        if not args.no_cpu_baseline:
-            aux["tt_adjoint_continuous"].update(cpu_cont_adjoint(wl, float(it_c.mean()), nsrc))
-        log(f"continuous adjoint: {el:.2f} s for {nsrc} sources, mean {it_c.mean():.1f} iterations")
+        aux = aux_section(wl, nsrc, dev, args.cpu_baseline != "off")
 
     def summary(r):
         return {"value": round(nsrc * r["steps"] / r["elapsed"], 4), "ms_per_step": round(1e3 * r["elapsed"] / r["steps"], 2),
-                "mean_iters_fwd": round(float(r["it_f"].mean()), 2), "mean_iters_adj": round(float(r["it_a"].mean()), 2),
-                "chi": r["chi"]}
+                "steps": r["steps"], "mean_iters_fwd": round(float(r["it_f"].mean()), 2),
+                "mean_iters_adj": round(float(r["it_a"].mean()), 2), "chi": r["chi"], "converged": r["converged"]}
 
     start = "warm start (U-Net prediction, plain sweeps to the same tol)" if warm is not None else "plain start"
     line = {
-        "metric": METRIC, "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": steps_main,
-        "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / steps_main, 2), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "metric": METRIC, "value": round(value, 4) if all_converged else None, "unit": "solves/s", "n_gpus": 1,
+        "steps": steps_main, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / steps_main, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "plain": summary(runs["plain"]) if "plain" in runs else None,
         "warm": dict(summary(runs["warm"]), predict_ms=round(runs["warm"]["predict_ms"], 2)) if "warm" in runs else None,
+        "plain_host_polled": summary(runs["plain_polled"]) if "plain_polled" in runs else None,
+        "plain_graph_replay": summary(runs["plain_graph"]) if "plain_graph" in runs else None,
         "plain_continuous_adjoint": summary(runs["continuous"]) if "continuous" in runs else None,
         "roofline_only": bool(args.roofline_only),
         "config": {"workload": f"sph101: 101^3 spherical (0-100 km, 4x4 deg), GRF model, {nsrc} sources, "
                                f"{len(wl['rec'])} receivers, tol {tol:g}, {start}",
                    "nsrc": nsrc, "grid": list(g["n"]), "tol": tol, "kappa": kappa,
                    "mean_iters_fwd": round(float(it_f.mean()), 2), "mean_iters_adj": round(float(it_a.mean()), 2),
-                   "tile_k": {"fwd": tk_f or 16, "adj": tk_a or 48,
-                              "chosen_by": "autotune" if tuned else ("fixed" if (tk_f or tk_a) else "default")},
-                   "graph": bool(args.graph), "adjoint": args.adjoint,
-                   "source_groups": args.groups or max(1, min(4, nsrc // 32))},
+                   "tile_k": {"fwd": tk_f, "adj": tk_a,
+                              "chosen_by": "autotune" if tuned else ("fixed" if (args.tile_k_fwd or args.tile_k_adj
+                                                                                 or args.tile_k) else "default")},
+                   "source_groups": {"fwd": gr_f, "adj": gr_a},
+                   "solves": "asynchronous (iteration budget, no host polling)", "iteration_budgets": budgets,
+                   "adjoint": args.adjoint},
         "roofline": roofline, "cpu_baseline": cpu, "aux": aux,
     }
+    if not all_converged:
+        line["error"] = "not every source converged within its iteration budget"
     print(json.dumps(line), flush=True)
+    if not all_converged:
+        sys.exit(3)
 
 
 if __name__ == "__main__":

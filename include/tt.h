@@ -18,9 +18,14 @@
  *     n0 * (n1 + n2 - 1) * n1p < 2^31 with n1p = n1 + 7 rounded up to a
  *     multiple of 8 (the solver's per-node records use 32-bit indices).
  *   - Positions (sources, receivers) are [count][3] in the same axis units.
- *   - stream is a hipStream_t (NULL = default stream).  Work is enqueued on it;
- *     tt_forward and tt_adjoint additionally wait on it (they poll convergence
- *     from the host between iterations); the others return without waiting.
+ *   - stream is a hipStream_t (NULL = default stream).  Every call enqueues
+ *     its work on it and returns without waiting, and can be captured into a
+ *     hipGraph (stream capture) -- except tt_forward / tt_adjoint with
+ *     TT_FLAG_POLL or TT_FLAG_TIME_SWEEPS, which wait for completion.  Calls
+ *     allocate no device memory.  tt_forward / tt_adjoint with more than one
+ *     source group fork helper streams off `stream` and join them back with
+ *     events; the first such call of a host thread creates those streams and
+ *     events, so make it before capturing (or use groups = 1).
  *   - Workspace: ws/ws_bytes is caller-owned device memory of at least
  *     tt_workspace_size(...) bytes for the same arguments; its contents on
  *     entry do not matter and are scratch on exit.  Calls that overlap in
@@ -55,6 +60,10 @@ extern "C" {
 #define TT_OK 0
 #define TT_EINVAL (-1)
 #define TT_EHIP (-2)
+/* Not a return value: the per-source condition "max_iter reached without
+ * convergence", reported in status[] as -iterations (a captured or
+ * asynchronous call cannot return device facts). */
+#define TT_ENOCONV (-3)
 
 typedef struct tt_grid {
     int32_t n[3];   /* nodes per axis, each >= 4 */
@@ -88,9 +97,12 @@ typedef struct tt_opts {
 #define TT_MAX_GROUPS 8
 
 #define TT_FLAG_TIME_SWEEPS 1
-/* bit 1: capture one iteration (every sweep, boundary and convergence launch)
- * as a hipGraph once per call and replay it each iteration.  Ignored when
- * TT_FLAG_TIME_SWEEPS is set (per-launch events are recorded eagerly). */
+/* bit 1: capture iterations (every sweep, boundary and convergence launch)
+ * as a hipGraph once per call and replay it: one iteration per replay when
+ * polling, four when asynchronous.  Ignored when TT_FLAG_TIME_SWEEPS is set
+ * (per-launch events are recorded eagerly) and while the caller's stream is
+ * itself being captured (the launches then become nodes of the caller's
+ * graph). */
 #define TT_FLAG_GRAPH 2
 /* bit 2 (tt_adjoint only): solve the continuous adjoint equation (5) by upwind
  * finite volumes instead of the exact transpose of the discrete forward
@@ -104,6 +116,16 @@ typedef struct tt_opts {
  * give, so tt_kernel and tt_kernel_density apply unchanged.  It agrees with
  * the exact discrete gradient to first order in the grid spacing. */
 #define TT_FLAG_CONTINUOUS_ADJOINT 4
+/* bit 3 (tt_forward, tt_adjoint): host-polled iterations.  Without it a solve
+ * is asynchronous: exactly max_iter iterations are enqueued (max_iter is the
+ * iteration budget), a source that converges is marked inactive on the device
+ * and its workgroups exit at once in every later launch, and status[] is
+ * written on the device (read it after synchronising).  With it the host
+ * reads the count of active sources after each iteration (one iteration
+ * behind, so the device never idles on the poll), stops enqueuing as soon as
+ * every source has converged, and returns after completion.  Results are
+ * bit-identical either way. */
+#define TT_FLAG_POLL 8
 
 /* Bytes of device workspace needed by tt_forward (which = 0), tt_adjoint
  * (which = 1), tt_sample (which = 2) or tt_kernel (which = 3) for this grid,
@@ -126,9 +148,11 @@ int tt_source_params(const tt_grid* grid, const double* s, const double* xi, con
  *   src_pos [nsrc][3]   source positions; src_par [nsrc][3] = s0, xi0, eta0
  *   tau_init [nsrc][N]  initial tau (warm start) or NULL for tau = 1
  *   tau [nsrc][N]       out: tau, with traveltime T = T0 * tau
- *   status [nsrc]       out: iterations done if converged, -iterations if
- *                       max_iter was reached without convergence
- * tau may alias tau_init.  Waits for completion. */
+ *   status [nsrc]       out (device): iterations done if converged;
+ *                       -iterations if max_iter was reached without
+ *                       convergence (the TT_ENOCONV condition: outputs are
+ *                       still written)
+ * tau may alias tau_init.  Asynchronous on stream (see TT_FLAG_POLL). */
 int tt_forward(const tt_grid* grid, const double* s, const double* xi, const double* eta,
                int32_t nsrc, const double* src_pos, const double* src_par, const double* tau_init,
                const tt_opts* opts, double* tau, int32_t* status, void* ws, size_t ws_bytes,
@@ -202,7 +226,7 @@ int tt_misfit_cr(int32_t nsrc, int32_t nrec, const double* T_rec, const double* 
  *   lam [nsrc][N] out: adjoint field (0 on boundary rows of fixed nodes);
  *   status [nsrc] out: as for tt_forward; the convergence measure is
  *   sum|d lambda| / sum|lambda| over one iteration.
- * Waits for completion. */
+ * Asynchronous on stream (see TT_FLAG_POLL). */
 int tt_adjoint(const tt_grid* grid, const double* s, const double* xi, const double* eta,
                int32_t nsrc, const double* src_pos, const double* src_par, const double* tau,
                int32_t nrec, const double* rec_pos, const double* R, const tt_opts* opts,
@@ -269,6 +293,10 @@ int tt_mg_expand(const tt_grid* grid, int32_t H, const int32_t* m, const double*
  * of sweep-kernel launches they contain.  reset != 0 clears the totals after
  * reading.  Pointers may be NULL. */
 int tt_sweep_timing(int32_t which, double* total_ms, int64_t* launches, int32_t reset);
+
+/* The tile depth (tt_opts.tile_k) that tile_k = 0 selects: which = 0
+ * tt_forward, 1 tt_adjoint; 0 for any other value. */
+int32_t tt_default_tile_k(int32_t which);
 
 /* Message for the last nonzero return of the calling thread ("" if none). */
 const char* tt_last_error(void);

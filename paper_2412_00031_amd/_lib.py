@@ -23,7 +23,7 @@ class TTOpts(ctypes.Structure):
 
 EXPORTS = ["tt_workspace_size", "tt_source_params", "tt_forward", "tt_sample", "tt_misfit", "tt_misfit_cr", "tt_reloc_times", "tt_reloc_kernel",
            "tt_adjoint", "tt_kernel", "tt_kernel_density", "tt_mg_workspace_size", "tt_mg_project", "tt_mg_expand",
-           "tt_sweep_timing", "tt_last_error"]
+           "tt_sweep_timing", "tt_default_tile_k", "tt_last_error"]
 
 NN_EXPORTS = ["nn_to_bf16", "nn_from_bf16", "nn_conv3_pack", "nn_conv3_fwd", "nn_conv3_wgrad_work", "nn_conv3_wgrad",
               "nn_relu_mask", "nn_pool_fwd", "nn_pool_bwd", "nn_up_fwd", "nn_up_wgrad_work", "nn_up_bwd",
@@ -45,6 +45,8 @@ class NNUnetCfg(ctypes.Structure):
 TT_FLAG_TIME_SWEEPS = 1
 TT_FLAG_GRAPH = 2
 TT_FLAG_CONTINUOUS_ADJOINT = 4
+TT_FLAG_POLL = 8
+TT_ENOCONV = -3
 TT_MAX_GROUPS = 8
 
 _lib = None
@@ -104,6 +106,8 @@ def load(path=LIB_PATH):
     lib.tt_mg_expand.argtypes = [G, i32, ctypes.POINTER(i32), P, P, P, P]
     lib.tt_sweep_timing.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
     lib.tt_sweep_timing.restype = ctypes.c_int
+    lib.tt_default_tile_k.argtypes = [i32]
+    lib.tt_default_tile_k.restype = i32
     lib.tt_last_error.argtypes = []
     lib.tt_last_error.restype = ctypes.c_char_p
     for name in ("tt_source_params", "tt_forward", "tt_sample", "tt_misfit", "tt_misfit_cr", "tt_reloc_times",

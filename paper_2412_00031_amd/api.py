@@ -26,7 +26,8 @@ def _grid(grid):
     return g
 
 
-def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None, graph=False, groups=0, continuous=False):
+def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None, graph=False, groups=0, continuous=False,
+          poll=False):
     o = _lib.TTOpts()
     o.groups = int(groups)
     o.eps_hist = _dev(eps_hist, "eps_hist").value if eps_hist is not None else None
@@ -35,7 +36,7 @@ def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None, grap
     o.kappa = float(kappa)
     o.tile_k = int(tile_k)
     o.flags = ((_lib.TT_FLAG_TIME_SWEEPS if time_sweeps else 0) | (_lib.TT_FLAG_GRAPH if graph else 0)
-               | (_lib.TT_FLAG_CONTINUOUS_ADJOINT if continuous else 0))
+               | (_lib.TT_FLAG_CONTINUOUS_ADJOINT if continuous else 0) | (_lib.TT_FLAG_POLL if poll else 0))
     return o
 
 
@@ -105,23 +106,28 @@ def source_params(grid, s, xi, eta, src_pos):
 
 
 def forward(grid, s, xi, eta, src_pos, src_par, tol, max_iter, kappa, tau_init=None, tile_k=0, ws=None,
-            out=None, time_sweeps=False, eps_hist=None, graph=False, groups=0):
+            out=None, time_sweeps=False, eps_hist=None, graph=False, groups=0, poll=False, status=None):
     """Batched forward solve.  Returns (tau [nsrc, *n], status int32 [nsrc]).
     eps_hist: optional float64 device tensor [nsrc, max_iter] receiving the
     convergence measure of every iteration.  groups: concurrently iterated
-    source groups (0 = library default; results do not depend on it)."""
+    source groups (0 = library default; results do not depend on it).
+    poll=False (the library's default) enqueues exactly max_iter iterations on
+    the current stream and returns at once (capturable; max_iter is the
+    iteration budget and status is written on the device); poll=True stops as
+    soon as every source has converged and returns after completion."""
     lib = _lib.load()
     N = _N(grid)
     nsrc = int(src_pos.shape[0])
     dev = s.device
     tau = out if out is not None else torch.empty((nsrc,) + tuple(int(v) for v in grid["n"]), dtype=_F64, device=dev)
-    status = torch.zeros(nsrc, dtype=torch.int32, device=dev)
+    if status is None:
+        status = torch.empty(nsrc, dtype=torch.int32, device=dev)
     if ws is None:
         ws = workspace(grid, nsrc, 0, tile_k, dev, groups, time_sweeps)
     g = _grid(grid)
     if eps_hist is not None and eps_hist.numel() != nsrc * int(max_iter):
         raise ValueError("eps_hist must have nsrc * max_iter elements")
-    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph, groups)
+    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph, groups, poll=poll)
     ti = _dev(tau_init, "tau_init", numel=nsrc * N) if tau_init is not None else _null()
     _lib.check(lib.tt_forward(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
                               _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
@@ -223,22 +229,24 @@ def misfit_cr(T_rec, T_obs, cr_off, cr_pair, wcr, gamma, R, chi):
 
 
 def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, kappa, tile_k=0, ws=None,
-            out=None, time_sweeps=False, eps_hist=None, graph=False, groups=0, continuous=False):
+            out=None, time_sweeps=False, eps_hist=None, graph=False, groups=0, continuous=False, poll=False,
+            status=None):
     """Batched adjoint solve.  Returns (lambda [nsrc, *n], status int32 [nsrc]);
-    eps_hist and groups as for forward.  continuous=True solves Eq. (5) by
-    upwind finite volumes and returns P s V in place of lambda."""
+    eps_hist, groups and poll as for forward.  continuous=True solves Eq. (5)
+    by upwind finite volumes and returns P s V in place of lambda."""
     lib = _lib.load()
     N = _N(grid)
     nsrc, nrec = int(src_pos.shape[0]), int(rec_pos.shape[0])
     dev = s.device
     lam = out if out is not None else torch.empty((nsrc,) + tuple(int(v) for v in grid["n"]), dtype=_F64, device=dev)
-    status = torch.zeros(nsrc, dtype=torch.int32, device=dev)
+    if status is None:
+        status = torch.empty(nsrc, dtype=torch.int32, device=dev)
     if ws is None:
         ws = workspace(grid, nsrc, 1, tile_k, dev, groups, time_sweeps)
     g = _grid(grid)
     if eps_hist is not None and eps_hist.numel() != nsrc * int(max_iter):
         raise ValueError("eps_hist must have nsrc * max_iter elements")
-    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph, groups, continuous)
+    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph, groups, continuous, poll)
     _lib.check(lib.tt_adjoint(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
                               _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
                               _dev(src_par, "src_par", numel=3 * nsrc), _dev(tau, "tau", numel=nsrc * N), nrec,

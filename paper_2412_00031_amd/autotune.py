@@ -1,14 +1,19 @@
-"""Autotuner for the sweep tile depth (tile_k) of the forward and adjoint solves.
+"""Autotuner for the sweep launch shape of the forward and adjoint solves:
+the tile depth (tile_k, the hyperplane steps of one sweep tile) and the
+number of concurrently iterated source groups.
 
 For a grid and source count it times a few iterations of each solve for every
-candidate tile depth (the whole call, with the library's default source groups
-running concurrently, as in production), on the whole batch and on a quarter of
-it (the convergence tail of a solve runs with few sources left), and keeps the
-fastest sum.  Any tile depth gives
-bit-identical results, so the choice affects speed only.  Choices are cached in
-a JSON file keyed by (kind, coordinates, grid shape, source count, library
-build, device name), so a rebuilt library is tuned afresh; the file is
-``$TT_TUNE_CACHE`` or ``~/.cache/paper_2412_00031_amd/tiles.json``.
+candidate tile depth (the whole call, asynchronous as in production, with the
+library's default source groups), on the whole batch and on a quarter of it
+(the convergence tail of a solve runs with few sources left), keeps the
+fastest sum, and then times the source-group counts at that depth the same
+way.  Every candidate is timed over exactly the requested iterations: the
+tolerance is unreachable and the statuses are checked afterwards (a candidate
+that stopped early would look fast).  Any tile depth and any grouping give
+bit-identical results, so the choice affects speed only.  Choices are cached
+in a JSON file keyed by (kind, coordinates, grid shape, source count, library
+build, device name, hardware queues), so a rebuilt library is tuned afresh;
+the file is ``$TT_TUNE_CACHE`` or ``~/.cache/paper_2412_00031_amd/tiles.json``.
 """
 import json
 import os
@@ -18,6 +23,7 @@ import torch
 from . import _lib, api
 
 CANDIDATES = (8, 12, 16, 18, 20, 22, 24, 28, 32, 40, 48, 62)
+GROUP_CANDIDATES = (1, 2, 3, 4, 6, 8)
 
 
 def cache_path():
@@ -30,7 +36,8 @@ def cache_path():
 def _key(kind, grid, nsrc):
     n = "x".join(str(int(v)) for v in grid["n"])
     dev = torch.cuda.get_device_name().replace(":", " ") if torch.cuda.is_available() else "none"
-    return f"{kind}:{int(grid['coord'])}:{n}:{int(nsrc)}:{_lib.build_id()}:{dev}"
+    hwq = os.environ.get("GPU_MAX_HW_QUEUES", "default")
+    return f"{kind}:{int(grid['coord'])}:{n}:{int(nsrc)}:{_lib.build_id()}:{dev}:hwq{hwq}"
 
 
 def _load():
@@ -53,34 +60,44 @@ def _store(d):
         pass
 
 
-# Each candidate is timed as the solves run in production: the whole call
-# (sweeps, boundary passes, convergence checks) with the library's default
-# source groups running concurrently, over a fixed iteration count.
-def _elapsed_ms(fn):
+def _elapsed_ms(fn, iters):
+    """Device time of one call of fn (HIP events on the current stream, which
+    the binding hands to the library), after checking that every source ran
+    all `iters` iterations."""
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    fn()
+    _, st = fn()
     e1.record()
     torch.cuda.synchronize()
+    if not bool((st == -iters).all()):
+        raise RuntimeError(f"autotune: a timed solve did not run its {iters} iterations (statuses "
+                           f"{st.min().item()}..{st.max().item()}); its timing would be meaningless")
     return e0.elapsed_time(e1)
 
 
-def _time_fwd(grid, s, xi, eta, src, par, kappa, tk, iters):
-    return _elapsed_ms(lambda: api.forward(grid, s, xi, eta, src, par, 1e-300, iters, kappa, tile_k=tk))
+def _time(kind, grid, s, xi, eta, src, par, tau, rec, R, kappa, tk, groups, iters):
+    if kind == "fwd":
+        return _elapsed_ms(lambda: api.forward(grid, s, xi, eta, src, par, 1e-300, iters, kappa, tile_k=tk,
+                                               groups=groups), iters)
+    return _elapsed_ms(lambda: api.adjoint(grid, s, xi, eta, src, par, tau, rec, R, 1e-300, iters, kappa, tile_k=tk,
+                                           groups=groups), iters)
 
 
-def _time_adj(grid, s, xi, eta, src, par, tau, rec, R, kappa, tk, iters):
-    return _elapsed_ms(lambda: api.adjoint(grid, s, xi, eta, src, par, tau, rec, R, 1e-300, iters, kappa, tile_k=tk))
-
-
-def tune(grid, s, xi, eta, src, par, kappa, rec, R, iters=3, candidates=CANDIDATES, use_cache=True, log=None):
-    """Return {"fwd": tile_k, "adj": tile_k} for this grid and batch size."""
+def tune(grid, s, xi, eta, src, par, kappa, rec, R=None, iters=3, candidates=CANDIDATES,
+         group_candidates=GROUP_CANDIDATES, use_cache=True, log=None):
+    """Return {"fwd": tile_k, "adj": tile_k, "groups_fwd": g, "groups_adj": g}
+    for this grid and batch size.  R: the adjoint sources the adjoint solves
+    are timed with (any nonzero values; default all ones)."""
     nsrc = int(src.shape[0])
     cache = _load() if use_cache else {}
-    kf, ka = _key("fwd", grid, nsrc), _key("adj", grid, nsrc)
-    if use_cache and kf in cache and ka in cache:
-        return {"fwd": int(cache[kf]["tile_k"]), "adj": int(cache[ka]["tile_k"]), "cached": True}
+    keys = {kind: _key(kind, grid, nsrc) for kind in ("fwd", "adj")}
+    if use_cache and all(k in cache and "groups" in cache[k] for k in keys.values()):
+        return {"fwd": int(cache[keys["fwd"]]["tile_k"]), "adj": int(cache[keys["adj"]]["tile_k"]),
+                "groups_fwd": int(cache[keys["fwd"]]["groups"]), "groups_adj": int(cache[keys["adj"]]["groups"]),
+                "cached": True}
+    if R is None:
+        R = torch.ones((nsrc, int(rec.shape[0])), dtype=torch.float64, device=s.device)
     m2 = int(grid["n"][2]) - 2
     cands = sorted({min(c, m2, 62) for c in candidates})
     tau, _ = api.forward(grid, s, xi, eta, src, par, 1e-300, iters, kappa)
@@ -91,19 +108,21 @@ def tune(grid, s, xi, eta, src, par, kappa, rec, R, iters=3, candidates=CANDIDAT
     parts = [(src, par, tau, R)] + ([(src[:nq], par[:nq], tau[:nq], R[:nq])] if nq < nsrc else [])
     res = {}
     for kind in ("fwd", "adj"):
-        best, best_ms, times = None, None, {}
-        for tk in cands:
+        def cost(tk, groups):
             ms = 0.0
             for (sp, pp, tp, rp) in parts:
-                ms += min((_time_fwd(grid, s, xi, eta, sp, pp, kappa, tk, iters) if kind == "fwd" else
-                           _time_adj(grid, s, xi, eta, sp, pp, tp, rec, rp, kappa, tk, iters)) for _ in range(2))
-            times[tk] = round(ms, 3)
-            if best_ms is None or ms < best_ms:
-                best, best_ms = tk, ms
+                ms += min(_time(kind, grid, s, xi, eta, sp, pp, tp, rec, rp, kappa, tk, groups, iters)
+                          for _ in range(2))
+            return round(ms, 3)
+        times = {tk: cost(tk, 0) for tk in cands}
+        best = min(times, key=times.get)
+        gtimes = {gq: cost(best, gq) for gq in group_candidates if gq <= max(1, nsrc)}
+        bestg = min(gtimes, key=gtimes.get)
         res[kind] = best
-        cache[_key(kind, grid, nsrc)] = {"tile_k": best, "ms": times}
+        res["groups_" + kind] = bestg
+        cache[keys[kind]] = {"tile_k": best, "groups": bestg, "ms": times, "groups_ms": gtimes}
         if log:
-            log(f"autotune {kind}: tile_k {best} ({times})")
+            log(f"autotune {kind}: tile_k {best} ({times}); groups {bestg} ({gtimes})")
     if use_cache:
         _store(cache)
     res["cached"] = False

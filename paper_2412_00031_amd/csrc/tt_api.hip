@@ -298,26 +298,59 @@ int group_stream(int q, hipStream_t caller, hipStream_t* out) {
     return TT_OK;
 }
 
-// Enqueue iterations until no source is active.  The count of active sources
-// after iteration k is copied to pinned host memory; the host waits for it
-// while iteration k+1 is already queued, so the device never idles on the poll.
 // stream used only to capture graphs (capture is not allowed on the legacy
 // default stream); nothing runs on it
 thread_local hipStream_t g_capture_stream = nullptr;
 
-// Capture one iteration into an executable graph.
+// Capture `iters` iterations into an executable graph.
 template <typename Launch>
-int capture_iteration(Launch launch_one, hipGraphExec_t* exec) {
+int capture_iterations(Launch launch_one, int iters, hipGraphExec_t* exec) {
     if (!g_capture_stream) TT_HIP(hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     TT_HIP(hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal));
-    launch_one(g_capture_stream);
+    for (int q = 0; q < iters; ++q) launch_one(g_capture_stream);
     hipError_t e = hipStreamEndCapture(g_capture_stream, &graph);
     if (e != hipSuccess) return fail(TT_EHIP, "graph capture: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(TT_EHIP, "graph instantiate: %s", hipGetErrorString(e));
     return TT_OK;
+}
+
+// Per-thread, per-device events that fork the source groups off the caller's
+// stream and join them back (created on first use with timing disabled, and
+// kept: a call made while the caller's stream is being captured records and
+// waits on them like any stream work).
+thread_local hipEvent_t g_fork_ev[kMaxDevices] = {};
+thread_local hipEvent_t g_join_ev[kMaxDevices][TT_MAX_GROUPS] = {};
+
+int cached_event(hipEvent_t& ev, hipEvent_t* out) {
+    if (!ev) TT_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    *out = ev;
+    return TT_OK;
+}
+
+int device_index(int* dev) {
+    TT_HIP(hipGetDevice(dev));
+    if (*dev < 0 || *dev >= kMaxDevices) return fail(TT_EINVAL, "device index %d out of range", *dev);
+    return TT_OK;
+}
+
+// Graphs replayed by asynchronous calls: each is destroyed by a later call of
+// the same thread once the event recorded after its last replay has completed.
+thread_local std::vector<std::pair<hipGraphExec_t, hipEvent_t>> g_retired;
+
+void reclaim_graphs() {
+    size_t keep = 0;
+    for (size_t q = 0; q < g_retired.size(); ++q) {
+        if (hipEventQuery(g_retired[q].second) == hipSuccess) {
+            (void)hipGraphExecDestroy(g_retired[q].first);
+            (void)hipEventDestroy(g_retired[q].second);
+        } else {
+            g_retired[keep++] = g_retired[q];
+        }
+    }
+    g_retired.resize(keep);
 }
 
 // One group of a batched solve: its plan, kernel arguments and stream.
@@ -331,18 +364,19 @@ struct Group {
     bool done = false;
 };
 
-// Enqueue iterations of every group on its own stream until no source of any
-// group is active.  Each group's count of active sources after iteration k is
-// copied to pinned host memory; the host waits for it while iteration k+1 of
-// every group is already queued, so no stream idles on the poll.
+// Host-polled iterations (TT_FLAG_POLL): enqueue iterations of every group on
+// its own stream until no source of any group is active.  Each group's count
+// of active sources after iteration k is copied to pinned host memory; the
+// host waits for it while iteration k+1 of every group is already queued, so
+// no stream idles on the poll.  Returns with every group's work complete.
 template <typename Launch>
-int run_iterations(std::vector<Group>& gs, bool use_graph, Launch launch_one) {
+int run_polled(std::vector<Group>& gs, bool use_graph, Launch launch_one) {
     int* host = nullptr;
     int rc = pinned_counter(&host);
     if (rc) return rc;
     int result = TT_OK;
     for (auto& g : gs) {
-        if (use_graph && (rc = capture_iteration([&](hipStream_t s_) { launch_one(g, s_); }, &g.exec))) {
+        if (use_graph && (rc = capture_iterations([&](hipStream_t s_) { launch_one(g, s_); }, 1, &g.exec))) {
             result = rc;
             break;
         }
@@ -396,11 +430,75 @@ int run_iterations(std::vector<Group>& gs, bool use_graph, Launch launch_one) {
         if (g.ev[0]) (void)hipEventDestroy(g.ev[0]);
         if (g.ev[1]) (void)hipEventDestroy(g.ev[1]);
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess && result == TT_OK) result = fail(TT_EHIP, "kernel launch: %s", hipGetErrorString(e));
     return result;
 }
+
+// Asynchronous iterations (the default): every group gets exactly max_iter
+// iterations enqueued on its stream and nothing waits on the host.  A source
+// that converges is marked inactive on the device and its workgroups exit at
+// once in later launches, so the iterations past the last source's
+// convergence cost launch overhead only.  With use_graph, kGraphChunk
+// iterations are captured once per group and replayed (not while the caller's
+// stream is itself being captured: the launches then go into the caller's
+// graph).
+constexpr int kGraphChunk = 4;
+
+template <typename Launch>
+int run_async(std::vector<Group>& gs, bool use_graph, Launch launch_one) {
+    if (use_graph) reclaim_graphs();  // (never while the caller's stream is captured: it queries events)
+    int rc = TT_OK;
+    for (auto& g : gs) {
+        const int it = g.P.max_iter;
+        if (use_graph && it >= kGraphChunk) {
+            if ((rc = capture_iterations([&](hipStream_t s_) { launch_one(g, s_); }, kGraphChunk, &g.exec)))
+                return rc;
+            for (int q = 0; q + kGraphChunk <= it; q += kGraphChunk) TT_HIP(hipGraphLaunch(g.exec, g.st));
+            for (int q = it - it % kGraphChunk; q < it; ++q) launch_one(g, g.st);
+            hipEvent_t done = nullptr;
+            TT_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+            TT_HIP(hipEventRecord(done, g.st));
+            g_retired.push_back({g.exec, done});
+            g.exec = nullptr;
+        } else {
+            for (int q = 0; q < it; ++q) launch_one(g, g.st);
+        }
+    }
+    TT_HIP(hipGetLastError());
+    return TT_OK;
+}
+
+// After the iterations (and any per-group kernels after them): join the
+// groups' streams back into the caller's stream (asynchronous) or wait for
+// them (polled; run_polled has already waited for the iterations).
+int finish_groups(std::vector<Group>& gs, hipStream_t caller, bool polled) {
+    if (polled) {
+        for (auto& g : gs) TT_HIP(hipStreamSynchronize(g.st));
+        return TT_OK;
+    }
+    int dev = 0, rc = device_index(&dev);
+    if (rc) return rc;
+    for (size_t q = 1; q < gs.size(); ++q) {
+        hipEvent_t ev = nullptr;
+        if ((rc = cached_event(g_join_ev[dev][q], &ev))) return rc;
+        TT_HIP(hipEventRecord(ev, gs[q].st));
+        TT_HIP(hipStreamWaitEvent(caller, ev, 0));
+    }
+    return TT_OK;
+}
+
+// Whether work enqueued on `st` is being captured into a graph.
+bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
+}
+
+// Host-polled solve: asked for, or implied by per-launch sweep timing (whose
+// events are read back when the call returns).
+bool polled_mode(const tt_opts* o) { return (o->flags & (TT_FLAG_POLL | TT_FLAG_TIME_SWEEPS)) != 0; }
 
 // Workspace bytes of a solve split into `groups` groups (one region per group).
 size_t grouped_total(const tt::Geo& G, int nsrc, int groups, int which) {
@@ -422,7 +520,8 @@ int make_groups(const tt::Geo& G, int nsrc, int groups, int which, void* ws, siz
     if (ws_bytes < need) return fail(TT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
     hipEvent_t fork = nullptr;
     if (groups > 1) {
-        TT_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        int dev = 0, rc0 = device_index(&dev);
+        if (rc0 || (rc0 = cached_event(g_fork_ev[dev], &fork))) return rc0;
         TT_HIP(hipEventRecord(fork, caller));
     }
     gs.resize(groups);
@@ -444,7 +543,6 @@ int make_groups(const tt::Geo& G, int nsrc, int groups, int which, void* ws, siz
             if (e != hipSuccess) rc = fail(TT_EHIP, "stream wait: %s", hipGetErrorString(e));
         }
     }
-    if (fork) (void)hipEventDestroy(fork);
     return rc;
 }
 
@@ -480,6 +578,10 @@ int check_ptrs(std::initializer_list<const void*> ps) {
 extern "C" {
 
 const char* tt_last_error(void) { return g_err.c_str(); }
+
+int32_t tt_default_tile_k(int32_t which) {
+    return which == 0 ? kDefaultTileKFwd : (which == 1 ? kDefaultTileKAdj : 0);
+}
 
 int tt_sweep_timing(int32_t which, double* total_ms, int64_t* launches, int32_t reset) {
     if (which < 0 || which > 1) return fail(TT_EINVAL, "which must be 0 or 1");
@@ -547,9 +649,12 @@ int tt_forward(const tt_grid* grid, const double* s, const double* xi, const dou
         tt::launch_fwd_init(g.P, g.a, tau_init ? tau_init + (long long)q0 * G.N : nullptr, s, xi, eta, g.st);
     }
     TT_HIP(hipGetLastError());
-    const bool graph = (opts->flags & TT_FLAG_GRAPH) && !(opts->flags & TT_FLAG_TIME_SWEEPS);
-    rc = run_iterations(gs, graph, [&](Group& g, hipStream_t s_) { tt::launch_fwd_iteration(g.P, g.a, s_); });
+    const bool polled = polled_mode(opts);
+    const bool graph = (opts->flags & TT_FLAG_GRAPH) && !(opts->flags & TT_FLAG_TIME_SWEEPS) && !capturing(caller);
+    auto one = [&](Group& g, hipStream_t s_) { tt::launch_fwd_iteration(g.P, g.a, s_); };
+    rc = polled ? run_polled(gs, graph, one) : run_async(gs, graph, one);
     collect_timing(ev, 0);
+    if (rc == TT_OK) rc = finish_groups(gs, caller, polled);
     return rc;
 }
 
@@ -699,15 +804,17 @@ int tt_adjoint(const tt_grid* grid, const double* s, const double* xi, const dou
                             g.st);
     }
     TT_HIP(hipGetLastError());
-    const bool graph = (opts->flags & TT_FLAG_GRAPH) && !(opts->flags & TT_FLAG_TIME_SWEEPS);
-    rc = run_iterations(gs, graph, [&](Group& g, hipStream_t s_) { tt::launch_adj_iteration(g.P, g.a, s_); });
+    const bool polled = polled_mode(opts);
+    const bool graph = (opts->flags & TT_FLAG_GRAPH) && !(opts->flags & TT_FLAG_TIME_SWEEPS) && !capturing(caller);
+    auto one = [&](Group& g, hipStream_t s_) { tt::launch_adj_iteration(g.P, g.a, s_); };
+    rc = polled ? run_polled(gs, graph, one) : run_async(gs, graph, one);
     collect_timing(ev, 1);
     if (rc == TT_OK && (opts->flags & TT_FLAG_CONTINUOUS_ADJOINT)) {
         for (int q = 0; q < groups; ++q)
             tt::launch_cadj_scale(gs[q].P, s, lam + (long long)group_begin(nsrc, groups, q) * G.N, gs[q].st);
         TT_HIP(hipGetLastError());
-        for (int q = 0; q < groups; ++q) TT_HIP(hipStreamSynchronize(gs[q].st));
     }
+    if (rc == TT_OK) rc = finish_groups(gs, caller, polled);
     return rc;
 }
 

@@ -35,13 +35,13 @@ def evaluate(nsrc=512, ref_sources=32, weights=WEIGHTS, device="cuda", max_iter=
         torch.cuda.synchronize()
         return out, time.perf_counter() - t0
 
-    (tau_p, st_p), t_p = timed(lambda: api.forward(g, s, xi, eta, src, par, tol, max_iter, kappa))
+    (tau_p, st_p), t_p = timed(lambda: api.forward(g, s, xi, eta, src, par, tol, max_iter, kappa, poll=True))
     log(f"plain: {t_p:.2f} s")
     init, t_pred = timed(lambda: warm.predict(s, xi, eta, src, par))
-    (tau_w, st_w), t_w = timed(lambda: api.forward(g, s, xi, eta, src, par, tol, max_iter, kappa, tau_init=init))
+    (tau_w, st_w), t_w = timed(lambda: api.forward(g, s, xi, eta, src, par, tol, max_iter, kappa, tau_init=init, poll=True))
     log(f"warm: {t_pred:.2f} s prediction + {t_w:.2f} s sweeps")
     q = min(ref_sources, nsrc)
-    tau_r, st_r = api.forward(g, s, xi, eta, src[:q], par[:q], 1e-13, max_iter, kappa)
+    tau_r, st_r = api.forward(g, s, xi, eta, src[:q], par[:q], 1e-13, max_iter, kappa, poll=True)
     ip, iw, ir = (x.cpu().numpy() for x in (st_p, st_w, st_r))
     if (ip <= 0).any() or (iw <= 0).any() or (ir <= 0).any():
         raise RuntimeError("a solve did not converge")

@@ -202,7 +202,7 @@ def build_training_set(grid, nmodels, nsrc_per_model, seed, kappa=1.05, tol=1e-6
         dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)
         s_d, xi_d, eta_d, src_d = dev(s), dev(xi), dev(eta), dev(src)
         par = api.source_params(grid, s_d, xi_d, eta_d, src_d)
-        tau, st = api.forward(grid, s_d, xi_d, eta_d, src_d, par, tol, 5000, kappa)
+        tau, st = api.forward(grid, s_d, xi_d, eta_d, src_d, par, tol, 5000, kappa, poll=True)
         f = nn.warm_features(grid, s_d, xi_d, eta_d, src_d, par, stride, dims)
         t, m = nn.warm_target(grid, tau, stride, dims, with_mask=mask is None)
         if mask is None:

@@ -21,7 +21,7 @@ def declared_functions():
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         text = re.sub(r"//[^\n]*", "", text)
         text = re.sub(r"#[^\n]*", "", text)
-        for m in re.finditer(r"\b(?:int|size_t|void|const\s+char\s*\*)\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", text):
+        for m in re.finditer(r"\b(?:int|int32_t|size_t|void|const\s+char\s*\*)\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", text):
             names.add(m.group(1))
     return names
 
@@ -129,3 +129,12 @@ def test_tune_cache_key_names_build_and_device(libpath, monkeypatch):
     assert _lib.build_id() in k1 and k1 != autotune._key("adj", g, 8) and k1 != autotune._key("fwd", g, 9)
     monkeypatch.setattr(_lib, "_build_id", "0" * 16)
     assert autotune._key("fwd", g, 8) != k1
+
+
+def test_default_tile_depths_exported(libpath):
+    """tile_k = 0 selects the depths the library exports (one shared place for
+    the bench's labels and traffic lookups)."""
+    from paper_2412_00031_amd import _lib
+    lib = _lib.load()
+    assert 1 <= lib.tt_default_tile_k(0) <= 62 and 1 <= lib.tt_default_tile_k(1) <= 62
+    assert lib.tt_default_tile_k(2) == 0

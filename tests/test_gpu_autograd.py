@@ -85,7 +85,28 @@ def test_autograd_matches_fd_with_common_receiver_pairs(torch_cuda):
 
 @pytest.mark.slow
 def test_autograd_matches_fd_101(torch_cuda):
-    """101^3 spherical GRF model: central differences at 16 random cells
-    (s, xi, eta in turn) on a subset of 4 sources."""
+    """101^3 spherical GRF model, the whole 128-source, 500-receiver batch of
+    the benchmark workload: central differences at 16 random cells (s, xi, eta
+    in turn)."""
     wl = W.sph101(with_true=False)
-    _fd_check(torch_cuda, wl, 4, 16, 11, 1e-13, steps=(2e-5, 2e-4, 2e-4), rtol=1e-4)
+    _fd_check(torch_cuda, wl, 128, 16, 11, 1e-13, steps=(2e-5, 2e-4, 2e-4), rtol=1e-4)
+
+
+def test_autograd_raises_when_a_solve_does_not_converge(torch_cuda):
+    """chi and its gradient are defined by converged fields: a forward solve
+    (or an adjoint solve) that stops at max_iter before tol raises, naming the
+    sources, instead of returning numbers from unconverged fields."""
+    from paper_2412_00031_amd.autograd import NotConverged, misfit
+    wl = W.small_spherical(n=(12, 13, 14), nsrc=2, nrec=6, seed=45)
+    T_obs = W.straight_line_times(wl["grid"], wl["src"], wl["rec"], 6.4)
+    s, xi, eta, prob = _problem(torch_cuda, wl, 2, T_obs, 1e-12)
+    prob["max_iter"] = 1
+    with pytest.raises(NotConverged, match=r"forward solve did not converge for source\(s\) \[0, 1\]"):
+        misfit(s, xi, eta, prob)
+    # the forward converges, the adjoint gets one iteration
+    prob["max_iter"] = 400
+    prob["adj_max_iter"] = 1
+    m = s.clone().requires_grad_(True)
+    chi = misfit(m, xi, eta, prob)
+    with pytest.raises(NotConverged, match="adjoint solve did not converge"):
+        chi.backward()

@@ -43,7 +43,7 @@ def _gpu(torch, wl, R, tol, max_iter, tile_k=0, groups=0, graph=False, fwd_tol=1
     s, xi, eta = (_dev(torch, wl[k]) for k in ("s", "xi", "eta"))
     src, rec = _dev(torch, wl["src"]), _dev(torch, wl["rec"])
     par = api.source_params(g, s, xi, eta, src)
-    tau, st = api.forward(g, s, xi, eta, src, par, fwd_tol, 2000, wl["kappa"])
+    tau, st = api.forward(g, s, xi, eta, src, par, fwd_tol, 2000, wl["kappa"], poll=True)
     assert (st.cpu().numpy() > 0).all()
     lam, st_a = api.adjoint(g, s, xi, eta, src, par, tau, rec, _dev(torch, R), tol, max_iter, wl["kappa"],
                             tile_k=tile_k, groups=groups, graph=graph, continuous=True)

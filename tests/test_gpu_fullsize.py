@@ -3,11 +3,15 @@ spherical grid, 128 sources, default tiles), and the 256-source batched
 workload with common-source pairs.
 
 The oracle cannot solve 128 sources at 101^3 in a test, so these checks use
+converged oracle solves of sampled sources (run on parallel host threads) and
 what holds at any size: the homogeneous closed form, parity of truncated
 solves (a fixed number of iterations, compared field by field with the
-oracle on sampled sources), batch invariance, run-to-run determinism, and
-oracle parity on sampled sources of the 61^3 batch.
+oracle), batch invariance, run-to-run determinism, and oracle parity on
+sampled sources of the 61^3 batch.
 """
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -85,8 +89,8 @@ def test_fullsize_converges_batch_invariant_deterministic(torch_cuda, sph101):
 
     def run(srcs, Rs):
         par = api.source_params(g, s, xi, eta, srcs)
-        tau, st = api.forward(g, s, xi, eta, srcs, par, tol, 1000, kap)
-        lam, sa = api.adjoint(g, s, xi, eta, srcs, par, tau, rec, Rs, tol, 1000, kap)
+        tau, st = api.forward(g, s, xi, eta, srcs, par, tol, 1000, kap, poll=True)
+        lam, sa = api.adjoint(g, s, xi, eta, srcs, par, tau, rec, Rs, tol, 1000, kap, poll=True)
         grad = api.kernel(g, s, xi, eta, srcs, par, tau, lam)
         torch_cuda.cuda.synchronize()
         return tau, st.cpu().numpy(), lam, sa.cpu().numpy(), grad
@@ -115,10 +119,10 @@ def test_sph61_batch_with_pairs(torch_cuda):
     pairs = _dev(torch_cuda, wl["pairs"], torch_cuda.int32)
     T_obs = W.straight_line_times(g, wl["src"], wl["rec"], 6.2)
     par = api.source_params(g, s, xi, eta, src)
-    tau, st = api.forward(g, s, xi, eta, src, par, tol, 1000, kap)
+    tau, st = api.forward(g, s, xi, eta, src, par, tol, 1000, kap, poll=True)
     T = api.sample(g, src, par, tau, rec)
     chi, R = api.misfit(T, _dev(torch_cuda, T_obs), pairs=pairs)
-    lam, sa = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, tol, 1000, kap)
+    lam, sa = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, tol, 1000, kap, poll=True)
     torch_cuda.cuda.synchronize()
     st, sa = st.cpu().numpy(), sa.cpu().numpy()
     assert (st > 0).all() and (sa > 0).all()
@@ -188,3 +192,53 @@ def test_fullsize_per_step_kernels_parity(torch_cuda, sph101):
                         wcr=_dev(torch, wcr), gamma=1.0)
     assert abs(chi.item() - (chi_o + c2)) <= 1e-12 * (chi_o + c2)
     assert rel_inf(R.cpu().numpy(), R_o) <= 1e-14
+
+
+def _oracle_solve(wl, par, q, R, tol, max_iter):
+    """Converged forward and adjoint solve of source q by the oracle (one host
+    thread; the C oracle releases the interpreter lock)."""
+    g, kap = wl["grid"], wl["kappa"]
+    otau, itf, cf, _ = O.forward(g, wl["s"], wl["xi"], wl["eta"], wl["src"][q], par[q], kap, tol, max_iter)
+    rhs = O.adjoint_rhs(g, wl["src"][q], par[q], wl["rec"], R[q])
+    olam, ita, ca, _ = O.adjoint(g, wl["s"], wl["xi"], wl["eta"], wl["src"][q], par[q], kap, otau, rhs, tol, max_iter)
+    return otau, (itf if cf else -itf), olam, (ita if ca else -ita)
+
+
+def _host_threads(want):
+    return max(1, min(want, len(os.sched_getaffinity(0)), 16))
+
+
+@pytest.mark.slow
+def test_fullsize_converged_parity(torch_cuda, sph101):
+    """The benchmark's solves as it runs them (101^3, all 128 sources, tol
+    1e-6, default tiles and source groups, asynchronous with an iteration
+    budget) converged, against converged oracle solves of sampled sources:
+    equal iteration counts, tau to 1e-12, lambda to 1e-10, and the kernels
+    summed over those sources (Eqs. (6)-(8)) to 1e-10."""
+    from paper_2412_00031_amd import api
+    wl = sph101
+    g, kap, tol = wl["grid"], wl["kappa"], wl["tol"]
+    s, xi, eta = (_dev(torch_cuda, wl[k]) for k in ("s", "xi", "eta"))
+    src, rec, R = _dev(torch_cuda, wl["src"]), _dev(torch_cuda, wl["rec"]), _dev(torch_cuda, wl["R"])
+    par = api.source_params(g, s, xi, eta, src)
+    tau, st = api.forward(g, s, xi, eta, src, par, tol, 120, kap)
+    lam, sa = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, tol, 120, kap)
+    sel = [0, 77, 127]
+    gsel = api.kernel(g, s, xi, eta, src[sel].contiguous(), par[sel].contiguous(), tau[sel].contiguous(),
+                      lam[sel].contiguous())
+    torch_cuda.cuda.synchronize()
+    st, sa = st.cpu().numpy(), sa.cpu().numpy()
+    assert (st > 0).all() and (sa > 0).all(), (st.min(), sa.min())
+    opar = O.source_params(g, wl["s"], wl["xi"], wl["eta"], wl["src"])
+    assert rel_inf(par.cpu().numpy(), opar) <= 1e-15
+    with ThreadPoolExecutor(_host_threads(len(sel))) as ex:
+        res = list(ex.map(lambda q: _oracle_solve(wl, opar, q, wl["R"], tol, 200), sel))
+    ograd = np.zeros((3,) + tuple(g["n"]))
+    for q, (otau, itf, olam, ita) in zip(sel, res):
+        assert itf == st[q] and ita == sa[q], (q, itf, st[q], ita, sa[q])
+        assert rel_inf(tau[q].cpu().numpy(), otau) <= 1e-12, q
+        assert rel_inf(lam[q].cpu().numpy(), olam) <= 1e-10, q
+        O.kernel(g, wl["s"], wl["xi"], wl["eta"], wl["src"][q], opar[q], kap, otau, olam, ograd)
+    gg = gsel.cpu().numpy()
+    for c in range(3):
+        assert rel_inf(gg[c], ograd[c]) <= 1e-10, c

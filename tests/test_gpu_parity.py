@@ -142,16 +142,17 @@ def test_graph_replay_matches_eager(torch_cuda):
     g, kap = wl["grid"], wl["kappa"]
     s, xi, eta, src, rec, R = (_dev(torch_cuda, wl[k]) for k in ("s", "xi", "eta", "src", "rec", "R"))
     par = api.source_params(g, s, xi, eta, src)
-    ref_tau, ref_st = api.forward(g, s, xi, eta, src, par, 1e-10, 200, kap)
-    ref_lam, ref_sa = api.adjoint(g, s, xi, eta, src, par, ref_tau, rec, R, 1e-10, 200, kap)
+    ref_tau, ref_st = api.forward(g, s, xi, eta, src, par, 1e-10, 200, kap, poll=True)
+    ref_lam, ref_sa = api.adjoint(g, s, xi, eta, src, par, ref_tau, rec, R, 1e-10, 200, kap, poll=True)
     for rep in range(3):
-        tau, st = api.forward(g, s, xi, eta, src, par, 1e-10, 200, kap, graph=True)
-        torch_cuda.cuda.synchronize()
-        assert torch_cuda.equal(st, ref_st) and torch_cuda.equal(tau, ref_tau), rep
-        lam, sa = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, 1e-10, 200, kap, graph=True)
-        torch_cuda.cuda.synchronize()
-        assert torch_cuda.equal(sa, ref_sa) and torch_cuda.equal(lam, ref_lam), rep
-        _ = (tau * 2.0).sum().item()  # eager work between replays
+        for poll in (True, False):
+            tau, st = api.forward(g, s, xi, eta, src, par, 1e-10, 200, kap, graph=True, poll=poll)
+            torch_cuda.cuda.synchronize()
+            assert torch_cuda.equal(st, ref_st) and torch_cuda.equal(tau, ref_tau), (rep, poll)
+            lam, sa = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, 1e-10, 200, kap, graph=True, poll=poll)
+            torch_cuda.cuda.synchronize()
+            assert torch_cuda.equal(sa, ref_sa) and torch_cuda.equal(lam, ref_lam), (rep, poll)
+            _ = (tau * 2.0).sum().item()  # eager work between replays
 
 
 def test_source_groups_bitwise(torch_cuda):
@@ -165,20 +166,22 @@ def test_source_groups_bitwise(torch_cuda):
     s, xi, eta, src, rec, R = (_dev(torch_cuda, wl[k]) for k in ("s", "xi", "eta", "src", "rec", "R"))
     par = api.source_params(g, s, xi, eta, src)
 
-    def run(groups, graph=False):
+    def run(groups, graph=False, poll=False):
         hf = torch_cuda.zeros((7, 300), dtype=torch_cuda.float64, device="cuda")
         ha = torch_cuda.zeros((7, 300), dtype=torch_cuda.float64, device="cuda")
-        tau, st = api.forward(g, s, xi, eta, src, par, 1e-10, 300, kap, groups=groups, eps_hist=hf, graph=graph)
+        tau, st = api.forward(g, s, xi, eta, src, par, 1e-10, 300, kap, groups=groups, eps_hist=hf, graph=graph,
+                              poll=poll)
         lam, sa = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, 1e-10, 300, kap, groups=groups, eps_hist=ha,
-                              graph=graph)
+                              graph=graph, poll=poll)
         torch_cuda.cuda.synchronize()
         return [x.cpu().numpy() for x in (tau, st, hf, lam, sa, ha)]
 
     ref = run(1)
-    for groups, graph in ((2, False), (3, False), (7, False), (3, True), (0, False)):
-        got = run(groups, graph)
+    for groups, graph, poll in ((2, False, False), (3, False, True), (7, False, False), (3, True, False),
+                                (3, True, True), (0, False, True), (1, False, True)):
+        got = run(groups, graph, poll)
         for a, b in zip(got, ref):
-            assert np.array_equal(a, b), (groups, graph)
+            assert np.array_equal(a, b), (groups, graph, poll)
     o = oracle_path(wl, 1e-10, 300, R=wl["R"])
     assert np.array_equal(ref[1], o["it_f"]) and np.array_equal(ref[4], o["it_a"])
     assert rel_inf(ref[0], o["tau"]) <= TOL_TAU and rel_inf(ref[3], o["lam"]) <= TOL_ADJ
@@ -196,11 +199,11 @@ def test_kernel_density_parity(torch_cuda, zeta, eps_rel):
     g, kap = wl["grid"], wl["kappa"]
     s, xi, eta, src, rec, R = (_dev(torch_cuda, wl[k]) for k in ("s", "xi", "eta", "src", "rec", "R"))
     par = api.source_params(g, s, xi, eta, src)
-    tau, _ = api.forward(g, s, xi, eta, src, par, 1e-13, 1000, kap)
-    lam, _ = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, 1e-13, 1000, kap)
+    tau, _ = api.forward(g, s, xi, eta, src, par, 1e-13, 1000, kap, poll=True)
+    lam, _ = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, 1e-13, 1000, kap, poll=True)
     grad = api.kernel(g, s, xi, eta, src, par, tau, lam)
     ones = torch_cuda.ones_like(R)
-    lam1, _ = api.adjoint(g, s, xi, eta, src, par, tau, rec, ones, 1e-13, 1000, kap)
+    lam1, _ = api.adjoint(g, s, xi, eta, src, par, tau, rec, ones, 1e-13, 1000, kap, poll=True)
     dens = api.kernel(g, s, xi, eta, src, par, tau, lam1)[0].contiguous()
     o = oracle_path(wl, 1e-13, 1000, R=wl["R"])
     od = np.zeros((3,) + tuple(g["n"]))
@@ -456,9 +459,9 @@ def test_maximum_source_count(torch_cuda):
     s, xi, eta, rec = (_dev(torch_cuda, wl[k]) for k in ("s", "xi", "eta", "rec"))
     srcd = _dev(torch_cuda, src)
     par = api.source_params(g, s, xi, eta, srcd)
-    tau, st_f = api.forward(g, s, xi, eta, srcd, par, 1e-11, 300, kap)
+    tau, st_f = api.forward(g, s, xi, eta, srcd, par, 1e-11, 300, kap, poll=True)
     T = api.sample(g, srcd, par, tau, rec)
-    lam, st_a = api.adjoint(g, s, xi, eta, srcd, par, tau, rec, _dev(torch_cuda, R), 1e-11, 300, kap)
+    lam, st_a = api.adjoint(g, s, xi, eta, srcd, par, tau, rec, _dev(torch_cuda, R), 1e-11, 300, kap, poll=True)
     torch_cuda.cuda.synchronize()
     sel = [0, 1, 16383, 16384, 32767, 32768, 49151, 49152, nmax - 1]
     par_o = O.source_params(g, wl["s"], wl["xi"], wl["eta"], src[sel])
@@ -482,8 +485,32 @@ def test_maximum_source_count(torch_cuda):
 
 
 @pytest.mark.slow
-def test_sph61_two_sources(torch_cuda):
+def test_sph61_all_sources_summed_kernels(torch_cuda):
+    """The 61^3 spherical workload with all of its 32 sources: iteration
+    counts, fields of every source and the kernels summed over all 32
+    (Eqs. (6)-(8)) against the oracle (its sources solved on parallel host
+    threads, summed in ascending source order)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
     wl = W.sph61(nsrc=32)
-    op = oracle_path(wl, wl["tol"], 300, R=wl["R"][:2], nsrc=2)
-    gp = gpu_path(torch_cuda, wl, wl["tol"], 300, R=wl["R"][:2], nsrc=2)
-    assert_parity(gp, op)
+    g, kap, tol = wl["grid"], wl["kappa"], wl["tol"]
+    gp = gpu_path(torch_cuda, wl, tol, 300, R=wl["R"])
+    par = O.source_params(g, wl["s"], wl["xi"], wl["eta"], wl["src"])
+
+    def solve(q):
+        tau, itf, cf, _ = O.forward(g, wl["s"], wl["xi"], wl["eta"], wl["src"][q], par[q], kap, tol, 300)
+        rhs = O.adjoint_rhs(g, wl["src"][q], par[q], wl["rec"], wl["R"][q])
+        lam, ita, ca, _ = O.adjoint(g, wl["s"], wl["xi"], wl["eta"], wl["src"][q], par[q], kap, tau, rhs, tol, 300)
+        return tau, (itf if cf else -itf), lam, (ita if ca else -ita)
+
+    with ThreadPoolExecutor(max(1, min(16, len(os.sched_getaffinity(0))))) as ex:
+        res = list(ex.map(solve, range(32)))
+    grad = np.zeros((3,) + tuple(g["n"]))
+    for q, (tau, itf, lam, ita) in enumerate(res):
+        assert itf == gp["it_f"][q] and ita == gp["it_a"][q], q
+        assert rel_inf(gp["tau"][q], tau) <= TOL_TAU, q
+        assert rel_inf(gp["lam"][q], lam) <= TOL_ADJ, q
+        O.kernel(g, wl["s"], wl["xi"], wl["eta"], wl["src"][q], par[q], kap, tau, lam, grad)
+    assert (gp["it_f"] > 0).all() and (gp["it_a"] > 0).all()
+    for c in range(3):
+        assert rel_inf(gp["grad"][c], grad[c]) <= TOL_ADJ, (c, rel_inf(gp["grad"][c], grad[c]))

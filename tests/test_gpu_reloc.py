@@ -42,7 +42,7 @@ def test_reloc_parity(torch_cuda, nfield, nev):
     s, xi, eta = (_dev(torch, wl[k]) for k in ("s", "xi", "eta"))
     recd, evd = _dev(torch, rec), _dev(torch, ev)
     par = api.source_params(g, s, xi, eta, recd)
-    tau, st = api.forward(g, s, xi, eta, recd, par, tol, 2000, kappa)
+    tau, st = api.forward(g, s, xi, eta, recd, par, tol, 2000, kappa, poll=True)
     T = api.reloc_times(g, recd, par, tau, evd, _dev(torch, t0))
     chi, R = api.misfit(T, _dev(torch, T_obs), None, _dev(torch, pairs, torch.int32), None, 0.8, 1.2,
                         cr=(_dev(torch, off, torch.int32), _dev(torch, cpair, torch.int32)), gamma=0.6)

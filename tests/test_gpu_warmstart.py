@@ -23,7 +23,7 @@ def _setup(torch, nsrc, first=0):
 
 def _solve(torch, wl, s, xi, eta, src, par, tol, init=None):
     from paper_2412_00031_amd import api
-    return api.forward(wl["grid"], s, xi, eta, src, par, tol, 20000, wl["kappa"], tau_init=init)
+    return api.forward(wl["grid"], s, xi, eta, src, par, tol, 20000, wl["kappa"], tau_init=init, poll=True)
 
 
 def test_shipped_network_cuts_sweeps_at_equal_accuracy(torch_cuda):
