@@ -30,6 +30,7 @@ int fail(int code, const char* fmt, ...) {
 namespace {
 using tt::fail;
 
+
 #define TT_HIP(call)                                                                          \
     do {                                                                                      \
         hipError_t e_ = (call);                                                               \
@@ -451,21 +452,35 @@ template <typename Launch>
 int run_async(std::vector<Group>& gs, bool use_graph, Launch launch_one) {
     if (use_graph) reclaim_graphs();  // (never while the caller's stream is captured: it queries events)
     int rc = TT_OK;
-    for (auto& g : gs) {
-        const int it = g.P.max_iter;
-        if (use_graph && it >= kGraphChunk) {
-            if ((rc = capture_iterations([&](hipStream_t s_) { launch_one(g, s_); }, kGraphChunk, &g.exec)))
-                return rc;
-            for (int q = 0; q + kGraphChunk <= it; q += kGraphChunk) TT_HIP(hipGraphLaunch(g.exec, g.st));
-            for (int q = it - it % kGraphChunk; q < it; ++q) launch_one(g, g.st);
-            hipEvent_t done = nullptr;
-            TT_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
-            TT_HIP(hipEventRecord(done, g.st));
-            g_retired.push_back({g.exec, done});
-            g.exec = nullptr;
-        } else {
-            for (int q = 0; q < it; ++q) launch_one(g, g.st);
+    const int chunk = use_graph ? kGraphChunk : 1;
+    for (auto& g : gs)
+        if (use_graph && g.P.max_iter >= kGraphChunk &&
+            (rc = capture_iterations([&](hipStream_t s_) { launch_one(g, s_); }, kGraphChunk, &g.exec)))
+            return rc;
+    // Enqueue round-robin over the groups, one iteration (or one replayed
+    // chunk) at a time: a launch blocks the host while its stream's queue is
+    // full, and enqueuing one group's whole budget first would hold the other
+    // groups back until that group had nearly finished.
+    int maxit = 0;
+    for (auto& g : gs) maxit = g.P.max_iter > maxit ? g.P.max_iter : maxit;
+    for (int q = 0; q < maxit; q += chunk) {
+        for (auto& g : gs) {
+            const int it = g.P.max_iter;
+            if (q >= it) continue;
+            if (g.exec && q + kGraphChunk <= it) {
+                TT_HIP(hipGraphLaunch(g.exec, g.st));
+            } else {
+                for (int r = q; r < it && r < q + chunk; ++r) launch_one(g, g.st);
+            }
         }
+    }
+    for (auto& g : gs) {
+        if (!g.exec) continue;
+        hipEvent_t done = nullptr;
+        TT_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        TT_HIP(hipEventRecord(done, g.st));
+        g_retired.push_back({g.exec, done});
+        g.exec = nullptr;
     }
     TT_HIP(hipGetLastError());
     return TT_OK;
@@ -573,6 +588,51 @@ int check_ptrs(std::initializer_list<const void*> ps) {
     return TT_OK;
 }
 
+// Forward solve on a workspace that the caller checked (tt_forward) or the
+// scratch array provides (tt_forward_noalloc, one source group); the plan
+// checks are done by the callers.
+int forward_run(const tt::Geo& G, const double* s, const double* xi, const double* eta, int32_t nsrc,
+                const double* src_pos, const double* src_par, const double* tau_init, const tt_opts* opts, double* tau,
+                int32_t* status, void* ws, size_t ws_bytes, int groups, hipStream_t caller) {
+    int rc = TT_OK;
+    std::vector<Group> gs;
+    if ((rc = make_groups(G, nsrc, groups, 0, ws, ws_bytes, opts, caller, gs))) return rc;
+    std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
+    for (int q = 0; q < groups; ++q) {
+        Group& g = gs[q];
+        const int q0 = group_begin(nsrc, groups, q);
+        g.P.eps_hist = opts->eps_hist ? opts->eps_hist + (long long)q0 * opts->max_iter : nullptr;
+        if (opts->flags & TT_FLAG_TIME_SWEEPS) g.P.timing = &ev;
+        tt::launch_tables(g.P, g.st);
+        tt::launch_src_setup(g.P, src_pos + 3LL * q0, src_par + 3LL * q0, g.st);
+        g.a = tt::make_args(g.P, s, xi, eta, tau + (long long)q0 * G.N, status + q0);
+        tt::launch_fwd_init(g.P, g.a, tau_init ? tau_init + (long long)q0 * G.N : nullptr, s, xi, eta, g.st);
+    }
+    TT_HIP(hipGetLastError());
+    const bool polled = polled_mode(opts);
+    const bool graph = (opts->flags & TT_FLAG_GRAPH) && !(opts->flags & TT_FLAG_TIME_SWEEPS) && !capturing(caller);
+    auto one = [&](Group& g, hipStream_t s_) { tt::launch_fwd_iteration(g.P, g.a, s_); };
+    rc = polled ? run_polled(gs, graph, one) : run_async(gs, graph, one);
+    collect_timing(ev, 0);
+    if (rc == TT_OK) rc = finish_groups(gs, caller, polled);
+    return rc;
+}
+
+// Argument and tiling checks shared by the forward entry points.
+int forward_checks(const tt_grid* grid, int32_t nsrc, const tt_opts* opts, std::initializer_list<const void*> ptrs,
+                   tt::Geo* G) {
+    int rc = check_grid(grid);
+    if (rc || (rc = check_opts(opts))) return rc;
+    if (nsrc < 0) return fail(TT_EINVAL, "nsrc < 0");
+    if (nsrc > 65535) return fail(TT_EINVAL, "nsrc > 65535");
+    if (nsrc > 0 && (rc = check_ptrs(ptrs))) return rc;
+    *G = make_geo(grid, tile_k_of(opts, 0));
+    tt::Plan P;
+    fill_plan(P, *G, 1);
+    if (P.max_plane_tiles > 65535) return fail(TT_EINVAL, "too many tiles per tile-plane; raise opts.tile_k");
+    return check_tiling(P);
+}
+
 }  // namespace
 
 extern "C" {
@@ -620,42 +680,11 @@ int tt_forward(const tt_grid* grid, const double* s, const double* xi, const dou
                const double* src_pos, const double* src_par, const double* tau_init, const tt_opts* opts, double* tau,
                int32_t* status, void* ws, size_t ws_bytes, void* stream) {
     g_err.clear();
-    int rc = check_grid(grid);
-    if (rc || (rc = check_opts(opts))) return rc;
-    if (nsrc < 0) return fail(TT_EINVAL, "nsrc < 0");
-    if (nsrc == 0) return TT_OK;
-    if (nsrc > 65535) return fail(TT_EINVAL, "nsrc > 65535");
-    if ((rc = check_ptrs({s, xi, eta, src_pos, src_par, tau, status, ws}))) return rc;
-    tt::Geo G = make_geo(grid, tile_k_of(opts, 0));
-    {
-        tt::Plan P;
-        fill_plan(P, G, 1);
-        if (P.max_plane_tiles > 65535) return fail(TT_EINVAL, "too many tiles per tile-plane; raise opts.tile_k");
-        if ((rc = check_tiling(P))) return rc;
-    }
-    const int groups = groups_of(opts, nsrc);
-    hipStream_t caller = (hipStream_t)stream;
-    std::vector<Group> gs;
-    if ((rc = make_groups(G, nsrc, groups, 0, ws, ws_bytes, opts, caller, gs))) return rc;
-    std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> ev;
-    for (int q = 0; q < groups; ++q) {
-        Group& g = gs[q];
-        const int q0 = group_begin(nsrc, groups, q);
-        g.P.eps_hist = opts->eps_hist ? opts->eps_hist + (long long)q0 * opts->max_iter : nullptr;
-        if (opts->flags & TT_FLAG_TIME_SWEEPS) g.P.timing = &ev;
-        tt::launch_tables(g.P, g.st);
-        tt::launch_src_setup(g.P, src_pos + 3LL * q0, src_par + 3LL * q0, g.st);
-        g.a = tt::make_args(g.P, s, xi, eta, tau + (long long)q0 * G.N, status + q0);
-        tt::launch_fwd_init(g.P, g.a, tau_init ? tau_init + (long long)q0 * G.N : nullptr, s, xi, eta, g.st);
-    }
-    TT_HIP(hipGetLastError());
-    const bool polled = polled_mode(opts);
-    const bool graph = (opts->flags & TT_FLAG_GRAPH) && !(opts->flags & TT_FLAG_TIME_SWEEPS) && !capturing(caller);
-    auto one = [&](Group& g, hipStream_t s_) { tt::launch_fwd_iteration(g.P, g.a, s_); };
-    rc = polled ? run_polled(gs, graph, one) : run_async(gs, graph, one);
-    collect_timing(ev, 0);
-    if (rc == TT_OK) rc = finish_groups(gs, caller, polled);
-    return rc;
+    tt::Geo G;
+    int rc = forward_checks(grid, nsrc, opts, {s, xi, eta, src_pos, src_par, tau, status, ws}, &G);
+    if (rc || nsrc == 0) return rc;
+    return forward_run(G, s, xi, eta, nsrc, src_pos, src_par, tau_init, opts, tau, status, ws, ws_bytes,
+                       groups_of(opts, nsrc), (hipStream_t)stream);
 }
 
 int tt_sample(const tt_grid* grid, int32_t nsrc, const double* src_pos, const double* src_par, const double* tau,
