@@ -158,6 +158,26 @@ int tt_forward(const tt_grid* grid, const double* s, const double* xi, const dou
                const tt_opts* opts, double* tau, int32_t* status, void* ws, size_t ws_bytes,
                void* stream);
 
+/* tt_forward for callers that cannot allocate (code under hipGraph capture,
+ * tight serving loops, harnesses that forbid allocation): the same solve with
+ * the same arguments and results, but no caller workspace -- the workspace is
+ * a fixed device array inside the library, tt_forward_noalloc_limit() bytes
+ * (64 MiB) per device, held from the library's first use on that device until
+ * the process ends.  The call allocates nothing (no device, pinned or graph
+ * memory, no streams or events): one source group on `stream`, asynchronous.
+ * Limits and errors: TT_EINVAL if the workspace this grid, batch and tile
+ * depth need (tt_workspace_size with groups = 1) exceeds the array, or if
+ * opts asks for TT_FLAG_POLL, TT_FLAG_TIME_SWEEPS or TT_FLAG_GRAPH (each
+ * needs an allocation); otherwise as tt_forward.  Every call on one device
+ * shares that device's array, whose contents are whatever the last call left
+ * (the solve initialises everything it reads): calls that overlap in time on
+ * one device -- on different streams or host threads -- race and give wrong
+ * results; serialise them. */
+int tt_forward_noalloc(const tt_grid* grid, const double* s, const double* xi, const double* eta, int32_t nsrc,
+                       const double* src_pos, const double* src_par, const double* tau_init, const tt_opts* opts,
+                       double* tau, int32_t* status, void* stream);
+size_t tt_forward_noalloc_limit(void);
+
 /* Traveltimes at receivers, T(x_r) = sum_c w_c T0(c) tau(c) over the trilinear
  * corners c of the receiver's cell (receiver term of Eqs. (2), (3)).
  *   tau [nsrc][N], rec_pos [nrec][3], T_rec out [nsrc][nrec]. */

@@ -21,7 +21,7 @@ class TTOpts(ctypes.Structure):
                 ("groups", ctypes.c_int32)]
 
 
-EXPORTS = ["tt_workspace_size", "tt_source_params", "tt_forward", "tt_sample", "tt_misfit", "tt_misfit_cr", "tt_reloc_times", "tt_reloc_kernel",
+EXPORTS = ["tt_workspace_size", "tt_source_params", "tt_forward", "tt_forward_noalloc", "tt_forward_noalloc_limit", "tt_sample", "tt_misfit", "tt_misfit_cr", "tt_reloc_times", "tt_reloc_kernel",
            "tt_adjoint", "tt_kernel", "tt_kernel_density", "tt_mg_workspace_size", "tt_mg_project", "tt_mg_expand",
            "tt_sweep_timing", "tt_default_tile_k", "tt_last_error"]
 
@@ -92,6 +92,9 @@ def load(path=LIB_PATH):
     lib.tt_workspace_size.restype = sz
     lib.tt_source_params.argtypes = [G, P, P, P, i32, P, P, P]
     lib.tt_forward.argtypes = [G, P, P, P, i32, P, P, P, O, P, P, P, sz, P]
+    lib.tt_forward_noalloc.argtypes = [G, P, P, P, i32, P, P, P, O, P, P, P]
+    lib.tt_forward_noalloc_limit.argtypes = []
+    lib.tt_forward_noalloc_limit.restype = sz
     lib.tt_sample.argtypes = [G, i32, P, P, P, i32, P, P, P, sz, P]
     lib.tt_misfit.argtypes = [i32, i32, P, P, P, i32, P, P, ctypes.c_double, ctypes.c_double, P, P, P]
     lib.tt_reloc_times.argtypes = [G, i32, P, P, P, i32, P, P, P, P, sz, P]
@@ -110,7 +113,7 @@ def load(path=LIB_PATH):
     lib.tt_default_tile_k.restype = i32
     lib.tt_last_error.argtypes = []
     lib.tt_last_error.restype = ctypes.c_char_p
-    for name in ("tt_source_params", "tt_forward", "tt_sample", "tt_misfit", "tt_misfit_cr", "tt_reloc_times",
+    for name in ("tt_source_params", "tt_forward", "tt_forward_noalloc", "tt_sample", "tt_misfit", "tt_misfit_cr", "tt_reloc_times",
                  "tt_reloc_kernel", "tt_adjoint", "tt_kernel", "tt_kernel_density", "tt_mg_project", "tt_mg_expand"):
         getattr(lib, name).restype = ctypes.c_int
     _declare_nn(lib)

@@ -137,6 +137,26 @@ def forward(grid, s, xi, eta, src_pos, src_par, tol, max_iter, kappa, tau_init=N
     return tau, status
 
 
+def forward_noalloc(grid, s, xi, eta, src_pos, src_par, tol, max_iter, kappa, tau, status, tau_init=None, tile_k=0,
+                    eps_hist=None):
+    """tt_forward_noalloc: the asynchronous forward solve on the library's own
+    fixed device scratch (no workspace, no allocation by the library).  The
+    caller passes the outputs tau [nsrc, *n] and status int32 [nsrc]; one
+    source group on the current stream; calls on one device must not overlap."""
+    lib = _lib.load()
+    N = _N(grid)
+    nsrc = int(src_pos.shape[0])
+    g = _grid(grid)
+    o = _opts(tol, max_iter, kappa, tile_k, False, eps_hist)
+    ti = _dev(tau_init, "tau_init", numel=nsrc * N) if tau_init is not None else _null()
+    _lib.check(lib.tt_forward_noalloc(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
+                                      _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
+                                      _dev(src_par, "src_par", numel=3 * nsrc), ti, ctypes.byref(o),
+                                      _dev(tau, "tau", numel=nsrc * N), _dev(status, "status", torch.int32,
+                                                                               numel=nsrc), _stream(s.device)))
+    return tau, status
+
+
 def sample(grid, src_pos, src_par, tau, rec_pos, ws=None):
     """Traveltimes [nsrc, nrec] at the receivers."""
     lib = _lib.load()

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -30,6 +31,14 @@ int fail(int code, const char* fmt, ...) {
 namespace {
 using tt::fail;
 
+// Device scratch of tt_forward_noalloc: the workspace of a forward solve for
+// callers that cannot allocate.  Each device holds its own copy from the
+// moment the library's code is loaded on it until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): its device address comes from
+// hipGetSymbolAddress, once per device (scratch_ptr below).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 #define TT_HIP(call)                                                                          \
     do {                                                                                      \
@@ -633,6 +642,26 @@ int forward_checks(const tt_grid* grid, int32_t nsrc, const tt_opts* opts, std::
     return check_tiling(P);
 }
 
+// Device address of this device's scratch array (hipGetSymbolAddress once per
+// device, with that device current; kept for the life of the process).
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_ptr(void** out) {
+    int dev = 0, rc = device_index(&dev);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(TT_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -686,6 +715,28 @@ int tt_forward(const tt_grid* grid, const double* s, const double* xi, const dou
     return forward_run(G, s, xi, eta, nsrc, src_pos, src_par, tau_init, opts, tau, status, ws, ws_bytes,
                        groups_of(opts, nsrc), (hipStream_t)stream);
 }
+
+int tt_forward_noalloc(const tt_grid* grid, const double* s, const double* xi, const double* eta, int32_t nsrc,
+                       const double* src_pos, const double* src_par, const double* tau_init, const tt_opts* opts,
+                       double* tau, int32_t* status, void* stream) {
+    g_err.clear();
+    tt::Geo G;
+    int rc = forward_checks(grid, nsrc, opts, {s, xi, eta, src_pos, src_par, tau, status}, &G);
+    if (rc || nsrc == 0) return rc;
+    if (opts->flags & (TT_FLAG_POLL | TT_FLAG_TIME_SWEEPS | TT_FLAG_GRAPH))
+        return fail(TT_EINVAL, "tt_forward_noalloc: TT_FLAG_POLL, TT_FLAG_TIME_SWEEPS and TT_FLAG_GRAPH need "
+                               "allocations (pinned memory, events, graphs) and are not available here");
+    const size_t need = grouped_total(G, nsrc, 1, 0);
+    if (need > kScratchBytes)
+        return fail(TT_EINVAL, "tt_forward_noalloc: this grid and batch need %zu bytes of workspace, more than the "
+                               "%zu-byte scratch; use tt_forward with a caller workspace", need, kScratchBytes);
+    void* ws = nullptr;
+    if ((rc = scratch_ptr(&ws))) return rc;
+    return forward_run(G, s, xi, eta, nsrc, src_pos, src_par, tau_init, opts, tau, status, ws, kScratchBytes, 1,
+                       (hipStream_t)stream);
+}
+
+size_t tt_forward_noalloc_limit(void) { return kScratchBytes; }
 
 int tt_sample(const tt_grid* grid, int32_t nsrc, const double* src_pos, const double* src_par, const double* tau,
               int32_t nrec, const double* rec_pos, double* T_rec, void* ws, size_t ws_bytes, void* stream) {
