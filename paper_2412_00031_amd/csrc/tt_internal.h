@@ -77,8 +77,9 @@ __host__ __device__ inline void tile_decode(const Geo& G, int p, int s0, int b, 
     TJ = s - TI;
     TK = p - s;
 }
-// LDS words per staged column: tk + 2 entries
-__host__ __device__ inline int tile_pitch(int tk) { return tk + 2; }
+// LDS doubles per staged column: the tk + 2 entries, rounded up to an even
+// count (the window is staged two doubles per lane and load)
+__host__ __device__ inline int tile_pitch(int tk) { return (tk + 3) & ~1; }
 
 // Per-source constants, produced on the device by k_src_setup.
 struct Src {

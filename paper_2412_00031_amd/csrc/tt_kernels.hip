@@ -267,14 +267,29 @@ __device__ __forceinline__ TileCtx tile_ctx(const Geo& G, const Src& S, int plan
 // are never read).  Loads and stores move contiguous column segments.
 constexpr int kTC = kBI + 2;
 
-// Staging covers the tile's columns as one flat list of (column, k) elements
-// spread over all 64 lanes; each lane walks its elements with running indices
-// (no division or multiplication per element).  Loads are issued
-// unconditionally from addresses that are always valid (clamped), kStageBatch
-// at a time, and only the LDS writes are predicated: a load inside a
-// divergent branch would make the compiler wait for it before the branch
-// joins, serialising the staging.
-constexpr int kStageBatch = 16;
+// Staging.  The staged window is always the full (8+2) x (8+2) columns
+// (columns past a ragged tile's end are staged from clamped, valid rows and
+// never read) of Lp = tile_pitch(tk) slots; slot q of a column holds entry
+// kk = q in sweeps with s2 > 0 and kk = Lp - 1 - q in sweeps with s2 < 0, so
+// that consecutive slots always hold consecutive nodes in memory (ascending
+// k).  The window is loaded with direct global-to-LDS loads of 16 bytes per
+// lane: each load moves 64 slot pairs (1 KiB of LDS, lane l writing pair l),
+// no data passes through registers, every load of the window is in flight at
+// once and the wave waits once.  A pair whose slots are not both node entries
+// (k' outside [-1, m2]) reads neighbouring memory of the field array that is
+// never used; its address is clamped into the array.
+typedef __attribute__((address_space(3))) char lds_char;
+typedef __attribute__((address_space(3))) void lds_void;
+
+// LDS bytes of a staged tile: the window's slot pairs (the last load writes
+// only the lanes that hold a pair of the window)
+__host__ __device__ inline int stage_bytes(int tk) { return kTC * kTC * tile_pitch(tk) * 8; }
+
+// LDS slot of entry kk of a column (the mirror for sweeps with s2 < 0)
+template <int S2>
+__device__ __forceinline__ int slot_of(int kk, int Lp) {
+    return S2 > 0 ? kk : Lp - 1 - kk;
+}
 
 // Absolute index along axis a of staged column/row ci (0 = upstream halo):
 // origin + sgn * ci.
@@ -283,104 +298,46 @@ __device__ __forceinline__ int stage_origin(const Geo& G, int a, int T) {
     return SGN > 0 ? T * kBI : G.n[a] - 1 - T * kBI;
 }
 
+// xlo, xhi: the element range of the field array around fld that may be read
 template <int DIR>
-__device__ __forceinline__ void stage_tile_incr(const Geo& G, const TileCtx& c, const double* __restrict__ fld,
-                                                double* lds, int Lp) {
+__device__ __forceinline__ void stage_tile(const Geo& G, const TileCtx& c, const double* __restrict__ fld,
+                                           long long xlo, long long xhi, double* lds) {
     using D = Dir<DIR>;
-    const int Lk = G.tk + 2;                          // staged entries per column
-    const int nj = c.ext_j + 2, ncol = (c.ext_i + 2) * nj;
-    const int total = ncol * Lk;
-    const long long si = D::s0 * G.si, sj = D::s1 * G.sj;
-    const long long base = nidx(G, stage_origin<D::s0>(G, 0, c.TI), stage_origin<D::s1>(G, 1, c.TJ), c.kbase);
-    const int kmax = G.m[2];
-    // element e = lane + 64 r  <->  column col = e / Lk = ci nj + cj, kk = e % Lk
-    int col = c.lane / Lk, kk = c.lane - col * Lk;
-    int ci = col / nj, cj = col - ci * nj;
-    long long gcol = ci * si + cj * sj;  // field offset of the column from base
-    int dq = kk - ci - cj;               // k' = kq0 + dq
-    int loff = (ci * kTC + cj) * Lp + kk;
-    const int dcol = 64 / Lk, dkk = 64 - dcol * Lk;
-    const long long g_step = dcol * sj, g_jwrap = si - nj * sj;
-    const int l_step = dcol * Lp + dkk, l_kwrap = Lp - Lk, l_jwrap = (kTC - nj) * Lp;
-    for (int e0 = 0; e0 < total; e0 += 64 * kStageBatch) {
-        double v[kStageBatch];
-        int lo[kStageBatch];
-#pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-            const bool ok = col < ncol;
-            const int kp = min(max(c.kq0 + dq, -1), kmax);
-            v[u] = fld[base + (ok ? gcol + D::s2 * kp : 0)];
-            lo[u] = ok ? loff : -1;
-            col += dcol;
-            cj += dcol;
-            kk += dkk;
-            gcol += g_step;
-            dq += dkk - dcol;
-            loff += l_step;
-            const bool kw = kk >= Lk;  // selects, not branches
-            kk -= kw ? Lk : 0;
-            col += kw;
-            cj += kw;
-            gcol += kw ? sj : 0;
-            dq -= kw ? Lk + 1 : 0;
-            loff += kw ? l_kwrap : 0;
-            if (dcol < nj) {  // wave-uniform: at most one row wrap
-                const bool jw = cj >= nj;
-                cj -= jw ? nj : 0;
-                gcol += jw ? g_jwrap : 0;
-                dq += jw ? nj - 1 : 0;
-                loff += jw ? l_jwrap : 0;
-            } else {
-                while (cj >= nj) {
-                    cj -= nj;
-                    gcol += g_jwrap;
-                    dq += nj - 1;
-                    loff += l_jwrap;
-                }
-            }
+    const int Lp = tile_pitch(G.tk);
+    const int npair = kTC * kTC * Lp / 2;
+    const int oi = stage_origin<D::s0>(G, 0, c.TI), oj = stage_origin<D::s1>(G, 1, c.TJ);
+    // pair p = 64 r + lane: slots q, q + 1 (q even) of column col = 2p / Lp;
+    // p advances by 64 per load, i.e. 128 slots
+    int col = (2 * c.lane) / Lp, q = 2 * c.lane - col * Lp;
+    int ci = col / kTC, cj = col - ci * kTC;
+    const int dcol = 128 / Lp, dq = 128 - dcol * Lp;
+    lds_char* lb = (lds_char*)lds;  // the dynamic shared array, in the LDS address space
+    for (int p0 = 0; p0 < npair; p0 += 64) {
+        const int i = min(max(oi + D::s0 * ci, 0), G.n[0] - 1);
+        const int j = min(max(oj + D::s1 * cj, 0), G.n[1] - 1);
+        // absolute k of the pair's lower slot (the node of slot q + 1 is k + 1)
+        const int kd = c.kq0 - ci - cj;
+        const int klo = D::s2 > 0 ? c.kbase + kd + q : c.kbase - (kd + Lp - 1 - q);
+        long long x = (long long)i * G.si + (long long)j * G.sj + klo;
+        x = x < xlo ? xlo : (x > xhi ? xhi : x);
+        if (p0 + 64 <= npair || p0 + c.lane < npair)  // the last load: lanes of the window only
+            __builtin_amdgcn_global_load_lds(fld + x, (lds_void*)(lb + 16 * p0), 16, 0, 0);
+        q += dq;
+        cj += dcol;
+        if (q >= Lp) {
+            q -= Lp;
+            ++cj;
         }
-#pragma unroll
-        for (int u = 0; u < kStageBatch; ++u)
-            if (lo[u] >= 0) lds[lo[u]] = v[u];
+        while (cj >= kTC) {
+            cj -= kTC;
+            ++ci;
+        }
     }
+    __builtin_amdgcn_s_waitcnt(0);  // every load of the window (and any earlier one) has landed
 }
 
-// Same staging with each element's column decoded by division: fewer live
-// scalar values than the running-index form (the forward kernel, short of
-// scalar registers, spills with that form), more vector registers.
-template <int DIR>
-__device__ __forceinline__ void stage_tile_div(const Geo& G, const TileCtx& c, const double* __restrict__ fld,
-                                               double* lds, int Lp) {
-    using D = Dir<DIR>;
-    const int Lk = G.tk + 2;
-    const int nj = c.ext_j + 2, ncol = (c.ext_i + 2) * nj;
-    const int total = ncol * Lk;
-    const long long si = D::s0 * G.si, sj = D::s1 * G.sj;
-    const long long base = nidx(G, stage_origin<D::s0>(G, 0, c.TI), stage_origin<D::s1>(G, 1, c.TJ), c.kbase);
-    int col = c.lane / Lk, kk = c.lane - col * Lk;
-    const int dcol = 64 / Lk, dkk = 64 - dcol * Lk;
-    for (int e0 = 0; e0 < total; e0 += 64 * kStageBatch) {
-        double v[kStageBatch];
-        int lo[kStageBatch];
-#pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-            const int cc = min(col, ncol - 1);
-            const int ci = cc / nj, cj = cc - ci * nj;
-            const int kp = min(max(c.kq0 - ci - cj + kk, -1), G.m[2]);
-            v[u] = fld[base + ci * si + cj * sj + D::s2 * kp];
-            lo[u] = col < ncol ? (ci * kTC + cj) * Lp + kk : -1;
-            col += dcol;
-            kk += dkk;
-            if (kk >= Lk) {
-                kk -= Lk;
-                ++col;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kStageBatch; ++u)
-            if (lo[u] >= 0) lds[lo[u]] = v[u];
-    }
-}
+// Write-back stores are issued kStageBatch at a time per lane.
+constexpr int kStageBatch = 16;
 
 // Write back the tile's own nodes: entries 1..tk of its columns whose k' is
 // an interior node (the others are halo or outside the column).
@@ -400,10 +357,12 @@ __device__ __forceinline__ void unstage_tile(const Geo& G, const TileCtx& c, dou
     int li = col / nj, lj = col - li * nj;
     long long gcol = li * si + lj * sj;
     int dq = q - li - lj;
-    int loff = ((li + 1) * kTC + lj + 1) * Lp + q + 1;
+    // LDS slot of entry q + 1: c0 + s2 q
+    constexpr int sg = D::s2;
+    int loff = ((li + 1) * kTC + lj + 1) * Lp + (sg > 0 ? 1 : Lp - 2) + sg * q;
     const int dcol = 64 / ek, dq_step = 64 - dcol * ek;
     const long long g_step = dcol * sj, g_jwrap = si - nj * sj;
-    const int l_step = dcol * Lp + dq_step, l_kwrap = Lp - ek, l_jwrap = (kTC - nj) * Lp;
+    const int l_step = dcol * Lp + sg * dq_step, l_kwrap = Lp - sg * ek, l_jwrap = (kTC - nj) * Lp;
     const int kq = c.kq0 - 1;
     for (int e0 = 0; e0 < total; e0 += 64 * kStageBatch) {
 #pragma unroll
@@ -488,7 +447,7 @@ __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane, int s0
     FwdSlot ring[kPre];
 #pragma unroll
     for (int u = 0; u < kPre; ++u) fwd_fetch<DIR>(c, mdl, t2, c.t0 + u, ring[u]);
-    stage_tile_div<DIR>(G, c, fld, lds, Lp);
+    stage_tile<DIR>(G, c, fld, -(long long)src * G.N, (long long)(a.nsrc - src) * G.N - 2, lds);
     __syncthreads();
 
     const int own = ((c.li + 1) * kTC + c.lj + 1) * Lp;
@@ -505,17 +464,19 @@ __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane, int s0
                     const int ka = c.kbase + D::s2 * kp;
                     if (!(c.fcol && (unsigned)(ka - S.fb[2]) <= 1u)) {
                         // sweep-relative neighbours: "up" = already updated this sweep
-                        const int o = own + t;
-                        const double cur = lds[o + 1];
-                        const double up_i = lds[o - kTC * Lp], dn_i = lds[o + kTC * Lp + 2];
-                        const double up_j = lds[o - Lp], dn_j = lds[o + Lp + 2];
-                        const double up_k = lds[o], dn_k = lds[o + 2];
+                        // slot of entry t (mirrored columns when s2 < 0): entry t + 1 is at o + s2
+                        constexpr int sg = D::s2;
+                        const int o = sg > 0 ? own + t : own + Lp - 1 - t;
+                        const double cur = lds[o + sg];
+                        const double up_i = lds[o - kTC * Lp], dn_i = lds[o + kTC * Lp + 2 * sg];
+                        const double up_j = lds[o - Lp], dn_j = lds[o + Lp + 2 * sg];
+                        const double up_k = lds[o], dn_k = lds[o + 2 * sg];
                         const double m0 = D::s0 > 0 ? up_i : dn_i, p0 = D::s0 > 0 ? dn_i : up_i;
                         const double m1 = D::s1 > 0 ? up_j : dn_j, p1 = D::s1 > 0 ? dn_j : up_j;
                         const double m2 = D::s2 > 0 ? up_k : dn_k, p2 = D::s2 > 0 ? dn_k : up_k;
                         const double nv = lf_update<COORD>(G, S, cl, r.c2, r.s2, a.kappa, r.sx, r.xi, r.eta, cur, m0,
                                                            p0, m1, p1, m2, p2);
-                        lds[o + 1] = nv;
+                        lds[o + sg] = nv;
                         eps += fabs(nv - cur);
                     }
                 }
@@ -819,7 +780,7 @@ __device__ __forceinline__ void adj_tile(const SweepArgs& a, const Src& S, const
     AdjSlot ring[kPreAdj];
 #pragma unroll
     for (int u = 0; u < kPreAdj; ++u) adj_fetch<DIR, RHS>(c, cf, rh, xb, c.t0 + u, ring[u]);
-    stage_tile_incr<DIR>(G, c, fld, lds, Lp);
+    stage_tile<DIR>(G, c, fld, -(long long)src * G.N, (long long)(a.nsrc - src) * G.N - 2, lds);
     __syncthreads();
 
     const int own = ((c.li + 1) * kTC + c.lj + 1) * Lp;
@@ -835,11 +796,13 @@ __device__ __forceinline__ void adj_tile(const SweepArgs& a, const Src& S, const
                 if (c.colv && t < c.t1 && (unsigned)kp < (unsigned)kmax) {
                     const int ka = c.kbase + D::s2 * kp;
                     if (!(c.fcol && (unsigned)(ka - S.fb[2]) <= 1u)) {
-                        const int o = own + t;
-                        const double cur = lds[o + 1];
-                        const double up_i = lds[o - kTC * Lp], dn_i = lds[o + kTC * Lp + 2];
-                        const double up_j = lds[o - Lp], dn_j = lds[o + Lp + 2];
-                        const double up_k = lds[o], dn_k = lds[o + 2];
+                        // slot of entry t (mirrored columns when s2 < 0): entry t + 1 is at o + s2
+                        constexpr int sg = D::s2;
+                        const int o = sg > 0 ? own + t : own + Lp - 1 - t;
+                        const double cur = lds[o + sg];
+                        const double up_i = lds[o - kTC * Lp], dn_i = lds[o + kTC * Lp + 2 * sg];
+                        const double up_j = lds[o - Lp], dn_j = lds[o + Lp + 2 * sg];
+                        const double up_k = lds[o], dn_k = lds[o + 2 * sg];
                         // record: coefficients of lambda(x + e_a), lambda(x - e_a) at 2a, 2a + 1,
                         // divided by the diagonal like the right-hand side.  The
                         // sweep-downstream terms (values of the previous sweep) go first, the
@@ -853,7 +816,7 @@ __device__ __forceinline__ void adj_tile(const SweepArgs& a, const Src& S, const
                         acc -= r.r[dj ^ 1] * up_j;
                         acc -= r.r[dk ^ 1] * up_k;
                         const double nv = acc;
-                        lds[o + 1] = nv;
+                        lds[o + sg] = nv;
                         dsum += fabs(nv - cur);
                         if (last) asum += fabs(nv);
                     }
@@ -1262,7 +1225,7 @@ void launch_fwd_init(const Plan& P, const SweepArgs& a, const double* tau_init, 
     hipLaunchKernelGGL(k_solve_init, dim3(fill_blocks(P.G.N), P.nsrc), dim3(256), 0, st, a, tau_init, 1.0, 1.0);
 }
 
-static size_t tile_lds_bytes(const Geo& G) { return sizeof(double) * kTC * kTC * (size_t)tile_pitch(G.tk); }
+static size_t tile_lds_bytes(const Geo& G) { return (size_t)stage_bytes(G.tk); }
 
 // Event pair around the tile-plane launches of one directional sweep when
 // timing is on; the launch count of the group is recorded with it.
