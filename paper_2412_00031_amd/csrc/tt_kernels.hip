@@ -275,9 +275,11 @@ constexpr int kTC = kBI + 2;
 // k).  The window is loaded with direct global-to-LDS loads of 16 bytes per
 // lane: each load moves 64 slot pairs (1 KiB of LDS, lane l writing pair l),
 // no data passes through registers, every load of the window is in flight at
-// once and the wave waits once.  A pair whose slots are not both node entries
-// (k' outside [-1, m2]) reads neighbouring memory of the field array that is
-// never used; its address is clamped into the array.
+// once and the wave waits once.  Pairs with no node entry (k' outside
+// [-1, m2]) and pairs of columns past a ragged tile's halo are not loaded
+// (their slots are never read); a pair with one node entry reads one
+// neighbouring element of the field array that is never used (its address is
+// clamped into the array).
 typedef __attribute__((address_space(3))) char lds_char;
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -320,7 +322,12 @@ __device__ __forceinline__ void stage_tile(const Geo& G, const TileCtx& c, const
         const int klo = D::s2 > 0 ? c.kbase + kd + q : c.kbase - (kd + Lp - 1 - q);
         long long x = (long long)i * G.si + (long long)j * G.sj + klo;
         x = x < xlo ? xlo : (x > xhi ? xhi : x);
-        if (p0 + 64 <= npair || p0 + c.lane < npair)  // the last load: lanes of the window only
+        // k' of the pair's entries: [kpa, kpa + 1] (s2 > 0) or [kpa - 1, kpa] (s2 < 0)
+        const int kpa = D::s2 > 0 ? kd + q : kd + Lp - 1 - q;
+        const bool node = D::s2 > 0 ? (kpa >= -2 && kpa <= G.m[2]) : (kpa >= -1 && kpa <= G.m[2] + 1);
+        // only pairs that hold a node entry of a column the tile reads (its own
+        // columns and their i'/j' halo), and in the last load only the window's lanes
+        if (node && ci < c.ext_i + 2 && cj < c.ext_j + 2 && (p0 + 64 <= npair || p0 + c.lane < npair))
             __builtin_amdgcn_global_load_lds(fld + x, (lds_void*)(lb + 16 * p0), 16, 0, 0);
         q += dq;
         cj += dcol;
