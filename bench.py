@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="use the library's default tile depths")
     ap.add_argument("--no-sweep-timing", action="store_true",
                     help="skip the per-launch sweep events (roofline then unmeasured)")
+    ap.add_argument("--obs", choices=("true-model", "straight"), default="true-model",
+                    help="observed times: a forward solve in the independent true model (default), or straight-line "
+                         "times (no solve before the measured steps; for counter runs)")
     ap.add_argument("--max-iter", type=int, default=1000,
                     help="iteration cap of the host-polled calibration and comparison steps")
     ap.add_argument("--budget-margin", type=int, default=8,
@@ -349,16 +352,19 @@ def main():
     nsrc = args.nsrc
     lib = _lib.load()
 
-    # observations: forward solve in the independent "true" model (untimed)
-    st_, xt_, et_ = t(wl["s_true"]), t(wl["xi_true"]), t(wl["eta_true"])
-    par_t = api.source_params(g, st_, xt_, et_, src)
-    tau_t, st_t = api.forward(g, st_, xt_, et_, src, par_t, tol, 1000, kappa, poll=True)
-    T_obs = api.sample(g, src, par_t, tau_t, rec)
-    del tau_t
-    torch.cuda.synchronize()
-    if (st_t <= 0).any():
-        sys.exit("observations: the true-model forward solve did not converge")
-    log("observations ready")
+    if args.obs == "true-model":
+        # observations: forward solve in the independent "true" model (untimed)
+        st_, xt_, et_ = t(wl["s_true"]), t(wl["xi_true"]), t(wl["eta_true"])
+        par_t = api.source_params(g, st_, xt_, et_, src)
+        tau_t, st_t = api.forward(g, st_, xt_, et_, src, par_t, tol, 1000, kappa, poll=True)
+        T_obs = api.sample(g, src, par_t, tau_t, rec)
+        del tau_t
+        torch.cuda.synchronize()
+        if (st_t <= 0).any():
+            sys.exit("observations: the true-model forward solve did not converge")
+    else:
+        T_obs = t(W.straight_line_times(g, wl["src"], wl["rec"], 6.4))
+    log(f"observations ready ({args.obs})")
 
     tk_f = args.tile_k_fwd or args.tile_k
     tk_a = args.tile_k_adj or args.tile_k
