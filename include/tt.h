@@ -77,7 +77,7 @@ typedef struct tt_opts {
     int32_t max_iter;  /* >= 1 */
     double kappa;      /* Lax-Friedrichs viscosity factor, >= max sqrt(1 + 2|xi|) */
     int32_t tile_k;    /* k-extent of one sweep tile, 1..62; 0 = library default
-                          (16 for tt_forward, 28 for tt_adjoint) */
+                          (tt_default_tile_k) */
     int32_t flags;     /* bit 0 (TT_FLAG_TIME_SWEEPS): time the sweep kernels with a HIP
                           event pair around the tile-plane launches of every
                           directional sweep on the call's stream (tt_sweep_timing) */
@@ -126,6 +126,14 @@ typedef struct tt_opts {
  * every source has converged, and returns after completion.  Results are
  * bit-identical either way. */
 #define TT_FLAG_POLL 8
+/* bit 4 (tt_adjoint; also pass it to tt_workspace_size): keep one copy of the
+ * adjoint's per-node coefficient records, in node order (48 bytes per node
+ * and source), instead of four row-coalesced copies laid out so that every
+ * sweep direction reads whole cache lines (4 x 48 bytes x n0 (n1 + n2 - 1)
+ * n1p per source, about 9x the compact size at 101^3).  For batches whose
+ * workspace would not fit otherwise; the sweeps are slower (about 30 % at
+ * 101^3 x 128 sources).  Results are bit-identical. */
+#define TT_FLAG_COMPACT_ADJOINT 16
 
 /* Bytes of device workspace needed by tt_forward (which = 0), tt_adjoint
  * (which = 1), tt_sample (which = 2) or tt_kernel (which = 3) for this grid,

@@ -27,7 +27,7 @@ def _grid(grid):
 
 
 def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None, graph=False, groups=0, continuous=False,
-          poll=False):
+          poll=False, compact=False):
     o = _lib.TTOpts()
     o.groups = int(groups)
     o.eps_hist = _dev(eps_hist, "eps_hist").value if eps_hist is not None else None
@@ -36,7 +36,8 @@ def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None, grap
     o.kappa = float(kappa)
     o.tile_k = int(tile_k)
     o.flags = ((_lib.TT_FLAG_TIME_SWEEPS if time_sweeps else 0) | (_lib.TT_FLAG_GRAPH if graph else 0)
-               | (_lib.TT_FLAG_CONTINUOUS_ADJOINT if continuous else 0) | (_lib.TT_FLAG_POLL if poll else 0))
+               | (_lib.TT_FLAG_CONTINUOUS_ADJOINT if continuous else 0) | (_lib.TT_FLAG_POLL if poll else 0)
+               | (_lib.TT_FLAG_COMPACT_ADJOINT if compact else 0))
     return o
 
 
@@ -77,15 +78,16 @@ def _N(grid):
     return int(n[0]) * int(n[1]) * int(n[2])
 
 
-def workspace(grid, nsrc, which, tile_k=0, device=None, groups=0, time_sweeps=False):
+def workspace(grid, nsrc, which, tile_k=0, device=None, groups=0, time_sweeps=False, compact=False):
     """Device workspace (uint8 tensor) for forward (0), adjoint (1), sample (2), kernel (3);
-    groups / time_sweeps as for the solve that will use it (its size depends on
-    the number of source groups).  An empty batch needs no workspace: zero bytes."""
+    groups / time_sweeps / compact as for the solve that will use it (its size
+    depends on the number of source groups and, for the adjoint, on the record
+    layout).  An empty batch needs no workspace: zero bytes."""
     lib = _lib.load()
     if int(nsrc) == 0:
         return torch.empty(0, dtype=torch.uint8, device=device)
     g = _grid(grid)
-    o = _opts(1e-6, 1, 1.0, tile_k, time_sweeps=time_sweeps, groups=groups)
+    o = _opts(1e-6, 1, 1.0, tile_k, time_sweeps=time_sweeps, groups=groups, compact=compact)
     nbytes = lib.tt_workspace_size(ctypes.byref(g), int(nsrc), ctypes.byref(o), int(which))
     if nbytes == 0:
         raise ValueError("invalid grid or source count for the workspace")
@@ -250,10 +252,12 @@ def misfit_cr(T_rec, T_obs, cr_off, cr_pair, wcr, gamma, R, chi):
 
 def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, kappa, tile_k=0, ws=None,
             out=None, time_sweeps=False, eps_hist=None, graph=False, groups=0, continuous=False, poll=False,
-            status=None):
+            status=None, compact=False):
     """Batched adjoint solve.  Returns (lambda [nsrc, *n], status int32 [nsrc]);
     eps_hist, groups and poll as for forward.  continuous=True solves Eq. (5)
-    by upwind finite volumes and returns P s V in place of lambda."""
+    by upwind finite volumes and returns P s V in place of lambda.
+    compact=True keeps one node-order copy of the coefficient records (a
+    ninth of the workspace at 101^3; slower sweeps, identical results)."""
     lib = _lib.load()
     N = _N(grid)
     nsrc, nrec = int(src_pos.shape[0]), int(rec_pos.shape[0])
@@ -262,11 +266,11 @@ def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, 
     if status is None:
         status = torch.empty(nsrc, dtype=torch.int32, device=dev)
     if ws is None:
-        ws = workspace(grid, nsrc, 1, tile_k, dev, groups, time_sweeps)
+        ws = workspace(grid, nsrc, 1, tile_k, dev, groups, time_sweeps, compact)
     g = _grid(grid)
     if eps_hist is not None and eps_hist.numel() != nsrc * int(max_iter):
         raise ValueError("eps_hist must have nsrc * max_iter elements")
-    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph, groups, continuous, poll)
+    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph, groups, continuous, poll, compact)
     _lib.check(lib.tt_adjoint(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
                               _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
                               _dev(src_par, "src_par", numel=3 * nsrc), _dev(tau, "tau", numel=nsrc * N), nrec,

@@ -145,13 +145,13 @@ tt::Geo make_geo(const tt_grid* g, int tk) {
 // Workspace layout (each region 256-byte aligned):
 //   Src[nsrc] | tab0[n0] | tab1[n1] | tab2[n2] | active[nsrc] | iter[nsrc] | counter |
 //   part[nsrc*nslots] | model[4*Sa*4] (forward) | part2[nsrc*nslots] (adjoint) |
-//   coef[nsrc*4*Sa*6] | diag[nsrc*N] | rhs[nsrc*N] | box[nsrc*6] | bnd_in, bnd_rhs[nsrc*NB] (adjoint)
+//   coef[nsrc*4*Sa*6] (or [nsrc*N*6] compact) | diag[nsrc*N] | rhs[nsrc*N] | box[nsrc*6] | bnd_in, bnd_rhs[nsrc*NB] (adjoint)
 struct Layout {
     size_t off_src, off_t0, off_t1, off_t2, off_active, off_iter, off_counter, off_part, off_part2, off_coef,
         off_diag, off_rhs, off_box, off_bnd, off_model, total;
 };
 
-Layout layout(const tt::Geo& G, int nsrc, int nslots, int which) {
+Layout layout(const tt::Geo& G, int nsrc, int nslots, int which, bool compact = false) {
     Layout L;
     size_t o = 0;
     L.off_src = o; o = align_up(o + sizeof(tt::Src) * (size_t)nsrc);
@@ -177,7 +177,8 @@ Layout layout(const tt::Geo& G, int nsrc, int nslots, int which) {
     }
     if (which == 1) {
         L.off_part2 = o; o = align_up(o + sizeof(double) * (size_t)nsrc * nslots);
-        L.off_coef = o; o = align_up(o + sizeof(double) * 6 * 4 * (size_t)nsrc * (size_t)G.Sa);
+        L.off_coef = o;
+        o = align_up(o + sizeof(double) * 6 * (size_t)nsrc * (compact ? (size_t)G.N : 4 * (size_t)G.Sa));
         L.off_diag = o; o = align_up(o + sizeof(double) * (size_t)nsrc * (size_t)G.N);
         L.off_rhs = o; o = align_up(o + sizeof(double) * (size_t)nsrc * (size_t)G.N);
         L.off_box = o; o = align_up(o + sizeof(int) * 6 * (size_t)nsrc);
@@ -525,22 +526,25 @@ bool capturing(hipStream_t st) {
 bool polled_mode(const tt_opts* o) { return (o->flags & (TT_FLAG_POLL | TT_FLAG_TIME_SWEEPS)) != 0; }
 
 // Workspace bytes of a solve split into `groups` groups (one region per group).
-size_t grouped_total(const tt::Geo& G, int nsrc, int groups, int which) {
+size_t grouped_total(const tt::Geo& G, int nsrc, int groups, int which, bool compact = false) {
     size_t total = 0;
     for (int q = 0; q < groups; ++q) {
         const int n = group_begin(nsrc, groups, q + 1) - group_begin(nsrc, groups, q);
         tt::Plan P;
         fill_plan(P, G, n);
-        total += layout(G, n, P.nslots, which).total;
+        total += layout(G, n, P.nslots, which, compact).total;
     }
     return total;
 }
+
+bool compact_of(const tt_opts* o) { return o && (o->flags & TT_FLAG_COMPACT_ADJOINT); }
 
 // Plans of the groups of a solve, bound to consecutive workspace regions, with
 // their streams made to wait for the work already queued on the caller's stream.
 int make_groups(const tt::Geo& G, int nsrc, int groups, int which, void* ws, size_t ws_bytes, const tt_opts* opts,
                 hipStream_t caller, std::vector<Group>& gs) {
-    const size_t need = grouped_total(G, nsrc, groups, which);
+    const bool compact = which == 1 && compact_of(opts);
+    const size_t need = grouped_total(G, nsrc, groups, which, compact);
     if (ws_bytes < need) return fail(TT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
     hipEvent_t fork = nullptr;
     if (groups > 1) {
@@ -555,8 +559,9 @@ int make_groups(const tt::Geo& G, int nsrc, int groups, int which, void* ws, siz
         Group& g = gs[q];
         const int n = group_begin(nsrc, groups, q + 1) - group_begin(nsrc, groups, q);
         fill_plan(g.P, G, n);
-        Layout L = layout(G, n, g.P.nslots, which);
+        Layout L = layout(G, n, g.P.nslots, which, compact);
         bind_workspace(g.P, base, L);
+        g.P.compact = compact;
         base += L.total;
         g.P.kappa = opts->kappa;
         g.P.tol = opts->tol;
@@ -688,7 +693,7 @@ size_t tt_workspace_size(const tt_grid* grid, int32_t nsrc, const tt_opts* opts,
     if (opts && (opts->groups < 0 || opts->groups > TT_MAX_GROUPS)) return 0;
     if (opts && (opts->tile_k < 0 || opts->tile_k > tt::kMaxTileK)) return 0;
     tt::Geo G = make_geo(grid, tile_k_of(opts, which));
-    return grouped_total(G, nsrc, which <= 1 ? groups_of(opts, nsrc) : 1, which);
+    return grouped_total(G, nsrc, which <= 1 ? groups_of(opts, nsrc) : 1, which, which == 1 && compact_of(opts));
 }
 
 int tt_source_params(const tt_grid* grid, const double* s, const double* xi, const double* eta, int32_t nsrc,

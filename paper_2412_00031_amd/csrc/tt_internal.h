@@ -24,7 +24,7 @@ constexpr int kBI = 8;        // column block of one wave: 8 x 8 (i, j) columns
 constexpr int kBJ = 8;
 constexpr int kWave = 64;
 constexpr int kBndThreads = 256;
-constexpr int kMaxTileK = 62;  // k-extent of a sweep tile; the staged column (tk + 2) fits one wave
+constexpr int kMaxTileK = 62;  // k-extent of a forward sweep tile; the staged column (tk + 2) fits one wave
 
 // Kernel-argument copy of the grid.
 struct Geo {
@@ -240,7 +240,7 @@ struct Plan {
     int* counter = nullptr;
     double* part = nullptr;
     double* part2 = nullptr;
-    double* coef = nullptr;   // adjoint: [nsrc][4][Sa][6] (line-aligned row-coalesced layouts)
+    double* coef = nullptr;   // adjoint: [nsrc][4][Sa][6] (line-aligned row-coalesced layouts) or [nsrc][N][6]
     double* diag = nullptr;   // adjoint: diagonal of each node's row [nsrc][N]
     double* rhs = nullptr;    // adjoint: right-hand side divided by the diagonal [nsrc][N]
     int* box = nullptr;       // adjoint: index box of each source's nonzero rhs [nsrc][6]
@@ -248,6 +248,7 @@ struct Plan {
     double* bnd_in = nullptr; // adjoint: [nsrc][NB] (continuous adjoint: boundary pass scratch)
     double* bnd_rhs = nullptr; // adjoint: right-hand side of the boundary nodes, [nsrc][NB]
     bool continuous = false;  // adjoint: upwind discretisation of Eq. (5) instead of the exact transpose
+    bool compact = false;     // adjoint: one node-order copy of the coefficient records
     std::vector<int> plane_count;  // tiles of each non-empty tile-plane
     std::vector<int> plane_id;     // its tile-plane number TI + TJ + TK
     std::vector<int> plane_s0;     // its first tile column sum TI + TJ
@@ -263,7 +264,7 @@ struct SweepArgs {
     const double *s, *xi, *eta;
     const Src* src;
     double* field;          // tau or lambda [nsrc][N]
-    const double* coef;     // adjoint coefficients [nsrc][4][Sa][6]
+    const double* coef;     // adjoint coefficients [nsrc][4][Sa][6], or [nsrc][N][6] when compact
     const double* rhs;      // adjoint right-hand side / diagonal [nsrc][N]
     const int* box;         // [nsrc][6]: i, j, k ranges of the nonzero rhs (empty: lo > hi)
     const double* model;    // forward model records [4][Sa][4]
@@ -277,6 +278,7 @@ struct SweepArgs {
     int* counter;
     double* eps_hist;       // optional [nsrc][max_iter]
     int nslots, nbblocks, nsrc, max_iter;
+    int compact;            // adjoint records in node order (TT_FLAG_COMPACT_ADJOINT)
     double kappa, tol;
 };
 

@@ -610,16 +610,21 @@ __device__ __forceinline__ double row_off(const Geo& G, const Col& c, const Loc&
 }
 
 // Adjoint coefficient records: the six couplings of a node's column equation
-// divided by its diagonal (48 bytes), in the four aligned layouts.
+// divided by its diagonal (48 bytes).  Default: four line-aligned
+// row-coalesced layouts per source (arec_idx), so the 8 records a tile row
+// reads on one step are whole 128-byte lines in every sweep direction.
+// Compact (TT_FLAG_COMPACT_ADJOINT): one copy per source in node order
+// [nsrc][N][6], a ninth of the memory at 101^3; a lane's records for
+// consecutive steps are then contiguous along its column, but a tile row's
+// records lie on different lines.
 constexpr int kRec = 6;
 
 // store a node's row {c+_0, c-_0, c+_1, c-_1, c+_2, c-_2, diag, -} divided by
-// its diagonal into the four layouts, the diagonal into diag_all, and a zero
-// right-hand side (k_adj_rhs adds to it); a zero diagonal (no row) stores a
-// zero record
+// its diagonal, the diagonal into diag_all, and a zero right-hand side
+// (k_adj_rhs adds to it); a zero diagonal (no row) stores a zero record
 __device__ __forceinline__ void store_record(const Geo& G, double* __restrict__ coef_all, double* __restrict__ diag_all,
                                              double* __restrict__ rhs_all, int src, long long x, int i, int j, int k,
-                                             const double (&out)[8]) {
+                                             const double (&out)[8], int compact) {
     const double d = out[6];
     double2 rec[3];
 #pragma unroll
@@ -627,15 +632,22 @@ __device__ __forceinline__ void store_record(const Geo& G, double* __restrict__ 
         rec[q] = d != 0.0 ? make_double2(out[2 * q] / d, out[2 * q + 1] / d) : make_double2(0.0, 0.0);
     diag_all[(long long)src * G.N + x] = d;
     rhs_all[(long long)src * G.N + x] = 0.0;
+    if (compact) {
+        double2* cf = reinterpret_cast<double2*>(coef_all + ((long long)src * G.N + x) * kRec);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) cf[q] = rec[q];
+        return;
+    }
     for (int lay = 0; lay < 4; ++lay) {
-        double2* cf = reinterpret_cast<double2*>(coef_all + (((long long)src * 4 + lay) * G.Sa + arec_idx(G, lay, i, j, k)) * kRec);
+        double2* cf =
+            reinterpret_cast<double2*>(coef_all + (((long long)src * 4 + lay) * G.Sa + arec_idx(G, lay, i, j, k)) * kRec);
 #pragma unroll
         for (int q = 0; q < 3; ++q) cf[q] = rec[q];
     }
 }
 
 // Coefficients of the transposed system at every node of every source, stored
-// in the adjoint layouts as the column equation of x divided by its diagonal
+// as the column equation of x divided by its diagonal
 // J_xx: record {in+_0, in-_0, in+_1, in-_1, in+_2, in-_2} / J_xx, with
 // in+-_a = J_{x +- e_a, x}, the coefficient of lambda(x +- e_a) (zero unless x
 // is interior and not fixed).  J_xx goes to diag [nsrc][N] (0 where there is
@@ -687,7 +699,7 @@ __global__ void __launch_bounds__(256) k_adj_coef(SweepArgs a, const double* __r
             }
         }
     }
-    store_record(G, coef_all, diag_all, rhs_all, src, x, i, j, k, out);
+    store_record(G, coef_all, diag_all, rhs_all, src, x, i, j, k, out, a.compact);
 }
 
 // d chi / d tau = sum_m R_m w_c T0(c) (discrete adjoint), or the point sources
@@ -744,19 +756,21 @@ struct AdjSlot {
     double b;
 };
 
-template <int DIR, bool RHS>
+template <int DIR, bool RHS, bool COMPACT>
 __device__ __forceinline__ void adj_fetch(const TileCtx& c, const double* __restrict__ cf,
                                           const double* __restrict__ rh, long long xb, int t, AdjSlot& r) {
     using D = Dir<DIR>;
     const int kp = min(max(c.kp0 + t, c.kplo), c.kphi);
-    const double2* rc = reinterpret_cast<const double2*>(cf + (c.rbase + c.rstep * kp) * (long long)kRec);
+    const long long x = xb + D::s2 * kp;
+    const double2* rc =
+        reinterpret_cast<const double2*>(cf + (COMPACT ? x : (long long)(c.rbase + c.rstep * kp)) * kRec);
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         const double2 v = rc[q];
         r.r[2 * q] = v.x;
         r.r[2 * q + 1] = v.y;
     }
-    r.b = RHS ? rh[xb + D::s2 * kp] : 0.0;
+    r.b = RHS ? rh[x] : 0.0;
 }
 
 // does the tile (its columns, and the k' range of its slab) meet the index box
@@ -772,13 +786,14 @@ __device__ __forceinline__ bool tile_meets_box(const Geo& G, const TileCtx& c, c
     return ia <= bx[1] && ib >= bx[0] && ja <= bx[3] && jb >= bx[2] && ka <= bx[5] && kb >= bx[4] && kq0 <= kq1;
 }
 
-template <int DIR, bool RHS>
+template <int DIR, bool RHS, bool COMPACT>
 __device__ __forceinline__ void adj_tile(const SweepArgs& a, const Src& S, const TileCtx& c, int src, double* lds) {
     using D = Dir<DIR>;
     const Geo& G = a.G;
     constexpr bool last = (DIR == 7);
     double* __restrict__ fld = a.field + (long long)src * G.N;
-    const double* __restrict__ cf = a.coef + ((long long)src * 4 + D::lay) * G.Sa * kRec;
+    const double* __restrict__ cf =
+        a.coef + (COMPACT ? (long long)src * G.N : ((long long)src * 4 + D::lay) * G.Sa) * kRec;
     const double* __restrict__ rh = a.rhs + (long long)src * G.N;
     const long long xb = nidx(G, c.i, c.j, c.kbase);
     const int Lp = tile_pitch(G.tk);
@@ -786,7 +801,7 @@ __device__ __forceinline__ void adj_tile(const SweepArgs& a, const Src& S, const
 
     AdjSlot ring[kPreAdj];
 #pragma unroll
-    for (int u = 0; u < kPreAdj; ++u) adj_fetch<DIR, RHS>(c, cf, rh, xb, c.t0 + u, ring[u]);
+    for (int u = 0; u < kPreAdj; ++u) adj_fetch<DIR, RHS, COMPACT>(c, cf, rh, xb, c.t0 + u, ring[u]);
     stage_tile<DIR>(G, c, fld, -(long long)src * G.N, (long long)(a.nsrc - src) * G.N - 2, lds);
     __syncthreads();
 
@@ -828,7 +843,7 @@ __device__ __forceinline__ void adj_tile(const SweepArgs& a, const Src& S, const
                         if (last) asum += fabs(nv);
                     }
                 }
-                adj_fetch<DIR, RHS>(c, cf, rh, xb, t + kPreAdj, r);
+                adj_fetch<DIR, RHS, COMPACT>(c, cf, rh, xb, t + kPreAdj, r);
             }
         }
     }
@@ -842,7 +857,7 @@ __device__ __forceinline__ void adj_tile(const SweepArgs& a, const Src& S, const
     }
 }
 
-template <int COORD, int DIR>
+template <int COORD, int DIR, bool COMPACT>
 __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane, int s0) {
     extern __shared__ double lds[];
     const int src = blockIdx.x;
@@ -858,8 +873,8 @@ __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane, int s0
         return;
     }
     // wave-uniform: only tiles that meet the right-hand side read it
-    if (tile_meets_box<DIR>(G, c, a.box + src * 6)) adj_tile<DIR, true>(a, S, c, src, lds);
-    else adj_tile<DIR, false>(a, S, c, src, lds);
+    if (tile_meets_box<DIR>(G, c, a.box + src * 6)) adj_tile<DIR, true, COMPACT>(a, S, c, src, lds);
+    else adj_tile<DIR, false, COMPACT>(a, S, c, src, lds);
 }
 
 // Transposed boundary pass: lambda_b = rhs_b - sum_{rows r != b} J_{r, b} lambda_r,
@@ -1045,7 +1060,7 @@ __global__ void __launch_bounds__(256) k_cadj_coef(SweepArgs a, const double* __
         }
         out[6] = diag > 0.0 ? diag : HUGE_VAL;
     }
-    store_record(G, coef_all, diag_all, rhs_all, src, x, i, j, k, out);
+    store_record(G, coef_all, diag_all, rhs_all, src, x, i, j, k, out, a.compact);
 }
 
 // Boundary pass of the continuous system, Jacobi: every boundary node's new P
@@ -1058,13 +1073,13 @@ __global__ void __launch_bounds__(kBndThreads) k_cadj_bnd_calc(SweepArgs a, doub
     if (b >= G.NB) return;
     const Src S = a.src[src];
     const double* P = a.field + (long long)src * G.N;
-    const double* cf = a.coef + (long long)src * 4 * G.Sa * kRec;  // layout 0
+    const double* cf = a.coef + (long long)src * (a.compact ? G.N : 4 * G.Sa) * kRec;  // compact, or layout 0
     int i, j, k;
     bnd_decode(G, b, i, j, k);
     double nv = 0.0;
     if (!in_fixed(S, i, j, k)) {
-        const double* r = cf + arec_idx(G, 0, i, j, k) * kRec;  // the row divided by its diagonal
         const long long x = nidx(G, i, j, k);
+        const double* r = cf + (a.compact ? x : arec_idx(G, 0, i, j, k)) * kRec;  // the row divided by its diagonal
         const int id[3] = {i, j, k};
         const long long st[3] = {G.si, G.sj, 1};
         double acc = a.rhs[(long long)src * G.N + nidx(G, i, j, k)];
@@ -1203,6 +1218,7 @@ SweepArgs make_args(const Plan& P, const double* s, const double* xi, const doub
     a.nslots = P.nslots;
     a.nbblocks = P.nbblocks;
     a.nsrc = P.nsrc;
+    a.compact = P.compact ? 1 : 0;
     a.max_iter = P.max_iter;
     a.kappa = P.kappa;
     a.tol = P.tol;
@@ -1265,9 +1281,9 @@ constexpr SweepFn pick_fwd(int d, std::integer_sequence<int, DS...>) {
     return t[d];
 }
 
-template <int COORD, int... DS>
+template <int COORD, bool COMPACT, int... DS>
 constexpr SweepFn pick_adj(int d, std::integer_sequence<int, DS...>) {
-    SweepFn t[] = {k_adj_sweep<COORD, DS>...};
+    SweepFn t[] = {k_adj_sweep<COORD, DS, COMPACT>...};
     return t[d];
 }
 
@@ -1276,9 +1292,10 @@ SweepFn fwd_sweep_fn(int coord, int d) {
                       : pick_fwd<0>(d, std::make_integer_sequence<int, 8>{});
 }
 
-SweepFn adj_sweep_fn(int coord, int d) {
-    return coord == 1 ? pick_adj<1>(d, std::make_integer_sequence<int, 8>{})
-                      : pick_adj<0>(d, std::make_integer_sequence<int, 8>{});
+SweepFn adj_sweep_fn(int coord, int d, bool compact) {
+    const auto seq = std::make_integer_sequence<int, 8>{};
+    if (compact) return coord == 1 ? pick_adj<1, true>(d, seq) : pick_adj<0, true>(d, seq);
+    return coord == 1 ? pick_adj<1, false>(d, seq) : pick_adj<0, false>(d, seq);
 }
 
 void launch_fwd_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
@@ -1318,7 +1335,7 @@ void launch_adj_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
     for (int d = 0; d < 8; ++d) {
         {
         TimedLaunch tl(P, st, P.nplanes);
-        const SweepFn fn = adj_sweep_fn(P.G.coord, d);
+        const SweepFn fn = adj_sweep_fn(P.G.coord, d, P.compact);
         for (int p = 0; p < P.nplanes; ++p)
             hipLaunchKernelGGL(fn, dim3(P.nsrc, P.plane_count[p]), dim3(64), tile_lds_bytes(P.G), st, a,
                                P.plane_id[p], P.plane_s0[p]);

@@ -94,6 +94,9 @@ def test_workspace_sizes_host_logic(libpath):
         assert 0 < a <= b
     with pytest.raises(ValueError):
         api.workspace(g, 1, 0, tile_k=63)
+    # the compact adjoint records take one node-order copy instead of four row layouts
+    fast, compact = api.workspace(g, 3, 1).numel(), api.workspace(g, 3, 1, compact=True).numel()
+    assert 0 < compact < fast
     with pytest.raises(ValueError):
         api.workspace(g, -1, 1)
 

@@ -59,7 +59,7 @@ def oracle_path(wl, tol, max_iter, R=None, T_obs=None, adj_tol=None, max_iter_ad
 
 
 def gpu_path(torch, wl, tol, max_iter, R=None, T_obs=None, adj_tol=None, max_iter_adj=None, tile_k=0,
-             tau_init=None, nsrc=None):
+             tau_init=None, nsrc=None, tile_k_adj=None):
     from paper_2412_00031_amd import api
     g = wl["grid"]
     s, xi, eta = (_dev(torch, wl[k]) for k in ("s", "xi", "eta"))
@@ -82,7 +82,7 @@ def gpu_path(torch, wl, tol, max_iter, R=None, T_obs=None, adj_tol=None, max_ite
     else:
         Rd = _dev(torch, R)
     lam, st_a = api.adjoint(g, s, xi, eta, src, par, tau, rec, Rd, adj_tol or tol, max_iter_adj or max_iter,
-                            wl["kappa"], tile_k=tile_k)
+                            wl["kappa"], tile_k=tile_k if tile_k_adj is None else tile_k_adj)
     grad = api.kernel(g, s, xi, eta, src, par, tau, lam)
     torch.cuda.synchronize()
     c = lambda t: t.cpu().numpy()
@@ -123,14 +123,16 @@ def test_small_spherical_several_tiles(torch_cuda):
 def test_tile_shapes_bitwise(torch_cuda):
     """Any tile depth visits the same dependencies: results are bit-identical.
     The grids have ragged 8 x 8 tile columns (interior 19, 17, 21 and 27, 3, 2)
-    and slab depths below, near and above the hyperplane extent of a column."""
+    and slab depths below, near and above the hyperplane extent of a column
+    (forward depths up to 62, adjoint depths up to its limit of 16)."""
     for n, seed in (((21, 19, 23), 11), ((29, 5, 4), 12)):
         wl = W.small_spherical(n=n, nsrc=2, seed=seed)
-        ref = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=62)
-        for tk in (1, 2, 3, 5, 7, 8, 13, 21, 32, 48):
-            gp = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=tk)
+        ref = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=62, tile_k_adj=16)
+        for tk, tka in ((1, 1), (2, 2), (3, 3), (5, 5), (7, 7), (8, 8), (13, 13), (21, 4), (32, 11), (48, 6),
+                        (62, 9), (16, 12), (10, 14), (12, 15)):
+            gp = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=tk, tile_k_adj=tka)
             for key in ("tau", "lam", "grad", "it_f", "it_a", "T"):
-                assert np.array_equal(gp[key], ref[key]), (n, tk, key)
+                assert np.array_equal(gp[key], ref[key]), (n, tk, tka, key)
 
 
 def test_graph_replay_matches_eager(torch_cuda):
@@ -185,6 +187,43 @@ def test_source_groups_bitwise(torch_cuda):
     o = oracle_path(wl, 1e-10, 300, R=wl["R"])
     assert np.array_equal(ref[1], o["it_f"]) and np.array_equal(ref[4], o["it_a"])
     assert rel_inf(ref[0], o["tau"]) <= TOL_TAU and rel_inf(ref[3], o["lam"]) <= TOL_ADJ
+
+
+def test_compact_adjoint_records_bitwise(torch_cuda):
+    """The compact record layout (one node-order copy of the adjoint's
+    coefficient records, TT_FLAG_COMPACT_ADJOINT) reads the same couplings in
+    the same order: discrete and continuous adjoint fields and statuses equal
+    the row-layout run bit for bit at several tile depths and groupings (the
+    convergence histories too at the same tile depth; other depths sum the
+    per-tile partial sums in another grouping), and the oracle agrees."""
+    from paper_2412_00031_amd import api
+    wl = W.small_spherical(n=(21, 19, 23), nsrc=5, nrec=10, seed=27)
+    g, kap = wl["grid"], wl["kappa"]
+    s, xi, eta, src, rec, R = (_dev(torch_cuda, wl[k]) for k in ("s", "xi", "eta", "src", "rec", "R"))
+    par = api.source_params(g, s, xi, eta, src)
+    tau, st = api.forward(g, s, xi, eta, src, par, 1e-11, 300, kap)
+    for continuous in (False, True):
+        Rc = R.abs() + 0.05 if continuous else R
+        ref = None
+        for compact, tk, groups in ((False, 0, 0), (True, 0, 0), (True, 5, 2), (True, 24, 1), (True, 62, 3)):
+            h = torch_cuda.zeros((5, 300), dtype=torch_cuda.float64, device="cuda")
+            lam, sa = api.adjoint(g, s, xi, eta, src, par, tau, rec, Rc, 1e-11, 300, kap, tile_k=tk, groups=groups,
+                                  eps_hist=h, continuous=continuous, compact=compact)
+            torch_cuda.cuda.synchronize()
+            got = [x.cpu().numpy() for x in (lam, sa, h)]
+            if ref is None:
+                ref = got
+                continue
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (continuous, compact, tk, groups)
+            if tk == 0:
+                assert np.array_equal(got[2], ref[2]), (continuous, compact, groups)
+            else:
+                assert np.allclose(got[2], ref[2], rtol=1e-12, atol=0.0), (continuous, compact, tk, groups)
+    o = oracle_path(wl, 1e-11, 300, R=wl["R"])
+    lam, sa = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, 1e-11, 300, kap, compact=True)
+    torch_cuda.cuda.synchronize()
+    assert np.array_equal(sa.cpu().numpy(), o["it_a"])
+    assert rel_inf(lam.cpu().numpy(), o["lam"]) <= TOL_ADJ
 
 
 @pytest.mark.parametrize("zeta,eps_rel", [(0.5, 1e-3), (1.0, 0.0), (0.0, 0.1)])
