@@ -242,3 +242,38 @@ def test_fullsize_converged_parity(torch_cuda, sph101):
     gg = gsel.cpu().numpy()
     for c in range(3):
         assert rel_inf(gg[c], ograd[c]) <= 1e-10, c
+
+
+@pytest.mark.slow
+def test_121_by_512_adjoint_fits_with_compact_records(torch_cuda):
+    """The warm-start evaluation geometry (121^3 spherical, 512 sources) through
+    forward and adjoint solves as ONE batch: the row-layout adjoint records
+    would need more than the GPU's 288 GB, the compact node-order records
+    (TT_FLAG_COMPACT_ADJOINT) fit beside the fields; every source converges,
+    and sampled sources equal the same sources solved in a batch of their own
+    with the row-layout records, bit for bit."""
+    from paper_2412_00031_amd import api
+    torch = torch_cuda
+    wl = W.sph121()
+    g, kap, tol = wl["grid"], wl["kappa"], wl["tol"]
+    rng = np.random.default_rng(5101)
+    rec_h = W.random_surface_nodes(g, 500, rng)
+    R_h = rng.normal(0.0, 0.1, (len(wl["src"]), len(rec_h)))
+    fast = api.workspace(g, 1, 1, compact=False).numel() * 512
+    compact = api.workspace(g, 1, 1, compact=True).numel() * 512
+    assert fast > 288e9 > 4 * compact, (fast, compact)
+    s, xi, eta, src, rec, R = (_dev(torch, a) for a in (wl["s"], wl["xi"], wl["eta"], wl["src"], rec_h, R_h))
+    par = api.source_params(g, s, xi, eta, src)
+    tau, st = api.forward(g, s, xi, eta, src, par, tol, 200, kap, poll=True)
+    lam, sa = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, tol, 200, kap, poll=True, compact=True)
+    torch.cuda.synchronize()
+    st_h, sa_h = st.cpu().numpy(), sa.cpu().numpy()
+    assert (st_h > 0).all() and (sa_h > 0).all(), (st_h.min(), sa_h.min())
+    sel = [0, 255, 511]
+    tau2, st2 = api.forward(g, s, xi, eta, src[sel].contiguous(), par[sel].contiguous(), tol, 200, kap, poll=True)
+    lam2, sa2 = api.adjoint(g, s, xi, eta, src[sel].contiguous(), par[sel].contiguous(), tau2, rec,
+                            R[sel].contiguous(), tol, 200, kap, poll=True)
+    torch.cuda.synchronize()
+    for q, p in enumerate(sel):
+        assert int(st2[q]) == st_h[p] and int(sa2[q]) == sa_h[p]
+        assert torch.equal(tau2[q], tau[p]) and torch.equal(lam2[q], lam[p]), p
