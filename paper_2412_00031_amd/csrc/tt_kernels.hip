@@ -300,44 +300,63 @@ __device__ __forceinline__ int stage_origin(const Geo& G, int a, int T) {
     return SGN > 0 ? T * kBI : G.n[a] - 1 - T * kBI;
 }
 
-// xlo, xhi: the element range of the field array around fld that may be read
+// xlo, xhi: the element range of the field array around fld that may be read.
+// Per lane the loop keeps running indices: the pair's column (ci, cj) and slot
+// q, y = the column's element offset minus s2 (ci + cj) (the shear), and
+// w = -(ci + cj); element and k' of the pair's lower slot are then one add each.
+// Offsets are 32-bit: the host keeps N below 2^31, and a loaded pair lies in
+// [-1, N] around fld.
 template <int DIR>
 __device__ __forceinline__ void stage_tile(const Geo& G, const TileCtx& c, const double* __restrict__ fld,
                                            long long xlo, long long xhi, double* lds) {
     using D = Dir<DIR>;
+    constexpr int sg = D::s2;
     const int Lp = tile_pitch(G.tk);
     const int npair = kTC * kTC * Lp / 2;
+    const int si = (int)G.si, sj = (int)G.sj;
     const int oi = stage_origin<D::s0>(G, 0, c.TI), oj = stage_origin<D::s1>(G, 1, c.TJ);
+    const int lo = (int)(xlo > -1 ? xlo : -1), hi = (int)(xhi < G.N ? xhi : G.N);
     // pair p = 64 r + lane: slots q, q + 1 (q even) of column col = 2p / Lp;
     // p advances by 64 per load, i.e. 128 slots
     int col = (2 * c.lane) / Lp, q = 2 * c.lane - col * Lp;
     int ci = col / kTC, cj = col - ci * kTC;
     const int dcol = 128 / Lp, dq = 128 - dcol * Lp;
+    // (unsigned: columns outside the grid, never loaded, may leave the int range)
+    unsigned y = (unsigned)(oi + D::s0 * ci) * si + (unsigned)(oj + D::s1 * cj) * sj - sg * (ci + cj);
+    int w = -(ci + cj);
+    // element of the lower slot: x = y + x0 + q; its k': kpa = kq0 + w + q (s2 > 0)
+    // or kq0 + w + Lp - 1 - q (s2 < 0), whose pair holds [kpa, kpa + 1] or [kpa - 1, kpa]
+    const int x0 = c.kbase + sg * c.kq0 + (sg > 0 ? 0 : 1 - Lp);
+    const int ka0 = sg > 0 ? c.kq0 + 2 : c.kq0 + Lp;  // kpa + (2 or 1) = ka0 + w + sg q
+    const unsigned kspan = (unsigned)G.m[2] + 2;
+    const int ei = c.ext_i + 2, ej = c.ext_j + 2;
+    const unsigned dy_q = (unsigned)(D::s1 * sj - sg), dy = dcol * dy_q;
+    const unsigned dy_w = (unsigned)(D::s0 * si) - (unsigned)(kTC * D::s1 * sj) + sg * (kTC - 1);
     lds_char* lb = (lds_char*)lds;  // the dynamic shared array, in the LDS address space
     for (int p0 = 0; p0 < npair; p0 += 64) {
-        const int i = min(max(oi + D::s0 * ci, 0), G.n[0] - 1);
-        const int j = min(max(oj + D::s1 * cj, 0), G.n[1] - 1);
-        // absolute k of the pair's lower slot (the node of slot q + 1 is k + 1)
-        const int kd = c.kq0 - ci - cj;
-        const int klo = D::s2 > 0 ? c.kbase + kd + q : c.kbase - (kd + Lp - 1 - q);
-        long long x = (long long)i * G.si + (long long)j * G.sj + klo;
-        x = x < xlo ? xlo : (x > xhi ? xhi : x);
-        // k' of the pair's entries: [kpa, kpa + 1] (s2 > 0) or [kpa - 1, kpa] (s2 < 0)
-        const int kpa = D::s2 > 0 ? kd + q : kd + Lp - 1 - q;
-        const bool node = D::s2 > 0 ? (kpa >= -2 && kpa <= G.m[2]) : (kpa >= -1 && kpa <= G.m[2] + 1);
-        // only pairs that hold a node entry of a column the tile reads (its own
-        // columns and their i'/j' halo), and in the last load only the window's lanes
-        if (node && ci < c.ext_i + 2 && cj < c.ext_j + 2 && (p0 + 64 <= npair || p0 + c.lane < npair))
+        int x = (int)(y + x0 + q);
+        x = min(max(x, lo), hi);
+        // only pairs that hold a node entry (k' in [-1, m2]) of a column the tile
+        // reads (its own columns and their i'/j' halo), and in the last load only
+        // the window's lanes
+        const bool node = (unsigned)(ka0 + w + sg * q) <= kspan;
+        if (node && ci < ei && cj < ej && (p0 + 64 <= npair || p0 + c.lane < npair))
             __builtin_amdgcn_global_load_lds(fld + x, (lds_void*)(lb + 16 * p0), 16, 0, 0);
         q += dq;
         cj += dcol;
+        y += dy;
+        w -= dcol;
         if (q >= Lp) {
             q -= Lp;
             ++cj;
+            y += dy_q;
+            --w;
         }
         while (cj >= kTC) {
             cj -= kTC;
             ++ci;
+            y += dy_w;
+            w += kTC - 1;
         }
     }
     __builtin_amdgcn_s_waitcnt(0);  // every load of the window (and any earlier one) has landed
@@ -347,61 +366,58 @@ __device__ __forceinline__ void stage_tile(const Geo& G, const TileCtx& c, const
 constexpr int kStageBatch = 16;
 
 // Write back the tile's own nodes: entries 1..tk of its columns whose k' is
-// an interior node (the others are halo or outside the column).
+// an interior node (the others are halo or outside the column).  Element
+// e = 64 r + lane is entry q + 1 (q = e % tk) of own column col = e / tk =
+// li nj + lj; per lane the loop keeps col, q, lj, that entry's k' (kp), its
+// element offset around fld (x, 32-bit like the staging) and its LDS slot
+// (loff), each advanced by a constant per element plus a carry when q wraps
+// and one when lj wraps.
 template <int DIR>
 __device__ __forceinline__ void unstage_tile(const Geo& G, const TileCtx& c, double* __restrict__ fld,
                                              const double* lds, int Lp) {
     using D = Dir<DIR>;
+    constexpr int sg = D::s2;
     const int ek = G.tk;
     const int nj = c.ext_j, n = c.ext_i * nj, total = n * ek;
-    const long long si = D::s0 * G.si, sj = D::s1 * G.sj;
-    const long long base = nidx(G, stage_origin<D::s0>(G, 0, c.TI) + D::s0, stage_origin<D::s1>(G, 1, c.TJ) + D::s1,
-                                c.kbase);
+    const int si = D::s0 * (int)G.si, sj = D::s1 * (int)G.sj;
+    const int base = (int)nidx(G, stage_origin<D::s0>(G, 0, c.TI) + D::s0, stage_origin<D::s1>(G, 1, c.TJ) + D::s1,
+                               c.kbase);
     const unsigned kmax = (unsigned)G.m[2];
-    // element e <-> column col = e / ek = li nj + lj, q = e % ek (entry q + 1,
-    // k' = kq0 - 1 - li - lj + q)
     int col = c.lane / ek, q = c.lane - col * ek;
     int li = col / nj, lj = col - li * nj;
-    long long gcol = li * si + lj * sj;
-    int dq = q - li - lj;
-    // LDS slot of entry q + 1: c0 + s2 q
-    constexpr int sg = D::s2;
+    int kp = c.kq0 - 1 - li - lj + q;
+    // (unsigned: lanes past the tile's columns, never stored, may leave the int range)
+    unsigned x = (unsigned)base + (unsigned)li * si + (unsigned)lj * sj + sg * kp;
     int loff = ((li + 1) * kTC + lj + 1) * Lp + (sg > 0 ? 1 : Lp - 2) + sg * q;
-    const int dcol = 64 / ek, dq_step = 64 - dcol * ek;
-    const long long g_step = dcol * sj, g_jwrap = si - nj * sj;
-    const int l_step = dcol * Lp + sg * dq_step, l_kwrap = Lp - sg * ek, l_jwrap = (kTC - nj) * Lp;
-    const int kq = c.kq0 - 1;
+    const int dcol = 64 / ek, dq = 64 - dcol * ek;
+    const int kp_step = dq - dcol, kp_q = -1 - ek, kp_j = nj - 1;
+    const unsigned x_step = (unsigned)(dcol * sj + sg * (dq - dcol));
+    const unsigned x_q = (unsigned)(sj - sg * (1 + ek));
+    const unsigned x_j = (unsigned)si - (unsigned)(nj * sj) + sg * (nj - 1);
+    const int l_step = dcol * Lp + sg * dq, l_q = Lp - sg * ek, l_j = (kTC - nj) * Lp;
     for (int e0 = 0; e0 < total; e0 += 64 * kStageBatch) {
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u) {
-            const int kp = kq + dq;
-            if (col < n && (unsigned)kp < kmax) fld[base + gcol + D::s2 * kp] = lds[loff];
+            if (col < n && (unsigned)kp < kmax) fld[(int)x] = lds[loff];
             col += dcol;
             lj += dcol;
-            q += dq_step;
-            gcol += g_step;
-            dq += dq_step - dcol;
+            q += dq;
+            kp += kp_step;
+            x += x_step;
             loff += l_step;
-            const bool kw = q >= ek;
-            q -= kw ? ek : 0;
-            col += kw;
-            lj += kw;
-            gcol += kw ? sj : 0;
-            dq -= kw ? ek + 1 : 0;
-            loff += kw ? l_kwrap : 0;
-            if (dcol < nj) {
-                const bool jw = lj >= nj;
-                lj -= jw ? nj : 0;
-                gcol += jw ? g_jwrap : 0;
-                dq += jw ? nj - 1 : 0;
-                loff += jw ? l_jwrap : 0;
-            } else {
-                while (lj >= nj) {
-                    lj -= nj;
-                    gcol += g_jwrap;
-                    dq += nj - 1;
-                    loff += l_jwrap;
-                }
+            if (q >= ek) {
+                q -= ek;
+                ++col;
+                ++lj;
+                kp += kp_q;
+                x += x_q;
+                loff += l_q;
+            }
+            while (lj >= nj) {
+                lj -= nj;
+                kp += kp_j;
+                x += x_j;
+                loff += l_j;
             }
         }
     }
