@@ -131,13 +131,23 @@ __device__ __forceinline__ bool in_fixed(const Src& S, int i, int j, int k) {
     return (unsigned)(i - S.fb[0]) <= 1u && (unsigned)(j - S.fb[1]) <= 1u && (unsigned)(k - S.fb[2]) <= 1u;
 }
 
+// 1/sqrt(x) for x > 0 to about an ulp: the hardware estimate (good to about
+// 23 bits) refined by two Newton steps y <- y (3 - x y^2) / 2.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y *= fma(-h * y, y, 1.5);
+    y *= fma(-h * y, y, 1.5);
+    return y;
+}
+
 // T0 and its scaled gradient t at a node of column c with axis-2 table value
-// (c2, s2) = (cos phi, sin phi) or (x, 0).
+// (c2, s2) = (cos phi, sin phi) or (x, 0); rq = 1/sqrt(Q) = s0 / T0 (0 at the
+// source itself, where the factor vanishes).
 template <int COORD>
-__device__ __forceinline__ void factor(const Src& S, const Col& c, double c2, double s2, double& T0,
-                                       double t[3]) {
+__device__ __forceinline__ void factor(const Src& S, const Col& c, double c2, double s2, double& T0, double t[3],
+                                       double& rq) {
     double d0, d1, d2;
-    double er0 = 0, er1 = 0, er2 = 0, et0 = 0, et1 = 0, et2 = 0;
     if (COORD == 1) {
         double D0 = c.rct * c2 - S.Xs[0];
         double D1 = c.rct * s2 - S.Xs[1];
@@ -145,8 +155,6 @@ __device__ __forceinline__ void factor(const Src& S, const Col& c, double c2, do
         d0 = D0 * S.E[0] + D1 * S.E[1] + D2 * S.E[2];
         d1 = D0 * S.E[3] + D1 * S.E[4] + D2 * S.E[5];
         d2 = D0 * S.E[6] + D1 * S.E[7] + D2 * S.E[8];
-        er0 = c.ct * c2; er1 = c.ct * s2; er2 = c.st;
-        et0 = -c.st * c2; et1 = -c.st * s2; et2 = c.ct;
     } else {
         d0 = c.x0 - S.Xs[0];
         d1 = c.ct - S.Xs[1];
@@ -159,23 +167,33 @@ __device__ __forceinline__ void factor(const Src& S, const Col& c, double c2, do
     if (!(Q > 0.0)) {
         T0 = 0.0;
         t[0] = t[1] = t[2] = 0.0;
+        rq = 0.0;
         return;
     }
-    double sq = sqrt(Q);
-    T0 = S.s0 * sq;
-    double f = S.s0 / sq;
+    rq = rsqrt_nr(Q);
+    T0 = S.s0 * (Q * rq);
+    double f = S.s0 * rq;
     if (COORD == 1) {
+        // gradient in the embedding, then on the node's local unit vectors
+        // r^ = (ct c2, ct s2, st), theta^ = (-st c2, -st s2, ct), phi^ = (-s2, c2, 0)
         double G0 = f * (m0 * S.E[0] + m1 * S.E[3] + m2 * S.E[6]);
         double G1 = f * (m0 * S.E[1] + m1 * S.E[4] + m2 * S.E[7]);
         double G2 = f * (m0 * S.E[2] + m1 * S.E[5] + m2 * S.E[8]);
-        t[0] = G0 * er0 + G1 * er1 + G2 * er2;
-        t[1] = G0 * et0 + G1 * et1 + G2 * et2;
-        t[2] = -G0 * s2 + G1 * c2;
+        double hz = G0 * c2 + G1 * s2;
+        t[0] = c.ct * hz + c.st * G2;
+        t[1] = c.ct * G2 - c.st * hz;
+        t[2] = G1 * c2 - G0 * s2;
     } else {
         t[0] = f * m0;
         t[1] = f * m1;
         t[2] = f * m2;
     }
+}
+
+template <int COORD>
+__device__ __forceinline__ void factor(const Src& S, const Col& c, double c2, double s2, double& T0, double t[3]) {
+    double rq;
+    factor<COORD>(S, c, c2, s2, T0, t, rq);
 }
 
 // Local state of the factored Hamiltonian at an interior node: P, M P, H.
@@ -202,20 +220,42 @@ __device__ __forceinline__ void local_state(const Geo& G, const Src& S, const Co
 }
 
 // Lax-Friedrichs update: the tau(x) that zeroes
-//   G_x = H(q, tau_old(x)) - sum_a sigma_a (dn_a - 2 tau(x) + up_a) / (2 h_a) - s(x).
+//   G_x = H(q, tau_old(x)) - sum_a sigma_a (dn_a - 2 tau(x) + up_a) / (2 h_a) - s(x),
+// sigma_a = kappa T0 g_a.  With C = sum_a g_a / h_a (g_0 = 1) it reads
+//   tau(x) = (s - H) / (kappa T0 C) + sum_a w_a (up_a + dn_a),  w_a = g_a / (2 h_a C),
+// and 1 / (kappa T0 C) = rho / sqrt(Q) with rho = 1 / (kappa s0 C): LfCol holds
+// the column's constants, so an update has no division.
+struct LfCol {
+    double v1, v2;      // g_a / (2 h_a) of axes 1, 2 (central differences)
+    double w0, w1, w2;  // averaging weights w_a
+    double rho;
+};
+
+__device__ __forceinline__ LfCol lf_col(const Geo& G, const Src& S, const Col& c, double kappa) {
+    LfCol W;
+    const double iC = 1.0 / (G.invh[0] + c.g1 * G.invh[1] + c.g2 * G.invh[2]);
+    W.v1 = c.g1 * G.inv2h[1];
+    W.v2 = c.g2 * G.inv2h[2];
+    W.w0 = G.inv2h[0] * iC;
+    W.w1 = W.v1 * iC;
+    W.w2 = W.v2 * iC;
+    W.rho = iC / (kappa * S.s0);
+    return W;
+}
+
 template <int COORD>
-__device__ __forceinline__ double lf_update(const Geo& G, const Src& S, const Col& c, double c2, double s2,
-                                            double kappa, double sx, double xi, double eta, double tx,
-                                            double up0, double dn0, double up1, double dn1, double up2,
-                                            double dn2) {
-    Loc L;
-    local_state<COORD>(G, S, c, c2, s2, xi, eta, tx, up0, dn0, up1, dn1, up2, dn2, L);
-    double kT = kappa * L.T0;
-    double num = sx - L.H +
-                 kT * ((up0 + dn0) * G.inv2h[0] + c.g1 * (up1 + dn1) * G.inv2h[1] +
-                       c.g2 * (up2 + dn2) * G.inv2h[2]);
-    double den = kT * (G.invh[0] + c.g1 * G.invh[1] + c.g2 * G.invh[2]);
-    return num / den;
+__device__ __forceinline__ double lf_update(const Geo& G, const Src& S, const Col& c, const LfCol& W, double c2,
+                                            double s2, double sx, double xi, double eta, double tx, double up0,
+                                            double dn0, double up1, double dn1, double up2, double dn2) {
+    double T0, t[3], rq;
+    factor<COORD>(S, c, c2, s2, T0, t, rq);
+    const double P0 = T0 * ((dn0 - up0) * G.inv2h[0]) + tx * t[0];
+    const double P1 = T0 * ((dn1 - up1) * W.v1) + tx * t[1];
+    const double P2 = T0 * ((dn2 - up2) * W.v2) + tx * t[2];
+    const double MP1 = (1.0 - 2.0 * xi) * P1 + 2.0 * eta * P2;
+    const double MP2 = 2.0 * eta * P1 + (1.0 + 2.0 * xi) * P2;
+    const double H = sqrt(P0 * P0 + P1 * MP1 + P2 * MP2);
+    return (sx - H) * (W.rho * rq) + ((up0 + dn0) * W.w0 + (up1 + dn1) * W.w1 + (up2 + dn2) * W.w2);
 }
 
 // ----- state of one batched solve (host side) -----

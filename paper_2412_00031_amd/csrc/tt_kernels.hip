@@ -461,6 +461,7 @@ __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane, int s0
         return;
     }
     const Col cl = make_col(G, a.T, c.i, c.j);
+    const LfCol W = lf_col(G, S, cl, a.kappa);
     double* __restrict__ fld = a.field + (long long)src * G.N;
     const double* __restrict__ mdl = a.model + (long long)D::lay * G.Sa * 4;
     const double2* __restrict__ t2 = a.T.t2;
@@ -497,7 +498,7 @@ __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane, int s0
                         const double m0 = D::s0 > 0 ? up_i : dn_i, p0 = D::s0 > 0 ? dn_i : up_i;
                         const double m1 = D::s1 > 0 ? up_j : dn_j, p1 = D::s1 > 0 ? dn_j : up_j;
                         const double m2 = D::s2 > 0 ? up_k : dn_k, p2 = D::s2 > 0 ? dn_k : up_k;
-                        const double nv = lf_update<COORD>(G, S, cl, r.c2, r.s2, a.kappa, r.sx, r.xi, r.eta, cur, m0,
+                        const double nv = lf_update<COORD>(G, S, cl, W, r.c2, r.s2, r.sx, r.xi, r.eta, cur, m0,
                                                            p0, m1, p1, m2, p2);
                         lds[o + sg] = nv;
                         eps += fabs(nv - cur);
