@@ -141,10 +141,17 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
     return y;
 }
 
+// sqrt(x) for x >= 0 to about an ulp, as x / sqrt(x) without a branch: 0 at
+// x = 0, and x / sqrt(DBL_MIN) below the smallest normal double (Hamiltonians
+// that small do not occur)
+__device__ __forceinline__ double sqrt_nr(double x) { return x * rsqrt_nr(fmax(x, 2.2250738585072014e-308)); }
+
 // T0 and its scaled gradient t at a node of column c with axis-2 table value
 // (c2, s2) = (cos phi, sin phi) or (x, 0); rq = 1/sqrt(Q) = s0 / T0 (0 at the
-// source itself, where the factor vanishes).
-template <int COORD>
+// source itself, where the factor vanishes).  OFF_SOURCE: the caller never
+// asks at the source itself (Q > 0; the sweeps skip the fixed cell), so there
+// is no branch.
+template <int COORD, bool OFF_SOURCE = false>
 __device__ __forceinline__ void factor(const Src& S, const Col& c, double c2, double s2, double& T0, double t[3],
                                        double& rq) {
     double d0, d1, d2;
@@ -164,7 +171,7 @@ __device__ __forceinline__ void factor(const Src& S, const Col& c, double c2, do
     double m1 = S.mi11 * d1 + S.mi12 * d2;
     double m2 = S.mi12 * d1 + S.mi22 * d2;
     double Q = d0 * m0 + d1 * m1 + d2 * m2;
-    if (!(Q > 0.0)) {
+    if (!OFF_SOURCE && !(Q > 0.0)) {
         T0 = 0.0;
         t[0] = t[1] = t[2] = 0.0;
         rq = 0.0;
@@ -193,7 +200,7 @@ __device__ __forceinline__ void factor(const Src& S, const Col& c, double c2, do
 template <int COORD>
 __device__ __forceinline__ void factor(const Src& S, const Col& c, double c2, double s2, double& T0, double t[3]) {
     double rq;
-    factor<COORD>(S, c, c2, s2, T0, t, rq);
+    factor<COORD, false>(S, c, c2, s2, T0, t, rq);
 }
 
 // Local state of the factored Hamiltonian at an interior node: P, M P, H.
@@ -245,16 +252,17 @@ __device__ __forceinline__ LfCol lf_col(const Geo& G, const Src& S, const Col& c
 
 template <int COORD>
 __device__ __forceinline__ double lf_update(const Geo& G, const Src& S, const Col& c, const LfCol& W, double c2,
-                                            double s2, double sx, double xi, double eta, double tx, double up0,
-                                            double dn0, double up1, double dn1, double up2, double dn2) {
+                                            double s2, double sx, double ma, double mb, double mc, double tx,
+                                            double up0, double dn0, double up1, double dn1, double up2, double dn2) {
     double T0, t[3], rq;
-    factor<COORD>(S, c, c2, s2, T0, t, rq);
+    factor<COORD, true>(S, c, c2, s2, T0, t, rq);
     const double P0 = T0 * ((dn0 - up0) * G.inv2h[0]) + tx * t[0];
     const double P1 = T0 * ((dn1 - up1) * W.v1) + tx * t[1];
     const double P2 = T0 * ((dn2 - up2) * W.v2) + tx * t[2];
-    const double MP1 = (1.0 - 2.0 * xi) * P1 + 2.0 * eta * P2;
-    const double MP2 = 2.0 * eta * P1 + (1.0 + 2.0 * xi) * P2;
-    const double H = sqrt(P0 * P0 + P1 * MP1 + P2 * MP2);
+    // (ma, mb, mc) = (1 - 2 xi, 2 eta, 1 + 2 xi): the lower-right block of M
+    const double MP1 = ma * P1 + mb * P2;
+    const double MP2 = mb * P1 + mc * P2;
+    const double H = sqrt_nr(P0 * P0 + P1 * MP1 + P2 * MP2);
     return (sx - H) * (W.rho * rq) + ((up0 + dn0) * W.w0 + (up1 + dn1) * W.w1 + (up2 + dn2) * W.w2);
 }
 
@@ -284,7 +292,7 @@ struct Plan {
     double* diag = nullptr;   // adjoint: diagonal of each node's row [nsrc][N]
     double* rhs = nullptr;    // adjoint: right-hand side divided by the diagonal [nsrc][N]
     int* box = nullptr;       // adjoint: index box of each source's nonzero rhs [nsrc][6]
-    double* model = nullptr;  // forward: [4][Sa][4] = (s, xi, eta, 0) (aligned row-coalesced layouts)
+    double* model = nullptr;  // forward: [4][Sa][4] = (s, 1 - 2 xi, 2 eta, 1 + 2 xi) (aligned row-coalesced layouts)
     double* bnd_in = nullptr; // adjoint: [nsrc][NB] (continuous adjoint: boundary pass scratch)
     double* bnd_rhs = nullptr; // adjoint: right-hand side of the boundary nodes, [nsrc][NB]
     bool continuous = false;  // adjoint: upwind discretisation of Eq. (5) instead of the exact transpose

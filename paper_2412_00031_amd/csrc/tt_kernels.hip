@@ -214,6 +214,9 @@ struct TileCtx {
     bool colv, fcol;
     int i, j;
     int rbase, rstep;  // record index of this lane's column at k' = 0, and its change per k'
+    // forward fetches: record and axis-2 table index at step 0 and their
+    // bounds (the clamp of k' to [kplo, kphi] mapped to each index)
+    int rr0, rrlo, rrhi, tt0, ttlo, tthi;
     int slot;          // partial-sum slot of the tile within one directional sweep
 };
 
@@ -250,6 +253,12 @@ __device__ __forceinline__ TileCtx tile_ctx(const Geo& G, const Src& S, int plan
     const int w0 = D::fam == 0 ? c.j + c.kbase : c.j - c.kbase + G.n[2] - 1;
     c.rbase = (c.i * G.W + w0) * G.n1p + c.j + G.joff[D::s1 > 0 ? 0 : 1];
     c.rstep = D::s1 * G.n1p;
+    c.rr0 = c.rbase + c.rstep * c.kp0;
+    c.rrlo = c.rbase + c.rstep * (D::s1 > 0 ? c.kplo : c.kphi);
+    c.rrhi = c.rbase + c.rstep * (D::s1 > 0 ? c.kphi : c.kplo);
+    c.tt0 = c.kbase + D::s2 * c.kp0;
+    c.ttlo = c.kbase + D::s2 * (D::s2 > 0 ? c.kplo : c.kphi);
+    c.tthi = c.kbase + D::s2 * (D::s2 > 0 ? c.kphi : c.kplo);
     c.slot = (c.TI * G.nt[1] + c.TJ) * G.nt[2] + (c.TK - col_tile_lo(G, c.TI + c.TJ));
     return c;
 }
@@ -429,20 +438,21 @@ constexpr int kPre = 3;       // forward: steps are long (the full update)
 constexpr int kPreAdj = 6;    // adjoint: short steps, so look further ahead
 
 struct FwdSlot {
-    double sx, xi, eta, c2, s2;
+    double sx, ma, mb, mc, c2, s2;  // s, the anisotropy block (1 - 2 xi, 2 eta, 1 + 2 xi), axis-2 table
 };
 
 // unconditional: k' is clamped into the lane's range in the tile, so the address is always valid
 template <int DIR>
 __device__ __forceinline__ void fwd_fetch(const TileCtx& c, const double* __restrict__ mdl,
                                           const double2* __restrict__ t2, int t, FwdSlot& r) {
-    const int kp = min(max(c.kp0 + t, c.kplo), c.kphi);
-    const double2* m = reinterpret_cast<const double2*>(mdl + (c.rbase + c.rstep * kp) * 4LL);
+    const unsigned ri = (unsigned)min(max(c.rr0 + c.rstep * t, c.rrlo), c.rrhi);
+    const double2* m = reinterpret_cast<const double2*>(mdl + (size_t)ri * 4);
     const double2 m0 = m[0], m1 = m[1];
     r.sx = m0.x;
-    r.xi = m0.y;
-    r.eta = m1.x;
-    const double2 tv = t2[c.kbase + Dir<DIR>::s2 * kp];
+    r.ma = m0.y;
+    r.mb = m1.x;
+    r.mc = m1.y;
+    const double2 tv = t2[(unsigned)min(max(c.tt0 + Dir<DIR>::s2 * t, c.ttlo), c.tthi)];
     r.c2 = tv.x;
     r.s2 = tv.y;
 }
@@ -498,7 +508,7 @@ __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane, int s0
                         const double m0 = D::s0 > 0 ? up_i : dn_i, p0 = D::s0 > 0 ? dn_i : up_i;
                         const double m1 = D::s1 > 0 ? up_j : dn_j, p1 = D::s1 > 0 ? dn_j : up_j;
                         const double m2 = D::s2 > 0 ? up_k : dn_k, p2 = D::s2 > 0 ? dn_k : up_k;
-                        const double nv = lf_update<COORD>(G, S, cl, W, r.c2, r.s2, r.sx, r.xi, r.eta, cur, m0,
+                        const double nv = lf_update<COORD>(G, S, cl, W, r.c2, r.s2, r.sx, r.ma, r.mb, r.mc, cur, m0,
                                                            p0, m1, p1, m2, p2);
                         lds[o + sg] = nv;
                         eps += fabs(nv - cur);
@@ -514,7 +524,7 @@ __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane, int s0
     if (c.lane == 0) a.part[(long long)src * a.nslots + DIR * G.ntiles + c.slot] = eps;
 }
 
-// model records (s, xi, eta, 0) in the four aligned layouts
+// model records (s, 1 - 2 xi, 2 eta, 1 + 2 xi) in the four aligned layouts
 __global__ void k_model_records(Geo G, const double* __restrict__ s, const double* __restrict__ xi,
                                 const double* __restrict__ eta, double* __restrict__ out) {
     const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -522,7 +532,8 @@ __global__ void k_model_records(Geo G, const double* __restrict__ s, const doubl
     const int k = (int)(x % G.n[2]);
     const long long q = x / G.n[2];
     const int j = (int)(q % G.n[1]), i = (int)(q / G.n[1]);
-    const double2 v0 = make_double2(s[x], xi[x]), v1 = make_double2(eta[x], 0.0);
+    // the lower-right block of M = [[1 - 2 xi, 2 eta], [2 eta, 1 + 2 xi]]
+    const double2 v0 = make_double2(s[x], 1.0 - 2.0 * xi[x]), v1 = make_double2(2.0 * eta[x], 1.0 + 2.0 * xi[x]);
     for (int lay = 0; lay < 4; ++lay) {
         double2* o = reinterpret_cast<double2*>(out + ((long long)lay * G.Sa + arec_idx(G, lay, i, j, k)) * 4);
         o[0] = v0;
