@@ -22,7 +22,7 @@ import torch
 
 from . import _lib, api
 
-CANDIDATES = (8, 12, 16, 18, 20, 22, 24, 28, 32, 40, 48, 62)
+CANDIDATES = (8, 12, 14, 16, 18, 20, 22, 24, 28, 32, 40, 48, 62)
 GROUP_CANDIDATES = (1, 2, 3, 4, 6, 8)
 
 
