@@ -85,7 +85,15 @@ def parse():
                     help="which forward start to time (both: plain, then warm-started)")
     ap.add_argument("--weights", default=None, help="U-Net weights (.npz) of the warm start")
     ap.add_argument("--groups", type=int, default=0,
-                    help="concurrently iterated source groups of each solve (0: library default)")
+                    help="concurrently iterated source groups of each solve (0: autotuned, or the library "
+                         "default with --no-autotune)")
+    ap.add_argument("--order", choices=("iterations", "natural"), default="iterations",
+                    help="source order of the batch: by the iteration counts of a host-polled forward solve "
+                         "before the timed region, most first, so that each source group holds sources that "
+                         "converge together (iterations), or as generated (natural)")
+    ap.add_argument("--tune-iters", action="store_true",
+                    help="tune the source groups on a few iterations of the whole batch instead of whole "
+                         "solves to tol")
     ap.add_argument("--adjoint", choices=("discrete", "continuous"), default="discrete",
                     help="adjoint of the timed steps: the exact discrete transpose (default) or the upwind "
                          "discretisation of Eq. (5)")
@@ -366,6 +374,21 @@ def main():
         T_obs = t(W.straight_line_times(g, wl["src"], wl["rec"], 6.4))
     log(f"observations ready ({args.obs})")
 
+    if args.order == "iterations":
+        # scheduling input, like the tuner's choices: sources that take the
+        # most iterations first, so that each contiguous source group holds
+        # sources that converge together and a group's launches do not carry
+        # one slow source through a tail of otherwise finished ones
+        par0 = api.source_params(g, s, xi, eta, src)
+        _, st0 = api.forward(g, s, xi, eta, src, par0, tol, 1000, kappa, poll=True)
+        c0 = st0.cpu().numpy()
+        if (c0 <= 0).any():
+            sys.exit("ordering: the forward solve did not converge")
+        perm = torch.as_tensor(np.argsort(-c0, kind="stable"), device=dev)
+        src, T_obs = src[perm].contiguous(), T_obs[perm].contiguous()
+        del par0, st0
+        log(f"sources ordered by forward iterations ({int(c0.max())} .. {int(c0.min())})")
+
     tk_f = args.tile_k_fwd or args.tile_k
     tk_a = args.tile_k_adj or args.tile_k
     gr_f = gr_a = args.groups
@@ -373,7 +396,8 @@ def main():
     if (tk_f == 0 or tk_a == 0) and not args.no_autotune:
         from paper_2412_00031_amd import autotune
         par0 = api.source_params(g, s, xi, eta, src)
-        tuned = autotune.tune(g, s, xi, eta, src, par0, kappa, rec, log=log)
+        tuned = autotune.tune(g, s, xi, eta, src, par0, kappa, rec, log=log,
+                              tol=None if args.tune_iters else tol)
         tk_f, tk_a = tk_f or tuned["fwd"], tk_a or tuned["adj"]
         if args.groups == 0:
             gr_f, gr_a = tuned["groups_fwd"], tuned["groups_adj"]
@@ -576,6 +600,8 @@ def main():
                               "chosen_by": "autotune" if tuned else ("fixed" if (args.tile_k_fwd or args.tile_k_adj
                                                                                  or args.tile_k) else "default")},
                    "source_groups": {"fwd": gr_f, "adj": gr_a},
+                   "source_order": ("by forward iterations of a host-polled solve before timing, most first"
+                                    if args.order == "iterations" else "as generated"),
                    "solves": "asynchronous (iteration budget, no host polling)", "iteration_budgets": budgets,
                    "adjoint": args.adjoint},
         "roofline": roofline, "cpu_baseline": cpu, "aux": aux,

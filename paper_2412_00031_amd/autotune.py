@@ -6,14 +6,23 @@ For a grid and source count it times a few iterations of each solve for every
 candidate tile depth (the whole call, asynchronous as in production, with the
 library's default source groups), on the whole batch and on a quarter of it
 (the convergence tail of a solve runs with few sources left), keeps the
-fastest sum, and then times the source-group counts at that depth the same
-way.  Every candidate is timed over exactly the requested iterations: the
+fastest sum, and then times the source-group counts at that depth.  Every
+fixed-iteration candidate is timed over exactly the requested iterations: the
 tolerance is unreachable and the statuses are checked afterwards (a candidate
-that stopped early would look fast).  Any tile depth and any grouping give
-bit-identical results, so the choice affects speed only.  Choices are cached
-in a JSON file keyed by (kind, coordinates, grid shape, source count, library
-build, device name, hardware queues), so a rebuilt library is tuned afresh;
-the file is ``$TT_TUNE_CACHE`` or ``~/.cache/paper_2412_00031_amd/tiles.json``.
+that stopped early would look fast).
+
+With a tolerance (``tol``) the group counts are timed on whole solves of the
+batch to that tolerance instead: asynchronous, with the budget of a
+host-polled solve (its largest iteration count plus a margin), every status
+checked.  Groups matter most in the convergence tail, when each group's
+launches carry a few sources and the groups fill each other's idle units, and
+a few iterations of the whole batch do not show that.
+
+Any tile depth and any grouping give bit-identical results, so the choice
+affects speed only.  Choices are cached in a JSON file keyed by (kind,
+coordinates, grid shape, source count, library build, device name, hardware
+queues, tuning mode), so a rebuilt library is tuned afresh; the file is
+``$TT_TUNE_CACHE`` or ``~/.cache/paper_2412_00031_amd/tiles.json``.
 """
 import json
 import os
@@ -33,11 +42,12 @@ def cache_path():
     return os.path.join(os.path.expanduser("~"), ".cache", "paper_2412_00031_amd", "tiles.json")
 
 
-def _key(kind, grid, nsrc):
+def _key(kind, grid, nsrc, tol=None):
     n = "x".join(str(int(v)) for v in grid["n"])
     dev = torch.cuda.get_device_name().replace(":", " ") if torch.cuda.is_available() else "none"
     hwq = os.environ.get("GPU_MAX_HW_QUEUES", "default")
-    return f"{kind}:{int(grid['coord'])}:{n}:{int(nsrc)}:{_lib.build_id()}:{dev}:hwq{hwq}"
+    mode = "iters" if tol is None else f"tol{tol:g}"
+    return f"{kind}:{int(grid['coord'])}:{n}:{int(nsrc)}:{_lib.build_id()}:{dev}:hwq{hwq}:{mode}"
 
 
 def _load():
@@ -84,14 +94,39 @@ def _time(kind, grid, s, xi, eta, src, par, tau, rec, R, kappa, tk, groups, iter
                                            groups=groups), iters)
 
 
+BUDGET_MARGIN = 8
+
+
+def _solve(kind, grid, s, xi, eta, src, par, tau, rec, R, kappa, tol, budget, tk, groups, poll=False):
+    if kind == "fwd":
+        return api.forward(grid, s, xi, eta, src, par, tol, budget, kappa, tile_k=tk, groups=groups, poll=poll)
+    return api.adjoint(grid, s, xi, eta, src, par, tau, rec, R, tol, budget, kappa, tile_k=tk, groups=groups,
+                       poll=poll)
+
+
+def _converged_ms(kind, grid, s, xi, eta, src, par, tau, rec, R, kappa, tol, budget, tk, groups):
+    """Device time of a whole asynchronous solve to tol within `budget`
+    iterations; every source must converge."""
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    _, st = _solve(kind, grid, s, xi, eta, src, par, tau, rec, R, kappa, tol, budget, tk, groups)
+    e1.record()
+    torch.cuda.synchronize()
+    if not bool((st > 0).all()):
+        raise RuntimeError(f"autotune: a {kind} solve did not converge within its budget of {budget} iterations")
+    return e0.elapsed_time(e1)
+
+
 def tune(grid, s, xi, eta, src, par, kappa, rec, R=None, iters=3, candidates=CANDIDATES,
-         group_candidates=GROUP_CANDIDATES, use_cache=True, log=None):
+         group_candidates=GROUP_CANDIDATES, use_cache=True, log=None, tol=None):
     """Return {"fwd": tile_k, "adj": tile_k, "groups_fwd": g, "groups_adj": g}
     for this grid and batch size.  R: the adjoint sources the adjoint solves
-    are timed with (any nonzero values; default all ones)."""
+    are timed with (any nonzero values; default all ones).  tol: time the
+    group counts on whole solves to this tolerance (see the module notes)."""
     nsrc = int(src.shape[0])
     cache = _load() if use_cache else {}
-    keys = {kind: _key(kind, grid, nsrc) for kind in ("fwd", "adj")}
+    keys = {kind: _key(kind, grid, nsrc, tol) for kind in ("fwd", "adj")}
     if use_cache and all(k in cache and "groups" in cache[k] for k in keys.values()):
         return {"fwd": int(cache[keys["fwd"]]["tile_k"]), "adj": int(cache[keys["adj"]]["tile_k"]),
                 "groups_fwd": int(cache[keys["fwd"]]["groups"]), "groups_adj": int(cache[keys["adj"]]["groups"]),
@@ -116,7 +151,22 @@ def tune(grid, s, xi, eta, src, par, kappa, rec, R=None, iters=3, candidates=CAN
             return round(ms, 3)
         times = {tk: cost(tk, 0) for tk in cands}
         best = min(times, key=times.get)
-        gtimes = {gq: cost(best, gq) for gq in group_candidates if gq <= max(1, nsrc)}
+        gcands = [gq for gq in group_candidates if gq <= max(1, nsrc)]
+        if tol is None:
+            gtimes = {gq: cost(best, gq) for gq in gcands}
+        else:
+            # whole solves to tol: the forward from tau = 1, the adjoint at the
+            # converged forward field
+            tau_c = None
+            if kind == "adj":
+                tau_c, _ = _solve("fwd", grid, s, xi, eta, src, par, None, rec, R, kappa, tol, 1000, res["fwd"], 0,
+                                  poll=True)
+            _, st_p = _solve(kind, grid, s, xi, eta, src, par, tau_c, rec, R, kappa, tol, 1000, best, 0, poll=True)
+            if not bool((st_p > 0).all()):
+                raise RuntimeError(f"autotune: a host-polled {kind} solve did not converge in 1000 iterations")
+            budget = int(st_p.max().item()) + BUDGET_MARGIN
+            gtimes = {gq: round(min(_converged_ms(kind, grid, s, xi, eta, src, par, tau_c, rec, R, kappa, tol,
+                                                  budget, best, gq) for _ in range(2)), 3) for gq in gcands}
         bestg = min(gtimes, key=gtimes.get)
         res[kind] = best
         res["groups_" + kind] = bestg
