@@ -12,9 +12,10 @@ observed times come from a forward solve in an independent random model
 (computed before timing).
 
 The solves of a timed step are asynchronous: each enqueues its iteration
-budget (the largest iteration count of a host-polled calibration step of the
-same start, plus a margin) and nothing waits on the host; converged sources
-exit on the device.  After the timed steps every source's status is checked:
+budget and nothing waits on the host; converged sources exit on the device.
+The budgets are per source (its iteration count in a host-polled calibration
+step of the same start, plus a margin); each source group of a solve iterates
+the largest budget of its sources.  After the timed steps every source's status is checked:
 a source that reached its budget unconverged voids the value (null, exit 3).
 The plain path (tau = 1 start) and the warm-started path run the same steps
 back to back; value = sources per second (fwd + adjoint + kernel per source)
@@ -68,8 +69,11 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=1000,
                     help="iteration cap of the host-polled calibration and comparison steps")
     ap.add_argument("--budget-margin", type=int, default=8,
-                    help="iterations added to the calibration step's largest count to give the budget of the "
-                         "asynchronous solves")
+                    help="iterations added to each source's count in the calibration step to give its budget in "
+                         "the asynchronous solves")
+    ap.add_argument("--uniform-budget", action="store_true",
+                    help="one budget per solve (the largest calibrated count plus the margin) instead of "
+                         "per-source budgets")
     ap.add_argument("--compare-steps", type=int, default=3,
                     help="timed steps of the comparison paths (host-polled, graph replay, continuous adjoint); 0 "
                          "skips them")
@@ -427,17 +431,19 @@ def main():
         else:
             log(f"no warm-start weights at {wpath}: timing the plain path only")
 
-    budget = {"fwd": args.max_iter, "adj": args.max_iter}
+    budget = {"fwd": args.max_iter, "adj": args.max_iter, "fwd_src": None, "adj_src": None}
 
     def step(use_warm, poll=False, timed=False, graph=False, continuous=args.adjoint == "continuous"):
         par = api.source_params(g, s, xi, eta, src)
         init = warm.predict(s, xi, eta, src, par, out=init_buf) if use_warm else None
         api.forward(g, s, xi, eta, src, par, tol, budget["fwd"], kappa, tau_init=init, tile_k=tk_f, ws=ws_f,
-                    out=tau, time_sweeps=timed, graph=graph, groups=gr_f, poll=poll, status=st_f)
+                    out=tau, time_sweeps=timed, graph=graph, groups=gr_f, poll=poll, status=st_f,
+                    budgets=budget["fwd_src"])
         T = api.sample(g, src, par, tau, rec)
         chi, R = api.misfit(T, T_obs)
         api.adjoint(g, s, xi, eta, src, par, tau, rec, R, tol, budget["adj"], kappa, tile_k=tk_a, ws=ws_a, out=lam,
-                    time_sweeps=timed, graph=graph, groups=gr_a, continuous=continuous, poll=poll, status=st_a)
+                    time_sweeps=timed, graph=graph, groups=gr_a, continuous=continuous, poll=poll, status=st_a,
+                    budgets=budget["adj_src"])
         api.kernel(g, s, xi, eta, src, par, tau, lam, grad=grad.zero_())
         return chi
 
@@ -462,20 +468,26 @@ def main():
                     sweep=(api.sweep_timing(0, reset=True), api.sweep_timing(1, reset=True)))
 
     # Iteration budgets of the asynchronous solves: a host-polled step of each
-    # start finds the iteration counts, and the budget is the largest count
-    # plus a margin; every timed step's statuses are checked afterwards.
+    # start finds every source's iteration counts, and its budget is its count
+    # plus a margin (each source group iterates the largest budget of its
+    # sources); every timed step's statuses are checked afterwards.
     def calibrate(use_warm, continuous=False):
         step(use_warm, poll=True, continuous=continuous)
         torch.cuda.synchronize()
         f, a = st_f.cpu().numpy(), st_a.cpu().numpy()
         if (f <= 0).any() or (a <= 0).any():
             sys.exit(f"calibration step did not converge within {args.max_iter} iterations")
-        return int(f.max()), int(a.max())
+        return f.astype(np.int32), a.astype(np.int32)
 
-    def with_budget(fmax, amax, fn):
+    def with_budget(fc, ac, fn):
+        fb, ab = fc + args.budget_margin, ac + args.budget_margin
         def wrapped():
-            budget["fwd"], budget["adj"] = fmax + args.budget_margin, amax + args.budget_margin
-            return fn()
+            budget["fwd"], budget["adj"] = int(fb.max()), int(ab.max())
+            budget["fwd_src"], budget["adj_src"] = (None, None) if args.uniform_budget else (fb, ab)
+            try:
+                return fn()
+            finally:  # the other steps (host-polled) run to convergence within max_iter
+                budget.update(fwd=args.max_iter, adj=args.max_iter, fwd_src=None, adj_src=None)
         return wrapped
 
     runs, budgets, cal = {}, {}, {}
@@ -483,8 +495,11 @@ def main():
         cal["plain"] = calibrate(False)
         if warm is not None:
             cal["warm"] = calibrate(True)
-        budgets = {k: [v[0] + args.budget_margin, v[1] + args.budget_margin] for k, v in cal.items()}
-        log(f"iteration budgets (largest polled count + {args.budget_margin}): {budgets}")
+        budgets = {k: {"fwd": [int(v[0].min()) + args.budget_margin, int(v[0].max()) + args.budget_margin],
+                       "adj": [int(v[1].min()) + args.budget_margin, int(v[1].max()) + args.budget_margin]}
+                   for k, v in cal.items()}
+        log(f"iteration budgets (polled count + {args.budget_margin}, "
+            f"{'largest per solve' if args.uniform_budget else 'per source'}; min, max): {budgets}")
     if not args.roofline_only:
         runs["plain"] = run("plain", args.steps, args.warmup, with_budget(*cal["plain"], lambda: step(False)))
         if warm is not None:
@@ -603,6 +618,9 @@ def main():
                    "source_order": ("by forward iterations of a host-polled solve before timing, most first"
                                     if args.order == "iterations" else "as generated"),
                    "solves": "asynchronous (iteration budget, no host polling)", "iteration_budgets": budgets,
+                   "budget_rule": (f"largest calibrated count + {args.budget_margin} per solve" if args.uniform_budget
+                                   else f"calibrated count + {args.budget_margin} per source, the largest of a "
+                                        "source group's budgets for the group"),
                    "adjoint": args.adjoint},
         "roofline": roofline, "cpu_baseline": cpu, "aux": aux,
     }

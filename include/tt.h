@@ -92,6 +92,15 @@ typedef struct tt_opts {
                           convergence tail); 0 = automatic (nsrc / 32, at most
                           4); 1 when TT_FLAG_TIME_SWEEPS is set.  Results do not
                           depend on it. */
+    const int32_t* budgets;  /* optional HOST array [nsrc] of per-source iteration
+                          budgets, each in [1, max_iter] (e.g. the previous
+                          solve's counts plus a margin), or NULL: every source
+                          has max_iter.  An asynchronous solve gives each source
+                          group the largest budget of its sources, so a group of
+                          fast sources stops enqueuing early; a host-polled one
+                          stops a group at that budget too.  A source converges
+                          or reports -iterations as usual; results do not depend
+                          on the budgets otherwise.  Read during the call only. */
 } tt_opts;
 
 #define TT_MAX_GROUPS 8

@@ -18,7 +18,7 @@ class TTGrid(ctypes.Structure):
 class TTOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("kappa", ctypes.c_double),
                 ("tile_k", ctypes.c_int32), ("flags", ctypes.c_int32), ("eps_hist", ctypes.c_void_p),
-                ("groups", ctypes.c_int32)]
+                ("groups", ctypes.c_int32), ("budgets", ctypes.c_void_p)]
 
 
 EXPORTS = ["tt_workspace_size", "tt_source_params", "tt_forward", "tt_forward_noalloc", "tt_forward_noalloc_limit", "tt_sample", "tt_misfit", "tt_misfit_cr", "tt_reloc_times", "tt_reloc_kernel",

@@ -9,6 +9,7 @@ z/y/x km, 1 spherical r km / latitude rad / longitude rad), ``o`` and ``h``.
 """
 import ctypes
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -26,9 +27,22 @@ def _grid(grid):
     return g
 
 
+def _budgets(budgets, nsrc):
+    """Host int32 copy of per-source iteration budgets (kept alive by the
+    caller for the duration of the call), or None."""
+    if budgets is None:
+        return None
+    b = np.ascontiguousarray(np.asarray(budgets.cpu() if isinstance(budgets, torch.Tensor) else budgets,
+                                        dtype=np.int32).reshape(-1))
+    if b.size != nsrc:
+        raise ValueError(f"budgets must have one entry per source ({nsrc}), got {b.size}")
+    return b
+
+
 def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None, graph=False, groups=0, continuous=False,
-          poll=False, compact=False):
+          poll=False, compact=False, budgets=None):
     o = _lib.TTOpts()
+    o.budgets = budgets.ctypes.data if budgets is not None else None
     o.groups = int(groups)
     o.eps_hist = _dev(eps_hist, "eps_hist").value if eps_hist is not None else None
     o.tol = float(tol)
@@ -108,7 +122,8 @@ def source_params(grid, s, xi, eta, src_pos):
 
 
 def forward(grid, s, xi, eta, src_pos, src_par, tol, max_iter, kappa, tau_init=None, tile_k=0, ws=None,
-            out=None, time_sweeps=False, eps_hist=None, graph=False, groups=0, poll=False, status=None):
+            out=None, time_sweeps=False, eps_hist=None, graph=False, groups=0, poll=False, status=None,
+            budgets=None):
     """Batched forward solve.  Returns (tau [nsrc, *n], status int32 [nsrc]).
     eps_hist: optional float64 device tensor [nsrc, max_iter] receiving the
     convergence measure of every iteration.  groups: concurrently iterated
@@ -116,7 +131,9 @@ def forward(grid, s, xi, eta, src_pos, src_par, tol, max_iter, kappa, tau_init=N
     poll=False (the library's default) enqueues exactly max_iter iterations on
     the current stream and returns at once (capturable; max_iter is the
     iteration budget and status is written on the device); poll=True stops as
-    soon as every source has converged and returns after completion."""
+    soon as every source has converged and returns after completion.
+    budgets: optional per-source iteration budgets (host sequence of nsrc ints
+    in [1, max_iter]); each source group iterates the largest of its own."""
     lib = _lib.load()
     N = _N(grid)
     nsrc = int(src_pos.shape[0])
@@ -129,7 +146,8 @@ def forward(grid, s, xi, eta, src_pos, src_par, tol, max_iter, kappa, tau_init=N
     g = _grid(grid)
     if eps_hist is not None and eps_hist.numel() != nsrc * int(max_iter):
         raise ValueError("eps_hist must have nsrc * max_iter elements")
-    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph, groups, poll=poll)
+    bud = _budgets(budgets, nsrc)
+    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph, groups, poll=poll, budgets=bud)
     ti = _dev(tau_init, "tau_init", numel=nsrc * N) if tau_init is not None else _null()
     _lib.check(lib.tt_forward(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
                               _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
@@ -252,9 +270,9 @@ def misfit_cr(T_rec, T_obs, cr_off, cr_pair, wcr, gamma, R, chi):
 
 def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, kappa, tile_k=0, ws=None,
             out=None, time_sweeps=False, eps_hist=None, graph=False, groups=0, continuous=False, poll=False,
-            status=None, compact=False):
+            status=None, compact=False, budgets=None):
     """Batched adjoint solve.  Returns (lambda [nsrc, *n], status int32 [nsrc]);
-    eps_hist, groups and poll as for forward.  continuous=True solves Eq. (5)
+    eps_hist, groups, poll and budgets as for forward.  continuous=True solves Eq. (5)
     by upwind finite volumes and returns P s V in place of lambda.
     compact=True keeps one node-order copy of the coefficient records (a
     ninth of the workspace at 101^3; slower sweeps, identical results)."""
@@ -270,7 +288,9 @@ def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, 
     g = _grid(grid)
     if eps_hist is not None and eps_hist.numel() != nsrc * int(max_iter):
         raise ValueError("eps_hist must have nsrc * max_iter elements")
-    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph, groups, continuous, poll, compact)
+    bud = _budgets(budgets, nsrc)
+    o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph, groups, continuous, poll, compact,
+              budgets=bud)
     _lib.check(lib.tt_adjoint(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
                               _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
                               _dev(src_par, "src_par", numel=3 * nsrc), _dev(tau, "tau", numel=nsrc * N), nrec,

@@ -12,8 +12,8 @@ tolerance is unreachable and the statuses are checked afterwards (a candidate
 that stopped early would look fast).
 
 With a tolerance (``tol``) the group counts are timed on whole solves of the
-batch to that tolerance instead: asynchronous, with the budget of a
-host-polled solve (its largest iteration count plus a margin), every status
+batch to that tolerance instead: asynchronous, with per-source budgets from a
+host-polled solve (each source's iteration count plus a margin), every status
 checked.  Groups matter most in the convergence tail, when each group's
 launches carry a few sources and the groups fill each other's idle units, and
 a few iterations of the whole batch do not show that.
@@ -97,24 +97,27 @@ def _time(kind, grid, s, xi, eta, src, par, tau, rec, R, kappa, tk, groups, iter
 BUDGET_MARGIN = 8
 
 
-def _solve(kind, grid, s, xi, eta, src, par, tau, rec, R, kappa, tol, budget, tk, groups, poll=False):
+def _solve(kind, grid, s, xi, eta, src, par, tau, rec, R, kappa, tol, max_iter, tk, groups, poll=False,
+           budgets=None):
     if kind == "fwd":
-        return api.forward(grid, s, xi, eta, src, par, tol, budget, kappa, tile_k=tk, groups=groups, poll=poll)
-    return api.adjoint(grid, s, xi, eta, src, par, tau, rec, R, tol, budget, kappa, tile_k=tk, groups=groups,
-                       poll=poll)
+        return api.forward(grid, s, xi, eta, src, par, tol, max_iter, kappa, tile_k=tk, groups=groups, poll=poll,
+                           budgets=budgets)
+    return api.adjoint(grid, s, xi, eta, src, par, tau, rec, R, tol, max_iter, kappa, tile_k=tk, groups=groups,
+                       poll=poll, budgets=budgets)
 
 
-def _converged_ms(kind, grid, s, xi, eta, src, par, tau, rec, R, kappa, tol, budget, tk, groups):
-    """Device time of a whole asynchronous solve to tol within `budget`
-    iterations; every source must converge."""
+def _converged_ms(kind, grid, s, xi, eta, src, par, tau, rec, R, kappa, tol, budgets, tk, groups):
+    """Device time of a whole asynchronous solve to tol within per-source
+    iteration budgets; every source must converge."""
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    _, st = _solve(kind, grid, s, xi, eta, src, par, tau, rec, R, kappa, tol, budget, tk, groups)
+    _, st = _solve(kind, grid, s, xi, eta, src, par, tau, rec, R, kappa, tol, int(budgets.max()), tk, groups,
+                   budgets=budgets)
     e1.record()
     torch.cuda.synchronize()
     if not bool((st > 0).all()):
-        raise RuntimeError(f"autotune: a {kind} solve did not converge within its budget of {budget} iterations")
+        raise RuntimeError(f"autotune: a {kind} solve did not converge within its iteration budgets")
     return e0.elapsed_time(e1)
 
 
@@ -164,9 +167,9 @@ def tune(grid, s, xi, eta, src, par, kappa, rec, R=None, iters=3, candidates=CAN
             _, st_p = _solve(kind, grid, s, xi, eta, src, par, tau_c, rec, R, kappa, tol, 1000, best, 0, poll=True)
             if not bool((st_p > 0).all()):
                 raise RuntimeError(f"autotune: a host-polled {kind} solve did not converge in 1000 iterations")
-            budget = int(st_p.max().item()) + BUDGET_MARGIN
+            budgets = st_p.cpu().numpy() + BUDGET_MARGIN
             gtimes = {gq: round(min(_converged_ms(kind, grid, s, xi, eta, src, par, tau_c, rec, R, kappa, tol,
-                                                  budget, best, gq) for _ in range(2)), 3) for gq in gcands}
+                                                  budgets, best, gq) for _ in range(2)), 3) for gq in gcands}
         bestg = min(gtimes, key=gtimes.get)
         res[kind] = best
         res["groups_" + kind] = bestg

@@ -546,6 +546,11 @@ int make_groups(const tt::Geo& G, int nsrc, int groups, int which, void* ws, siz
     const bool compact = which == 1 && compact_of(opts);
     const size_t need = grouped_total(G, nsrc, groups, which, compact);
     if (ws_bytes < need) return fail(TT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    if (opts->budgets)
+        for (int q = 0; q < nsrc; ++q)
+            if (opts->budgets[q] < 1 || opts->budgets[q] > opts->max_iter)
+                return fail(TT_EINVAL, "opts.budgets[%d] = %d is outside [1, max_iter = %d]", q, opts->budgets[q],
+                            opts->max_iter);
     hipEvent_t fork = nullptr;
     if (groups > 1) {
         int dev = 0, rc0 = device_index(&dev);
@@ -566,6 +571,12 @@ int make_groups(const tt::Geo& G, int nsrc, int groups, int which, void* ws, siz
         g.P.kappa = opts->kappa;
         g.P.tol = opts->tol;
         g.P.max_iter = opts->max_iter;
+        if (opts->budgets) {  // the group iterates its largest per-source budget
+            g.P.max_iter = 1;
+            for (int k = group_begin(nsrc, groups, q); k < group_begin(nsrc, groups, q + 1); ++k)
+                g.P.max_iter = opts->budgets[k] > g.P.max_iter ? opts->budgets[k] : g.P.max_iter;
+        }
+        g.P.hist_stride = opts->max_iter;
         rc = group_stream(q, caller, &g.st);
         if (rc == TT_OK && q > 0) {
             hipError_t e = hipStreamWaitEvent(g.st, fork, 0);

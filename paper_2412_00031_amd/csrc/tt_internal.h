@@ -276,7 +276,8 @@ struct Plan {
     int nbblocks = 0;         // boundary-pass blocks per source
     int nslots = 0;           // partial-sum slots per source per iteration
     double kappa = 1.0, tol = 1e-6;
-    int max_iter = 1;
+    int max_iter = 1;         // iteration budget of this group
+    int hist_stride = 1;      // row length of eps_hist (the call's max_iter)
     double* eps_hist = nullptr;
     // workspace views
     Src* src = nullptr;
@@ -324,8 +325,8 @@ struct SweepArgs {
     double* part;
     double* part2;
     int* counter;
-    double* eps_hist;       // optional [nsrc][max_iter]
-    int nslots, nbblocks, nsrc, max_iter;
+    double* eps_hist;       // optional [nsrc][hist_stride]
+    int nslots, nbblocks, nsrc, max_iter, hist_stride;
     int compact;            // adjoint records in node order (TT_FLAG_COMPACT_ADJOINT)
     double kappa, tol;
 };

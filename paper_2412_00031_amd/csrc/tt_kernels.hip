@@ -590,7 +590,7 @@ __device__ __forceinline__ double fixed_sum(const double* p, int cnt, double* sh
 __device__ __forceinline__ void finish_iteration(const SweepArgs& a, int src, double eps) {
     const int it = a.iter[src] + 1;
     a.iter[src] = it;
-    if (a.eps_hist) a.eps_hist[(long long)src * a.max_iter + (it - 1)] = eps;
+    if (a.eps_hist) a.eps_hist[(long long)src * a.hist_stride + (it - 1)] = eps;
     if (eps < a.tol) {
         a.status[src] = it;
         a.active[src] = 0;
@@ -1248,6 +1248,7 @@ SweepArgs make_args(const Plan& P, const double* s, const double* xi, const doub
     a.nsrc = P.nsrc;
     a.compact = P.compact ? 1 : 0;
     a.max_iter = P.max_iter;
+    a.hist_stride = P.hist_stride;
     a.kappa = P.kappa;
     a.tol = P.tol;
     return a;

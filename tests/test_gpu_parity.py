@@ -189,6 +189,51 @@ def test_source_groups_bitwise(torch_cuda):
     assert rel_inf(ref[0], o["tau"]) <= TOL_TAU and rel_inf(ref[3], o["lam"]) <= TOL_ADJ
 
 
+def test_per_source_budgets(torch_cuda):
+    """Per-source iteration budgets: each source group iterates the largest
+    budget of its sources.  Budgets at or above every source's own count
+    change nothing (fields, statuses and convergence histories bit-identical
+    to a uniform budget, asynchronous and polled, several groupings); a group
+    whose budgets all fall short reports -budget for its sources while the
+    other group converges as before; out-of-range budgets are refused."""
+    from paper_2412_00031_amd import _lib, api
+    wl = W.small_spherical(n=(14, 15, 16), nsrc=6, nrec=10, seed=29)
+    g, kap = wl["grid"], wl["kappa"]
+    s, xi, eta, src, rec, R = (_dev(torch_cuda, wl[k]) for k in ("s", "xi", "eta", "src", "rec", "R"))
+    par = api.source_params(g, s, xi, eta, src)
+
+    def run(bf, ba, groups, poll):
+        hf = torch_cuda.zeros((6, 300), dtype=torch_cuda.float64, device="cuda")
+        ha = torch_cuda.zeros((6, 300), dtype=torch_cuda.float64, device="cuda")
+        tau, st = api.forward(g, s, xi, eta, src, par, 1e-10, 300, kap, groups=groups, eps_hist=hf, poll=poll,
+                              budgets=bf)
+        lam, sa = api.adjoint(g, s, xi, eta, src, par, tau, rec, R, 1e-10, 300, kap, groups=groups, eps_hist=ha,
+                              poll=poll, budgets=ba)
+        torch_cuda.cuda.synchronize()
+        return [x.cpu().numpy() for x in (tau, st, hf, lam, sa, ha)]
+
+    ref = run(None, None, 1, False)
+    cf, ca = ref[1], ref[4]
+    assert (cf > 0).all() and (ca > 0).all()
+    for groups, poll, extra in ((2, False, 0), (3, True, 0), (1, False, 0), (6, False, 2), (2, True, 5)):
+        got = run(cf + extra, ca + extra, groups, poll)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), (groups, poll, extra)
+    # two groups of three: the second group's budgets are all 1
+    short = cf.copy()
+    short[3:] = 1
+    tau2, st2 = api.forward(g, s, xi, eta, src, par, 1e-10, 300, kap, groups=2, budgets=short)
+    torch_cuda.cuda.synchronize()
+    st2 = st2.cpu().numpy()
+    assert np.array_equal(st2[:3], cf[:3]) and (st2[3:] == -1).all(), st2
+    assert np.array_equal(tau2.cpu().numpy()[:3], ref[0][:3])
+    for bad in ([0] + [5] * 5, [301] + [5] * 5):
+        with pytest.raises(_lib.TTError):
+            api.forward(g, s, xi, eta, src, par, 1e-10, 300, kap, budgets=bad)
+    with pytest.raises(ValueError):
+        api.forward(g, s, xi, eta, src, par, 1e-10, 300, kap, budgets=[5] * 5)
+
+
 def test_compact_adjoint_records_bitwise(torch_cuda):
     """The compact record layout (one node-order copy of the adjoint's
     coefficient records, TT_FLAG_COMPACT_ADJOINT) reads the same couplings in
