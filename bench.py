@@ -378,11 +378,12 @@ def main():
         T_obs = t(W.straight_line_times(g, wl["src"], wl["rec"], 6.4))
     log(f"observations ready ({args.obs})")
 
-    if args.order == "iterations":
+    if args.order == "iterations" and not args.roofline_only:
         # scheduling input, like the tuner's choices: sources that take the
         # most iterations first, so that each contiguous source group holds
         # sources that converge together and a group's launches do not carry
-        # one slow source through a tail of otherwise finished ones
+        # one slow source through a tail of otherwise finished ones (the
+        # roofline step runs one group, where the order does not matter)
         par0 = api.source_params(g, s, xi, eta, src)
         _, st0 = api.forward(g, s, xi, eta, src, par0, tol, 1000, kappa, poll=True)
         c0 = st0.cpu().numpy()
