@@ -141,3 +141,21 @@ def test_default_tile_depths_exported(libpath):
     lib = _lib.load()
     assert 1 <= lib.tt_default_tile_k(0) <= 62 and 1 <= lib.tt_default_tile_k(1) <= 62
     assert lib.tt_default_tile_k(2) == 0
+
+
+def test_budget_marshalling_host_logic():
+    """Per-source iteration budgets are marshalled as a host int32 array of
+    one entry per source (lists, numpy arrays and CPU tensors alike); a wrong
+    length is refused before any library call; the options struct carries its
+    address."""
+    import torch
+    from paper_2412_00031_amd import api
+    b = api._budgets([3, 4, 5], 3)
+    assert b.dtype == np.int32 and b.tolist() == [3, 4, 5] and b.flags["C_CONTIGUOUS"]
+    assert api._budgets(torch.tensor([7, 8], dtype=torch.int64), 2).tolist() == [7, 8]
+    assert api._budgets(None, 4) is None
+    with pytest.raises(ValueError):
+        api._budgets([1, 2], 3)
+    o = api._opts(1e-6, 10, 1.0, budgets=b)
+    assert o.budgets == b.ctypes.data and o.max_iter == 10
+    assert api._opts(1e-6, 10, 1.0).budgets is None
