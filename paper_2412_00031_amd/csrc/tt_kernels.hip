@@ -75,6 +75,8 @@ __device__ __forceinline__ long long bnd_encode(const Geo& G, int i, int j, int 
 }
 
 __device__ __forceinline__ bool on_bnd(const Geo& G, int a, int idx) { return idx == 0 || idx == G.n[a] - 1; }
+// boundary node (i, j, k) on a k face only: its column is interior
+__device__ __forceinline__ bool kface_only(const Geo& G, int i, int j) { return !on_bnd(G, 0, i) && !on_bnd(G, 1, j); }
 
 // Row-coalesced record layouts.  On a sweep hyperplane the 8 lanes of one
 // tile row (fixed i, consecutive j) satisfy j + rho k = const with
@@ -361,11 +363,20 @@ __device__ __forceinline__ void stage_tile(const Geo& G, const TileCtx& c, const
             y += dy_q;
             --w;
         }
-        while (cj >= kTC) {
+        // cj < kTC + dcol + 1: one wrap unless dcol >= kTC (pitches below 13)
+        if (cj >= kTC) {
             cj -= kTC;
             ++ci;
             y += dy_w;
             w += kTC - 1;
+            if (dcol >= kTC) {
+                while (cj >= kTC) {
+                    cj -= kTC;
+                    ++ci;
+                    y += dy_w;
+                    w += kTC - 1;
+                }
+            }
         }
     }
     __builtin_amdgcn_s_waitcnt(0);  // every load of the window (and any earlier one) has landed
@@ -422,13 +433,53 @@ __device__ __forceinline__ void unstage_tile(const Geo& G, const TileCtx& c, dou
                 x += x_q;
                 loff += l_q;
             }
-            while (lj >= nj) {
+            // lj < nj + dcol: one wrap unless dcol >= nj
+            if (lj >= nj) {
                 lj -= nj;
                 kp += kp_j;
                 x += x_j;
                 loff += l_j;
+                if (dcol >= nj) {
+                    while (lj >= nj) {
+                        lj -= nj;
+                        kp += kp_j;
+                        x += x_j;
+                        loff += l_j;
+                    }
+                }
             }
         }
+    }
+}
+
+// Forward sweeps: a boundary node on a k face only (its column is interior)
+// copies the column's interior end node k' = 0 or m2 - 1 (the boundary rule
+// copies the inward neighbour along the last boundary axis, here k).  Nothing
+// else in a sweep reads or writes it, so the tile that finalises the end node
+// sets it right after its walk, next to the column it has just written back;
+// the boundary pass skips those nodes (strided ones: each sits in a cache line
+// of its own) and the change joins the tile's convergence sum.  (The adjoint
+// keeps them in its boundary pass: its value also needs the node's right-hand
+// side and coupling, loaded after the walk, which cost the sweep more than the
+// pass saved.)
+template <int DIR>
+__device__ __forceinline__ void fwd_kface_nodes(const Geo& G, const Src& S, const TileCtx& c, double* __restrict__ fld,
+                                                const double* lds, int own, int Lp, double& eps) {
+    using D = Dir<DIR>;
+    constexpr int sg = D::s2;
+    if (!c.colv) return;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int kin = e == 0 ? 0 : G.m[2] - 1;                // the interior end node's k'
+        const int t = kin - c.kp0;                              // the step that updated it
+        if (t < c.t0 || t >= c.t1) continue;
+        const int kb = c.kbase + sg * (e == 0 ? -1 : G.m[2]);  // absolute k of the boundary node
+        if (in_fixed(S, c.i, c.j, kb)) continue;
+        const int o = sg > 0 ? own + t : own + Lp - 1 - t;
+        const double nv = lds[o + sg];                       // entry t + 1: the end node
+        const double old = lds[e == 0 ? o : o + 2 * sg];     // entry t or t + 2: the boundary node
+        fld[nidx(G, c.i, c.j, kb)] = nv;
+        eps += fabs(nv - old);
     }
 }
 
@@ -520,6 +571,7 @@ __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane, int s0
     }
     __syncthreads();
     unstage_tile<DIR>(G, c, fld, lds, Lp);
+    fwd_kface_nodes<DIR>(G, S, c, fld, lds, own, Lp, eps);
     eps = wave_sum(eps);
     if (c.lane == 0) a.part[(long long)src * a.nslots + DIR * G.ntiles + c.slot] = eps;
 }
@@ -570,7 +622,8 @@ __global__ void __launch_bounds__(kBndThreads) k_fwd_bnd(SweepArgs a, int dir) {
     if (b < G.NB) {
         int i, j, k;
         bnd_decode(G, b, i, j, k);
-        if (!in_fixed(S, i, j, k)) {
+        // (the sweeps set the nodes on a k face only)
+        if (!in_fixed(S, i, j, k) && !kface_only(G, i, j)) {
             const double nv = fwd_bval<3>(G, S, fld, i, j, k);
             const long long x = nidx(G, i, j, k);
             d = fabs(nv - fld[x]);
