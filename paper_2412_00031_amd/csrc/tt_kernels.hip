@@ -382,72 +382,49 @@ __device__ __forceinline__ void stage_tile(const Geo& G, const TileCtx& c, const
     __builtin_amdgcn_s_waitcnt(0);  // every load of the window (and any earlier one) has landed
 }
 
-// Write-back stores are issued kStageBatch at a time per lane.
-constexpr int kStageBatch = 16;
-
 // Write back the tile's own nodes: entries 1..tk of its columns whose k' is
-// an interior node (the others are halo or outside the column).  Element
-// e = 64 r + lane is entry q + 1 (q = e % tk) of own column col = e / tk =
-// li nj + lj; per lane the loop keeps col, q, lj, that entry's k' (kp), its
-// element offset around fld (x, 32-bit like the staging) and its LDS slot
-// (loff), each advanced by a constant per element plus a carry when q wraps
-// and one when lj wraps.
+// an interior node (the others are halo or outside the column).  The columns
+// are taken as the full 8 x 8 (those past a ragged tile's end are skipped)
+// in chunks of 16 entries: in chunk ch, lane (g, r) = (lane / 16, lane % 16)
+// takes entry q + 1, q = ch + r, of own column (li, lj) = (u / 2, 4 (u % 2) + g)
+// at step u = 0..15.  A step's element offset and LDS slot then differ from
+// the lane's first ones by a wave-uniform amount, and every LDS read of a
+// chunk is issued before its stores.  (Reads of skipped entries stay inside
+// the window: their slots lie less than 16 past either end of an own
+// column, and the columns beside it in LDS are staged ones.)
 template <int DIR>
 __device__ __forceinline__ void unstage_tile(const Geo& G, const TileCtx& c, double* __restrict__ fld,
                                              const double* lds, int Lp) {
     using D = Dir<DIR>;
     constexpr int sg = D::s2;
     const int ek = G.tk;
-    const int nj = c.ext_j, n = c.ext_i * nj, total = n * ek;
     const int si = D::s0 * (int)G.si, sj = D::s1 * (int)G.sj;
     const int base = (int)nidx(G, stage_origin<D::s0>(G, 0, c.TI) + D::s0, stage_origin<D::s1>(G, 1, c.TJ) + D::s1,
                                c.kbase);
     const unsigned kmax = (unsigned)G.m[2];
-    int col = c.lane / ek, q = c.lane - col * ek;
-    int li = col / nj, lj = col - li * nj;
-    int kp = c.kq0 - 1 - li - lj + q;
-    // (unsigned: lanes past the tile's columns, never stored, may leave the int range)
-    unsigned x = (unsigned)base + (unsigned)li * si + (unsigned)lj * sj + sg * kp;
-    int loff = ((li + 1) * kTC + lj + 1) * Lp + (sg > 0 ? 1 : Lp - 2) + sg * q;
-    const int dcol = 64 / ek, dq = 64 - dcol * ek;
-    const int kp_step = dq - dcol, kp_q = -1 - ek, kp_j = nj - 1;
-    const unsigned x_step = (unsigned)(dcol * sj + sg * (dq - dcol));
-    const unsigned x_q = (unsigned)(sj - sg * (1 + ek));
-    const unsigned x_j = (unsigned)si - (unsigned)(nj * sj) + sg * (nj - 1);
-    const int l_step = dcol * Lp + sg * dq, l_q = Lp - sg * ek, l_j = (kTC - nj) * Lp;
-    for (int e0 = 0; e0 < total; e0 += 64 * kStageBatch) {
+    const int g = c.lane >> 4, r = c.lane & 15;
+    const bool colj0 = g < c.ext_j, colj1 = g + 4 < c.ext_j;
+    // node (li, lj, entry q + 1): element base + li si + lj sj + s2 k', with
+    // k' = kq0 - 1 - li - lj + q, and slot ((li + 1) kTC + lj + 1) Lp + q + 1
+    // (mirrored: Lp - 2 - q)
+    const unsigned xa = (unsigned)(si - sg), xb = 4u * (unsigned)(sj - sg);
+    const int la = kTC * Lp, lb = 4 * Lp;
+    for (int ch = 0; ch < ek; ch += 16) {
+        const int q = ch + r;
+        // (unsigned: lanes past the tile's entries, never stored, may leave the int range)
+        const unsigned x0 = (unsigned)base + (unsigned)(sg * (c.kq0 - 1 + q)) + (unsigned)g * (unsigned)(sj - sg);
+        const int l0 = (kTC + g + 1) * Lp + (sg > 0 ? 1 : Lp - 2) + sg * q;
+        const int kp0 = c.kq0 - 1 - g + q;
+        double v[16];
 #pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-            if (col < n && (unsigned)kp < kmax) fld[(int)x] = lds[loff];
-            col += dcol;
-            lj += dcol;
-            q += dq;
-            kp += kp_step;
-            x += x_step;
-            loff += l_step;
-            if (q >= ek) {
-                q -= ek;
-                ++col;
-                ++lj;
-                kp += kp_q;
-                x += x_q;
-                loff += l_q;
-            }
-            // lj < nj + dcol: one wrap unless dcol >= nj
-            if (lj >= nj) {
-                lj -= nj;
-                kp += kp_j;
-                x += x_j;
-                loff += l_j;
-                if (dcol >= nj) {
-                    while (lj >= nj) {
-                        lj -= nj;
-                        kp += kp_j;
-                        x += x_j;
-                        loff += l_j;
-                    }
-                }
-            }
+        for (int u = 0; u < 16; ++u)
+            v[u] = lds[l0 + __builtin_amdgcn_readfirstlane((u >> 1) * la + (u & 1) * lb)];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int li = u >> 1, b = u & 1;
+            if (li < c.ext_i && (b ? colj1 : colj0) && q < ek && (unsigned)(kp0 - li - 4 * b) < kmax)
+                fld[(int)(x0 + (unsigned)__builtin_amdgcn_readfirstlane((int)((unsigned)li * xa + (unsigned)b * xb)))] =
+                    v[u];
         }
     }
 }
