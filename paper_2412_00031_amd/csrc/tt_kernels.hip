@@ -284,18 +284,18 @@ constexpr int kTC = kBI + 2;
 // kk = q in sweeps with s2 > 0 and kk = Lp - 1 - q in sweeps with s2 < 0, so
 // that consecutive slots always hold consecutive nodes in memory (ascending
 // k).  The window is loaded with direct global-to-LDS loads of 16 bytes per
-// lane: each load moves 64 slot pairs (1 KiB of LDS, lane l writing pair l),
-// no data passes through registers, every load of the window is in flight at
-// once and the wave waits once.  Pairs with no node entry (k' outside
-// [-1, m2]) and pairs of columns past a ragged tile's halo are not loaded
-// (their slots are never read); a pair with one node entry reads one
-// neighbouring element of the field array that is never used (its address is
-// clamped into the array).
+// lane (lane l of a load writes the l-th slot pair from the load's LDS
+// address): each load covers 64 / (Lp / 2) whole columns, so a lane keeps its
+// column offset and slot pair in every load, no data passes through
+// registers, every load of the window is in flight at once and the wave waits
+// once.  Pairs with no node entry (k' outside [-1, m2]) and pairs of columns
+// past a ragged tile's halo are not loaded (their slots are never read); a
+// pair with one node entry reads one neighbouring element of the field array
+// that is never used (its address is clamped into the array).
 typedef __attribute__((address_space(3))) char lds_char;
 typedef __attribute__((address_space(3))) void lds_void;
 
-// LDS bytes of a staged tile: the window's slot pairs (the last load writes
-// only the lanes that hold a pair of the window)
+// LDS bytes of a staged tile: the window's slot pairs
 __host__ __device__ inline int stage_bytes(int tk) { return kTC * kTC * tile_pitch(tk) * 8; }
 
 // LDS slot of entry kk of a column (the mirror for sweeps with s2 < 0)
@@ -312,70 +312,59 @@ __device__ __forceinline__ int stage_origin(const Geo& G, int a, int T) {
 }
 
 // xlo, xhi: the element range of the field array around fld that may be read.
-// Per lane the loop keeps running indices: the pair's column (ci, cj) and slot
-// q, y = the column's element offset minus s2 (ci + cj) (the shear), and
-// w = -(ci + cj); element and k' of the pair's lower slot are then one add each.
-// Offsets are 32-bit: the host keeps N below 2^31, and a loaded pair lies in
-// [-1, N] around fld.
+// Load r covers columns cb = r cpi .. cb + cpi - 1 (cpi = 64 / (Lp / 2));
+// lane l takes slots q, q + 1 (q = 2 (l % (Lp / 2))) of column cb + l / (Lp / 2)
+// (lanes past cpi whole columns stay idle).  Per lane the loop keeps that
+// column's (ci, cj), y = the element of its lower slot, and d = the k' test
+// value of the pair, each advanced by a constant per load plus a carry when cj
+// wraps.  Offsets are 32-bit: the host keeps N below 2^31, and a loaded pair
+// lies in [-1, N] around fld.
 template <int DIR>
 __device__ __forceinline__ void stage_tile(const Geo& G, const TileCtx& c, const double* __restrict__ fld,
                                            long long xlo, long long xhi, double* lds) {
     using D = Dir<DIR>;
     constexpr int sg = D::s2;
     const int Lp = tile_pitch(G.tk);
-    const int npair = kTC * kTC * Lp / 2;
+    const int hp = Lp >> 1, cpi = 64 / hp;
     const int si = (int)G.si, sj = (int)G.sj;
     const int oi = stage_origin<D::s0>(G, 0, c.TI), oj = stage_origin<D::s1>(G, 1, c.TJ);
     const int lo = (int)(xlo > -1 ? xlo : -1), hi = (int)(xhi < G.N ? xhi : G.N);
-    // pair p = 64 r + lane: slots q, q + 1 (q even) of column col = 2p / Lp;
-    // p advances by 64 per load, i.e. 128 slots
-    int col = (2 * c.lane) / Lp, q = 2 * c.lane - col * Lp;
-    int ci = col / kTC, cj = col - ci * kTC;
-    const int dcol = 128 / Lp, dq = 128 - dcol * Lp;
-    // (unsigned: columns outside the grid, never loaded, may leave the int range)
-    unsigned y = (unsigned)(oi + D::s0 * ci) * si + (unsigned)(oj + D::s1 * cj) * sj - sg * (ci + cj);
-    int w = -(ci + cj);
-    // element of the lower slot: x = y + x0 + q; its k': kpa = kq0 + w + q (s2 > 0)
-    // or kq0 + w + Lp - 1 - q (s2 < 0), whose pair holds [kpa, kpa + 1] or [kpa - 1, kpa]
+    const int dc = c.lane / hp, q = 2 * (c.lane - dc * hp);
+    const bool lane_on = dc < cpi;
+    int ci = dc / kTC, cj = dc - ci * kTC;
+    // lower slot q holds entry kk = q (s2 > 0) or Lp - 1 - q (s2 < 0) of the
+    // column, node k' = kq0 - ci - cj + kk at element kbase + s2 k'; the pair
+    // holds a node entry iff its lower entry's k' + (2 or 1) lies in [0, m2 + 2]
     const int x0 = c.kbase + sg * c.kq0 + (sg > 0 ? 0 : 1 - Lp);
-    const int ka0 = sg > 0 ? c.kq0 + 2 : c.kq0 + Lp;  // kpa + (2 or 1) = ka0 + w + sg q
+    const int ka0 = sg > 0 ? c.kq0 + 2 : c.kq0 + Lp;
+    // (unsigned: columns outside the grid, never loaded, may leave the int range)
+    unsigned y = (unsigned)(oi + D::s0 * ci) * si + (unsigned)(oj + D::s1 * cj) * sj - sg * (ci + cj) + x0 + q;
+    int d = ka0 - (ci + cj) + sg * q;
     const unsigned kspan = (unsigned)G.m[2] + 2;
     const int ei = c.ext_i + 2, ej = c.ext_j + 2;
-    const unsigned dy_q = (unsigned)(D::s1 * sj - sg), dy = dcol * dy_q;
+    const unsigned dy = (unsigned)cpi * (unsigned)(D::s1 * sj - sg);
     const unsigned dy_w = (unsigned)(D::s0 * si) - (unsigned)(kTC * D::s1 * sj) + sg * (kTC - 1);
     lds_char* lb = (lds_char*)lds;  // the dynamic shared array, in the LDS address space
-    for (int p0 = 0; p0 < npair; p0 += 64) {
-        int x = (int)(y + x0 + q);
-        x = min(max(x, lo), hi);
-        // only pairs that hold a node entry (k' in [-1, m2]) of a column the tile
-        // reads (its own columns and their i'/j' halo), and in the last load only
-        // the window's lanes
-        const bool node = (unsigned)(ka0 + w + sg * q) <= kspan;
-        if (node && ci < ei && cj < ej && (p0 + 64 <= npair || p0 + c.lane < npair))
-            __builtin_amdgcn_global_load_lds(fld + x, (lds_void*)(lb + 16 * p0), 16, 0, 0);
-        q += dq;
-        cj += dcol;
-        y += dy;
-        w -= dcol;
-        if (q >= Lp) {
-            q -= Lp;
-            ++cj;
-            y += dy_q;
-            --w;
+    for (int cb = 0; cb < kTC * kTC; cb += cpi) {
+        if (lane_on && ci < ei && cj < ej && (unsigned)d <= kspan) {
+            const int x = min(max((int)y, lo), hi);
+            __builtin_amdgcn_global_load_lds(fld + x, (lds_void*)(lb + 16 * cb * hp), 16, 0, 0);
         }
-        // cj < kTC + dcol + 1: one wrap unless dcol >= kTC (pitches below 13)
-        if (cj >= kTC) {
-            cj -= kTC;
-            ++ci;
-            y += dy_w;
-            w += kTC - 1;
-            if (dcol >= kTC) {
-                while (cj >= kTC) {
-                    cj -= kTC;
-                    ++ci;
-                    y += dy_w;
-                    w += kTC - 1;
-                }
+        cj += cpi;
+        y += dy;
+        d -= cpi;
+        // one wrap (taken as selects) unless cpi >= kTC (pitches below 14)
+        const bool wrap = cj >= kTC;
+        cj -= wrap ? kTC : 0;
+        ci += wrap ? 1 : 0;
+        y += wrap ? dy_w : 0u;
+        d += wrap ? kTC - 1 : 0;
+        if (cpi >= kTC) {
+            while (cj >= kTC) {
+                cj -= kTC;
+                ++ci;
+                y += dy_w;
+                d += kTC - 1;
             }
         }
     }
