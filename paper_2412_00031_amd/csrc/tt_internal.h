@@ -232,12 +232,21 @@ __device__ __forceinline__ void local_state(const Geo& G, const Src& S, const Co
 //   tau(x) = (s - H) / (kappa T0 C) + sum_a w_a (up_a + dn_a),  w_a = g_a / (2 h_a C),
 // and 1 / (kappa T0 C) = rho / sqrt(Q) with rho = 1 / (kappa s0 C): LfCol holds
 // the column's constants, so an update has no division.
+//
+// The factor enters through T0 = s0 Q rq and its scaled gradient t = s0 rq u
+// (rq = 1 / sqrt(Q), u = the gradient direction of the factor() notes without
+// the s0 rq), so P_a = T0 q_a + tau t_a = s0 rq R_a with R_a = Q q_a + tau u_a and
+// H = s0 rq sqrt(R . M R): the update forms R, not T0 and t.  Along a spherical
+// column X = (rct c2, rct s2, rst), so d = E (X - Xs) is d_i = A_i c2 + B_i s2 + C_i
+// with column constants A, B, C.
 struct LfCol {
     double v1, v2;      // g_a / (2 h_a) of axes 1, 2 (central differences)
     double w0, w1, w2;  // averaging weights w_a
     double rho;
+    double A[3], B[3], C[3];  // d_i along the column (spherical); Cartesian: C = (x0, y) - Xs
 };
 
+template <int COORD>
 __device__ __forceinline__ LfCol lf_col(const Geo& G, const Src& S, const Col& c, double kappa) {
     LfCol W;
     const double iC = 1.0 / (G.invh[0] + c.g1 * G.invh[1] + c.g2 * G.invh[2]);
@@ -247,6 +256,18 @@ __device__ __forceinline__ LfCol lf_col(const Geo& G, const Src& S, const Col& c
     W.w1 = W.v1 * iC;
     W.w2 = W.v2 * iC;
     W.rho = iC / (kappa * S.s0);
+    if (COORD == 1) {
+        const double D2 = c.rst - S.Xs[2];
+        for (int i = 0; i < 3; ++i) {
+            W.A[i] = c.rct * S.E[3 * i];
+            W.B[i] = c.rct * S.E[3 * i + 1];
+            W.C[i] = D2 * S.E[3 * i + 2] - (S.Xs[0] * S.E[3 * i] + S.Xs[1] * S.E[3 * i + 1]);
+        }
+    } else {
+        W.A[0] = W.A[1] = W.A[2] = W.B[0] = W.B[1] = W.B[2] = W.C[2] = 0.0;
+        W.C[0] = c.x0 - S.Xs[0];
+        W.C[1] = c.ct - S.Xs[1];
+    }
     return W;
 }
 
@@ -254,15 +275,43 @@ template <int COORD>
 __device__ __forceinline__ double lf_update(const Geo& G, const Src& S, const Col& c, const LfCol& W, double c2,
                                             double s2, double sx, double ma, double mb, double mc, double tx,
                                             double up0, double dn0, double up1, double dn1, double up2, double dn2) {
-    double T0, t[3], rq;
-    factor<COORD, true>(S, c, c2, s2, T0, t, rq);
-    const double P0 = T0 * ((dn0 - up0) * G.inv2h[0]) + tx * t[0];
-    const double P1 = T0 * ((dn1 - up1) * W.v1) + tx * t[1];
-    const double P2 = T0 * ((dn2 - up2) * W.v2) + tx * t[2];
+    double d0, d1, d2;
+    if (COORD == 1) {
+        d0 = fma(c2, W.A[0], fma(s2, W.B[0], W.C[0]));
+        d1 = fma(c2, W.A[1], fma(s2, W.B[1], W.C[1]));
+        d2 = fma(c2, W.A[2], fma(s2, W.B[2], W.C[2]));
+    } else {
+        d0 = W.C[0];
+        d1 = W.C[1];
+        d2 = c2 - S.Xs[2];
+    }
+    const double m1 = S.mi11 * d1 + S.mi12 * d2;
+    const double m2 = S.mi12 * d1 + S.mi22 * d2;
+    const double Q = d0 * d0 + d1 * m1 + d2 * m2;  // > 0: the sweeps skip the fixed cell
+    const double rq = rsqrt_nr(Q);
+    double u0, u1, u2;
+    if (COORD == 1) {
+        // E^T m in the embedding, then on the node's local unit vectors
+        // r^ = (ct c2, ct s2, st), theta^ = (-st c2, -st s2, ct), phi^ = (-s2, c2, 0)
+        const double G0 = d0 * S.E[0] + m1 * S.E[3] + m2 * S.E[6];
+        const double G1 = d0 * S.E[1] + m1 * S.E[4] + m2 * S.E[7];
+        const double G2 = d0 * S.E[2] + m1 * S.E[5] + m2 * S.E[8];
+        const double hz = G0 * c2 + G1 * s2;
+        u0 = c.ct * hz + c.st * G2;
+        u1 = c.ct * G2 - c.st * hz;
+        u2 = G1 * c2 - G0 * s2;
+    } else {
+        u0 = d0;
+        u1 = m1;
+        u2 = m2;
+    }
+    const double R0 = Q * ((dn0 - up0) * G.inv2h[0]) + tx * u0;
+    const double R1 = Q * ((dn1 - up1) * W.v1) + tx * u1;
+    const double R2 = Q * ((dn2 - up2) * W.v2) + tx * u2;
     // (ma, mb, mc) = (1 - 2 xi, 2 eta, 1 + 2 xi): the lower-right block of M
-    const double MP1 = ma * P1 + mb * P2;
-    const double MP2 = mb * P1 + mc * P2;
-    const double H = sqrt_nr(P0 * P0 + P1 * MP1 + P2 * MP2);
+    const double MR1 = ma * R1 + mb * R2;
+    const double MR2 = mb * R1 + mc * R2;
+    const double H = (S.s0 * rq) * sqrt_nr(R0 * R0 + R1 * MR1 + R2 * MR2);
     return (sx - H) * (W.rho * rq) + ((up0 + dn0) * W.w0 + (up1 + dn1) * W.w1 + (up2 + dn2) * W.w2);
 }
 

@@ -488,7 +488,7 @@ __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane, int s0
         return;
     }
     const Col cl = make_col(G, a.T, c.i, c.j);
-    const LfCol W = lf_col(G, S, cl, a.kappa);
+    const LfCol W = lf_col<COORD>(G, S, cl, a.kappa);
     double* __restrict__ fld = a.field + (long long)src * G.N;
     const double* __restrict__ mdl = a.model + (long long)D::lay * G.Sa * 4;
     const double2* __restrict__ t2 = a.T.t2;
