@@ -143,6 +143,12 @@ typedef struct tt_opts {
  * workspace would not fit otherwise; the sweeps are slower (about 30 % at
  * 101^3 x 128 sources).  Results are bit-identical. */
 #define TT_FLAG_COMPACT_ADJOINT 16
+/* bit 5 (tt_adjoint only): lam holds the initial field of the iteration on
+ * entry (every source's [N] block; nodes of the fixed cell are reset to 0)
+ * instead of lambda = 0, e.g. the previous inversion step's lambda of the same
+ * sources.  The solve converges to the same tolerance as from 0; the start
+ * changes the iteration count and the result only within that tolerance. */
+#define TT_FLAG_ADJOINT_INIT 32
 
 /* Bytes of device workspace needed by tt_forward (which = 0), tt_adjoint
  * (which = 1), tt_sample (which = 2) or tt_kernel (which = 3) for this grid,
@@ -261,6 +267,7 @@ int tt_misfit_cr(int32_t nsrc, int32_t nrec, const double* T_rec, const double* 
  *   tau [nsrc][N] converged forward fields; rec_pos [nrec][3];
  *   R [nsrc][nrec] adjoint sources (e.g. from tt_misfit);
  *   lam [nsrc][N] out: adjoint field (0 on boundary rows of fixed nodes);
+ *       in/out with TT_FLAG_ADJOINT_INIT (its initial field);
  *   status [nsrc] out: as for tt_forward; the convergence measure is
  *   sum|d lambda| / sum|lambda| over one iteration.
  * Asynchronous on stream (see TT_FLAG_POLL). */

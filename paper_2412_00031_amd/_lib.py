@@ -47,6 +47,7 @@ TT_FLAG_GRAPH = 2
 TT_FLAG_CONTINUOUS_ADJOINT = 4
 TT_FLAG_POLL = 8
 TT_FLAG_COMPACT_ADJOINT = 16
+TT_FLAG_ADJOINT_INIT = 32
 TT_ENOCONV = -3
 TT_MAX_GROUPS = 8
 

@@ -40,7 +40,7 @@ def _budgets(budgets, nsrc):
 
 
 def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None, graph=False, groups=0, continuous=False,
-          poll=False, compact=False, budgets=None):
+          poll=False, compact=False, budgets=None, adjoint_init=False):
     o = _lib.TTOpts()
     o.budgets = budgets.ctypes.data if budgets is not None else None
     o.groups = int(groups)
@@ -51,7 +51,7 @@ def _opts(tol, max_iter, kappa, tile_k=0, time_sweeps=False, eps_hist=None, grap
     o.tile_k = int(tile_k)
     o.flags = ((_lib.TT_FLAG_TIME_SWEEPS if time_sweeps else 0) | (_lib.TT_FLAG_GRAPH if graph else 0)
                | (_lib.TT_FLAG_CONTINUOUS_ADJOINT if continuous else 0) | (_lib.TT_FLAG_POLL if poll else 0)
-               | (_lib.TT_FLAG_COMPACT_ADJOINT if compact else 0))
+               | (_lib.TT_FLAG_COMPACT_ADJOINT if compact else 0) | (_lib.TT_FLAG_ADJOINT_INIT if adjoint_init else 0))
     return o
 
 
@@ -270,17 +270,21 @@ def misfit_cr(T_rec, T_obs, cr_off, cr_pair, wcr, gamma, R, chi):
 
 def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, kappa, tile_k=0, ws=None,
             out=None, time_sweeps=False, eps_hist=None, graph=False, groups=0, continuous=False, poll=False,
-            status=None, compact=False, budgets=None):
+            status=None, compact=False, budgets=None, lam_init=None):
     """Batched adjoint solve.  Returns (lambda [nsrc, *n], status int32 [nsrc]);
     eps_hist, groups, poll and budgets as for forward.  continuous=True solves Eq. (5)
     by upwind finite volumes and returns P s V in place of lambda.
     compact=True keeps one node-order copy of the coefficient records (a
-    ninth of the workspace at 101^3; slower sweeps, identical results)."""
+    ninth of the workspace at 101^3; slower sweeps, identical results).
+    lam_init [nsrc, *n]: the iteration's initial field instead of 0 (e.g. the
+    continuous adjoint's P s V); it may be the out tensor itself."""
     lib = _lib.load()
     N = _N(grid)
     nsrc, nrec = int(src_pos.shape[0]), int(rec_pos.shape[0])
     dev = s.device
     lam = out if out is not None else torch.empty((nsrc,) + tuple(int(v) for v in grid["n"]), dtype=_F64, device=dev)
+    if lam_init is not None and lam_init.data_ptr() != lam.data_ptr():
+        lam.copy_(lam_init.reshape(lam.shape))
     if status is None:
         status = torch.empty(nsrc, dtype=torch.int32, device=dev)
     if ws is None:
@@ -290,7 +294,7 @@ def adjoint(grid, s, xi, eta, src_pos, src_par, tau, rec_pos, R, tol, max_iter, 
         raise ValueError("eps_hist must have nsrc * max_iter elements")
     bud = _budgets(budgets, nsrc)
     o = _opts(tol, max_iter, kappa, tile_k, time_sweeps, eps_hist, graph, groups, continuous, poll, compact,
-              budgets=bud)
+              budgets=bud, adjoint_init=lam_init is not None)
     _lib.check(lib.tt_adjoint(ctypes.byref(g), _dev(s, "s", numel=N), _dev(xi, "xi", numel=N),
                               _dev(eta, "eta", numel=N), nsrc, _dev(src_pos, "src_pos", numel=3 * nsrc),
                               _dev(src_par, "src_par", numel=3 * nsrc), _dev(tau, "tau", numel=nsrc * N), nrec,

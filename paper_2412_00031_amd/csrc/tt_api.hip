@@ -897,7 +897,7 @@ int tt_adjoint(const tt_grid* grid, const double* s, const double* xi, const dou
         tt::launch_src_setup(g.P, src_pos + 3LL * q0, src_par + 3LL * q0, g.st);
         g.a = tt::make_args(g.P, s, xi, eta, lam + (long long)q0 * G.N, status + q0);
         tt::launch_adj_init(g.P, g.a, tau + (long long)q0 * G.N, nrec, rec_pos, R ? R + (long long)q0 * nrec : nullptr,
-                            g.st);
+                            (opts->flags & TT_FLAG_ADJOINT_INIT) ? lam + (long long)q0 * G.N : nullptr, g.st);
     }
     TT_HIP(hipGetLastError());
     const bool polled = polled_mode(opts);

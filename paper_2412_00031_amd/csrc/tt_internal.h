@@ -390,7 +390,7 @@ void launch_fwd_init(const Plan& P, const SweepArgs& a, const double* tau_init, 
                      const double* eta, hipStream_t st);
 void launch_fwd_iteration(const Plan& P, const SweepArgs& a, hipStream_t st);
 void launch_adj_init(const Plan& P, const SweepArgs& a, const double* tau, int nrec, const double* rec_pos,
-                     const double* R, hipStream_t st);
+                     const double* R, const double* init, hipStream_t st);
 void launch_adj_iteration(const Plan& P, const SweepArgs& a, hipStream_t st);
 void launch_cadj_scale(const Plan& P, const double* s, double* lam, hipStream_t st);
 void launch_sample(const Plan& P, const double* tau, int nrec, const double* rec_pos, double* out,

@@ -166,7 +166,8 @@ __global__ void k_fill(double* __restrict__ p, long long n, double v) {
 }
 
 // initialise a solve: field = init (or v0), fixed nodes = vfix; flags and counters
-__global__ void k_solve_init(SweepArgs a, const double* __restrict__ init, double v0, double vfix) {
+// init may alias the field: each element is read and then written by one thread
+__global__ void k_solve_init(SweepArgs a, const double* init, double v0, double vfix) {
     const int src = blockIdx.y;
     const Src S = a.src[src];
     double* f = a.field + (long long)src * a.G.N;
@@ -216,9 +217,9 @@ struct TileCtx {
     bool colv, fcol;
     int i, j;
     int rbase, rstep;  // record index of this lane's column at k' = 0, and its change per k'
-    // forward fetches: record and axis-2 table index at step 0 and their
-    // bounds (the clamp of k' to [kplo, kphi] mapped to each index)
-    int rr0, rrlo, rrhi, tt0, ttlo, tthi;
+    // forward fetches: record and axis-2 table index at step 0, and the step
+    // range [tlo, thi] that the clamp of k' to [kplo, kphi] allows
+    int rr0, tt0, tlo, thi;
     int slot;          // partial-sum slot of the tile within one directional sweep
 };
 
@@ -256,11 +257,9 @@ __device__ __forceinline__ TileCtx tile_ctx(const Geo& G, const Src& S, int plan
     c.rbase = (c.i * G.W + w0) * G.n1p + c.j + G.joff[D::s1 > 0 ? 0 : 1];
     c.rstep = D::s1 * G.n1p;
     c.rr0 = c.rbase + c.rstep * c.kp0;
-    c.rrlo = c.rbase + c.rstep * (D::s1 > 0 ? c.kplo : c.kphi);
-    c.rrhi = c.rbase + c.rstep * (D::s1 > 0 ? c.kphi : c.kplo);
     c.tt0 = c.kbase + D::s2 * c.kp0;
-    c.ttlo = c.kbase + D::s2 * (D::s2 > 0 ? c.kplo : c.kphi);
-    c.tthi = c.kbase + D::s2 * (D::s2 > 0 ? c.kphi : c.kplo);
+    c.tlo = c.kplo - c.kp0;
+    c.thi = c.kphi - c.kp0;
     c.slot = (c.TI * G.nt[1] + c.TJ) * G.nt[2] + (c.TK - col_tile_lo(G, c.TI + c.TJ));
     return c;
 }
@@ -462,14 +461,17 @@ struct FwdSlot {
 template <int DIR>
 __device__ __forceinline__ void fwd_fetch(const TileCtx& c, const double* __restrict__ mdl,
                                           const double2* __restrict__ t2, int t, FwdSlot& r) {
-    const unsigned ri = (unsigned)min(max(c.rr0 + c.rstep * t, c.rrlo), c.rrhi);
+    // the step clamped to the lane's k' range; |rstep| = n1p < 2^23 and the
+    // step is below 64, so the product is a 24-bit one
+    const int tc = min(max(t, c.tlo), c.thi);
+    const unsigned ri = (unsigned)(c.rr0 + __mul24(c.rstep, tc));
     const double2* m = reinterpret_cast<const double2*>(mdl + (size_t)ri * 4);
     const double2 m0 = m[0], m1 = m[1];
     r.sx = m0.x;
     r.ma = m0.y;
     r.mb = m1.x;
     r.mc = m1.y;
-    const double2 tv = t2[(unsigned)min(max(c.tt0 + Dir<DIR>::s2 * t, c.ttlo), c.tthi)];
+    const double2 tv = t2[(unsigned)(c.tt0 + Dir<DIR>::s2 * tc)];
     r.c2 = tv.x;
     r.s2 = tv.y;
 }
@@ -809,8 +811,9 @@ __device__ __forceinline__ void adj_fetch(const TileCtx& c, const double* __rest
     using D = Dir<DIR>;
     const int kp = min(max(c.kp0 + t, c.kplo), c.kphi);
     const long long x = xb + D::s2 * kp;
+    // |rstep| = n1p < 2^23 and 0 <= kp < n2 <= 8192: a 24-bit product
     const double2* rc =
-        reinterpret_cast<const double2*>(cf + (COMPACT ? x : (long long)(c.rbase + c.rstep * kp)) * kRec);
+        reinterpret_cast<const double2*>(cf + (COMPACT ? x : (long long)(c.rbase + __mul24(c.rstep, kp))) * kRec);
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         const double2 v = rc[q];
@@ -1361,7 +1364,7 @@ void launch_fwd_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
 }
 
 void launch_adj_init(const Plan& P, const SweepArgs& a, const double* tau, int nrec, const double* rec,
-                     const double* R, hipStream_t st) {
+                     const double* R, const double* init, hipStream_t st) {
     hipLaunchKernelGGL(k_fill, dim3(fill_blocks(2 * P.G.NB * P.nsrc)), dim3(256), 0, st, P.bnd_in,
                        2 * P.G.NB * P.nsrc, 0.0);  // bnd_in and bnd_rhs
     const dim3 grid(blocks_for(P.G.N, 256), P.nsrc);
@@ -1376,7 +1379,7 @@ void launch_adj_init(const Plan& P, const SweepArgs& a, const double* tau, int n
         else hipLaunchKernelGGL(k_adj_coef<0>, grid, dim3(256), 0, st, a, tau, P.coef, P.bnd_in, P.diag, P.rhs);
         hipLaunchKernelGGL(k_adj_rhs<0>, rgrid, dim3(64), 0, st, a, P.diag, P.rhs, P.box, nrec, rec, R, t0);
     }
-    hipLaunchKernelGGL(k_solve_init, dim3(fill_blocks(P.G.N), P.nsrc), dim3(256), 0, st, a, nullptr, 0.0, 0.0);
+    hipLaunchKernelGGL(k_solve_init, dim3(fill_blocks(P.G.N), P.nsrc), dim3(256), 0, st, a, init, 0.0, 0.0);
 }
 
 void launch_adj_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {

@@ -55,6 +55,19 @@ def test_binding_declares_every_header_symbol():
     assert declared_functions() == set(_lib.EXPORTS) | set(_lib.NN_EXPORTS)
 
 
+def test_binding_constants_match_the_header():
+    """Every TT_* integer constant of include/tt.h has the same value in the binding."""
+    from paper_2412_00031_amd import _lib
+    text = open(os.path.join(INCLUDE, "tt.h")).read()
+    defs = dict(re.findall(r"#define\s+(TT_[A-Z0-9_]+)\s+(-?\d+)\b", text))
+    assert {"TT_FLAG_POLL", "TT_FLAG_COMPACT_ADJOINT", "TT_FLAG_ADJOINT_INIT"} <= set(defs)
+    for name, v in defs.items():
+        if hasattr(_lib, name):
+            assert getattr(_lib, name) == int(v), name
+    flags = [int(v) for k, v in defs.items() if k.startswith("TT_FLAG_")]
+    assert len(set(flags)) == len(flags) and all(f & (f - 1) == 0 for f in flags)
+
+
 def test_last_error_without_gpu(libpath):
     """A host-checked argument error is reported without touching a device."""
     from paper_2412_00031_amd import _lib
