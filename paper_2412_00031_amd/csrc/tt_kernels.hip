@@ -476,13 +476,17 @@ __device__ __forceinline__ void fwd_fetch(const TileCtx& c, const double* __rest
     r.s2 = tv.y;
 }
 
-template <int COORD, int DIR>
+// TKC: the tile depth as a compile-time constant (0: read from the geometry),
+// so that LDS offsets become immediates and the staging and write-back index
+// arithmetic folds; the host picks an instance whose TKC equals the depth.
+template <int COORD, int DIR, int TKC>
 __global__ void __launch_bounds__(64) k_fwd_sweep(SweepArgs a, int plane, int s0) {
     using D = Dir<DIR>;
     extern __shared__ double lds[];
     const int src = blockIdx.x;
     if (!a.active[src]) return;
-    const Geo& G = a.G;
+    Geo G = a.G;
+    if (TKC > 0) G.tk = TKC;
     const Src S = a.src[src];
     const TileCtx c = tile_ctx<DIR>(G, S, plane, s0);
     if (c.t1 <= c.t0) {  // a ragged column's slab with no nodes
@@ -1326,9 +1330,9 @@ struct TimedLaunch {
 // Sweep kernels are instantiated per coordinate system and direction.
 typedef void (*SweepFn)(SweepArgs, int, int);
 
-template <int COORD, int... DS>
+template <int COORD, int TKC, int... DS>
 constexpr SweepFn pick_fwd(int d, std::integer_sequence<int, DS...>) {
-    SweepFn t[] = {k_fwd_sweep<COORD, DS>...};
+    SweepFn t[] = {k_fwd_sweep<COORD, DS, TKC>...};
     return t[d];
 }
 
@@ -1338,9 +1342,22 @@ constexpr SweepFn pick_adj(int d, std::integer_sequence<int, DS...>) {
     return t[d];
 }
 
-SweepFn fwd_sweep_fn(int coord, int d) {
-    return coord == 1 ? pick_fwd<1>(d, std::make_integer_sequence<int, 8>{})
-                      : pick_fwd<0>(d, std::make_integer_sequence<int, 8>{});
+// forward sweep instances with a compile-time tile depth (the autotuner's
+// usual choices); other depths run the generic instance
+template <int COORD>
+SweepFn fwd_sweep_fn_c(int tk, int d) {
+    const auto seq = std::make_integer_sequence<int, 8>{};
+    switch (tk) {
+        case 16: return pick_fwd<COORD, 16>(d, seq);
+        case 20: return pick_fwd<COORD, 20>(d, seq);
+        case 24: return pick_fwd<COORD, 24>(d, seq);
+        case 28: return pick_fwd<COORD, 28>(d, seq);
+        default: return pick_fwd<COORD, 0>(d, seq);
+    }
+}
+
+SweepFn fwd_sweep_fn(int coord, int tk, int d) {
+    return coord == 1 ? fwd_sweep_fn_c<1>(tk, d) : fwd_sweep_fn_c<0>(tk, d);
 }
 
 SweepFn adj_sweep_fn(int coord, int d, bool compact) {
@@ -1353,7 +1370,7 @@ void launch_fwd_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
     for (int d = 0; d < 8; ++d) {
         {
         TimedLaunch tl(P, st, P.nplanes);
-        const SweepFn fn = fwd_sweep_fn(P.G.coord, d);
+        const SweepFn fn = fwd_sweep_fn(P.G.coord, P.G.tk, d);
         for (int p = 0; p < P.nplanes; ++p)
             hipLaunchKernelGGL(fn, dim3(P.nsrc, P.plane_count[p]), dim3(64), tile_lds_bytes(P.G), st, a,
                                P.plane_id[p], P.plane_s0[p]);

@@ -129,10 +129,22 @@ def test_tile_shapes_bitwise(torch_cuda):
         wl = W.small_spherical(n=n, nsrc=2, seed=seed)
         ref = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=62, tile_k_adj=16)
         for tk, tka in ((1, 1), (2, 2), (3, 3), (5, 5), (7, 7), (8, 8), (13, 13), (21, 4), (32, 11), (48, 6),
-                        (62, 9), (16, 12), (10, 14), (12, 15)):
+                        (62, 9), (16, 12), (10, 14), (12, 15), (20, 2), (24, 10), (28, 13)):
             gp = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=tk, tile_k_adj=tka)
             for key in ("tau", "lam", "grad", "it_f", "it_a", "T"):
                 assert np.array_equal(gp[key], ref[key]), (n, tk, tka, key)
+
+
+def test_compiled_tile_depths_bitwise_cartesian(torch_cuda):
+    """The forward sweep has instances compiled for tile depths 16, 20, 24 and
+    28 besides the generic one: on a Cartesian grid (the spherical instances are
+    covered above) each gives the generic instance's results bit for bit."""
+    wl = W.cartesian41()
+    ref = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=30, tile_k_adj=16)
+    for tk in (16, 20, 24, 28):
+        gp = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=tk, tile_k_adj=16)
+        for key in ("tau", "lam", "grad", "it_f", "it_a", "T"):
+            assert np.array_equal(gp[key], ref[key]), (tk, key)
 
 
 def test_graph_replay_matches_eager(torch_cuda):
