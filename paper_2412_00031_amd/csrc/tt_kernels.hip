@@ -841,9 +841,9 @@ __device__ __forceinline__ bool tile_meets_box(const Geo& G, const TileCtx& c, c
 }
 
 template <int DIR, bool RHS, bool COMPACT>
-__device__ __forceinline__ void adj_tile(const SweepArgs& a, const Src& S, const TileCtx& c, int src, double* lds) {
+__device__ __forceinline__ void adj_tile(const SweepArgs& a, const Geo& G, const Src& S, const TileCtx& c, int src,
+                                         double* lds) {
     using D = Dir<DIR>;
-    const Geo& G = a.G;
     constexpr bool last = (DIR == 7);
     double* __restrict__ fld = a.field + (long long)src * G.N;
     const double* __restrict__ cf =
@@ -911,12 +911,14 @@ __device__ __forceinline__ void adj_tile(const SweepArgs& a, const Src& S, const
     }
 }
 
-template <int COORD, int DIR, bool COMPACT>
+// TKC: compile-time tile depth as for k_fwd_sweep (0: from the geometry)
+template <int COORD, int DIR, bool COMPACT, int TKC>
 __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane, int s0) {
     extern __shared__ double lds[];
     const int src = blockIdx.x;
     if (!a.active[src]) return;
-    const Geo& G = a.G;
+    Geo G = a.G;
+    if (TKC > 0) G.tk = TKC;
     const Src S = a.src[src];
     const TileCtx c = tile_ctx<DIR>(G, S, plane, s0);
     if (c.t1 <= c.t0) {  // a ragged column's slab with no nodes
@@ -927,8 +929,8 @@ __global__ void __launch_bounds__(64) k_adj_sweep(SweepArgs a, int plane, int s0
         return;
     }
     // wave-uniform: only tiles that meet the right-hand side read it
-    if (tile_meets_box<DIR>(G, c, a.box + src * 6)) adj_tile<DIR, true, COMPACT>(a, S, c, src, lds);
-    else adj_tile<DIR, false, COMPACT>(a, S, c, src, lds);
+    if (tile_meets_box<DIR>(G, c, a.box + src * 6)) adj_tile<DIR, true, COMPACT>(a, G, S, c, src, lds);
+    else adj_tile<DIR, false, COMPACT>(a, G, S, c, src, lds);
 }
 
 // Transposed boundary pass: lambda_b = rhs_b - sum_{rows r != b} J_{r, b} lambda_r,
@@ -1336,9 +1338,9 @@ constexpr SweepFn pick_fwd(int d, std::integer_sequence<int, DS...>) {
     return t[d];
 }
 
-template <int COORD, bool COMPACT, int... DS>
+template <int COORD, bool COMPACT, int TKC, int... DS>
 constexpr SweepFn pick_adj(int d, std::integer_sequence<int, DS...>) {
-    SweepFn t[] = {k_adj_sweep<COORD, DS, COMPACT>...};
+    SweepFn t[] = {k_adj_sweep<COORD, DS, COMPACT, TKC>...};
     return t[d];
 }
 
@@ -1360,10 +1362,24 @@ SweepFn fwd_sweep_fn(int coord, int tk, int d) {
     return coord == 1 ? fwd_sweep_fn_c<1>(tk, d) : fwd_sweep_fn_c<0>(tk, d);
 }
 
-SweepFn adj_sweep_fn(int coord, int d, bool compact) {
+// adjoint instances with a compile-time tile depth for the full record
+// layouts (the autotuner's usual choices); compact records and other depths
+// run the generic instance
+template <int COORD>
+SweepFn adj_sweep_fn_c(int tk, int d, bool compact) {
     const auto seq = std::make_integer_sequence<int, 8>{};
-    if (compact) return coord == 1 ? pick_adj<1, true>(d, seq) : pick_adj<0, true>(d, seq);
-    return coord == 1 ? pick_adj<1, false>(d, seq) : pick_adj<0, false>(d, seq);
+    if (compact) return pick_adj<COORD, true, 0>(d, seq);
+    switch (tk) {
+        case 28: return pick_adj<COORD, false, 28>(d, seq);
+        case 32: return pick_adj<COORD, false, 32>(d, seq);
+        case 40: return pick_adj<COORD, false, 40>(d, seq);
+        case 48: return pick_adj<COORD, false, 48>(d, seq);
+        default: return pick_adj<COORD, false, 0>(d, seq);
+    }
+}
+
+SweepFn adj_sweep_fn(int coord, int tk, int d, bool compact) {
+    return coord == 1 ? adj_sweep_fn_c<1>(tk, d, compact) : adj_sweep_fn_c<0>(tk, d, compact);
 }
 
 void launch_fwd_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
@@ -1403,7 +1419,7 @@ void launch_adj_iteration(const Plan& P, const SweepArgs& a, hipStream_t st) {
     for (int d = 0; d < 8; ++d) {
         {
         TimedLaunch tl(P, st, P.nplanes);
-        const SweepFn fn = adj_sweep_fn(P.G.coord, d, P.compact);
+        const SweepFn fn = adj_sweep_fn(P.G.coord, P.G.tk, d, P.compact);
         for (int p = 0; p < P.nplanes; ++p)
             hipLaunchKernelGGL(fn, dim3(P.nsrc, P.plane_count[p]), dim3(64), tile_lds_bytes(P.G), st, a,
                                P.plane_id[p], P.plane_s0[p]);

@@ -124,27 +124,29 @@ def test_tile_shapes_bitwise(torch_cuda):
     """Any tile depth visits the same dependencies: results are bit-identical.
     The grids have ragged 8 x 8 tile columns (interior 19, 17, 21 and 27, 3, 2)
     and slab depths below, near and above the hyperplane extent of a column
-    (forward depths up to 62, adjoint depths up to its limit of 16)."""
+    (depths up to 62 in both solves, among them every depth with a compiled
+    instance)."""
     for n, seed in (((21, 19, 23), 11), ((29, 5, 4), 12)):
         wl = W.small_spherical(n=n, nsrc=2, seed=seed)
         ref = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=62, tile_k_adj=16)
         for tk, tka in ((1, 1), (2, 2), (3, 3), (5, 5), (7, 7), (8, 8), (13, 13), (21, 4), (32, 11), (48, 6),
-                        (62, 9), (16, 12), (10, 14), (12, 15), (20, 2), (24, 10), (28, 13)):
+                        (62, 9), (16, 12), (10, 14), (12, 15), (20, 28), (24, 32), (28, 40), (22, 48)):
             gp = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=tk, tile_k_adj=tka)
             for key in ("tau", "lam", "grad", "it_f", "it_a", "T"):
                 assert np.array_equal(gp[key], ref[key]), (n, tk, tka, key)
 
 
 def test_compiled_tile_depths_bitwise_cartesian(torch_cuda):
-    """The forward sweep has instances compiled for tile depths 16, 20, 24 and
-    28 besides the generic one: on a Cartesian grid (the spherical instances are
-    covered above) each gives the generic instance's results bit for bit."""
+    """The sweeps have instances compiled for some tile depths (forward 16, 20,
+    24, 28; adjoint 28, 32, 40, 48) besides the generic one: on a Cartesian grid
+    (the spherical instances are covered above) each gives the generic
+    instance's results bit for bit."""
     wl = W.cartesian41()
-    ref = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=30, tile_k_adj=16)
-    for tk in (16, 20, 24, 28):
-        gp = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=tk, tile_k_adj=16)
+    ref = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=30, tile_k_adj=30)
+    for tk, tka in ((16, 28), (20, 32), (24, 40), (28, 48)):
+        gp = gpu_path(torch_cuda, wl, 1e-9, 200, R=wl["R"], tile_k=tk, tile_k_adj=tka)
         for key in ("tau", "lam", "grad", "it_f", "it_a", "T"):
-            assert np.array_equal(gp[key], ref[key]), (tk, key)
+            assert np.array_equal(gp[key], ref[key]), (tk, tka, key)
 
 
 def test_graph_replay_matches_eager(torch_cuda):
