@@ -450,7 +450,7 @@ __device__ __forceinline__ void fwd_kface_nodes(const Geo& G, const Src& S, cons
 
 // The per-node records a step needs (model, table) are loaded kPre steps
 // ahead into a ring slot indexed by the wave-uniform step number.
-constexpr int kPre = 3;       // forward: steps are long (the full update)
+constexpr int kPre = 4;       // forward: steps are long (the full update)
 constexpr int kPreAdj = 6;    // adjoint: short steps, so look further ahead
 
 struct FwdSlot {
